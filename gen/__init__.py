@@ -1,0 +1,15 @@
+"""Seeded synthetic inputs shared by the oracle side and the device side.
+
+This package only builds *inputs*: the coefficients of the 5-point elliptic
+operator (eq. (8) coefficients placed as in the five-point system eq. (10)),
+land masks, bathymetry and right-hand sides.  It holds none of the solver's
+arithmetic (no PCG, no approximate inverse).
+"""
+from .orca import (  # noqa: F401
+    Problem,
+    box_problem,
+    orca_problem,
+    ensemble_problems,
+    rhs_normal,
+    CONFIG_SEED_BASE,
+)

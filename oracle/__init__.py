@@ -1,0 +1,252 @@
+"""Oracle: plain FP64 CPU reference of the PCG-AINV method (test infrastructure).
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The device library never calls into it and it never
+calls into the device library; the two share only the seeded inputs of `gen`.
+
+The arithmetic lives in `oracle.c` (plain C, one thread, sequential sums,
+-ffp-contract=off); this module only marshals numpy arrays into it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+# A different build of the same source may be named here (mutation checks).
+_LIB = os.environ.get("PCGA_ORACLE_LIB", os.path.join(_HERE, "liboracle.so"))
+
+OK, NOCONV, EINVAL, EBREAKDOWN, ENOMEM = 0, 1, -1, -2, -3
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so from oracle.c with gcc (unfused FP64)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+                        "-shared", "-std=c99", "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+_p = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_dbl = ctypes.c_double
+_int = ctypes.c_int
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = ctypes.CDLL(_LIB)
+        L.ora_spmv.argtypes = [_i64, _i64, _int, _p, _p, _p, _p, _p]
+        L.ora_spmv.restype = None
+        L.ora_ainv_setup.argtypes = [_i64, _i64, _int, _p, _p, _p, _dbl,
+                                     ctypes.POINTER(_p), ctypes.POINTER(_i64),
+                                     ctypes.POINTER(_i64)]
+        L.ora_ainv_setup.restype = _int
+        L.ora_ainv_export.argtypes = [_p, _p, _p, _p, _p]
+        L.ora_ainv_export.restype = None
+        L.ora_ainv_free.argtypes = [_p]
+        L.ora_ainv_free.restype = None
+        L.ora_zt_apply.argtypes = [_i64, _p, _p, _p, _p, _p, _p]
+        L.ora_zt_apply.restype = None
+        L.ora_z_apply.argtypes = [_i64, _p, _p, _p, _p, _p]
+        L.ora_z_apply.restype = None
+        L.ora_prec_apply.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _p]
+        L.ora_prec_apply.restype = None
+        L.ora_pcg.argtypes = [_i64, _i64, _int, _p, _p, _p, _p, _p, _p, _p, _p, _p,
+                              _dbl, _i64, ctypes.POINTER(_i64), _p, _p, _p]
+        L.ora_pcg.restype = _int
+        L.ora_pcg_mixed.argtypes = [_i64, _i64, _int, _p, _p, _p, _p, _p, _p, _p, _p,
+                                    _p, _dbl, _dbl, _i64, _i64, ctypes.POINTER(_i64),
+                                    ctypes.POINTER(_i64), _p]
+        L.ora_pcg_mixed.restype = _int
+        L.ora_fsai_band.argtypes = [_i64, _i64, _int, _p, _p, _p, _i64, _p, _p]
+        L.ora_fsai_band.restype = _int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status, msg=""):
+        super().__init__(f"oracle status {status} {msg}")
+        self.status = status
+
+
+class AInv:
+    """Z (strict upper part, CSC: colptr/rowidx/val, rows ascending) and D."""
+
+    def __init__(self, n, colptr, rowidx, val, D):
+        self.n = n
+        self.colptr = colptr
+        self.rowidx = rowidx
+        self.val = val
+        self.D = D
+
+    @property
+    def nnz_off(self) -> int:
+        return int(self.colptr[-1])
+
+    def dense_z(self) -> np.ndarray:
+        Z = np.eye(self.n)
+        for j in range(self.n):
+            for a in range(self.colptr[j], self.colptr[j + 1]):
+                Z[self.rowidx[a], j] = self.val[a]
+        return Z
+
+
+def spmv(p, x):
+    """y = A x, rows summed in increasing column order."""
+    x = _f64(x)
+    y = np.empty_like(x)
+    lib().ora_spmv(p.nx, p.ny, int(p.periodic), _ptr(_f64(p.diag)), _ptr(_f64(p.ae)),
+                   _ptr(_f64(p.an)), _ptr(x), _ptr(y))
+    return y
+
+
+def ainv_setup(p, tau) -> AInv:
+    """AINV by A-orthogonalisation with drop tolerance tau (tau=inf: Jacobi)."""
+    L = lib()
+    h = ctypes.c_void_p()
+    nnz = ctypes.c_int64()
+    brow = ctypes.c_int64()
+    diag, ae, an = _f64(p.diag), _f64(p.ae), _f64(p.an)
+    st = L.ora_ainv_setup(p.nx, p.ny, int(p.periodic), _ptr(diag), _ptr(ae), _ptr(an),
+                          float(tau), ctypes.byref(h), ctypes.byref(nnz), ctypes.byref(brow))
+    if st != OK:
+        raise OracleError(st, f"(breakdown row {brow.value})")
+    n = p.nx * p.ny
+    colptr = np.empty(n + 1, dtype=np.int64)
+    rowidx = np.empty(max(nnz.value, 1), dtype=np.int64)
+    val = np.empty(max(nnz.value, 1), dtype=np.float64)
+    D = np.empty(n, dtype=np.float64)
+    L.ora_ainv_export(h, _ptr(colptr), _ptr(rowidx), _ptr(val), _ptr(D))
+    L.ora_ainv_free(h)
+    return AInv(n, colptr, rowidx[: nnz.value], val[: nnz.value], D)
+
+
+def zt_apply(F: AInv, r):
+    r = _f64(r)
+    t = np.empty_like(r)
+    lib().ora_zt_apply(F.n, _ptr(F.colptr), _ptr(F.rowidx), _ptr(F.val), _ptr(F.D),
+                       _ptr(r), _ptr(t))
+    return t
+
+
+def z_apply(F: AInv, t):
+    t = _f64(t)
+    s = np.empty_like(t)
+    lib().ora_z_apply(F.n, _ptr(F.colptr), _ptr(F.rowidx), _ptr(F.val), _ptr(t), _ptr(s))
+    return s
+
+
+def prec_apply(F: AInv, r):
+    r = _f64(r)
+    s = np.empty_like(r)
+    tmp = np.empty_like(r)
+    lib().ora_prec_apply(F.n, _ptr(F.colptr), _ptr(F.rowidx), _ptr(F.val), _ptr(F.D),
+                         _ptr(r), _ptr(s), _ptr(tmp))
+    return s
+
+
+class PCGResult:
+    def __init__(self, x, iters, hist, status, alphas=None, betas=None):
+        self.x = x
+        self.iters = iters
+        self.hist = hist
+        self.status = status
+        self.alphas = alphas
+        self.betas = betas
+
+
+def pcg(p, F: AInv, b=None, x0=None, tol=1e-10, maxit=None, scalars=False) -> PCGResult:
+    """Algorithm 1 in FP64.  Returns x, iteration count and residual history."""
+    n = p.nx * p.ny
+    b = _f64(p.b if b is None else b)
+    x = np.zeros(n) if x0 is None else _f64(x0).copy()
+    maxit = n if maxit is None else int(maxit)
+    hist = np.zeros(maxit + 1)
+    it = ctypes.c_int64()
+    al = np.zeros(max(maxit, 1)) if scalars else None
+    be = np.zeros(max(maxit, 1)) if scalars else None
+    st = lib().ora_pcg(p.nx, p.ny, int(p.periodic), _ptr(_f64(p.diag)), _ptr(_f64(p.ae)),
+                       _ptr(_f64(p.an)), _ptr(F.colptr), _ptr(F.rowidx), _ptr(F.val),
+                       _ptr(F.D), _ptr(b), _ptr(x), float(tol), maxit, ctypes.byref(it),
+                       _ptr(hist), _ptr(al) if scalars else None,
+                       _ptr(be) if scalars else None)
+    if st < 0:
+        raise OracleError(st)
+    k = it.value
+    return PCGResult(x, k, hist[: k + 1].copy(), st,
+                     al[:k].copy() if scalars else None,
+                     be[: max(k - 1, 0)].copy() if scalars else None)
+
+
+class MixedResult:
+    def __init__(self, x, outer, inner_total, outer_hist, status):
+        self.x = x
+        self.outer = outer
+        self.inner_total = inner_total
+        self.outer_hist = outer_hist
+        self.status = status
+
+
+def pcg_mixed(p, F: AInv, b=None, x0=None, tol=1e-10, inner_tol=1e-5, max_outer=30,
+              inner_maxit=None) -> MixedResult:
+    """FP64 refinement around an FP32 inner PCG (FP64 scalars)."""
+    n = p.nx * p.ny
+    b = _f64(p.b if b is None else b)
+    x = np.zeros(n) if x0 is None else _f64(x0).copy()
+    inner_maxit = n if inner_maxit is None else int(inner_maxit)
+    hist = np.zeros(max_outer + 1)
+    o = ctypes.c_int64()
+    tot = ctypes.c_int64()
+    st = lib().ora_pcg_mixed(p.nx, p.ny, int(p.periodic), _ptr(_f64(p.diag)),
+                             _ptr(_f64(p.ae)), _ptr(_f64(p.an)), _ptr(F.colptr),
+                             _ptr(F.rowidx), _ptr(F.val), _ptr(F.D), _ptr(b), _ptr(x),
+                             float(tol), float(inner_tol), int(max_outer), inner_maxit,
+                             ctypes.byref(o), ctypes.byref(tot), _ptr(hist))
+    if st < 0:
+        raise OracleError(st)
+    return MixedResult(x, o.value, tot.value, hist[: o.value + 1].copy(), st)
+
+
+def fsai_band(p, q):
+    """The paper's banded factor of T (|col-row|<=1 part of A), band q."""
+    n = p.nx * p.ny
+    zb = np.zeros(n * max(q, 1))
+    D = np.zeros(n)
+    st = lib().ora_fsai_band(p.nx, p.ny, int(p.periodic), _ptr(_f64(p.diag)),
+                             _ptr(_f64(p.ae)), _ptr(_f64(p.an)), int(q), _ptr(zb), _ptr(D))
+    if st != OK:
+        raise OracleError(st)
+    # convert to CSC AInv (drop structural zeros outside the matrix)
+    colptr = np.zeros(n + 1, dtype=np.int64)
+    rows, vals = [], []
+    for j in range(n):
+        for m in range(q - 1, -1, -1):         # rows ascending: j-q .. j-1
+            r = j - 1 - m
+            if r >= 0:
+                v = zb[j * q + (q - 1 - m)]
+                if v != 0.0:
+                    rows.append(r)
+                    vals.append(v)
+        colptr[j + 1] = len(rows)
+    return AInv(n, colptr, np.array(rows, dtype=np.int64), np.array(vals), D), zb
