@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Benchmark: PCG-AINV iterations/s on the 1442x1021 ORCA025-shaped grid.
+
+One step = one full FP64 PCG-AINV solve (Algorithm 1, P = Z D^-1 Z^T, drop
+tolerance 0.05) of the synthetic 1442x1021 problem from x0 = 0 to relative
+residual 1e-10, inputs resident in HBM.  `value` = iterations per second over
+the K timed steps.  The same JSON line carries the mixed-precision solve (FP32
+inner PCG + FP64 refinement) on the same GPU, the diagonal (Jacobi)
+preconditioner baseline, the roofline of the dominant kernel (HIP-event
+timing on the solver stream), and the FP64 oracle timed on the host.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+NX, NY, TAU, TOL = 1442, 1021, 0.05, 1e-10
+PEAK_HBM_GBS = 8000.0
+METRIC = "PCG iter/s + HBM GB/s @1442x1021 FP64 vs mixed; served solves/s, p99 lat"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(n, nnz_off, word):
+    """Algorithmic bytes per launch of the three iteration kernels (each array
+    once; Z entries = value + 4-byte index).  word = 8 (FP64) or 4 (FP32)."""
+    return {
+        "stencil": 7 * word * n,                       # s, d_old, diag, ae, an in; d, q out
+        "axpy_zt": 8 * word * n + (word + 4) * nnz_off,  # r, q, d, x, D^-1 in; r', x, t out; Z^T
+        "z_dot": 3 * word * n + (word + 4) * nnz_off,    # t, r' in; s out; Z
+    }
+
+
+def cpu_baseline(p, seconds=15.0):
+    """The FP64 oracle (single thread) on a bounded sample of the workload."""
+    import oracle
+    t0 = time.perf_counter()
+    F = oracle.ainv_setup(p, TAU)
+    setup_s = time.perf_counter() - t0
+    # calibrate on a few iterations, then run a sample of ~`seconds`
+    t0 = time.perf_counter()
+    oracle.pcg(p, F, tol=0.0, maxit=5)
+    per_it = (time.perf_counter() - t0) / 5
+    m = max(10, int(seconds / per_it))
+    t0 = time.perf_counter()
+    r = oracle.pcg(p, F, tol=0.0, maxit=m)
+    dt = time.perf_counter() - t0
+    return {"value": r.iters / dt, "unit": "iter/s", "cores": 1, "kind": "oracle",
+            "sample": f"{r.iters} FP64 PCG-AINV iterations of the oracle on the 1442x1021 "
+                      f"problem from x0=0 (setup {setup_s:.1f}s excluded), one thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--chunk", type=int, default=32)
+    ap.add_argument("--max-blocks", type=int, default=2048)
+    ap.add_argument("--no-graph", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
+                                   "design note (latitude bands + halo exchange), not built",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1210_1878_amd as P
+    from gen import orca
+
+    assert torch.cuda.is_available(), "bench.py needs a ROCm device"
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    p = orca.orca_problem(NX, NY, orca.CONFIG_SEED_BASE + 2)
+    log(f"generated {NX}x{NY} in {time.perf_counter() - t0:.1f}s")
+    A = P.Stencil5.from_problem(p)
+    t0 = time.perf_counter()
+    G = P.ainv_setup(A, TAU)
+    setup_s = time.perf_counter() - t0
+    log(f"ainv_setup {setup_s:.2f}s nnz_off={G.nnz_off} ({G.nnz_off / p.n:.2f}/cell)")
+    S64 = P.Solver(A, G, "fp64", device=dev)
+    Smx = P.Solver(A, G, "mixed", device=dev)
+    for S in (S64, Smx):
+        S.tune(chunk=args.chunk, use_graph=not args.no_graph, max_blocks=args.max_blocks)
+    b = torch.from_numpy(p.b).to(dev)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        S64.solve(b, tol=TOL)
+        Smx.solve_mixed(b, tol=TOL)
+    torch.cuda.synchronize()
+
+    # ---- timed region: K FP64 solves -------------------------------------
+    iters = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = S64.solve(b, tol=TOL)
+        iters += r.iters
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    it_s = iters / dt
+    log(f"fp64: {args.steps} solves, {iters} iterations, {dt * 1e3 / args.steps:.2f} ms/solve, "
+        f"{it_s:.0f} it/s, true relres {r.true_relres:.2e}")
+    fp64_true = r.true_relres
+    fp64_iters = r.iters
+
+    # ---- mixed precision on the same GPU ---------------------------------
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        m = Smx.solve_mixed(b, tol=TOL, inner_tol=1e-5, max_outer=30)
+    torch.cuda.synchronize()
+    dtm = (time.perf_counter() - t0) / args.steps
+    x64 = S64.solve(b, tol=TOL).x
+    err_mx = float((m.x - x64).norm() / x64.norm())
+    log(f"mixed: {dtm * 1e3:.2f} ms/solve, outer {m.outer}, inner {m.inner_total}, "
+        f"true relres {m.true_relres:.2e}, |x_mixed - x_fp64|/|x_fp64| {err_mx:.2e}")
+
+    # ---- Jacobi (NEMO diagonal preconditioner) baseline on the GPU ---------
+    Gj = P.ainv_setup(A, float("inf"))
+    Sj = P.Solver(A, Gj, "fp64", device=dev)
+    Sj.tune(chunk=args.chunk, use_graph=not args.no_graph, max_blocks=args.max_blocks)
+    Sj.solve(b, tol=TOL)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rj = Sj.solve(b, tol=TOL)
+    torch.cuda.synchronize()
+    dtj = time.perf_counter() - t0
+    log(f"jacobi: {rj.iters} iterations, {dtj * 1e3:.2f} ms/solve")
+
+    # ---- roofline of the dominant kernel (HIP events on the solver stream) --
+    ms = S64.profile_iteration(b, reps=100)
+    ms32 = Smx.profile_iteration(b, reps=100)
+    kb = kernel_bytes(p.n, G.nnz_off, 8)
+    kb32 = kernel_bytes(p.n, G.nnz_off, 4)
+    names = list(kb)
+    gbs = {k: kb[k] / (ms[i] * 1e-3) / 1e9 for i, k in enumerate(names)}
+    gbs32 = {k: kb32[k] / (ms32[i] * 1e-3) / 1e9 for i, k in enumerate(names)}
+    dom = max(range(3), key=lambda i: ms[i])
+    log("fp64 kernels ms: " + ", ".join(f"{k}={ms[i]:.4f} ({gbs[k]:.0f} GB/s)" for i, k in enumerate(names)))
+    log("fp32 kernels ms: " + ", ".join(f"{k}={ms32[i]:.4f} ({gbs32[k]:.0f} GB/s)" for i, k in enumerate(names)))
+    b_iter = sum(kb.values())
+    b_iter32 = sum(kb32.values())
+    it_time = sum(ms) * 1e-3
+    roof = {"bound": "hbm", "kernel": f"k_{names[dom]}<double>",
+            "achieved": round(gbs[names[dom]], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(gbs[names[dom]] / PEAK_HBM_GBS, 4), "traffic": None,
+            "bytes_per_launch": kb[names[dom]], "ms_per_launch": ms[dom]}
+
+    cpu = None
+    if not args.no_cpu:
+        log(f"cpu baseline (oracle, ~{args.cpu_seconds:.0f}s)")
+        cpu = cpu_baseline(p, args.cpu_seconds)
+        log(f"cpu: {cpu['value']:.2f} it/s")
+
+    out = {
+        "metric": METRIC, "value": round(it_s, 1), "unit": "iter/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "ORCA025-shaped 1442x1021 lat-lon grid (lat -78..90, EW periodic, "
+                               "35% land, seeded depth 500-5500 m), AINV drop tol 0.05, FP64 "
+                               "PCG to relres 1e-10 from x0=0",
+                   "nx": NX, "ny": NY, "n": p.n, "nnz_off": G.nnz_off, "tol": TOL,
+                   "drop_tol": TAU, "iters_per_solve": fp64_iters, "chunk": args.chunk,
+                   "graph": not args.no_graph, "max_blocks": args.max_blocks},
+        "fp64": {"iters": fp64_iters, "ms_per_solve": round(dt * 1e3 / args.steps, 3),
+                 "true_relres": fp64_true, "model_bytes_per_iter": b_iter,
+                 "model_gbs_per_iter_kernels": round(b_iter / it_time / 1e9, 1),
+                 "model_gbs_whole_solve": round(b_iter * it_s / 1e9, 1),
+                 "kernel_ms": dict(zip(names, [round(v, 5) for v in ms]))},
+        "mixed": {"ms_per_solve": round(dtm * 1e3, 3), "outer": m.outer, "inner_iters": m.inner_total,
+                  "inner_it_s": round(m.inner_total / dtm, 1), "true_relres": m.true_relres,
+                  "rel_err_vs_fp64": err_mx, "speedup_vs_fp64": round(dt / args.steps / dtm, 3),
+                  "model_bytes_per_inner_iter": b_iter32,
+                  "kernel_ms": dict(zip(names, [round(v, 5) for v in ms32]))},
+        "jacobi": {"iters": rj.iters, "ms_per_solve": round(dtj * 1e3, 3),
+                   "true_relres": rj.true_relres},
+        "setup_s": round(setup_s, 3),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

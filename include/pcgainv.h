@@ -1,0 +1,186 @@
+/*
+ * pcgainv.h -- C ABI of the MI355X PCG-AINV solver for the five-point
+ * elliptic sea-surface system.
+ *
+ * Method: preconditioned conjugate gradient (Algorithm 1 of Cuomo, De Michele,
+ * Farina, Chinnici, "A PCG implementation of an elliptic kernel in an ocean
+ * global circulation model based on GPU libraries") with the factored
+ * approximate inverse P = Z D^-1 Z^T ~ A^-1 (Sec. 3-4), where Z is unit upper
+ * triangular and is computed by A-orthogonalisation with a drop tolerance
+ * (the AINV of the paper's ref. [book4-14]; the threshold variant is the
+ * "drop tolerance" Bridson class discussed in Sec. 5).
+ *
+ * Conventions shared by every call
+ *   - All functions return an int status: PCGA_OK (0), PCGA_NOCONV (1, a
+ *     result is still produced), or a negative error code.  No function
+ *     aborts or throws across the ABI; pcga_strerror() names the code and
+ *     pcga_last_error() gives a message for the calling thread.
+ *   - Host pointers are plain C arrays owned by the caller.  Device pointers
+ *     are HIP device addresses on the current device, owned by the caller.
+ *   - The library never allocates device memory.  The caller provides one
+ *     device workspace per solver (size from pcga_workspace_bytes) and
+ *     keeps it alive until pcga_solver_destroy.  The library allocates only
+ *     small host and pinned-host buffers of its own.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default
+ *     stream.  All device work of a solver is ordered on its stream.
+ *
+ * Grid and storage (the natural ordering of Sec. 3: west->east, then
+ * south->north).  Cell (i, j), 0 <= i < nx, 0 <= j < ny, has index
+ * k = j*nx + i.  The operator is the symmetric positive definite negation of
+ * eq. (10): A[k,k] = sum of the cell's face coefficients, A[k,nbr] = -c_face.
+ * It is passed in "A5" form: three arrays of n = nx*ny doubles,
+ *   diag[k] = A[k,k],  ae[k] = A[k, east(k)],  an[k] = A[k, k+nx],
+ * where east(k) of a cell with i = nx-1 is the cell with i = 0 of the same
+ * row when PCGA_PERIODIC_X is set (east-west periodic globe), and does not
+ * exist otherwise (then ae[k] must be 0).  an[k] of the last row must be 0.
+ * Land cells are identity rows (diag 1, no couplings) with zero right-hand
+ * side.
+ */
+#ifndef PCGAINV_H
+#define PCGAINV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define PCGA_OK 0
+#define PCGA_NOCONV 1       /* maxit / max_outer reached; x and history valid */
+#define PCGA_EINVAL (-1)    /* bad shape, pointer, flag or non-5-point input  */
+#define PCGA_EBREAKDOWN (-2)/* pivot p_i <= 0 in setup, or (d,q) <= 0 / rho <= 0 */
+#define PCGA_ENAN (-3)      /* NaN or Inf met in the iteration               */
+#define PCGA_EHIP (-4)      /* HIP runtime error; see pcga_last_error()       */
+#define PCGA_ENOMEM (-5)    /* workspace too small or host allocation failed  */
+
+#define PCGA_PERIODIC_X 1u
+
+/* precision of a solver */
+#define PCGA_FP64 0         /* A, Z, vectors and scalars in FP64              */
+#define PCGA_MIXED 1        /* FP32 inner PCG (A, Z, vectors), FP64 scalars,  */
+                            /* FP64 residual, solution and outer refinement   */
+
+typedef struct pcga_a5 {
+    int32_t nx, ny;
+    uint32_t flags;         /* PCGA_PERIODIC_X or 0 */
+    const double *diag, *ae, *an;  /* host, n = nx*ny each, caller-owned */
+} pcga_a5_t;
+
+typedef struct pcga_ainv pcga_ainv_t;       /* opaque host (Z, D) */
+typedef struct pcga_solver pcga_solver_t;   /* opaque device solver */
+
+const char *pcga_strerror(int status);
+const char *pcga_last_error(void);
+
+/* ---- preconditioner setup (host, FP64) ---------------------------------
+ * pcga_ainv_setup: A-orthogonalisation of A with drop tolerance `drop_tol`
+ * (Sec. 3-5; ref. [book4-14]).  Z := I; for i = 0..n-1 (natural order):
+ * p_i = a_i^T z_i (row i of A, columns ascending); every later column z_j
+ * with c_j = a_i^T z_j != 0 is updated z_j <- z_j - (c_j/p_i) z_i, after
+ * which its touched off-diagonal entries with |z| < drop_tol or z == 0 are
+ * removed (an entry equal to drop_tol is kept).  D = diag(p).
+ * drop_tol = 0 gives the exact inverse factor; drop_tol = +inf gives Z = I,
+ * D = diag(A) (the diagonal preconditioner of eq. (11)-(12)).
+ * Deterministic: unfused FP64 in a fixed operation order.
+ * Errors: EINVAL (shape/flags/negative tol/A5 edge rules), EBREAKDOWN
+ * (p_i <= 0: A is not an M/H-matrix), ENOMEM.  On error *out is NULL.
+ */
+int pcga_ainv_setup(const pcga_a5_t *A, double drop_tol, pcga_ainv_t **out);
+
+/* Sizes of a setup result: n and the number of stored off-diagonal entries
+ * of Z (the unit diagonal is implicit). */
+int pcga_ainv_info(const pcga_ainv_t *F, int64_t *n, int64_t *nnz_off);
+
+/* Export Z (strict upper part) in CSC with rows ascending in each column:
+ * colptr[n+1], rowidx[nnz_off], val[nnz_off]; and D[n].  Any pointer may be
+ * NULL to skip that array. */
+int pcga_ainv_export(const pcga_ainv_t *F, int64_t *colptr, int32_t *rowidx,
+                     double *val, double *D);
+
+/* Build (Z, D) from caller-given CSC data (strict upper part of a unit upper
+ * triangular Z, rows ascending per column, plus D > 0).  Lets a caller use a
+ * factor computed elsewhere, e.g. the paper's banded factor of T. */
+int pcga_ainv_import(int64_t n, const int64_t *colptr, const int32_t *rowidx,
+                     const double *val, const double *D, pcga_ainv_t **out);
+
+int pcga_ainv_free(pcga_ainv_t *F);
+
+/* ---- device solver ------------------------------------------------------
+ * pcga_workspace_bytes: device bytes needed for (A, F, precision).
+ * pcga_solver_create: validate, lay A and (Z, D) out in the workspace
+ * (row-major A5 arrays; Z^T and Z in sliced ELL with per-slice lanes per
+ * row), and bind the stream.  The solver keeps no pointer to A or F.
+ * Errors: EINVAL, ENOMEM (bytes too small), EHIP.
+ */
+int pcga_workspace_bytes(const pcga_a5_t *A, const pcga_ainv_t *F, int precision,
+                         size_t *bytes);
+int pcga_solver_create(const pcga_a5_t *A, const pcga_ainv_t *F, int precision,
+                       void *dev_workspace, size_t bytes, void *stream,
+                       pcga_solver_t **out);
+int pcga_solver_destroy(pcga_solver_t *S);
+
+/* Solver facts: n, nnz_off, precision, and the modelled device bytes one PCG
+ * iteration must move (each array once; FP64: 144 n + 24 nnz_pad, mixed inner:
+ * 72 n + 16 nnz_pad, nnz_pad = stored sliced-ELL entries of Z^T plus Z
+ * divided by 2). */
+int pcga_solver_info(const pcga_solver_t *S, int64_t *n, int64_t *nnz_off,
+                     int32_t *precision, double *bytes_per_iter);
+
+/* Launch tuning (used by the autotuner): iterations per chunk (even,
+ * 2..512), whether chunks are replayed through a captured HIP graph (1) or
+ * launched directly (0), and the maximum number of workgroups per kernel
+ * (8..4096; each workgroup streams one contiguous range of the grid).
+ * Takes effect at the next solve.  Results of a solve are bitwise
+ * reproducible for fixed settings. */
+int pcga_solver_tune(pcga_solver_t *S, int32_t chunk, int32_t use_graph, int32_t max_blocks);
+
+/* ---- solves --------------------------------------------------------------
+ * pcga_pcg_solve: Algorithm 1 with s = Z D^-1 Z^T r and the direction update
+ * d_{k+1} = s_{k+1} + beta_k d_k.  b_dev, x_dev: n FP64 device values; x_dev
+ * holds x0 on entry and x on return.  Stops when ||r_k||/||b|| <= tol
+ * (recursive residual, 2-norm) or k = maxit (maxit < 0 means n).
+ * hist_host (capacity hist_cap, may be NULL) receives ||r_k||/||b|| for
+ * k = 0..iters (truncated to hist_cap); *hist_len = iters + 1.
+ * *true_relres = ||b - A x||/||b|| recomputed in FP64 (NULL to skip).
+ * ||b|| = 0 gives x = 0, iters = 0, hist = {0}.
+ * Returns OK, NOCONV, EBREAKDOWN, ENAN, EINVAL (wrong precision), EHIP.
+ * Requires a PCGA_FP64 solver.  The call returns after the solve finished.
+ */
+int pcga_pcg_solve(pcga_solver_t *S, const double *b_dev, double *x_dev, double tol,
+                   int32_t maxit, int32_t *iters, double *hist_host, int32_t hist_cap,
+                   int32_t *hist_len, double *true_relres);
+
+/* pcga_pcg_solve_mixed: FP64 iterative refinement.  Outer step o: r = b - A x
+ * in FP64; stop if ||r||/||b|| <= tol; else solve A e = r with the FP32
+ * inner PCG (FP32 A, Z, D^-1 and vectors; FP64 alpha/beta/rho and dot sums)
+ * to relative residual inner_tol (at most inner_maxit iterations, < 0: n),
+ * then x += e in FP64.  At most max_outer corrections.  hist_host receives
+ * the outer true residuals ||b - A x_o||/||b||, o = 0..*outer.
+ * Requires a PCGA_MIXED solver. */
+int pcga_pcg_solve_mixed(pcga_solver_t *S, const double *b_dev, double *x_dev,
+                         double tol, double inner_tol, int32_t max_outer,
+                         int32_t inner_maxit, int32_t *outer, int32_t *inner_total,
+                         double *hist_host, int32_t hist_cap, int32_t *hist_len,
+                         double *true_relres);
+
+/* ---- single steps of the hot path (for parity tests and profiling) -------
+ * y = A x (FP64, the five-point product of eq. (10)). */
+int pcga_apply_a(pcga_solver_t *S, const double *x_dev, double *y_dev);
+/* t = D^-1 Z^T r and s = Z t, in the solver's inner precision (FP64 data for
+ * PCGA_FP64; FP32 data with FP64 input/output for PCGA_MIXED). */
+int pcga_apply_prec(pcga_solver_t *S, const double *r_dev, double *t_dev, double *s_dev);
+
+/* Average device time in milliseconds of each kernel of one PCG iteration,
+ * ms_out[0] = d-update + five-point product + (d,q); ms_out[1] = residual and
+ * solution update + D^-1 Z^T r; ms_out[2] = Z t + (s,r).  Measured with HIP
+ * events on the solver's stream over `reps` (1..100000) iterations started
+ * from x0 = 0 with no stopping test (FP64 kernels for PCGA_FP64, the FP32
+ * inner kernels for PCGA_MIXED).  For benchmarks; the solver stays usable. */
+int pcga_profile_iteration(pcga_solver_t *S, const double *b_dev, int32_t reps, double *ms_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCGAINV_H */

@@ -1,0 +1,275 @@
+"""Python face of the C ABI: the paper's problem statement as calls.
+
+    F = ainv_setup(A, drop_tol)                      # (Z, D), host FP64
+    x, iters, hist = pcg_solve(A, F, b, x0, tol, maxit)
+    res = pcg_solve_mixed(A, F, b, x0, tol, inner_tol=1e-5, max_outer=...)
+
+`A` is a Stencil5 (host numpy FP64 arrays in A5 form), `b` and `x0` are torch
+tensors on a ROCm device.  Torch provides the device memory (the solver's
+workspace is one uint8 tensor) and the stream; every step of the solve runs
+in the HIP kernels of libpcgainv.so.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import numpy as np
+
+from . import _lib
+from ._lib import FP64, MIXED, PERIODIC_X, check
+
+
+@dataclasses.dataclass
+class Stencil5:
+    """Five-point operator in A5 form (see include/pcgainv.h)."""
+    nx: int
+    ny: int
+    periodic: bool
+    diag: np.ndarray
+    ae: np.ndarray
+    an: np.ndarray
+
+    def __post_init__(self):
+        n = self.nx * self.ny
+        for f in ("diag", "ae", "an"):
+            a = np.ascontiguousarray(getattr(self, f), dtype=np.float64)
+            if a.shape != (n,):
+                raise ValueError(f"{f} must have shape ({n},)")
+            setattr(self, f, a)
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny
+
+    @classmethod
+    def from_problem(cls, p) -> "Stencil5":
+        return cls(p.nx, p.ny, bool(p.periodic), p.diag, p.ae, p.an)
+
+    def c_struct(self) -> _lib.A5:
+        return _lib.A5(self.nx, self.ny, PERIODIC_X if self.periodic else 0,
+                       self.diag.ctypes.data, self.ae.ctypes.data, self.an.ctypes.data)
+
+
+class AInv:
+    """Handle to (Z, D) computed on the host."""
+
+    def __init__(self, handle, keep=None):
+        self._h = handle
+        self._keep = keep
+        L = _lib.load()
+        n = ctypes.c_int64()
+        nnz = ctypes.c_int64()
+        check(L.pcga_ainv_info(self._h, ctypes.byref(n), ctypes.byref(nnz)), "pcga_ainv_info")
+        self.n = n.value
+        self.nnz_off = nnz.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def export(self):
+        """(colptr int64[n+1], rowidx int32[nnz], val float64[nnz], D float64[n])."""
+        L = _lib.load()
+        colptr = np.empty(self.n + 1, dtype=np.int64)
+        rowidx = np.empty(max(self.nnz_off, 1), dtype=np.int32)
+        val = np.empty(max(self.nnz_off, 1), dtype=np.float64)
+        D = np.empty(self.n, dtype=np.float64)
+        check(L.pcga_ainv_export(self._h, colptr.ctypes.data, rowidx.ctypes.data,
+                                 val.ctypes.data, D.ctypes.data), "pcga_ainv_export")
+        return colptr, rowidx[: self.nnz_off], val[: self.nnz_off], D
+
+    @classmethod
+    def from_csc(cls, n, colptr, rowidx, val, D) -> "AInv":
+        L = _lib.load()
+        colptr = np.ascontiguousarray(colptr, dtype=np.int64)
+        rowidx = np.ascontiguousarray(rowidx, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        D = np.ascontiguousarray(D, dtype=np.float64)
+        h = ctypes.c_void_p()
+        check(L.pcga_ainv_import(int(n), colptr.ctypes.data, rowidx.ctypes.data if len(rowidx) else None,
+                                 val.ctypes.data if len(val) else None, D.ctypes.data,
+                                 ctypes.byref(h)), "pcga_ainv_import")
+        return cls(h)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            try:
+                _lib.load().pcga_ainv_free(h)
+            except Exception:
+                pass
+            self._h = None
+
+
+def ainv_setup(A: Stencil5, drop_tol: float) -> AInv:
+    """Approximate inverse factor by A-orthogonalisation with a drop tolerance."""
+    L = _lib.load()
+    h = ctypes.c_void_p()
+    a5 = A.c_struct()
+    check(L.pcga_ainv_setup(ctypes.byref(a5), float(drop_tol), ctypes.byref(h)),
+          "pcga_ainv_setup")
+    return AInv(h)
+
+
+def _dev_ptr(t, dtype, n):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()
+            and t.numel() == n):
+        raise ValueError(f"expected a contiguous {dtype} device tensor with {n} elements")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclasses.dataclass
+class SolveResult:
+    x: object
+    iters: int
+    hist: np.ndarray
+    status: int
+    true_relres: float
+    outer: int = 0
+    inner_total: int = 0
+
+    def __iter__(self):          # x, iters, hist = pcg_solve(...)
+        return iter((self.x, self.iters, self.hist))
+
+
+class Solver:
+    """Device solver for one grid: A, Z^T/Z (sliced ELL) and D^-1 resident in
+    a torch-allocated workspace; FP64 or mixed precision."""
+
+    def __init__(self, A: Stencil5, F: AInv, precision: str = "fp64", device=None, stream=None):
+        import torch
+        L = _lib.load()
+        self.A = A
+        self.precision = {"fp64": FP64, "mixed": MIXED}[precision]
+        self.device = torch.device("cuda" if device is None else device)
+        a5 = A.c_struct()
+        nbytes = ctypes.c_size_t()
+        check(L.pcga_workspace_bytes(ctypes.byref(a5), F.handle, self.precision,
+                                     ctypes.byref(nbytes)), "pcga_workspace_bytes")
+        self.workspace_bytes = nbytes.value
+        with torch.cuda.device(self.device):
+            # a stream of its own (default priority): chunks are captured into
+            # HIP graphs, which the legacy default stream does not allow
+            self.stream = torch.cuda.Stream(self.device) if stream is None else stream
+            self.ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+            h = ctypes.c_void_p()
+            check(L.pcga_solver_create(ctypes.byref(a5), F.handle, self.precision,
+                                       ctypes.c_void_p(self.ws.data_ptr()), self.workspace_bytes,
+                                       ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+                  "pcga_solver_create")
+        self._h = h
+        n = ctypes.c_int64()
+        nnz = ctypes.c_int64()
+        prec = ctypes.c_int32()
+        bpi = ctypes.c_double()
+        check(L.pcga_solver_info(self._h, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(prec),
+                                 ctypes.byref(bpi)), "pcga_solver_info")
+        self.n = n.value
+        self.nnz_off = nnz.value
+        self.bytes_per_iter = bpi.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def tune(self, chunk=32, use_graph=True, max_blocks=2048):
+        check(_lib.load().pcga_solver_tune(self._h, int(chunk), int(bool(use_graph)),
+                                           int(max_blocks)), "pcga_solver_tune")
+
+    def _xb(self, b, x0):
+        import torch
+        # order the solver's stream after the caller's work on b / x0
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        if x0 is None:
+            x = torch.zeros(self.n, dtype=torch.float64, device=self.device)
+        else:
+            x = x0.clone()
+        return _dev_ptr(b, torch.float64, self.n), x, _dev_ptr(x, torch.float64, self.n)
+
+    def solve(self, b, x0=None, tol=1e-10, maxit=None, hist_cap=None) -> SolveResult:
+        L = _lib.load()
+        bp, x, xp = self._xb(b, x0)
+        maxit = -1 if maxit is None else int(maxit)
+        cap = (self.n if maxit < 0 else maxit) + 1 if hist_cap is None else int(hist_cap)
+        hist = np.zeros(max(cap, 1))
+        iters = ctypes.c_int32()
+        hl = ctypes.c_int32()
+        tr = ctypes.c_double()
+        st = L.pcga_pcg_solve(self._h, bp, xp, float(tol), maxit, ctypes.byref(iters),
+                              hist.ctypes.data, cap, ctypes.byref(hl), ctypes.byref(tr))
+        check(st, "pcga_pcg_solve", allow=(_lib.OK, _lib.NOCONV))
+        return SolveResult(x, iters.value, hist[: min(hl.value, cap)].copy(), st, tr.value)
+
+    def solve_mixed(self, b, x0=None, tol=1e-10, inner_tol=1e-5, max_outer=20,
+                    inner_maxit=None) -> SolveResult:
+        L = _lib.load()
+        bp, x, xp = self._xb(b, x0)
+        cap = max_outer + 1
+        hist = np.zeros(cap)
+        outer = ctypes.c_int32()
+        tot = ctypes.c_int32()
+        hl = ctypes.c_int32()
+        tr = ctypes.c_double()
+        st = L.pcga_pcg_solve_mixed(self._h, bp, xp, float(tol), float(inner_tol), int(max_outer),
+                                    -1 if inner_maxit is None else int(inner_maxit),
+                                    ctypes.byref(outer), ctypes.byref(tot), hist.ctypes.data, cap,
+                                    ctypes.byref(hl), ctypes.byref(tr))
+        check(st, "pcga_pcg_solve_mixed", allow=(_lib.OK, _lib.NOCONV))
+        return SolveResult(x, tot.value, hist[: hl.value].copy(), st, tr.value,
+                           outer=outer.value, inner_total=tot.value)
+
+    def apply_a(self, x):
+        import torch
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        y = torch.empty_like(x)
+        check(_lib.load().pcga_apply_a(self._h, _dev_ptr(x, torch.float64, self.n),
+                                       _dev_ptr(y, torch.float64, self.n)), "pcga_apply_a")
+        return y
+
+    def apply_prec(self, r):
+        import torch
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        t = torch.empty_like(r)
+        s = torch.empty_like(r)
+        check(_lib.load().pcga_apply_prec(self._h, _dev_ptr(r, torch.float64, self.n),
+                                          _dev_ptr(t, torch.float64, self.n),
+                                          _dev_ptr(s, torch.float64, self.n)), "pcga_apply_prec")
+        return t, s
+
+    def profile_iteration(self, b, reps=50):
+        """Average ms of the three iteration kernels (HIP events, solver stream)."""
+        import torch
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        ms = (ctypes.c_double * 3)()
+        check(_lib.load().pcga_profile_iteration(self._h, _dev_ptr(b, torch.float64, self.n),
+                                                 int(reps), ms), "pcga_profile_iteration")
+        return list(ms)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.load().pcga_solver_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pcg_solve(A: Stencil5, F: AInv, b, x0=None, tol=1e-10, maxit=None, solver=None) -> SolveResult:
+    """Algorithm 1 in FP64 on the device: returns (x, iters, hist) (plus status
+    and the FP64 true residual as attributes)."""
+    S = solver if solver is not None else Solver(A, F, "fp64", device=b.device)
+    return S.solve(b, x0, tol=tol, maxit=maxit)
+
+
+def pcg_solve_mixed(A: Stencil5, F: AInv, b, x0=None, tol=1e-10, inner_tol=1e-5, max_outer=20,
+                    inner_maxit=None, solver=None) -> SolveResult:
+    """FP32 inner PCG with FP64 iterative refinement."""
+    S = solver if solver is not None else Solver(A, F, "mixed", device=b.device)
+    return S.solve_mixed(b, x0, tol=tol, inner_tol=inner_tol, max_outer=max_outer,
+                         inner_maxit=inner_maxit)

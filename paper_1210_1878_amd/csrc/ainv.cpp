@@ -1,0 +1,186 @@
+// ainv.cpp -- host FP64 approximate-inverse setup (A-orthogonalisation with a
+// drop tolerance), the preconditioner of Sec. 3-5 in the threshold form of
+// the paper's ref. [book4-14].
+//
+// Left-looking organisation: column z_j is finished before z_{j+1} starts.
+// For column j the steps i < j are visited in increasing order; step i
+// applies z_j <- z_j - (a_i^T z_j / p_i) z_i when a_i^T z_j != 0 and then
+// removes the touched off-diagonal entries with |z| < tau or z == 0.  This
+// is the same sequence of floating-point operations on every column as the
+// right-looking statement of the method (each column is only ever modified
+// by earlier steps, in increasing order, each using a final z_i), so the
+// pattern and values are fully determined by the order rules:
+//   - a_i^T z sums over row i of A in increasing column order, unfused,
+//     starting from +0.0 and skipping absent entries;
+//   - a new entry takes the value 0.0 - m*v.
+// This file must be compiled without floating-point contraction.
+//
+// Candidate steps for column j are kept in a min-heap: a step i can touch
+// z_j only if row i of A has a column where z_j is nonzero, i.e. i is a grid
+// neighbour (or the cell itself) of some entry of z_j.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <functional>
+#include <new>
+#include <queue>
+#include <vector>
+
+#include "pcga_host.h"
+
+namespace pcga {
+
+// Sorted entries of row k of A (at most 5), zero couplings omitted.
+int A5View::row(int64_t k, int64_t *cols, double *vals) const {
+    const int64_t i = k % nx, j = k / nx;
+    struct E { int64_t c; double v; } e[5];
+    int m = 0;
+    const double w = (i > 0) ? ae[k - 1] : (periodic ? ae[k + nx - 1] : 0.0);
+    const int64_t wc = (i > 0) ? k - 1 : k + nx - 1;
+    const double east = (i < nx - 1 || periodic) ? ae[k] : 0.0;
+    const int64_t ec = (i < nx - 1) ? k + 1 : k - nx + 1;
+    if (j > 0 && an[k - nx] != 0.0) e[m++] = {k - nx, an[k - nx]};
+    if (w != 0.0) e[m++] = {wc, w};
+    e[m++] = {k, diag[k]};
+    if (east != 0.0) e[m++] = {ec, east};
+    if (j < ny - 1 && an[k] != 0.0) e[m++] = {k + nx, an[k]};
+    std::sort(e, e + m, [](const E &a, const E &b) { return a.c < b.c; });
+    for (int t = 0; t < m; t++) { cols[t] = e[t].c; vals[t] = e[t].v; }
+    return m;
+}
+
+int A5View::validate() const {
+    if (nx < 1 || ny < 1 || !diag || !ae || !an) return PCGA_EINVAL;
+    if ((int64_t)nx * ny > (int64_t)INT32_MAX) return PCGA_EINVAL;
+    if (periodic && nx < 3) return PCGA_EINVAL;
+    for (int64_t j = 0; j < ny; j++) {
+        for (int64_t i = 0; i < nx; i++) {
+            const int64_t k = j * nx + i;
+            if (!(diag[k] > 0.0) || !std::isfinite(diag[k])) return PCGA_EINVAL;
+            if (!std::isfinite(ae[k]) || !std::isfinite(an[k])) return PCGA_EINVAL;
+            if (!periodic && i == nx - 1 && ae[k] != 0.0) return PCGA_EINVAL;
+            if (j == ny - 1 && an[k] != 0.0) return PCGA_EINVAL;
+        }
+    }
+    return PCGA_OK;
+}
+
+// Rows of A whose stencil contains column r (A is symmetric, so these are the
+// columns of row r): r itself and its grid neighbours.
+static int stencil_of(const A5View &A, int64_t r, int64_t *out) {
+    const int64_t nx = A.nx, i = r % nx, j = r / nx;
+    int m = 0;
+    out[m++] = r;
+    if (i > 0) out[m++] = r - 1; else if (A.periodic) out[m++] = r + nx - 1;
+    if (i < nx - 1) out[m++] = r + 1; else if (A.periodic) out[m++] = r - nx + 1;
+    if (j > 0) out[m++] = r - nx;
+    if (j < A.ny - 1) out[m++] = r + nx;
+    return m;
+}
+
+int ainv_build(const A5View &A, double tau, AinvFactor &F, int64_t *bad_row) {
+    if (bad_row) *bad_row = -1;
+    int st = A.validate();
+    if (st) return st;
+    if (!(tau >= 0.0)) return PCGA_EINVAL;
+    const int64_t n = (int64_t)A.nx * A.ny;
+    try {
+        F.n = n;
+        F.colptr.assign(1, 0);
+        F.colptr.reserve(n + 1);
+        F.rowidx.clear();
+        F.val.clear();
+        F.D.assign(n, 0.0);
+
+        std::vector<double> w(n, 0.0);        // values of the column being built
+        std::vector<int64_t> live(n, -1);     // live[r] == j: entry r present in z_j
+        std::vector<int64_t> queued(n, -1);   // queued[i] == j: step i already queued
+        std::vector<int64_t> pattern;         // rows ever inserted into z_j
+        std::priority_queue<int64_t, std::vector<int64_t>, std::greater<int64_t>> steps;
+
+        int64_t cols[5];
+        double vals[5];
+        int64_t nb[5];
+
+        for (int64_t j = 0; j < n; j++) {
+            pattern.clear();
+            w[j] = 1.0;
+            live[j] = j;
+            pattern.push_back(j);
+            {
+                int m = stencil_of(A, j, nb);
+                for (int t = 0; t < m; t++)
+                    if (nb[t] < j && queued[nb[t]] != j) { queued[nb[t]] = j; steps.push(nb[t]); }
+            }
+            while (!steps.empty()) {
+                const int64_t i = steps.top();
+                steps.pop();
+                // c = a_i^T z_j
+                const int m = A.row(i, cols, vals);
+                double c = 0.0;
+                for (int t = 0; t < m; t++) {
+                    if (live[cols[t]] == j) {
+                        const double pr = vals[t] * w[cols[t]];
+                        c = c + pr;
+                    }
+                }
+                if (c == 0.0) continue;
+                const double mult = c / F.D[i];
+                // z_j <- z_j - mult * z_i ; z_i = stored off-diagonals + unit at i
+                const int64_t a0 = F.colptr[i], a1 = F.colptr[i + 1];
+                for (int64_t a = a0; a <= a1; a++) {
+                    const int64_t r = (a < a1) ? (int64_t)F.rowidx[a] : i;
+                    const double v = (a < a1) ? F.val[a] : 1.0;
+                    const double pr = mult * v;
+                    const bool had = (live[r] == j);
+                    const double nv = (had ? w[r] : 0.0) - pr;
+                    if (nv == 0.0 || std::fabs(nv) < tau) {
+                        if (had) live[r] = -1;
+                        continue;
+                    }
+                    w[r] = nv;
+                    if (!had) {
+                        live[r] = j;
+                        pattern.push_back(r);
+                        int mm = stencil_of(A, r, nb);
+                        for (int t = 0; t < mm; t++) {
+                            const int64_t s = nb[t];
+                            if (s > i && s < j && queued[s] != j) { queued[s] = j; steps.push(s); }
+                        }
+                    }
+                }
+            }
+            // p_j = a_j^T z_j
+            const int m = A.row(j, cols, vals);
+            double p = 0.0;
+            for (int t = 0; t < m; t++) {
+                if (live[cols[t]] == j) {
+                    const double pr = vals[t] * w[cols[t]];
+                    p = p + pr;
+                }
+            }
+            if (!(p > 0.0)) {
+                if (bad_row) *bad_row = j;
+                return PCGA_EBREAKDOWN;
+            }
+            F.D[j] = p;
+            // store the live off-diagonal entries, rows ascending
+            std::sort(pattern.begin(), pattern.end());
+            for (int64_t r : pattern) {
+                if (r != j && live[r] == j) {
+                    F.rowidx.push_back((int32_t)r);
+                    F.val.push_back(w[r]);
+                }
+                live[r] = -1;
+            }
+            F.colptr.push_back((int64_t)F.rowidx.size());
+        }
+    } catch (const std::bad_alloc &) {
+        return PCGA_ENOMEM;
+    }
+    return PCGA_OK;
+}
+
+}  // namespace pcga

@@ -1,0 +1,61 @@
+// pcga_host.h -- host-side data structures of the PCG-AINV library.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pcgainv.h"
+
+namespace pcga {
+
+// Read-only view of the five-point operator in A5 form (see pcgainv.h).
+struct A5View {
+    int64_t nx = 0, ny = 0;
+    bool periodic = false;
+    const double *diag = nullptr, *ae = nullptr, *an = nullptr;
+
+    int64_t n() const { return nx * ny; }
+    int row(int64_t k, int64_t *cols, double *vals) const;
+    int validate() const;
+};
+
+// Unit upper triangular Z (strict upper part in CSC, rows ascending) and D.
+struct AinvFactor {
+    int64_t n = 0;
+    std::vector<int64_t> colptr;
+    std::vector<int32_t> rowidx;
+    std::vector<double> val;
+    std::vector<double> D;
+    int64_t nnz_off() const { return colptr.empty() ? 0 : colptr.back(); }
+};
+
+int ainv_build(const A5View &A, double tau, AinvFactor &F, int64_t *bad_row);
+
+// Sliced ELL with a per-slice number of lanes per row ("SELL-L").
+//   A slice is one 64-lane wavefront.  It covers `nrows = 64 >> lpr_log2`
+//   consecutive rows starting at `row0`; lane l works on row
+//   row0 + (l >> lpr_log2) and takes entries e = c*2^lpr_log2 + (l & (2^lpr-1))
+//   for c = 0..width-1.  Entry (c, l) of slice s is stored at
+//   off[s] + c*64 + l (column-major in the slice, so each step c is one
+//   coalesced 64-wide load).  Padding entries have value 0 and point to the
+//   lane's own row.
+struct SellLayout {
+    int64_t nrows_total = 0;
+    std::vector<int32_t> row0;      // [nslices]
+    std::vector<int32_t> meta;      // [nslices]: lpr_log2 | (width << 8)
+    std::vector<int64_t> off;       // [nslices + 1] entry offsets
+    std::vector<int32_t> idx;       // [off.back()]
+    std::vector<double> val;        // [off.back()]
+    int64_t nslices() const { return (int64_t)row0.size(); }
+    int64_t entries() const { return off.empty() ? 0 : off.back(); }
+};
+
+// rows given as CSR (rowptr[m+1], col, val with columns ascending per row).
+void sell_build(int64_t m, const int64_t *rowptr, const int32_t *col, const double *val,
+                int target_width, SellLayout &L);
+
+std::string &last_error();
+int fail(int code, const std::string &msg);
+
+}  // namespace pcga

@@ -1,0 +1,889 @@
+// solver.hip -- C ABI of the PCG-AINV library: setup handles, workspace
+// layout, and the host driver of the device iteration.
+//
+// A solve is: a prologue (r0 = b - A x0, t = D^-1 Z^T r0, s0 = Z t, rho0,
+// d0 = s0; Algorithm 1 lines 1-4) and then chunks of `chunk` iterations,
+// each replayed from a captured HIP graph (or launched directly).  Every
+// kernel first reads the device `done` flag, so the iterations after
+// convergence cost one empty launch each and the iteration count is exact.
+// The host keeps two chunks in flight: it enqueues chunk c+1, then waits for
+// chunk c's snapshot of the control block (scalars, flag, history ring).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "pcga_host.h"
+
+namespace pcga {
+
+std::string &last_error() {
+    static thread_local std::string msg;
+    return msg;
+}
+
+int fail(int code, const std::string &msg) {
+    last_error() = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(PCGA_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+static int map_status(int s) {
+    switch (s) {
+        case kStOk: return PCGA_OK;
+        case kStNoconv: return PCGA_NOCONV;
+        case kStBreak: return PCGA_EBREAKDOWN;
+        case kStNan: return PCGA_ENAN;
+        default: return PCGA_EHIP;
+    }
+}
+
+}  // namespace pcga
+
+using namespace pcga;
+
+struct pcga_ainv {
+    AinvFactor F;
+};
+
+// ---------------------------------------------------------------------------
+// Workspace carving: one bump pass computes the size (base == nullptr) or
+// assigns the pointers.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *b) : base((char *)b) {}
+    template <class T>
+    T *take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+struct HostLayouts {
+    SellLayout zt, z;
+};
+
+int build_layouts(const AinvFactor &F, int target_width, HostLayouts &H) {
+    try {
+        const int64_t n = F.n;
+        // rows of Z^T = columns of Z: the CSC arrays read as CSR
+        sell_build(n, F.colptr.data(), F.rowidx.data(), F.val.data(), target_width, H.zt);
+        // rows of Z: transpose the CSC (columns visited in increasing order,
+        // so each row's columns come out ascending)
+        std::vector<int64_t> rp(n + 1, 0);
+        for (int64_t a = 0; a < F.nnz_off(); a++) rp[F.rowidx[a] + 1]++;
+        for (int64_t k = 0; k < n; k++) rp[k + 1] += rp[k];
+        std::vector<int32_t> col(F.nnz_off());
+        std::vector<double> val(F.nnz_off());
+        std::vector<int64_t> pos(rp.begin(), rp.end() - 1);
+        for (int64_t j = 0; j < n; j++)
+            for (int64_t a = F.colptr[j]; a < F.colptr[j + 1]; a++) {
+                const int64_t p = pos[F.rowidx[a]]++;
+                col[p] = (int32_t)j;
+                val[p] = F.val[a];
+            }
+        sell_build(n, rp.data(), col.data(), val.data(), target_width, H.z);
+    } catch (const std::bad_alloc &) {
+        return fail(PCGA_ENOMEM, "host allocation failed while building sliced-ELL layouts");
+    }
+    return PCGA_OK;
+}
+
+}  // namespace
+
+struct pcga_solver {
+    int precision = PCGA_FP64;
+    int64_t n = 0, nnz_off = 0;
+    int nx = 0, ny = 0, periodic = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+
+    DevOp<double> A64{};
+    DevOp<float> A32{};
+    DevSell<double> zt64{}, z64{};
+    DevSell<float> zt32{}, z32{};
+    double *dinv64 = nullptr;
+    float *dinv32 = nullptr;
+
+    // FP64 iteration vectors (PCGA_FP64)
+    double *x = nullptr, *r[2] = {nullptr, nullptr}, *s = nullptr, *d[2] = {nullptr, nullptr},
+           *q = nullptr, *t = nullptr;
+    // FP32 inner vectors and FP64 outer solution (PCGA_MIXED)
+    float *e32 = nullptr, *r32[2] = {nullptr, nullptr}, *s32 = nullptr,
+          *d32[2] = {nullptr, nullptr}, *q32 = nullptr, *t32 = nullptr;
+    double *x64[2] = {nullptr, nullptr};
+    float *tmp32 = nullptr;   // apply_prec staging (mixed)
+
+    double *partials = nullptr;
+    CtlBlock *cb = nullptr;
+    CtlBlock *snap[2] = {nullptr, nullptr};   // pinned host
+    hipEvent_t ev[2] = {nullptr, nullptr};
+
+    int ntiles = 0;
+    int g_st = 1, g_zt = 1, g_z = 1;
+    int max_blocks = 2048;
+    int chunk = 32;
+    bool use_graph = true;
+    hipGraphExec_t graph = nullptr;
+    int graph_chunk = 0;
+    int64_t sell_entries = 0;
+    double bytes_per_iter = 0.0;
+
+    void grids() {
+        const int gm = std::max(1, std::min(max_blocks, kMaxBlocks));
+        ntiles = (int)((n + kBlock - 1) / kBlock);
+        g_st = std::max(1, std::min(ntiles, gm));
+        const int nsz = precision == PCGA_FP64 ? zt64.nslices : zt32.nslices;
+        const int nsr = precision == PCGA_FP64 ? z64.nslices : z32.nslices;
+        g_zt = std::max(1, std::min((nsz + 3) / 4, gm));
+        g_z = std::max(1, std::min((nsr + 3) / 4, gm));
+    }
+};
+
+namespace {
+
+// Assign all device pointers of S from `base` (or size them when null).
+size_t carve(pcga_solver &S, void *base, const HostLayouts &H) {
+    Carver C(base);
+    const int64_t n = S.n;
+    const bool f64 = S.precision == PCGA_FP64;
+    S.A64.diag = C.take<double>(n);
+    S.A64.ae = C.take<double>(n);
+    S.A64.an = C.take<double>(n);
+    auto sell = [&](const SellLayout &L, auto &dst, auto tag) {
+        using T = decltype(tag);
+        dst.row0 = C.take<int32_t>(L.nslices());
+        dst.meta = C.take<int32_t>(L.nslices());
+        dst.off = C.take<int64_t>(L.nslices() + 1);
+        dst.idx = C.take<int32_t>(std::max<int64_t>(L.entries(), 1));
+        dst.val = C.take<T>(std::max<int64_t>(L.entries(), 1));
+        dst.nslices = (int32_t)L.nslices();
+        dst.nrows = (int32_t)L.nrows_total;
+    };
+    if (f64) {
+        S.dinv64 = C.take<double>(n);
+        sell(H.zt, S.zt64, double());
+        sell(H.z, S.z64, double());
+        S.x = C.take<double>(n);
+        S.r[0] = C.take<double>(n);
+        S.r[1] = C.take<double>(n);
+        S.s = C.take<double>(n);
+        S.d[0] = C.take<double>(n);
+        S.d[1] = C.take<double>(n);
+        S.q = C.take<double>(n);
+        S.t = C.take<double>(n);
+    } else {
+        S.A32.diag = C.take<float>(n);
+        S.A32.ae = C.take<float>(n);
+        S.A32.an = C.take<float>(n);
+        S.dinv32 = C.take<float>(n);
+        sell(H.zt, S.zt32, float());
+        sell(H.z, S.z32, float());
+        S.e32 = C.take<float>(n);
+        S.r32[0] = C.take<float>(n);
+        S.r32[1] = C.take<float>(n);
+        S.s32 = C.take<float>(n);
+        S.d32[0] = C.take<float>(n);
+        S.d32[1] = C.take<float>(n);
+        S.q32 = C.take<float>(n);
+        S.t32 = C.take<float>(n);
+        S.tmp32 = C.take<float>(n);
+        S.x64[0] = C.take<double>(n);
+        S.x64[1] = C.take<double>(n);
+    }
+    S.partials = C.take<double>(3 * (size_t)kMaxBlocks);
+    S.cb = C.take<CtlBlock>(1);
+    return C.off + 256;
+}
+
+A5View view_of(const pcga_a5_t *A) {
+    A5View V;
+    V.nx = A->nx;
+    V.ny = A->ny;
+    V.periodic = (A->flags & PCGA_PERIODIC_X) != 0;
+    V.diag = A->diag;
+    V.ae = A->ae;
+    V.an = A->an;
+    return V;
+}
+
+int check_a5(const pcga_a5_t *A) {
+    if (!A) return fail(PCGA_EINVAL, "A is NULL");
+    if (A->flags & ~PCGA_PERIODIC_X) return fail(PCGA_EINVAL, "unknown flag bits in A->flags");
+    A5View V = view_of(A);
+    if (V.validate() != PCGA_OK)
+        return fail(PCGA_EINVAL,
+                    "invalid A5 operator (shape, non-positive/non-finite diagonal, or "
+                    "couplings across a non-periodic edge / the last row)");
+    return PCGA_OK;
+}
+
+constexpr int kTargetWidth = 16;
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *pcga_strerror(int s) {
+    switch (s) {
+        case PCGA_OK: return "ok";
+        case PCGA_NOCONV: return "not converged (iteration limit reached)";
+        case PCGA_EINVAL: return "invalid argument";
+        case PCGA_EBREAKDOWN: return "breakdown (non-positive pivot or curvature)";
+        case PCGA_ENAN: return "NaN or Inf in the iteration";
+        case PCGA_EHIP: return "HIP runtime error";
+        case PCGA_ENOMEM: return "out of memory / workspace too small";
+        default: return "unknown status";
+    }
+}
+
+const char *pcga_last_error(void) { return last_error().c_str(); }
+
+int pcga_ainv_setup(const pcga_a5_t *A, double drop_tol, pcga_ainv_t **out) {
+    if (!out) return fail(PCGA_EINVAL, "out is NULL");
+    *out = nullptr;
+    int st = check_a5(A);
+    if (st) return st;
+    if (!(drop_tol >= 0.0)) return fail(PCGA_EINVAL, "drop_tol must be >= 0 (inf allowed)");
+    pcga_ainv *h = new (std::nothrow) pcga_ainv;
+    if (!h) return fail(PCGA_ENOMEM, "host allocation failed");
+    int64_t bad = -1;
+    st = ainv_build(view_of(A), drop_tol, h->F, &bad);
+    if (st) {
+        delete h;
+        if (st == PCGA_EBREAKDOWN)
+            return fail(st, "AINV breakdown: pivot p_i <= 0 at row " + std::to_string(bad));
+        return fail(st, "AINV setup failed");
+    }
+    *out = h;
+    return PCGA_OK;
+}
+
+int pcga_ainv_info(const pcga_ainv_t *F, int64_t *n, int64_t *nnz_off) {
+    if (!F) return fail(PCGA_EINVAL, "F is NULL");
+    if (n) *n = F->F.n;
+    if (nnz_off) *nnz_off = F->F.nnz_off();
+    return PCGA_OK;
+}
+
+int pcga_ainv_export(const pcga_ainv_t *F, int64_t *colptr, int32_t *rowidx, double *val,
+                     double *D) {
+    if (!F) return fail(PCGA_EINVAL, "F is NULL");
+    const AinvFactor &Z = F->F;
+    if (colptr) std::memcpy(colptr, Z.colptr.data(), (Z.n + 1) * sizeof(int64_t));
+    if (rowidx && Z.nnz_off()) std::memcpy(rowidx, Z.rowidx.data(), Z.nnz_off() * sizeof(int32_t));
+    if (val && Z.nnz_off()) std::memcpy(val, Z.val.data(), Z.nnz_off() * sizeof(double));
+    if (D) std::memcpy(D, Z.D.data(), Z.n * sizeof(double));
+    return PCGA_OK;
+}
+
+int pcga_ainv_import(int64_t n, const int64_t *colptr, const int32_t *rowidx,
+                     const double *val, const double *D, pcga_ainv_t **out) {
+    if (!out) return fail(PCGA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > INT32_MAX || !colptr || !D) return fail(PCGA_EINVAL, "bad n or NULL array");
+    if (colptr[0] != 0) return fail(PCGA_EINVAL, "colptr[0] must be 0");
+    for (int64_t j = 0; j < n; j++) {
+        if (colptr[j + 1] < colptr[j]) return fail(PCGA_EINVAL, "colptr not monotone");
+        if (!(D[j] > 0.0) || !std::isfinite(D[j])) return fail(PCGA_EINVAL, "D must be > 0");
+        for (int64_t a = colptr[j]; a < colptr[j + 1]; a++) {
+            if (!rowidx || !val) return fail(PCGA_EINVAL, "NULL rowidx/val with entries");
+            if (rowidx[a] < 0 || rowidx[a] >= j) return fail(PCGA_EINVAL, "Z must be strictly upper");
+            if (a > colptr[j] && rowidx[a] <= rowidx[a - 1])
+                return fail(PCGA_EINVAL, "rows must ascend within a column");
+            if (!std::isfinite(val[a])) return fail(PCGA_EINVAL, "non-finite value in Z");
+        }
+    }
+    pcga_ainv *h = new (std::nothrow) pcga_ainv;
+    if (!h) return fail(PCGA_ENOMEM, "host allocation failed");
+    try {
+        h->F.n = n;
+        h->F.colptr.assign(colptr, colptr + n + 1);
+        h->F.rowidx.assign(rowidx, rowidx + colptr[n]);
+        h->F.val.assign(val, val + colptr[n]);
+        h->F.D.assign(D, D + n);
+    } catch (const std::bad_alloc &) {
+        delete h;
+        return fail(PCGA_ENOMEM, "host allocation failed");
+    }
+    *out = h;
+    return PCGA_OK;
+}
+
+int pcga_ainv_free(pcga_ainv_t *F) {
+    delete F;
+    return PCGA_OK;
+}
+
+int pcga_workspace_bytes(const pcga_a5_t *A, const pcga_ainv_t *F, int precision,
+                         size_t *bytes) {
+    if (!bytes || !F) return fail(PCGA_EINVAL, "NULL argument");
+    int st = check_a5(A);
+    if (st) return st;
+    if (precision != PCGA_FP64 && precision != PCGA_MIXED)
+        return fail(PCGA_EINVAL, "precision must be PCGA_FP64 or PCGA_MIXED");
+    if (F->F.n != (int64_t)A->nx * A->ny) return fail(PCGA_EINVAL, "F does not match A");
+    HostLayouts H;
+    st = build_layouts(F->F, kTargetWidth, H);
+    if (st) return st;
+    pcga_solver S;
+    S.precision = precision;
+    S.n = F->F.n;
+    *bytes = carve(S, nullptr, H);
+    return PCGA_OK;
+}
+
+int pcga_solver_create(const pcga_a5_t *A, const pcga_ainv_t *F, int precision, void *ws,
+                       size_t bytes, void *stream, pcga_solver_t **out) {
+    if (!out) return fail(PCGA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!F || !ws) return fail(PCGA_EINVAL, "NULL F or workspace");
+    int st = check_a5(A);
+    if (st) return st;
+    if (precision != PCGA_FP64 && precision != PCGA_MIXED)
+        return fail(PCGA_EINVAL, "precision must be PCGA_FP64 or PCGA_MIXED");
+    const int64_t n = (int64_t)A->nx * A->ny;
+    if (F->F.n != n) return fail(PCGA_EINVAL, "F does not match A");
+    if (((uintptr_t)ws & 255u) != 0) return fail(PCGA_EINVAL, "workspace must be 256-byte aligned");
+
+    HostLayouts H;
+    st = build_layouts(F->F, kTargetWidth, H);
+    if (st) return st;
+    pcga_solver *S = new (std::nothrow) pcga_solver;
+    if (!S) return fail(PCGA_ENOMEM, "host allocation failed");
+    S->precision = precision;
+    S->n = n;
+    S->nnz_off = F->F.nnz_off();
+    S->nx = A->nx;
+    S->ny = A->ny;
+    S->periodic = (A->flags & PCGA_PERIODIC_X) ? 1 : 0;
+    S->stream = (hipStream_t)stream;
+    const size_t need = carve(*S, nullptr, H);
+    if (bytes < need) {
+        delete S;
+        return fail(PCGA_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+    }
+    S->ws = ws;
+    S->ws_bytes = bytes;
+    carve(*S, ws, H);
+    for (auto *dv : {&S->A64}) {
+        dv->nx = A->nx;
+        dv->ny = A->ny;
+        dv->periodic = S->periodic;
+        dv->n = (int32_t)n;
+    }
+    S->A32.nx = A->nx;
+    S->A32.ny = A->ny;
+    S->A32.periodic = S->periodic;
+    S->A32.n = (int32_t)n;
+    S->sell_entries = H.zt.entries() + H.z.entries();
+
+    auto fail_free = [&](int code) {
+        if (S->snap[0]) (void)hipHostFree(S->snap[0]);
+        if (S->snap[1]) (void)hipHostFree(S->snap[1]);
+        if (S->ev[0]) (void)hipEventDestroy(S->ev[0]);
+        if (S->ev[1]) (void)hipEventDestroy(S->ev[1]);
+        delete S;
+        return code;
+    };
+#define CR(expr)                                                                               \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail_free(fail(PCGA_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_))); \
+    } while (0)
+
+    CR(hipGetDevice(&S->device));
+    CR(hipHostMalloc((void **)&S->snap[0], sizeof(CtlBlock), hipHostMallocDefault));
+    CR(hipHostMalloc((void **)&S->snap[1], sizeof(CtlBlock), hipHostMallocDefault));
+    CR(hipEventCreateWithFlags(&S->ev[0], hipEventDisableTiming));
+    CR(hipEventCreateWithFlags(&S->ev[1], hipEventDisableTiming));
+
+    hipStream_t sm = S->stream;
+    const size_t nb8 = n * sizeof(double);
+    // operator (FP64 always; FP32 copy for the mixed inner solve)
+    CR(hipMemcpyAsync((void *)S->A64.diag, A->diag, nb8, hipMemcpyHostToDevice, sm));
+    CR(hipMemcpyAsync((void *)S->A64.ae, A->ae, nb8, hipMemcpyHostToDevice, sm));
+    CR(hipMemcpyAsync((void *)S->A64.an, A->an, nb8, hipMemcpyHostToDevice, sm));
+    std::vector<double> dinv(n);
+    for (int64_t k = 0; k < n; k++) dinv[k] = 1.0 / F->F.D[k];
+    auto up_sell = [&](const SellLayout &L, auto &dst) -> hipError_t {
+        using T = std::remove_const_t<std::remove_pointer_t<decltype(dst.val)>>;
+        hipError_t e;
+        e = hipMemcpyAsync((void *)dst.row0, L.row0.data(), L.row0.size() * 4, hipMemcpyHostToDevice, sm);
+        if (e) return e;
+        e = hipMemcpyAsync((void *)dst.meta, L.meta.data(), L.meta.size() * 4, hipMemcpyHostToDevice, sm);
+        if (e) return e;
+        e = hipMemcpyAsync((void *)dst.off, L.off.data(), L.off.size() * 8, hipMemcpyHostToDevice, sm);
+        if (e) return e;
+        if (L.entries() == 0) return hipSuccess;
+        e = hipMemcpyAsync((void *)dst.idx, L.idx.data(), L.idx.size() * 4, hipMemcpyHostToDevice, sm);
+        if (e) return e;
+        if constexpr (std::is_same_v<T, double>) {
+            return hipMemcpyAsync((void *)dst.val, L.val.data(), L.val.size() * 8,
+                                  hipMemcpyHostToDevice, sm);
+        } else {
+            std::vector<float> v32(L.val.begin(), L.val.end());
+            e = hipMemcpyAsync((void *)dst.val, v32.data(), v32.size() * 4, hipMemcpyHostToDevice, sm);
+            if (e) return e;
+            return hipStreamSynchronize(sm);   // v32 is a temporary
+        }
+    };
+    if (precision == PCGA_FP64) {
+        CR(hipMemcpyAsync(S->dinv64, dinv.data(), nb8, hipMemcpyHostToDevice, sm));
+        CR(up_sell(H.zt, S->zt64));
+        CR(up_sell(H.z, S->z64));
+    } else {
+        std::vector<float> f(n);
+        for (int64_t k = 0; k < n; k++) f[k] = (float)A->diag[k];
+        CR(hipMemcpyAsync((void *)S->A32.diag, f.data(), n * 4, hipMemcpyHostToDevice, sm));
+        CR(hipStreamSynchronize(sm));
+        for (int64_t k = 0; k < n; k++) f[k] = (float)A->ae[k];
+        CR(hipMemcpyAsync((void *)S->A32.ae, f.data(), n * 4, hipMemcpyHostToDevice, sm));
+        CR(hipStreamSynchronize(sm));
+        for (int64_t k = 0; k < n; k++) f[k] = (float)A->an[k];
+        CR(hipMemcpyAsync((void *)S->A32.an, f.data(), n * 4, hipMemcpyHostToDevice, sm));
+        CR(hipStreamSynchronize(sm));
+        for (int64_t k = 0; k < n; k++) f[k] = (float)dinv[k];
+        CR(hipMemcpyAsync(S->dinv32, f.data(), n * 4, hipMemcpyHostToDevice, sm));
+        CR(hipStreamSynchronize(sm));
+        CR(up_sell(H.zt, S->zt32));
+        CR(up_sell(H.z, S->z32));
+    }
+    CR(hipMemsetAsync(S->cb, 0, sizeof(CtlBlock), sm));
+    CR(hipStreamSynchronize(sm));
+#undef CR
+    S->grids();
+    // modelled compulsory bytes per iteration (see kernels.h):
+    //   stencil: s, d_old, diag, ae, an read; d_new, q written       7 n words
+    //   zt: r, q, d, x, dinv read; r', x, t written; Z^T entries     8 n words + E_zt
+    //   z:  t, r' read; s written; Z entries                         3 n words + E_z
+    const double E = (double)S->sell_entries;
+    if (precision == PCGA_FP64)
+        S->bytes_per_iter = 8.0 * 18.0 * n + 12.0 * E;
+    else
+        S->bytes_per_iter = 4.0 * 18.0 * n + 8.0 * E;
+    *out = S;
+    return PCGA_OK;
+}
+
+int pcga_solver_destroy(pcga_solver_t *S) {
+    if (!S) return PCGA_OK;
+    if (S->graph) (void)hipGraphExecDestroy(S->graph);
+    if (S->snap[0]) (void)hipHostFree(S->snap[0]);
+    if (S->snap[1]) (void)hipHostFree(S->snap[1]);
+    if (S->ev[0]) (void)hipEventDestroy(S->ev[0]);
+    if (S->ev[1]) (void)hipEventDestroy(S->ev[1]);
+    delete S;
+    return PCGA_OK;
+}
+
+int pcga_solver_info(const pcga_solver_t *S, int64_t *n, int64_t *nnz_off, int32_t *precision,
+                     double *bytes_per_iter) {
+    if (!S) return fail(PCGA_EINVAL, "S is NULL");
+    if (n) *n = S->n;
+    if (nnz_off) *nnz_off = S->nnz_off;
+    if (precision) *precision = S->precision;
+    if (bytes_per_iter) *bytes_per_iter = S->bytes_per_iter;
+    return PCGA_OK;
+}
+
+int pcga_solver_tune(pcga_solver_t *S, int32_t chunk, int32_t use_graph, int32_t max_blocks) {
+    if (!S) return fail(PCGA_EINVAL, "S is NULL");
+    if (chunk < 2 || chunk > 512 || (chunk & 1))
+        return fail(PCGA_EINVAL, "chunk must be even, 2..512");
+    if (max_blocks < 8 || max_blocks > kMaxBlocks)
+        return fail(PCGA_EINVAL, "max_blocks must be 8.." + std::to_string(kMaxBlocks));
+    if (S->graph && (chunk != S->graph_chunk || max_blocks != S->max_blocks)) {
+        (void)hipGraphExecDestroy(S->graph);
+        S->graph = nullptr;
+    }
+    S->chunk = chunk;
+    S->use_graph = use_graph != 0;
+    S->max_blocks = max_blocks;
+    S->grids();
+    return PCGA_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// iteration driver
+// ===========================================================================
+namespace {
+
+template <typename T>
+struct IterBufs {
+    DevOp<T> A;
+    DevSell<T> zt, z;
+    const T *dinv;
+    T *x, *r[2], *s, *d[2], *q, *t;
+};
+
+IterBufs<double> bufs64(pcga_solver &S) {
+    return {S.A64, S.zt64, S.z64, S.dinv64, S.x, {S.r[0], S.r[1]}, S.s, {S.d[0], S.d[1]}, S.q, S.t};
+}
+IterBufs<float> bufs32(pcga_solver &S) {
+    return {S.A32, S.zt32, S.z32, S.dinv32, S.e32, {S.r32[0], S.r32[1]}, S.s32,
+            {S.d32[0], S.d32[1]}, S.q32, S.t32};
+}
+
+template <typename T>
+void launch_iters(pcga_solver &S, const IterBufs<T> &B, int count) {
+    for (int it = 0; it < count; it++) {
+        const int p = it & 1;
+        k_stencil<T><<<S.g_st, kBlock, 0, S.stream>>>(B.A, B.s, B.d[p], B.d[p ^ 1], B.q, S.cb,
+                                                      S.partials, S.ntiles);
+        k_zt<T, true><<<S.g_zt, kBlock, 0, S.stream>>>(B.zt, B.dinv, B.r[p], B.q, B.d[p ^ 1],
+                                                       B.r[p ^ 1], B.x, B.t, S.cb, S.partials);
+        k_z<T, true, false><<<S.g_z, kBlock, 0, S.stream>>>(B.z, B.t, B.r[p ^ 1], B.s, S.cb,
+                                                           S.partials);
+    }
+}
+
+template <typename T>
+int prologue_prec(pcga_solver &S, const IterBufs<T> &B) {
+    // t = D^-1 Z^T r0 ; s0 = Z t ; rho0 = (s0, r0) ; beta = 0 ; d[0] = 0
+    HIP_TRY(hipMemsetAsync(B.d[0], 0, S.n * sizeof(T), S.stream));
+    k_zt<T, false><<<S.g_zt, kBlock, 0, S.stream>>>(B.zt, B.dinv, B.r[0], nullptr, nullptr,
+                                                    nullptr, nullptr, B.t, S.cb, S.partials);
+    k_z<T, true, true><<<S.g_z, kBlock, 0, S.stream>>>(B.z, B.t, B.r[0], B.s, S.cb, S.partials);
+    HIP_TRY(hipGetLastError());
+    return PCGA_OK;
+}
+
+int snapshot(pcga_solver &S, int slot) {
+    HIP_TRY(hipMemcpyAsync(S.snap[slot], S.cb, sizeof(CtlBlock), hipMemcpyDeviceToHost, S.stream));
+    HIP_TRY(hipEventRecord(S.ev[slot], S.stream));
+    return PCGA_OK;
+}
+
+int wait_snap(pcga_solver &S, int slot) {
+    HIP_TRY(hipEventSynchronize(S.ev[slot]));
+    return PCGA_OK;
+}
+
+template <typename T>
+int ensure_graph(pcga_solver &S, const IterBufs<T> &B) {
+    if (S.graph && S.graph_chunk == S.chunk) return PCGA_OK;
+    if (S.graph) {
+        (void)hipGraphExecDestroy(S.graph);
+        S.graph = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(S.stream, hipStreamCaptureModeThreadLocal));
+    launch_iters<T>(S, B, S.chunk);
+    hipError_t e = hipStreamEndCapture(S.stream, &g);
+    if (e != hipSuccess) return fail(PCGA_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&S.graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        S.graph = nullptr;
+        return fail(PCGA_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    S.graph_chunk = S.chunk;
+    return PCGA_OK;
+}
+
+// Run chunks until the device sets `done`.  hist_out receives entries
+// k_first..k (k_first = 1) as they arrive; returns the final snapshot slot.
+template <typename T>
+int run_chunks(pcga_solver &S, const IterBufs<T> &B, double *hist_out, int64_t hist_cap,
+               int64_t maxit, int &final_slot) {
+    int st;
+    if (S.use_graph) {
+        st = ensure_graph<T>(S, B);
+        if (st) return st;
+    }
+    auto launch = [&](int slot) -> int {
+        if (S.use_graph) {
+            HIP_TRY(hipGraphLaunch(S.graph, S.stream));
+        } else {
+            launch_iters<T>(S, B, S.chunk);
+            HIP_TRY(hipGetLastError());
+        }
+        return snapshot(S, slot);
+    };
+    int64_t seen = 0;
+    int64_t c = 0;
+    // Guards against a device-side failure to finish: the iteration count
+    // must advance with every chunk and cannot exceed maxit.
+    const int64_t max_chunks = maxit / S.chunk + 4;
+    if ((st = launch(0))) return st;
+    for (;;) {
+        if ((st = launch((c + 1) & 1))) return st;
+        if ((st = wait_snap(S, c & 1))) return st;
+        const CtlBlock *sn = S.snap[c & 1];
+        const int64_t k = sn->c.k;
+        if (!sn->c.done && (k <= seen || c > max_chunks)) {
+            (void)wait_snap(S, (c + 1) & 1);
+            return fail(PCGA_EHIP, "device iteration did not advance (k=" + std::to_string(k) + ")");
+        }
+        if (hist_out) {
+            for (int64_t i = seen + 1; i <= k && i < hist_cap; i++)
+                hist_out[i] = sn->hist[i & (kHistRing - 1)];
+        }
+        seen = k;
+        if (sn->c.done) {
+            if ((st = wait_snap(S, (c + 1) & 1))) return st;
+            final_slot = c & 1;
+            return PCGA_OK;
+        }
+        c++;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int pcga_pcg_solve(pcga_solver_t *S, const double *b_dev, double *x_dev, double tol, int32_t maxit,
+                   int32_t *iters, double *hist_host, int32_t hist_cap, int32_t *hist_len,
+                   double *true_relres) {
+    if (!S || !b_dev || !x_dev) return fail(PCGA_EINVAL, "NULL argument");
+    if (S->precision != PCGA_FP64) return fail(PCGA_EINVAL, "pcga_pcg_solve needs a PCGA_FP64 solver");
+    if (!(tol >= 0.0)) return fail(PCGA_EINVAL, "tol must be >= 0");
+    if (maxit < 0) maxit = (int32_t)std::min<int64_t>(S->n, INT32_MAX);
+    if (hist_cap < 0 || (hist_cap > 0 && !hist_host)) return fail(PCGA_EINVAL, "bad history buffer");
+    HIP_TRY(hipSetDevice(S->device));
+    pcga_solver &R = *S;
+    IterBufs<double> B = bufs64(R);
+    const size_t nb8 = R.n * sizeof(double);
+    HIP_TRY(hipMemcpyAsync(R.x, x_dev, nb8, hipMemcpyDeviceToDevice, R.stream));
+    k_residual<0><<<R.g_st, kBlock, 0, R.stream>>>(R.A64, R.x, b_dev, R.r[0], R.cb, R.partials,
+                                                   R.ntiles, tol, maxit);
+    int st = prologue_prec<double>(R, B);
+    if (st) return st;
+    if ((st = snapshot(R, 0))) return st;
+    if ((st = wait_snap(R, 0))) return st;
+    const Ctl c0 = R.snap[0]->c;
+    if (hist_cap > 0) hist_host[0] = R.snap[0]->hist[0];
+    if (c0.nb == 0.0) {
+        HIP_TRY(hipMemsetAsync(x_dev, 0, nb8, R.stream));
+        HIP_TRY(hipStreamSynchronize(R.stream));
+        if (iters) *iters = 0;
+        if (hist_len) *hist_len = 1;
+        if (hist_cap > 0) hist_host[0] = 0.0;
+        if (true_relres) *true_relres = 0.0;
+        return PCGA_OK;
+    }
+    int slot = 0;
+    if (!c0.done) {
+        if ((st = run_chunks<double>(R, B, hist_host, hist_cap, maxit, slot))) return st;
+    }
+    const Ctl cf = R.snap[slot]->c;
+    // true residual ||b - A x|| in FP64
+    k_residual<1><<<R.g_st, kBlock, 0, R.stream>>>(R.A64, R.x, b_dev, nullptr, R.cb, R.partials,
+                                                   R.ntiles, 0.0, 0);
+    HIP_TRY(hipMemcpyAsync(x_dev, R.x, nb8, hipMemcpyDeviceToDevice, R.stream));
+    if ((st = snapshot(R, 0))) return st;
+    if ((st = wait_snap(R, 0))) return st;
+    const Ctl ct = R.snap[0]->c;
+    if (iters) *iters = cf.k;
+    if (hist_len) *hist_len = cf.k + 1;
+    if (true_relres) *true_relres = std::sqrt(ct.rr_true) / std::sqrt(ct.bb);
+    const int rs = map_status(cf.status);
+    if (rs == PCGA_EBREAKDOWN) fail(rs, "PCG breakdown: (d,q) <= 0 or rho <= 0");
+    if (rs == PCGA_ENAN) fail(rs, "NaN/Inf in the PCG iteration");
+    return rs;
+}
+
+int pcga_pcg_solve_mixed(pcga_solver_t *S, const double *b_dev, double *x_dev, double tol,
+                         double inner_tol, int32_t max_outer, int32_t inner_maxit, int32_t *outer,
+                         int32_t *inner_total, double *hist_host, int32_t hist_cap,
+                         int32_t *hist_len, double *true_relres) {
+    if (!S || !b_dev || !x_dev) return fail(PCGA_EINVAL, "NULL argument");
+    if (S->precision != PCGA_MIXED)
+        return fail(PCGA_EINVAL, "pcga_pcg_solve_mixed needs a PCGA_MIXED solver");
+    if (!(tol >= 0.0) || !(inner_tol > 0.0) || max_outer < 0)
+        return fail(PCGA_EINVAL, "bad tolerances or max_outer");
+    if (inner_maxit < 0) inner_maxit = (int32_t)std::min<int64_t>(S->n, INT32_MAX);
+    if (hist_cap < 0 || (hist_cap > 0 && !hist_host)) return fail(PCGA_EINVAL, "bad history buffer");
+    HIP_TRY(hipSetDevice(S->device));
+    pcga_solver &R = *S;
+    IterBufs<float> B = bufs32(R);
+    const size_t nb8 = R.n * sizeof(double);
+    HIP_TRY(hipMemcpyAsync(R.x64[0], x_dev, nb8, hipMemcpyDeviceToDevice, R.stream));
+    int cur = 0, o = 0, total = 0, st = 0, result = PCGA_OK;
+    double rel = 0.0;
+    for (;;) {
+        if (o == 0)
+            k_refine<false><<<R.g_st, kBlock, 0, R.stream>>>(R.A64, R.x64[cur], nullptr, nullptr,
+                                                             b_dev, R.r32[0], R.cb, R.partials,
+                                                             R.ntiles, inner_tol, inner_maxit);
+        else {
+            k_refine<true><<<R.g_st, kBlock, 0, R.stream>>>(R.A64, R.x64[cur], R.e32,
+                                                            R.x64[cur ^ 1], b_dev, R.r32[0], R.cb,
+                                                            R.partials, R.ntiles, inner_tol,
+                                                            inner_maxit);
+            cur ^= 1;
+        }
+        HIP_TRY(hipGetLastError());
+        if ((st = snapshot(R, 0))) return st;
+        if ((st = wait_snap(R, 0))) return st;
+        const Ctl c = R.snap[0]->c;
+        if (c.bb == 0.0) {
+            HIP_TRY(hipMemsetAsync(x_dev, 0, nb8, R.stream));
+            HIP_TRY(hipStreamSynchronize(R.stream));
+            if (outer) *outer = 0;
+            if (inner_total) *inner_total = 0;
+            if (hist_len) *hist_len = 1;
+            if (hist_cap > 0) hist_host[0] = 0.0;
+            if (true_relres) *true_relres = 0.0;
+            return PCGA_OK;
+        }
+        rel = std::sqrt(c.rr_true) / std::sqrt(c.bb);
+        if (o < hist_cap) hist_host[o] = rel;
+        if (!(rel == rel) || std::isinf(rel)) { result = fail(PCGA_ENAN, "NaN/Inf in residual"); break; }
+        if (rel <= tol) { result = PCGA_OK; break; }
+        if (o == max_outer) { result = PCGA_NOCONV; break; }
+        // inner FP32 PCG for A e = r32, e0 = 0
+        HIP_TRY(hipMemsetAsync(B.x, 0, R.n * sizeof(float), R.stream));
+        if ((st = prologue_prec<float>(R, B))) return st;
+        if ((st = snapshot(R, 0))) return st;
+        if ((st = wait_snap(R, 0))) return st;
+        int slot = 0;
+        if (!R.snap[0]->c.done) {
+            if ((st = run_chunks<float>(R, B, nullptr, 0, inner_maxit, slot))) return st;
+        }
+        const Ctl ci = R.snap[slot]->c;
+        const int is = map_status(ci.status);
+        if (is == PCGA_EBREAKDOWN || is == PCGA_ENAN) {
+            result = fail(is, "inner FP32 PCG failed (breakdown or NaN)");
+            break;
+        }
+        total += ci.k;
+        o++;
+    }
+    HIP_TRY(hipMemcpyAsync(x_dev, R.x64[cur], nb8, hipMemcpyDeviceToDevice, R.stream));
+    HIP_TRY(hipStreamSynchronize(R.stream));
+    if (outer) *outer = o;
+    if (inner_total) *inner_total = total;
+    if (hist_len) *hist_len = o + 1;
+    if (true_relres) *true_relres = rel;
+    return result;
+}
+
+int pcga_apply_a(pcga_solver_t *S, const double *x_dev, double *y_dev) {
+    if (!S || !x_dev || !y_dev) return fail(PCGA_EINVAL, "NULL argument");
+    HIP_TRY(hipSetDevice(S->device));
+    k_apply_a<<<S->g_st, kBlock, 0, S->stream>>>(S->A64, x_dev, y_dev, S->ntiles);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    return PCGA_OK;
+}
+
+int pcga_apply_prec(pcga_solver_t *S, const double *r_dev, double *t_dev, double *s_dev) {
+    if (!S || !r_dev || !t_dev || !s_dev) return fail(PCGA_EINVAL, "NULL argument");
+    HIP_TRY(hipSetDevice(S->device));
+    const int gc = std::min(1024, (int)((S->n + kBlock - 1) / kBlock));
+    if (S->precision == PCGA_FP64) {
+        k_zt<double, false><<<S->g_zt, kBlock, 0, S->stream>>>(S->zt64, S->dinv64, r_dev, nullptr,
+                                                               nullptr, nullptr, nullptr, t_dev,
+                                                               S->cb, S->partials);
+        k_z<double, false, false><<<S->g_z, kBlock, 0, S->stream>>>(S->z64, t_dev, nullptr, s_dev,
+                                                                   S->cb, S->partials);
+    } else {
+        k_convert<double, float><<<gc, kBlock, 0, S->stream>>>((int)S->n, r_dev, S->r32[0]);
+        k_zt<float, false><<<S->g_zt, kBlock, 0, S->stream>>>(S->zt32, S->dinv32, S->r32[0],
+                                                              nullptr, nullptr, nullptr, nullptr,
+                                                              S->t32, S->cb, S->partials);
+        k_z<float, false, false><<<S->g_z, kBlock, 0, S->stream>>>(S->z32, S->t32, nullptr,
+                                                                  S->tmp32, S->cb, S->partials);
+        k_convert<float, double><<<gc, kBlock, 0, S->stream>>>((int)S->n, S->t32, t_dev);
+        k_convert<float, double><<<gc, kBlock, 0, S->stream>>>((int)S->n, S->tmp32, s_dev);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    return PCGA_OK;
+}
+
+int pcga_profile_iteration(pcga_solver_t *S, const double *b_dev, int32_t reps, double *ms_out) {
+    if (!S || !b_dev || !ms_out || reps < 1 || reps > 100000)
+        return fail(PCGA_EINVAL, "bad profile arguments");
+    HIP_TRY(hipSetDevice(S->device));
+    pcga_solver &R = *S;
+    const int big = INT32_MAX;
+    int st;
+    // start state: x0 = 0, tolerance 0 so that no kernel stops early
+    if (R.precision == PCGA_FP64) {
+        HIP_TRY(hipMemsetAsync(R.x, 0, R.n * sizeof(double), R.stream));
+        k_residual<0><<<R.g_st, kBlock, 0, R.stream>>>(R.A64, R.x, b_dev, R.r[0], R.cb, R.partials,
+                                                       R.ntiles, 0.0, big);
+        if ((st = prologue_prec<double>(R, bufs64(R)))) return st;
+    } else {
+        HIP_TRY(hipMemsetAsync(R.x64[0], 0, R.n * sizeof(double), R.stream));
+        k_refine<false><<<R.g_st, kBlock, 0, R.stream>>>(R.A64, R.x64[0], nullptr, nullptr, b_dev,
+                                                         R.r32[0], R.cb, R.partials, R.ntiles, 0.0,
+                                                         big);
+        HIP_TRY(hipMemsetAsync(R.e32, 0, R.n * sizeof(float), R.stream));
+        if ((st = prologue_prec<float>(R, bufs32(R)))) return st;
+    }
+    std::vector<hipEvent_t> ev(3 * (size_t)reps + 1);
+    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    auto cleanup = [&]() { for (auto &e : ev) (void)hipEventDestroy(e); };
+    auto run = [&](auto B) -> hipError_t {
+        using T = std::remove_pointer_t<decltype(B.x)>;
+        hipError_t e = hipEventRecord(ev[0], R.stream);
+        for (int i = 0; i < reps && e == hipSuccess; i++) {
+            const int p = i & 1;
+            k_stencil<T><<<R.g_st, kBlock, 0, R.stream>>>(B.A, B.s, B.d[p], B.d[p ^ 1], B.q, R.cb,
+                                                          R.partials, R.ntiles);
+            e = hipEventRecord(ev[3 * i + 1], R.stream);
+            k_zt<T, true><<<R.g_zt, kBlock, 0, R.stream>>>(B.zt, B.dinv, B.r[p], B.q, B.d[p ^ 1],
+                                                           B.r[p ^ 1], B.x, B.t, R.cb, R.partials);
+            if (e == hipSuccess) e = hipEventRecord(ev[3 * i + 2], R.stream);
+            k_z<T, true, false><<<R.g_z, kBlock, 0, R.stream>>>(B.z, B.t, B.r[p ^ 1], B.s, R.cb,
+                                                               R.partials);
+            if (e == hipSuccess) e = hipEventRecord(ev[3 * i + 3], R.stream);
+        }
+        if (e == hipSuccess) e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(R.stream);
+        return e;
+    };
+    hipError_t e = (R.precision == PCGA_FP64) ? run(bufs64(R)) : run(bufs32(R));
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(PCGA_EHIP, std::string("profile: ") + hipGetErrorString(e));
+    }
+    double acc[3] = {0, 0, 0};
+    for (int i = 0; i < reps; i++)
+        for (int kk = 0; kk < 3; kk++) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, ev[3 * i + kk], ev[3 * i + kk + 1]);
+            if (e != hipSuccess) {
+                cleanup();
+                return fail(PCGA_EHIP, std::string("profile: ") + hipGetErrorString(e));
+            }
+            acc[kk] += ms;
+        }
+    cleanup();
+    for (int kk = 0; kk < 3; kk++) ms_out[kk] = acc[kk] / reps;
+    return PCGA_OK;
+}
+
+}  // extern "C"

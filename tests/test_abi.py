@@ -1,0 +1,135 @@
+"""C ABI: the library loads, exports every declared entry point, and its host
+setup (no GPU involved) matches the oracle's approximate inverse bit for bit."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from gen import orca
+from paper_1210_1878_amd import _lib
+from paper_1210_1878_amd.api import AInv, Stencil5, ainv_setup
+from tests._cases import const_periodic, laplace1d
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "pcgainv.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pcga_\w+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 14
+    L = _lib.load()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_strerror_and_status_codes():
+    L = _lib.load()
+    for code in (0, 1, -1, -2, -3, -4, -5):
+        assert L.pcga_strerror(code)
+    assert b"unknown" in L.pcga_strerror(42)
+
+
+def _pattern_equal(ora, p, tau):
+    F = ora.ainv_setup(p, tau)
+    G = ainv_setup(Stencil5.from_problem(p), tau)
+    colptr, rowidx, val, D = G.export()
+    assert G.nnz_off == F.nnz_off
+    assert np.array_equal(colptr, F.colptr)
+    assert np.array_equal(rowidx.astype(np.int64), F.rowidx)
+    # same operation sequence, unfused FP64: values identical to the bit
+    assert np.array_equal(val.view(np.uint64), F.val.view(np.uint64))
+    assert np.array_equal(D.view(np.uint64), F.D.view(np.uint64))
+    return F
+
+
+@pytest.mark.parametrize("tau", [0.0, 0.05, 0.1, 0.3, np.inf])
+def test_setup_bitwise_equal_to_oracle_box(ora, tau):
+    _pattern_equal(ora, orca.box_problem(), tau)
+
+
+@pytest.mark.parametrize("tau", [0.0, 0.05, 0.1, np.inf])
+def test_setup_bitwise_equal_to_oracle_orca_small(ora, tau):
+    _pattern_equal(ora, orca.orca_problem(37, 23, 5), tau)
+
+
+@pytest.mark.parametrize("tau", [0.05, 0.1])
+def test_setup_bitwise_equal_to_oracle_orca2(ora, tau):
+    _pattern_equal(ora, orca.orca_problem(182, 149, orca.CONFIG_SEED_BASE + 1), tau)
+
+
+def test_setup_bitwise_periodic_constant(ora):
+    _pattern_equal(ora, const_periodic(9, 5), 0.0)
+    _pattern_equal(ora, const_periodic(9, 5), 0.02)
+
+
+@pytest.mark.slow
+def test_setup_bitwise_equal_to_oracle_orca025(ora):
+    """Full 1442x1021 grid at drop tolerance 0.05."""
+    _pattern_equal(ora, orca.orca_problem(1442, 1021, orca.CONFIG_SEED_BASE + 2), 0.05)
+
+
+def test_setup_errors():
+    p = laplace1d(8)
+    A = Stencil5.from_problem(p)
+    with pytest.raises(_lib.PcgaError) as e:
+        ainv_setup(A, -1.0)
+    assert e.value.status == _lib.EINVAL
+    bad = Stencil5(8, 1, False, p.diag.copy(), p.ae.copy(), p.an.copy())
+    bad.diag[3] = 0.5
+    with pytest.raises(_lib.PcgaError) as e:
+        ainv_setup(bad, 0.0)
+    assert e.value.status == _lib.EBREAKDOWN
+    bad2 = Stencil5(8, 1, False, p.diag.copy(), p.ae.copy(), p.an.copy())
+    bad2.ae[-1] = -1.0          # coupling across a non-periodic edge
+    with pytest.raises(_lib.PcgaError) as e:
+        ainv_setup(bad2, 0.1)
+    assert e.value.status == _lib.EINVAL
+    bad3 = Stencil5(2, 3, True, np.ones(6), np.zeros(6), np.zeros(6))   # periodic nx < 3
+    with pytest.raises(_lib.PcgaError) as e:
+        ainv_setup(bad3, 0.1)
+    assert e.value.status == _lib.EINVAL
+
+
+def test_import_roundtrip_and_validation():
+    p = orca.orca_problem(20, 12, 2)
+    G = ainv_setup(Stencil5.from_problem(p), 0.1)
+    colptr, rowidx, val, D = G.export()
+    H = AInv.from_csc(p.n, colptr, rowidx, val, D)
+    c2, r2, v2, D2 = H.export()
+    assert np.array_equal(c2, colptr) and np.array_equal(r2, rowidx)
+    assert np.array_equal(v2, val) and np.array_equal(D2, D)
+    with pytest.raises(_lib.PcgaError):
+        AInv.from_csc(p.n, colptr, rowidx, val, -D)          # D must be > 0
+    bad_rows = rowidx.copy()
+    if len(bad_rows):
+        j = int(np.searchsorted(colptr, 1, side="right")) - 1
+        bad_rows[0] = j + 5                                  # not strictly upper
+        with pytest.raises(_lib.PcgaError):
+            AInv.from_csc(p.n, colptr, bad_rows, val, D)
+
+
+def test_workspace_bytes_query():
+    L = _lib.load()
+    p = orca.orca_problem(182, 149, orca.CONFIG_SEED_BASE + 1)
+    A = Stencil5.from_problem(p)
+    G = ainv_setup(A, 0.1)
+    a5 = A.c_struct()
+    sizes = {}
+    for prec in (_lib.FP64, _lib.MIXED):
+        nb = ctypes.c_size_t()
+        assert L.pcga_workspace_bytes(ctypes.byref(a5), G.handle, prec, ctypes.byref(nb)) == 0
+        sizes[prec] = nb.value
+    n = p.n
+    # FP64: 3 operator + D^-1 + 8 vectors (8 B) + 2 sliced-ELL copies of Z (12 B/entry)
+    assert sizes[_lib.FP64] >= 8 * 12 * n + 24 * G.nnz_off
+    # mixed stores FP32 data plus the FP64 operator and solution
+    assert sizes[_lib.MIXED] < sizes[_lib.FP64] * 1.1
+    nb = ctypes.c_size_t()
+    assert L.pcga_workspace_bytes(ctypes.byref(a5), G.handle, 7, ctypes.byref(nb)) == _lib.EINVAL

@@ -1,0 +1,273 @@
+"""Device path vs the FP64 oracle, through the C ABI (needs an MI355X).
+
+Bars (the method's problem statement): solutions iteration-matched to
+relative 1e-9 in FP64, natural stopping iteration counts within +-2, true
+residuals at the 1e-10 target; single kernels within a few ulp of the
+oracle's operation, scaled by the magnitude of the terms they sum.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from gen import orca
+from tests._cases import const_periodic, laplace1d, tridiag_problem
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+
+def say(*a):
+    print("[gpu-parity]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    if not torch.cuda.is_available():
+        pytest.skip("no ROCm device")
+    import paper_1210_1878_amd as P
+    return P
+
+
+CASES = {
+    "box64x48": (lambda: orca.box_problem(), 0.1),
+    "orca182x149": (lambda: orca.orca_problem(182, 149, orca.CONFIG_SEED_BASE + 1), 0.1),
+    "orca182x149_jacobi": (lambda: orca.orca_problem(182, 149, orca.CONFIG_SEED_BASE + 1), np.inf),
+    "orca37x23_ragged": (lambda: orca.orca_problem(37, 23, 5), 0.05),
+    "periodic9x5_exact": (lambda: const_periodic(9, 5, b=np.random.default_rng(1).standard_normal(45)), 0.0),
+    "line100": (lambda: laplace1d(100), 0.1),
+    "orca3x7_min_periodic": (lambda: orca.orca_problem(3, 7, 3, land_frac=0.2), 0.1),
+}
+
+_cache = {}
+
+
+def case(name):
+    if name not in _cache:
+        mk, tau = CASES[name]
+        _cache[name] = (mk(), tau)
+    return _cache[name]
+
+
+def _abs_problem(p):
+    q = orca.Problem(p.nx, p.ny, p.periodic, np.abs(p.diag), np.abs(p.ae), np.abs(p.an),
+                     p.ocean, p.b)
+    return q
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_apply_a(pkg, ora, name):
+    p, tau = case(name)
+    say("apply_a", name, p.nx, p.ny)
+    S = pkg.Solver(pkg.Stencil5.from_problem(p), pkg.ainv_setup(pkg.Stencil5.from_problem(p), tau))
+    x = np.random.default_rng(11).standard_normal(p.n)
+    y = S.apply_a(dev(x)).cpu().numpy()
+    ref = ora.spmv(p, x)
+    mag = ora.spmv(_abs_problem(p), np.abs(x))
+    assert np.all(np.abs(y - ref) <= 8 * EPS * mag + 1e-300)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_apply_prec(pkg, ora, name, prec):
+    p, tau = case(name)
+    say("apply_prec", name, prec)
+    A = pkg.Stencil5.from_problem(p)
+    G = pkg.ainv_setup(A, tau)
+    F = ora.ainv_setup(p, tau)
+    S = pkg.Solver(A, G, prec)
+    r = np.random.default_rng(12).standard_normal(p.n)
+    t, s = S.apply_prec(dev(r))
+    t, s = t.cpu().numpy(), s.cpu().numpy()
+    t_ref = ora.zt_apply(F, r)
+    s_ref = ora.z_apply(F, t_ref)
+    Fa = ora.AInv(F.n, F.colptr, F.rowidx, np.abs(F.val), F.D)
+    t_mag = ora.zt_apply(Fa, np.abs(r))
+    s_mag = ora.z_apply(Fa, t_mag)
+    u = 4 * EPS if prec == "fp64" else 4 * np.finfo(np.float32).eps
+    width = max(8, int(np.diff(F.colptr).max()) + 2)
+    assert np.all(np.abs(t - t_ref) <= width * u * t_mag + 1e-300)
+    assert np.all(np.abs(s - s_ref) <= 2 * width * u * s_mag + 1e-300)
+
+
+def _solve_pair(pkg, ora, p, tau, tol, maxit=None, x0=None, b=None):
+    A = pkg.Stencil5.from_problem(p)
+    G = pkg.ainv_setup(A, tau)
+    F = ora.ainv_setup(p, tau)
+    b = p.b if b is None else b
+    S = pkg.Solver(A, G, "fp64")
+    g = S.solve(dev(b), None if x0 is None else dev(x0), tol=tol, maxit=maxit)
+    o = ora.pcg(p, F, b=b, x0=x0, tol=tol, maxit=maxit)
+    return g, o, S
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_pcg_iteration_matched(pkg, ora, name):
+    p, tau = case(name)
+    o0 = ora.pcg(p, ora.ainv_setup(p, tau), tol=1e-10)
+    K = max(o0.iters, 1)
+    say("pcg iteration-matched", name, "K =", K)
+    g, o, _ = _solve_pair(pkg, ora, p, tau, tol=0.0, maxit=K)
+    assert g.iters == o.iters == K
+    xo = o.x
+    assert np.linalg.norm(g.x.cpu().numpy() - xo) <= 1e-9 * np.linalg.norm(xo)
+    # residual histories agree as well
+    assert np.allclose(g.hist, o.hist, rtol=1e-6, atol=1e-14)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_pcg_natural_stop(pkg, ora, name):
+    p, tau = case(name)
+    say("pcg natural stop", name)
+    g, o, _ = _solve_pair(pkg, ora, p, tau, tol=1e-10)
+    assert g.status == 0 and o.status == 0
+    assert abs(g.iters - o.iters) <= 2
+    assert g.hist[-1] <= 1e-10
+    # FP64 true residual, recomputed independently with the oracle's product
+    x = g.x.cpu().numpy()
+    true = np.linalg.norm(p.b - ora.spmv(p, x)) / np.linalg.norm(p.b)
+    assert true <= 1.05e-10
+    assert abs(true - g.true_relres) <= 1e-3 * true + 1e-15
+
+
+@pytest.mark.parametrize("name", ["box64x48", "orca182x149", "orca37x23_ragged"])
+def test_mixed_reaches_fp64_residual(pkg, ora, name):
+    p, tau = case(name)
+    say("mixed", name)
+    A = pkg.Stencil5.from_problem(p)
+    S = pkg.Solver(A, pkg.ainv_setup(A, tau), "mixed")
+    m = S.solve_mixed(dev(p.b), tol=1e-10, inner_tol=1e-5, max_outer=20)
+    assert m.status == 0
+    x = m.x.cpu().numpy()
+    true = np.linalg.norm(p.b - ora.spmv(p, x)) / np.linalg.norm(p.b)
+    assert true <= 1e-10
+    assert abs(true - m.true_relres) <= 1e-3 * true + 1e-15
+    xo = ora.pcg(p, ora.ainv_setup(p, tau), tol=1e-12).x
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    say("  mixed outer", m.outer, "inner", m.inner_total, "rel err vs FP64 oracle", err)
+    om = ora.pcg_mixed(p, ora.ainv_setup(p, tau), tol=1e-10, inner_tol=1e-5)
+    assert abs(m.outer - om.outer) <= 1
+
+
+def test_edge_zero_rhs_and_warm_start(pkg, ora):
+    p, tau = case("orca182x149")
+    say("edge: zero rhs / warm start")
+    A = pkg.Stencil5.from_problem(p)
+    S = pkg.Solver(A, pkg.ainv_setup(A, tau))
+    z = S.solve(dev(np.zeros(p.n)), dev(np.ones(p.n)))
+    assert z.iters == 0 and z.status == 0 and float(z.x.abs().max()) == 0.0
+    assert list(z.hist) == [0.0]
+    full = S.solve(dev(p.b), tol=1e-10)
+    warm = S.solve(dev(p.b), full.x, tol=1e-10)
+    assert warm.iters == 0 and torch.equal(warm.x, full.x)
+    few = S.solve(dev(p.b), tol=1e-10, maxit=3)
+    assert few.status == 1 and few.iters == 3
+    o3 = ora.pcg(p, ora.ainv_setup(p, tau), tol=1e-10, maxit=3)
+    assert np.linalg.norm(few.x.cpu().numpy() - o3.x) <= 1e-12 * np.linalg.norm(o3.x)
+    Sm = pkg.Solver(A, pkg.ainv_setup(A, tau), "mixed")
+    zm = Sm.solve_mixed(dev(np.zeros(p.n)))
+    assert zm.outer == 0 and float(zm.x.abs().max()) == 0.0
+
+
+def test_edge_nan_and_breakdown(pkg, ora):
+    say("edge: NaN rhs / indefinite operator")
+    p, tau = case("box64x48")
+    A = pkg.Stencil5.from_problem(p)
+    S = pkg.Solver(A, pkg.ainv_setup(A, tau))
+    b = p.b.copy()
+    b[100] = np.nan
+    with pytest.raises(pkg.PcgaError) as e:
+        S.solve(dev(b))
+    assert e.value.status == -3
+    # tridiag(-0.9, 1, -0.9) is indefinite; Jacobi "preconditioner" D = 1
+    n = 64
+    q = tridiag_problem(np.ones(n), np.full(n, -0.9), b=np.random.default_rng(3).standard_normal(n))
+    with pytest.raises(ora.OracleError) as eo:
+        ora.pcg(q, ora.ainv_setup(q, np.inf), tol=1e-10)
+    assert eo.value.status == ora.EBREAKDOWN
+    Aq = pkg.Stencil5.from_problem(q)
+    Sq = pkg.Solver(Aq, pkg.ainv_setup(Aq, np.inf))
+    with pytest.raises(pkg.PcgaError) as eg:
+        Sq.solve(dev(q.b), tol=1e-10)
+    assert eg.value.status == -2
+
+
+def test_determinism_and_launch_modes(pkg):
+    p, tau = case("orca182x149")
+    say("determinism: graph vs direct, chunk sizes")
+    A = pkg.Stencil5.from_problem(p)
+    S = pkg.Solver(A, pkg.ainv_setup(A, tau))
+    ref = S.solve(dev(p.b), tol=1e-10)
+    for chunk, graph in ((32, True), (32, False), (2, True), (128, True)):
+        S.tune(chunk=chunk, use_graph=graph, max_blocks=2048)
+        r = S.solve(dev(p.b), tol=1e-10)
+        assert r.iters == ref.iters and torch.equal(r.x, ref.x)
+        assert np.array_equal(r.hist, ref.hist)
+
+
+# ---------------------------------------------------------------------------
+# full ORCA025-shaped size (1442 x 1021, drop tolerance 0.05), launch shape of
+# the benchmark
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def orca025(pkg, ora):
+    say("building 1442x1021 problem and setups")
+    p = orca.orca_problem(1442, 1021, orca.CONFIG_SEED_BASE + 2)
+    F = ora.ainv_setup(p, 0.05)
+    A = pkg.Stencil5.from_problem(p)
+    G = pkg.ainv_setup(A, 0.05)
+    return p, F, A, G
+
+
+def test_full_size_kernels(pkg, ora, orca025):
+    p, F, A, G = orca025
+    say("full size: apply_a, apply_prec")
+    S = pkg.Solver(A, G, "fp64")
+    x = np.random.default_rng(21).standard_normal(p.n)
+    y = S.apply_a(dev(x)).cpu().numpy()
+    mag = ora.spmv(_abs_problem(p), np.abs(x))
+    assert np.all(np.abs(y - ora.spmv(p, x)) <= 8 * EPS * mag + 1e-300)
+    t, s = S.apply_prec(dev(x))
+    t_ref = ora.zt_apply(F, x)
+    s_ref = ora.z_apply(F, t_ref)
+    Fa = ora.AInv(F.n, F.colptr, F.rowidx, np.abs(F.val), F.D)
+    t_mag = ora.zt_apply(Fa, np.abs(x))
+    s_mag = ora.z_apply(Fa, t_mag)
+    width = int(np.diff(F.colptr).max()) + 2
+    assert np.all(np.abs(t.cpu().numpy() - t_ref) <= width * 4 * EPS * t_mag)
+    assert np.all(np.abs(s.cpu().numpy() - s_ref) <= 2 * width * 4 * EPS * s_mag)
+
+
+def test_full_size_pcg(pkg, ora, orca025):
+    p, F, A, G = orca025
+    say("full size: 12 iterations matched, then natural stop")
+    S = pkg.Solver(A, G, "fp64")
+    g = S.solve(dev(p.b), tol=0.0, maxit=12)
+    o = ora.pcg(p, F, tol=0.0, maxit=12)
+    assert np.linalg.norm(g.x.cpu().numpy() - o.x) <= 1e-9 * np.linalg.norm(o.x)
+    assert np.allclose(g.hist, o.hist, rtol=1e-9)
+    full = S.solve(dev(p.b), tol=1e-10)
+    say("  iterations", full.iters, "true relres", full.true_relres)
+    assert full.status == 0
+    x = full.x.cpu().numpy()
+    true = np.linalg.norm(p.b - ora.spmv(p, x)) / np.linalg.norm(p.b)
+    assert true <= 1.05e-10
+
+
+def test_full_size_mixed(pkg, ora, orca025):
+    p, F, A, G = orca025
+    say("full size: mixed precision")
+    S = pkg.Solver(A, G, "mixed")
+    m = S.solve_mixed(dev(p.b), tol=1e-10, inner_tol=1e-5, max_outer=20)
+    say("  outer", m.outer, "inner", m.inner_total, "true", m.true_relres)
+    assert m.status == 0
+    x = m.x.cpu().numpy()
+    true = np.linalg.norm(p.b - ora.spmv(p, x)) / np.linalg.norm(p.b)
+    assert true <= 1e-10
