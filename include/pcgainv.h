@@ -180,6 +180,56 @@ int pcga_apply_prec(pcga_solver_t *S, const double *r_dev, double *t_dev, double
  * inner kernels for PCGA_MIXED).  For benchmarks; the solver stays usable. */
 int pcga_profile_iteration(pcga_solver_t *S, const double *b_dev, int32_t reps, double *ms_out);
 
+/* ---- batched solves (ensembles and continuous batching) -------------------
+ * A batch advances many independent solves with one launch of each iteration
+ * kernel for all of them.  An item (slot) is a PCGA_MIXED solver (its resident
+ * operator, D^-1 and Z) with nrhs right-hand sides (1, 2 or 4, solved
+ * together: A and Z are read once for all of them), each solved by the
+ * method of pcga_pcg_solve_mixed (FP32 inner PCG, FP64 refinement).  Items
+ * may be added and removed between pcga_batch_run calls; work of items added
+ * while others run overlaps on the device.  An item's result does not depend
+ * on the other items (its reductions use a block count fixed by its grid).
+ *
+ * Memory: the batch's control data lives in caller-provided device memory
+ * (pcga_batch_scratch_bytes), each item's vectors in its own caller-provided
+ * device workspace (pcga_batch_item_bytes); the library allocates none.
+ * Every solver and workspace must stay alive while its item is in the batch.
+ * All work runs on the batch's stream; the calls return after their device
+ * work finished.  Errors: EINVAL, ENOMEM (scratch / workspace too small, no
+ * free slot, batch too large), EHIP. */
+typedef struct pcga_batch pcga_batch_t;
+
+int pcga_batch_scratch_bytes(int32_t max_slots, size_t *bytes);
+int pcga_batch_item_bytes(const pcga_solver_t *S, int32_t nrhs, size_t *bytes);
+int pcga_batch_create(int32_t max_slots, void *scratch_dev, size_t scratch_bytes, void *stream,
+                      pcga_batch_t **out);
+int pcga_batch_destroy(pcga_batch_t *B);
+
+/* Add an item: b_dev[r], x0_dev[r] (n FP64 device values each, r < nrhs) are
+ * copied into the item workspace at once; x_out_dev[r] receive the solutions
+ * at pcga_batch_remove.  Tolerances as in pcga_pcg_solve_mixed
+ * (inner_maxit < 0 means n).  *slot receives the item's slot number. */
+int pcga_batch_add(pcga_batch_t *B, pcga_solver_t *S, int32_t nrhs, const double *const *b_dev,
+                   const double *const *x0_dev, double *const *x_out_dev, void *item_ws,
+                   size_t item_bytes, double tol, double inner_tol, int32_t max_outer,
+                   int32_t inner_maxit, int32_t *slot);
+
+/* Run up to `chunks` chunks of iterations (stops early once every item is
+ * done); *active receives the number of items not yet done. */
+int pcga_batch_run(pcga_batch_t *B, int32_t chunks, int32_t *active);
+
+/* Item results as of the last pcga_batch_run: done flag, status (PCGA_OK,
+ * PCGA_NOCONV, PCGA_EBREAKDOWN, PCGA_ENAN), outer steps, inner iterations,
+ * and true_relres[r] = ||b_r - A x_r|| / ||b_r|| (FP64) for r < nrhs. */
+int pcga_batch_query(pcga_batch_t *B, int32_t slot, int32_t *done, int32_t *status,
+                     int32_t *outer, int32_t *inner_total, double *true_relres);
+
+/* Write the item's solutions to its x_out_dev vectors and free the slot. */
+int pcga_batch_remove(pcga_batch_t *B, int32_t slot);
+
+/* Iterations per captured chunk (even, 2..512). */
+int pcga_batch_set_chunk(pcga_batch_t *B, int32_t chunk);
+
 #ifdef __cplusplus
 }
 #endif

@@ -59,9 +59,16 @@ _SIGS = {
     "pcga_apply_a": ([_p, _p, _p], ctypes.c_int),
     "pcga_apply_prec": ([_p, _p, _p, _p], ctypes.c_int),
     "pcga_profile_iteration": ([_p, _p, _i32, _pdbl], ctypes.c_int),
-    "pcga_batch_scratch_bytes": ([_i32, _p, ctypes.POINTER(_sz)], ctypes.c_int),
-    "pcga_batch_solve_mixed": ([_i32, _p, _p, _p, _dbl, _dbl, _i32, _i32, _p, _sz, _p, _p,
-                                _p, _p], ctypes.c_int),
+    "pcga_batch_scratch_bytes": ([_i32, ctypes.POINTER(_sz)], ctypes.c_int),
+    "pcga_batch_item_bytes": ([_p, _i32, ctypes.POINTER(_sz)], ctypes.c_int),
+    "pcga_batch_create": ([_i32, _p, _sz, _p, _pp], ctypes.c_int),
+    "pcga_batch_destroy": ([_p], ctypes.c_int),
+    "pcga_batch_add": ([_p, _p, _i32, _p, _p, _p, _p, _sz, _dbl, _dbl, _i32, _i32, _pi32],
+                       ctypes.c_int),
+    "pcga_batch_run": ([_p, _i32, _pi32], ctypes.c_int),
+    "pcga_batch_query": ([_p, _i32, _pi32, _pi32, _pi32, _pi32, _pdbl], ctypes.c_int),
+    "pcga_batch_remove": ([_p, _i32], ctypes.c_int),
+    "pcga_batch_set_chunk": ([_p, _i32], ctypes.c_int),
 }
 
 _lib = None

@@ -273,3 +273,101 @@ def pcg_solve_mixed(A: Stencil5, F: AInv, b, x0=None, tol=1e-10, inner_tol=1e-5,
     S = solver if solver is not None else Solver(A, F, "mixed", device=b.device)
     return S.solve_mixed(b, x0, tol=tol, inner_tol=inner_tol, max_outer=max_outer,
                          inner_maxit=inner_maxit)
+
+
+class Batch:
+    """Many mixed-precision solves advanced together (one launch per kernel per
+    iteration for all items); items can be added and removed between runs."""
+
+    def __init__(self, max_slots=64, device=None, stream=None, chunk=16):
+        import torch
+        L = _lib.load()
+        self.device = torch.device("cuda" if device is None else device)
+        nb = ctypes.c_size_t()
+        check(L.pcga_batch_scratch_bytes(int(max_slots), ctypes.byref(nb)), "pcga_batch_scratch_bytes")
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.Stream(self.device) if stream is None else stream
+            self.scratch = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+            h = ctypes.c_void_p()
+            check(L.pcga_batch_create(int(max_slots), ctypes.c_void_p(self.scratch.data_ptr()),
+                                      nb.value, ctypes.c_void_p(self.stream.cuda_stream),
+                                      ctypes.byref(h)), "pcga_batch_create")
+        self._h = h
+        self.items = {}
+        check(L.pcga_batch_set_chunk(self._h, int(chunk)), "pcga_batch_set_chunk")
+
+    @staticmethod
+    def item_bytes(solver, nrhs):
+        nb = ctypes.c_size_t()
+        check(_lib.load().pcga_batch_item_bytes(solver.handle, int(nrhs), ctypes.byref(nb)),
+              "pcga_batch_item_bytes")
+        return nb.value
+
+    def add(self, solver, B, X0=None, tol=1e-10, inner_tol=1e-5, max_outer=20, inner_maxit=None,
+            tag=None):
+        """B: [nrhs, n] float64 device tensor (nrhs in 1, 2, 4).  Returns the slot."""
+        import torch
+        L = _lib.load()
+        if B.dim() == 1:
+            B = B.unsqueeze(0)
+        nrhs, n = B.shape
+        B = B.contiguous()
+        X0 = torch.zeros_like(B) if X0 is None else X0.reshape(nrhs, n).contiguous()
+        X = torch.empty_like(B)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        nbytes = self.item_bytes(solver, nrhs)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        arr = ctypes.c_void_p * nrhs
+        bp = arr(*[B[r].data_ptr() for r in range(nrhs)])
+        xp = arr(*[X0[r].data_ptr() for r in range(nrhs)])
+        op = arr(*[X[r].data_ptr() for r in range(nrhs)])
+        slot = ctypes.c_int32()
+        check(L.pcga_batch_add(self._h, solver.handle, int(nrhs), bp, xp, op,
+                               ctypes.c_void_p(ws.data_ptr()), nbytes, float(tol), float(inner_tol),
+                               int(max_outer), -1 if inner_maxit is None else int(inner_maxit),
+                               ctypes.byref(slot)), "pcga_batch_add")
+        self.items[slot.value] = dict(solver=solver, B=B, X=X, ws=ws, nrhs=nrhs, tag=tag)
+        return slot.value
+
+    def run(self, chunks=1):
+        active = ctypes.c_int32()
+        check(_lib.load().pcga_batch_run(self._h, int(chunks), ctypes.byref(active)), "pcga_batch_run")
+        return active.value
+
+    def query(self, slot):
+        it = self.items[slot]
+        done, st, outer, inner = (ctypes.c_int32() for _ in range(4))
+        rel = (ctypes.c_double * 4)()
+        check(_lib.load().pcga_batch_query(self._h, int(slot), ctypes.byref(done), ctypes.byref(st),
+                                           ctypes.byref(outer), ctypes.byref(inner), rel),
+              "pcga_batch_query")
+        return dict(done=bool(done.value), status=st.value, outer=outer.value,
+                    inner_total=inner.value, true_relres=list(rel[: it["nrhs"]]))
+
+    def remove(self, slot):
+        """Write the solutions and free the slot; returns (X [nrhs, n], query dict)."""
+        q = self.query(slot)
+        check(_lib.load().pcga_batch_remove(self._h, int(slot)), "pcga_batch_remove")
+        it = self.items.pop(slot)
+        return it["X"], q
+
+    def solve(self, max_chunks=100000):
+        """Run until every item is done; returns {slot: (X, query)} and removes all."""
+        left = self.run(1)
+        guard = 0
+        while left > 0 and guard < max_chunks:
+            left = self.run(4)
+            guard += 1
+        return {s: self.remove(s) for s in list(self.items)}
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.load().pcga_batch_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -13,11 +13,12 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libpcgainv.so")
 BUILD = os.path.join(HERE, "_build")
 
 HOST_SOURCES = ["ainv.cpp", "layout.cpp"]
-HIP_SOURCES = ["solver.hip"]
+HIP_SOURCES = ["solver.hip", "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -36,14 +37,14 @@ def build(verbose: bool = False) -> str:
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
         _run(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-              "-Wall", "-Wextra", "-I", CSRC, "-I", "/opt/rocm/include",
+              "-Wall", "-Wextra", "-I", CSRC, "-I", INCLUDE, "-I", "/opt/rocm/include",
               "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
         _run([HIPCC, f"--offload-arch={ARCH}", "-std=c++17", "-O3", "-fPIC",
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-              "-Wall", "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj])
+              "-Wall", "-I", CSRC, "-I", INCLUDE, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     tmp = LIB + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs)

@@ -1,30 +1,37 @@
 // kernels.h -- gfx950 kernels of one PCG-AINV iteration and its prologue.
 //
-// One iteration of Algorithm 1 (with the preconditioned direction update
-// d = s + beta d) is three launches, each streaming its arrays once and
-// ending in a deterministic grid reduction finished by the last workgroup:
+// One iteration k of Algorithm 1 (with the preconditioned direction update
+// d = s + beta d) is three launches, each streaming its arrays once:
 //
-//   k_stencil  d_new = s + beta d_old;  q = A d_new;  (d_new, q)  -> alpha
-//   k_zt       r' = r - alpha q;  x += alpha d_new;  ||r'||^2;
-//              t = D^-1 Z^T r'    (r' is recomputed at the gathered rows)
-//                                                         -> stop test, history
-//   k_z        s = Z t;  (s, r')                               -> rho, beta
+//   k_stencil  rho_k = sum of (s,r) partials; beta = rho_k / rho_{k-1};
+//              d_new = s + beta d_old;  q = A d_new;  (d_new, q) partials
+//   k_zt       alpha = rho_k / sum of (d,q) partials;
+//              r' = r - alpha q;  x += alpha d_new;  ||r'||^2 partials;
+//              t = D^-1 Z^T r'   (r' is recomputed at the gathered rows)
+//   k_z        stop test on sqrt(sum ||r'||^2 partials) / ||b||;
+//              s = Z t;  (s, r') partials
 //
 // The three global dependencies of the method (alpha needs all of (d,q); the
-// Z^T gather needs r' at other rows; beta needs all of (s,r)) are exactly the
-// kernel boundaries.  d and r are double-buffered because neighbouring
-// workgroups read the old values while others write the new ones.
+// Z^T gather needs r' at other rows; beta needs all of (s,r)) are the kernel
+// boundaries.  No workgroup ever waits for another inside a launch: each
+// launch writes one partial sum per workgroup, and every workgroup of the
+// next launch adds all of them up in the same fixed order, so all workgroups
+// hold bitwise-identical scalars.  Coherence across the 8 XCDs is then only
+// needed at kernel boundaries, where the runtime provides it.
 //
-// Work split: a launch of G workgroups assigns each workgroup one contiguous
-// range of tiles (stencil) or slices (sliced ELL).  Workgroups are dispatched
+// d and r are double-buffered because neighbouring workgroups read old values
+// while others write new ones.
+//
+// Work split: a launch of G workgroups gives each workgroup one contiguous
+// range of cells or sliced-ELL slices.  Workgroups are dispatched
 // round-robin over the 8 XCDs, so the hardware index is remapped to make the
-// ranges of one XCD contiguous: grid neighbours (the rows above and below,
-// and the rows a Z column reaches) then live in the same L2.
+// ranges of one XCD contiguous: grid neighbours (rows above and below, rows a
+// Z column reaches) are then read from the same L2.
 //
-// Reductions: FP64 per-lane sums, a fixed butterfly per wavefront, a fixed
-// order over the 4 wavefronts, per-workgroup partials, and a fixed strided
-// order in the last workgroup.  Results are bitwise reproducible for a given
-// launch shape.
+// Memory-level parallelism: the stencil issues every load of its 2 cells per
+// thread before any arithmetic (branch-free neighbour indices); the sliced-ELL
+// kernels load 8 index/value pairs, then their 8 gathers, per step, and fetch
+// the headers of all of a wavefront's slices with one load.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -40,16 +47,20 @@ __device__ __forceinline__ int logical_block(int b, int G) {
     return x * q + (x < rem ? x : rem) + i;
 }
 
+__device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v < INFINITY; }
+__device__ __forceinline__ bool is_bad(double v) { return !(v == v) || v == INFINITY || v == -INFINITY; }
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
     return v;
 }
 
-// Sum NV values over the workgroup; the totals are valid in thread 0.
+// Sum NV values over the workgroup in a fixed order; result in every thread.
 template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV]) {
-    __shared__ double red[NV][kBlock / kWave];
+__device__ __forceinline__ void block_sum_all(double (&v)[NV]) {
+    __shared__ double red[NV][kWavesPerBlock];
+    __shared__ double tot[NV];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
     for (int q = 0; q < NV; q++) {
@@ -57,378 +68,529 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
         if (lane == 0) red[q][w] = s;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < NV) {
+        double s = 0.0;
 #pragma unroll
-        for (int q = 0; q < NV; q++) v[q] = ((red[q][0] + red[q][1]) + red[q][2]) + red[q][3];
+        for (int i = 0; i < kWavesPerBlock; i++) s += red[threadIdx.x][i];
+        tot[threadIdx.x] = s;
     }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; q++) v[q] = tot[q];
     __syncthreads();
 }
 
-// Publish this workgroup's sums; the last workgroup to arrive reduces all
-// partials (fixed order) and returns true with the totals in v (thread 0).
+// Total of G per-workgroup partials (stride kMaxBlocks between the NV
+// quantities), identical in every workgroup and thread.
+// All loads are issued before any is consumed (fixed trip count, predicated),
+// so the whole read costs one memory round trip.
 template <int NV>
-__device__ bool grid_finish(double (&v)[NV], double *partials, int G, int L, uint32_t *cnt) {
-    __shared__ int is_last;
-    block_sum<NV>(v);
-    if (threadIdx.x == 0) {
+__device__ __forceinline__ void sum_partials(const double *part, int G, double (&out)[NV]) {
+    constexpr int R = kMaxBlocks / kBS;
+    double v[NV][R];
 #pragma unroll
-        for (int q = 0; q < NV; q++) partials[q * kMaxBlocks + L] = v[q];
-        __threadfence();
-        const uint32_t prev = atomicAdd(cnt, 1u);
-        is_last = (prev == (uint32_t)(G - 1));
+    for (int i = 0; i < R; i++) {
+        const int b = threadIdx.x + i * kBS;
+        const int bb = b < G ? b : 0;
+#pragma unroll
+        for (int q = 0; q < NV; q++) v[q][i] = part[q * kMaxBlocks + bb];
     }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-    double acc[NV];
 #pragma unroll
-    for (int q = 0; q < NV; q++) acc[q] = 0.0;
-    for (int b = threadIdx.x; b < G; b += kBlock) {
+    for (int q = 0; q < NV; q++) {
+        out[q] = 0.0;
 #pragma unroll
-        for (int q = 0; q < NV; q++) acc[q] += partials[q * kMaxBlocks + b];
+        for (int i = 0; i < R; i++)
+            if (threadIdx.x + i * kBS < G) out[q] += v[q][i];
     }
-    block_sum<NV>(acc);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int q = 0; q < NV; q++) v[q] = acc[q];
-        *cnt = 0u;
-    }
-    return true;
+    block_sum_all<NV>(out);
 }
 
-// One 256-cell tile of the five-point product y = A v, where v(k) is a value
-// provider (it may combine several arrays on the fly).  East/west neighbours
-// come from LDS (row interior) or from v (periodic wrap); north/south from v.
-// Terms are added in increasing column order (south, west, self, east, north).
-template <typename T, typename V>
-__device__ __forceinline__ void stencil_tile(const DevOp<T> &A, int k0, const V &v, T *sh,
-                                             T &own, T &y, bool &valid) {
-    const int tid = threadIdx.x;
-    const int k = k0 + tid;
-    const int n = A.n, nx = A.nx;
-    valid = k < n;
-    own = valid ? v(k) : T(0);
-    sh[tid + 1] = own;
-    if (tid == 0) sh[0] = (k0 > 0) ? v(k0 - 1) : T(0);
-    if (tid == kBlock - 1) sh[kBlock + 1] = (k0 + kBlock < n) ? v(k0 + kBlock) : T(0);
-    __syncthreads();
+// Publish this workgroup's NV partial sums.
+template <int NV>
+__device__ __forceinline__ void put_partials(double (&v)[NV], double *part, int L) {
+    block_sum_all<NV>(v);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; q++) part[q * kMaxBlocks + L] = v[q];
+    }
+}
+
+__device__ __forceinline__ void range_of(int L, int G, int total, int &a, int &b) {
+    a = (int)(((int64_t)L * total) / G);
+    b = (int)(((int64_t)(L + 1) * total) / G);
+}
+
+// Neighbour indices and couplings of cell k, branch-free: an absent
+// neighbour points at k itself with a zero coupling.
+template <typename T>
+struct Nbr {
+    int kS, kW, kE, kN;
+    T cS, cW, cC, cE, cN;
+};
+
+template <typename T>
+__device__ __forceinline__ Nbr<T> neighbours(const DevOp<T> &A, int k) {
+    const int nx = A.nx;
+    int j = (int)((double)k * A.inv_nx);
+    if (j * nx > k) j--;
+    if ((j + 1) * nx <= k) j++;
+    const int i = k - j * nx;
+    Nbr<T> m;
+    const bool hasS = j > 0;
+    const bool hasW = i > 0 || A.periodic;
+    m.kS = hasS ? k - nx : k;
+    m.kN = (j < A.ny - 1) ? k + nx : k;
+    m.kW = (i > 0) ? k - 1 : (A.periodic ? k + nx - 1 : k);
+    m.kE = (i < nx - 1) ? k + 1 : (A.periodic ? k - nx + 1 : k);
+    const T aS = A.an[m.kS];
+    const T aW = A.ae[m.kW];
+    m.cS = hasS ? aS : T(0);
+    m.cW = hasW ? aW : T(0);
+    m.cC = A.diag[k];
+    m.cE = A.ae[k];     // zero across a non-periodic east edge (input rule)
+    m.cN = A.an[k];     // zero on the last row (input rule)
+    return m;
+}
+
+// y_k = (A v)_k with the terms in increasing column order for interior cells.
+template <typename T>
+__device__ __forceinline__ T apply_row(const Nbr<T> &m, T vS, T vW, T vC, T vE, T vN) {
+    T acc = m.cS * vS;
+    acc = fma(m.cW, vW, acc);
+    acc = fma(m.cC, vC, acc);
+    acc = fma(m.cE, vE, acc);
+    return fma(m.cN, vN, acc);
+}
+
+// Slice header of the sliced-ELL layout (wave-uniform, scalar loads).
+struct SliceMeta {
+    int row0, lg, width;
+    int64_t off;
+};
+
+// Headers of up to 64 slices of one wavefront, one per lane (a single
+// coalesced load), handed out with readlane: the wave pays one memory round
+// trip for all its headers.
+struct SliceHeaders {
+    int row0, meta, off_lo, off_hi;
+};
+
+template <typename T>
+__device__ __forceinline__ SliceHeaders load_headers(const DevSell<T> &M, int first, int stride,
+                                                     int count, int lane) {
+    SliceHeaders h{0, 0, 0, 0};
+    if (lane < count) {
+        const int sl = first + lane * stride;
+        h.row0 = M.row0[sl];
+        h.meta = M.meta[sl];
+        const int64_t o = M.off[sl];
+        h.off_lo = (int)(o & 0xffffffff);
+        h.off_hi = (int)(o >> 32);
+    }
+    return h;
+}
+
+__device__ __forceinline__ SliceMeta header_of(const SliceHeaders &h, int i) {
+    SliceMeta m;
+    m.row0 = __builtin_amdgcn_readlane(h.row0, i);
+    const int mt = __builtin_amdgcn_readlane(h.meta, i);
+    m.lg = mt & 255;
+    m.width = mt >> 8;
+    m.off = ((int64_t)__builtin_amdgcn_readlane(h.off_hi, i) << 32) |
+            (uint32_t)__builtin_amdgcn_readlane(h.off_lo, i);
+    return m;
+}
+
+// This lane's sum over its entries of one slice, acc = sum_c val[c] * g(idx[c])
+// in increasing c.  Batches of U: U index/value loads (streamed once, not kept
+// in cache), then U gathers, then U fused multiply-adds.
+#ifndef PCGA_SELL_NT
+#define PCGA_SELL_NT 1
+#endif
+template <typename P>
+__device__ __forceinline__ P stream_load(const P *p) {
+#if PCGA_SELL_NT
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+
+template <typename T, int U, typename Gth>
+__device__ __forceinline__ T lane_sum(const DevSell<T> &M, const SliceMeta &m, int lane,
+                                      const Gth &g) {
+    const int32_t *ip = M.idx + m.off + lane;
+    const T *vp = M.val + m.off + lane;
     T acc = T(0);
-    if (valid) {
-        const int j = k / nx;
-        const int i = k - j * nx;
-        if (j > 0) acc = A.an[k - nx] * v(k - nx);
-        if (i > 0) acc = fma(A.ae[k - 1], sh[tid], acc);
-        else if (A.periodic) acc = fma(A.ae[k + nx - 1], v(k + nx - 1), acc);
-        acc = fma(A.diag[k], own, acc);
-        if (i < nx - 1) acc = fma(A.ae[k], sh[tid + 2], acc);
-        else if (A.periodic) acc = fma(A.ae[k], v(k - nx + 1), acc);
-        if (j < A.ny - 1) acc = fma(A.an[k], v(k + nx), acc);
+    const int last = m.width - 1;
+    for (int cc = 0; cc < m.width; cc += U) {
+        // Past the slice width the last entry is re-read (an L1 hit) and its
+        // value replaced by zero: no branches, so every load of the batch is
+        // in flight at once.
+        int kk[U];
+        T zv[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int c = cc + u <= last ? cc + u : last;
+            kk[u] = stream_load(ip + (int64_t)c * kWave);
+            zv[u] = stream_load(vp + (int64_t)c * kWave);
+        }
+        T gv[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) gv[u] = g(kk[u]);
+#pragma unroll
+        for (int u = 0; u < U; u++) acc = fma(cc + u <= last ? zv[u] : T(0), gv[u], acc);
     }
-    y = acc;
-    __syncthreads();
+    return acc;
 }
 
-__device__ __forceinline__ void tile_range(int L, int G, int ntiles, int &t0, int &t1) {
-    t0 = (int)(((int64_t)L * ntiles) / G);
-    t1 = (int)(((int64_t)(L + 1) * ntiles) / G);
-}
+// Gather unroll per precision (register budget: all workgroups resident).
+#ifndef PCGA_SELL_U
+#define PCGA_SELL_U 8
+#endif
+template <typename T>
+struct SellUnroll { static constexpr int U = PCGA_SELL_U; };
 
 // ---------------------------------------------------------------------------
-// k_stencil: d_new = s + beta*d_old; q = A d_new; (d_new, q) -> alpha = rho/(d,q)
+// k_stencil: rho_k, beta; d_new = s + beta d_old; q = A d_new; (d_new,q) partials
+// par = k & 1 (fixed per position in a captured chunk; chunks are even).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_stencil(DevOp<T> A, const T *__restrict__ s,
-                                                    const T *__restrict__ dold,
-                                                    T *__restrict__ dnew, T *__restrict__ q,
-                                                    CtlBlock *cb, double *partials, int ntiles) {
+__global__ __launch_bounds__(kBS) void k_stencil(DevOp<T> A, const T *__restrict__ s,
+                                                 const T *__restrict__ dold,
+                                                 T *__restrict__ dnew, T *__restrict__ q,
+                                                 CtlBlock *cb, Partials P, int g_sr, int par) {
     Ctl *c = &cb->c;
     if (c->done) return;
     const int G = gridDim.x, L = logical_block(blockIdx.x, G);
-    const T beta = (T)c->beta;
-    __shared__ T sh[kBlock + 2];
-    auto val = [&](int k) { return fma(beta, dold[k], s[k]); };
-    double acc = 0.0;
-    int t0, t1;
-    tile_range(L, G, ntiles, t0, t1);
-    for (int t = t0; t < t1; t++) {
-        T own, y;
-        bool valid;
-        stencil_tile(A, t * kBlock, val, sh, own, y, valid);
-        if (valid) {
-            const int k = t * kBlock + threadIdx.x;
-            dnew[k] = own;
-            q[k] = y;
-            acc += (double)own * (double)y;
-        }
-    }
-    double v[1] = {acc};
-    if (grid_finish<1>(v, partials, G, L, &c->cnt[kCntStencil]) && threadIdx.x == 0) {
-        const double dq = v[0];
-        if (dq > 0.0 && dq < INFINITY) {
-            c->alpha = c->rho / dq;
-        } else {
-            c->status = (dq == dq && dq != INFINITY) ? kStBreak : kStNan;
+    double rs[1];
+    sum_partials<1>(P.sr, g_sr, rs);
+    const double rho = rs[0];
+    const int k = c->kk[par];
+    if (!finite_pos(rho)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            c->status = is_bad(rho) ? kStNan : kStBreak;
             c->done = 1;
         }
+        return;
     }
+    const double beta = (k == 0) ? 0.0 : rho / c->rho[par ^ 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) c->rho[par] = rho;
+    const T bt = (T)beta;
+    double acc = 0.0;
+    int c0, c1;
+    range_of(L, G, A.n, c0, c1);
+    for (int base = c0 + threadIdx.x; base < c1 + (int)threadIdx.x; base += kStep) {
+        T sv[kCPT][5], dv[kCPT][5];
+        Nbr<T> m[kCPT];
+        int kc[kCPT];
+#pragma unroll
+        for (int u = 0; u < kCPT; u++) {
+            kc[u] = base + u * kBS;
+            const int kk = kc[u] < c1 ? kc[u] : c1 - 1;
+            m[u] = neighbours(A, kk);
+            const int idx[5] = {m[u].kS, m[u].kW, kk, m[u].kE, m[u].kN};
+#pragma unroll
+            for (int e = 0; e < 5; e++) {
+                sv[u][e] = s[idx[e]];
+                dv[u][e] = dold[idx[e]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kCPT; u++) {
+            if (kc[u] < c1) {
+                T v[5];
+#pragma unroll
+                for (int e = 0; e < 5; e++) v[e] = fma(bt, dv[u][e], sv[u][e]);
+                const T y = apply_row(m[u], v[0], v[1], v[2], v[3], v[4]);
+                dnew[kc[u]] = v[2];
+                q[kc[u]] = y;
+                acc += (double)v[2] * (double)y;
+            }
+        }
+    }
+    double pv[1] = {acc};
+    put_partials<1>(pv, P.dq, L);
 }
 
 // ---------------------------------------------------------------------------
-// k_zt: t = D^-1 Z^T r'.  FUSED: r' = r - alpha q (written to rnext),
-// x += alpha d, ||r'||^2 -> stop test and history.  Not fused: r' = r.
-// Each wavefront handles slices of the sliced-ELL layout of Z^T (rows of Z^T
-// are the columns of Z; the unit diagonal is added last).
+// k_zt: t = D^-1 Z^T r'.  FUSED: alpha = rho_k / (d,q); r' = r - alpha q
+// (written to rnext), x += alpha d, ||r'||^2 partials.  Not fused: r' = r.
+// Rows of Z^T are the columns of Z; the unit diagonal is added last.
 // ---------------------------------------------------------------------------
 template <typename T, bool FUSED>
-__global__ __launch_bounds__(kBlock) void k_zt(DevSell<T> Zt, const T *__restrict__ dinv,
-                                               const T *__restrict__ rcur,
-                                               const T *__restrict__ q,
-                                               const T *__restrict__ dcur,
-                                               T *__restrict__ rnext, T *__restrict__ x,
-                                               T *__restrict__ t, CtlBlock *cb,
-                                               double *partials) {
+__global__ __launch_bounds__(kBS) void k_zt(DevSell<T> Zt, const T *__restrict__ dinv,
+                                            const T *__restrict__ rcur, const T *__restrict__ q,
+                                            const T *__restrict__ dcur, T *__restrict__ rnext,
+                                            T *__restrict__ x, T *__restrict__ t, CtlBlock *cb,
+                                            Partials P, int g_dq, int par) {
     Ctl *c = &cb->c;
-    if (FUSED && c->done) return;
-    const int G = gridDim.x, L = logical_block(blockIdx.x, G);
-    const T at = FUSED ? (T)c->alpha : T(0);
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    int s0, s1;
-    tile_range(L, G, Zt.nslices, s0, s1);
-    double rr = 0.0;
-    for (int sl = s0 + w; sl < s1; sl += kBlock / kWave) {
-        const int row0 = Zt.row0[sl];
-        const int meta = Zt.meta[sl];
-        const int64_t off = Zt.off[sl];
-        const int lg = meta & 255, width = meta >> 8;
-        const int row = row0 + (lane >> lg);
-        const int32_t *ip = Zt.idx + off + lane;
-        const T *vp = Zt.val + off + lane;
-        T acc = T(0);
-        for (int cc = 0; cc < width; cc++) {
-            const int kk = ip[(int64_t)cc * kWave];
-            const T zv = vp[(int64_t)cc * kWave];
-            const T rk = FUSED ? fma(-at, q[kk], rcur[kk]) : rcur[kk];
-            acc = fma(zv, rk, acc);
+    T at = T(0);
+    if (FUSED) {
+        if (c->done) return;
+        double dq[1];
+        sum_partials<1>(P.dq, g_dq, dq);
+        if (!finite_pos(dq[0])) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                c->status = is_bad(dq[0]) ? kStNan : kStBreak;
+                c->done = 1;
+            }
+            return;
         }
-        for (int o = (1 << lg) >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
-        if ((lane & ((1 << lg) - 1)) == 0 && row < Zt.nrows) {
-            const T rj = FUSED ? fma(-at, q[row], rcur[row]) : rcur[row];
+        const double alpha = c->rho[par] / dq[0];
+        if (blockIdx.x == 0 && threadIdx.x == 0) c->alpha = alpha;
+        at = (T)alpha;
+    }
+    const int G = gridDim.x, L = logical_block(blockIdx.x, G);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
+    int s0, s1;
+    range_of(L, G, Zt.nslices, s0, s1);
+    double rr = 0.0;
+    auto g = [&](int kk) { return FUSED ? fma(-at, q[kk], rcur[kk]) : rcur[kk]; };
+    const int nsw = (s1 - s0 - w + kWavesPerBlock - 1) / kWavesPerBlock;   // this wave's slices
+    for (int i0 = 0; i0 < nsw; i0 += kWave) {
+      const int cnt = nsw - i0 < kWave ? nsw - i0 : kWave;
+      const SliceHeaders hd = load_headers(Zt, s0 + w + i0 * kWavesPerBlock, kWavesPerBlock, cnt, lane);
+      for (int i = 0; i < cnt; i++) {
+        const SliceMeta m = header_of(hd, i);
+        // own-row operands first, so their latency overlaps the slice's loads
+        const int row = m.row0 + (lane >> m.lg);
+        const bool lead = (lane & ((1 << m.lg) - 1)) == 0 && row < Zt.nrows;
+        const int rw = row < Zt.nrows ? row : Zt.nrows - 1;
+        const T rj = g(rw);
+        const T dj = FUSED ? dcur[rw] : T(0);
+        const T xj = FUSED ? x[rw] : T(0);
+        const T ij = dinv[rw];
+        T acc = lane_sum<T, SellUnroll<T>::U>(Zt, m, lane, g);
+        for (int o = (1 << m.lg) >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+        if (lead) {
             if (FUSED) {
                 rnext[row] = rj;
-                x[row] = fma(at, dcur[row], x[row]);
+                x[row] = fma(at, dj, xj);
                 rr += (double)rj * (double)rj;
             }
-            t[row] = (acc + rj) * dinv[row];
+            t[row] = (acc + rj) * ij;
         }
+      }
     }
-    if (!FUSED) return;
-    double v[1] = {rr};
-    if (grid_finish<1>(v, partials, G, L, &c->cnt[kCntZt]) && threadIdx.x == 0) {
-        const double rel = sqrt(v[0]) / c->nb;
-        const int k = c->k + 1;
-        c->k = k;
-        c->relres = rel;
-        cb->hist[k & (kHistRing - 1)] = rel;
-        if (!(rel == rel) || rel == INFINITY) {
-            c->status = kStNan;
-            c->done = 1;
-        } else if (rel <= c->tol) {
-            c->status = kStOk;
-            c->done = 1;
-        } else if (k >= c->maxit) {
-            c->status = kStNoconv;
-            c->done = 1;
-        }
+    if (FUSED) {
+        double pv[1] = {rr};
+        put_partials<1>(pv, P.rr, L);
     }
 }
 
 // ---------------------------------------------------------------------------
-// k_z: s = Z t (unit diagonal implicit); DOT: (s, r) -> rho, beta.
-// FIRST (prologue): rho = (s0, r0), beta = 0 so that d0 = s0.
+// k_z: (DOT, not FIRST) stop test from the ||r'||^2 partials, then s = Z t and
+// (s, r') partials.  FIRST: prologue (no stop test).  Neither: s = Z t only.
 // ---------------------------------------------------------------------------
 template <typename T, bool DOT, bool FIRST>
-__global__ __launch_bounds__(kBlock) void k_z(DevSell<T> Z, const T *__restrict__ t,
-                                              const T *__restrict__ r, T *__restrict__ s,
-                                              CtlBlock *cb, double *partials) {
+__global__ __launch_bounds__(kBS) void k_z(DevSell<T> Z, const T *__restrict__ t,
+                                           const T *__restrict__ r, T *__restrict__ s,
+                                           CtlBlock *cb, Partials P, int g_rr, int par) {
     Ctl *c = &cb->c;
-    if (DOT && c->done) return;
-    const int G = gridDim.x, L = logical_block(blockIdx.x, G);
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    int s0, s1;
-    tile_range(L, G, Z.nslices, s0, s1);
-    double sr = 0.0;
-    for (int sl = s0 + w; sl < s1; sl += kBlock / kWave) {
-        const int row0 = Z.row0[sl];
-        const int meta = Z.meta[sl];
-        const int64_t off = Z.off[sl];
-        const int lg = meta & 255, width = meta >> 8;
-        const int row = row0 + (lane >> lg);
-        const int32_t *ip = Z.idx + off + lane;
-        const T *vp = Z.val + off + lane;
-        T acc = T(0);
-        for (int cc = 0; cc < width; cc++) {
-            const int jj = ip[(int64_t)cc * kWave];
-            acc = fma(vp[(int64_t)cc * kWave], t[jj], acc);
-        }
-        for (int o = (1 << lg) >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
-        if ((lane & ((1 << lg) - 1)) == 0 && row < Z.nrows) {
-            const T sk = t[row] + acc;
-            s[row] = sk;
-            if (DOT) sr += (double)sk * (double)r[row];
-        }
+    if (DOT) {
+        if (c->done) return;
     }
-    if (!DOT) return;
-    double v[1] = {sr};
-    if (grid_finish<1>(v, partials, G, L, &c->cnt[kCntZ]) && threadIdx.x == 0) {
-        const double rn = v[0];
-        if (rn > 0.0 && rn < INFINITY) {
-            c->beta = FIRST ? 0.0 : rn / c->rho;
-            c->rho = rn;
-        } else {
-            c->status = (rn == rn && rn != INFINITY) ? kStBreak : kStNan;
-            c->done = 1;
+    if (DOT && !FIRST) {
+        double rr[1];
+        sum_partials<1>(P.rr, g_rr, rr);
+        const int k = c->kk[par] + 1;
+        const double rel = sqrt(rr[0]) / c->nb;
+        const bool bad = is_bad(rel);
+        const bool conv = !bad && rel <= c->tol;
+        const bool stop = bad || conv || k >= c->maxit;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            c->kk[par ^ 1] = k;
+            c->k = k;
+            c->relres = rel;
+            cb->hist[k & (kHistRing - 1)] = rel;
+            if (stop) {
+                c->status = bad ? kStNan : (conv ? kStOk : kStNoconv);
+                c->done = 1;
+            }
         }
+        if (stop) return;
+    }
+    const int G = gridDim.x, L = logical_block(blockIdx.x, G);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
+    int s0, s1;
+    range_of(L, G, Z.nslices, s0, s1);
+    double sr = 0.0;
+    auto g = [&](int jj) { return t[jj]; };
+    const int nsw = (s1 - s0 - w + kWavesPerBlock - 1) / kWavesPerBlock;   // this wave's slices
+    for (int i0 = 0; i0 < nsw; i0 += kWave) {
+      const int cnt = nsw - i0 < kWave ? nsw - i0 : kWave;
+      const SliceHeaders hd = load_headers(Z, s0 + w + i0 * kWavesPerBlock, kWavesPerBlock, cnt, lane);
+      for (int i = 0; i < cnt; i++) {
+        const SliceMeta m = header_of(hd, i);
+        const int row = m.row0 + (lane >> m.lg);
+        const bool lead = (lane & ((1 << m.lg) - 1)) == 0 && row < Z.nrows;
+        const int rw = row < Z.nrows ? row : Z.nrows - 1;
+        const T tk = t[rw];
+        const T rk = DOT ? r[rw] : T(0);
+        T acc = lane_sum<T, SellUnroll<T>::U>(Z, m, lane, g);
+        for (int o = (1 << m.lg) >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+        if (lead) {
+            const T sk = tk + acc;
+            s[row] = sk;
+            if (DOT) sr += (double)sk * (double)rk;
+        }
+      }
+    }
+    if (DOT) {
+        double pv[1] = {sr};
+        put_partials<1>(pv, P.sr, L);
     }
 }
 
 // ---------------------------------------------------------------------------
-// k_residual (FP64): r = b - A x with ||b||^2 and ||r||^2.
-// MODE 0 (solve prologue): writes r, sets nb, tol, maxit, k = 0, hist[0],
-//   and done when ||b|| = 0, the start is converged, or maxit = 0.
-// MODE 1 (true residual): only the norms (bb, rr_true).
+// Residual passes (FP64): r = b - A x with ||b||^2, ||r||^2 partials in P.res.
+// WRITE: store r.  Finalised by k_fin_residual (one workgroup).
 // ---------------------------------------------------------------------------
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_residual(DevOp<double> A, const double *__restrict__ x,
-                                                     const double *__restrict__ b,
-                                                     double *__restrict__ r, CtlBlock *cb,
-                                                     double *partials, int ntiles, double tol,
-                                                     int maxit) {
-    Ctl *c = &cb->c;
+template <bool WRITE>
+__global__ __launch_bounds__(kBS) void k_residual(DevOp<double> A, const double *__restrict__ x,
+                                                  const double *__restrict__ b,
+                                                  double *__restrict__ r, Partials P) {
     const int G = gridDim.x, L = logical_block(blockIdx.x, G);
-    __shared__ double sh[kBlock + 2];
-    auto val = [&](int k) { return x[k]; };
     double bb = 0.0, rr = 0.0;
-    int t0, t1;
-    tile_range(L, G, ntiles, t0, t1);
-    for (int t = t0; t < t1; t++) {
-        double own, y;
-        bool valid;
-        stencil_tile(A, t * kBlock, val, sh, own, y, valid);
-        if (valid) {
-            const int k = t * kBlock + threadIdx.x;
-            const double bk = b[k];
-            const double rk = bk - y;
-            if (MODE == 0) r[k] = rk;
-            bb += bk * bk;
-            rr += rk * rk;
+    int c0, c1;
+    range_of(L, G, A.n, c0, c1);
+    for (int base = c0 + threadIdx.x; base < c1 + (int)threadIdx.x; base += kStep) {
+#pragma unroll
+        for (int u = 0; u < kCPT; u++) {
+            const int k = base + u * kBS;
+            if (k < c1) {
+                const Nbr<double> m = neighbours(A, k);
+                const double y = apply_row(m, x[m.kS], x[m.kW], x[k], x[m.kE], x[m.kN]);
+                const double bk = b[k];
+                const double rk = bk - y;
+                if (WRITE) r[k] = rk;
+                bb += bk * bk;
+                rr += rk * rk;
+            }
         }
     }
-    double v[2] = {bb, rr};
-    if (grid_finish<2>(v, partials, G, L, &c->cnt[kCntResid]) && threadIdx.x == 0) {
-        c->bb = v[0];
-        if (MODE == 0) {
-            const double nb = sqrt(v[0]);
-            c->nb = nb;
-            c->tol = tol;
-            c->maxit = maxit;
-            c->k = 0;
-            c->status = kStOk;
-            c->done = 0;
-            c->beta = 0.0;
-            const double rel = (nb > 0.0) ? sqrt(v[1]) / nb : 0.0;
-            c->relres = rel;
-            cb->hist[0] = rel;
-            if (!(rel == rel) || rel == INFINITY) {
-                c->status = kStNan;
-                c->done = 1;
-            } else if (nb == 0.0 || rel <= tol) {
-                c->done = 1;
-            } else if (maxit <= 0) {
-                c->status = kStNoconv;
-                c->done = 1;
-            }
-        } else {
-            c->rr_true = v[1];
-        }
+    double pv[2] = {bb, rr};
+    put_partials<2>(pv, P.res, L);
+}
+
+// MODE 0 (solve prologue): nb, tol, maxit, k = 0, hist[0], done when ||b|| = 0,
+// the start is converged or maxit = 0.  MODE 1 (true residual): bb, rr_true.
+template <int MODE>
+__global__ __launch_bounds__(kBS) void k_fin_residual(CtlBlock *cb, Partials P, int g,
+                                                      double tol, int maxit) {
+    double v[2];
+    sum_partials<2>(P.res, g, v);
+    if (threadIdx.x != 0) return;
+    Ctl *c = &cb->c;
+    c->bb = v[0];
+    if (MODE == 1) {
+        c->rr_true = v[1];
+        return;
+    }
+    const double nb = sqrt(v[0]);
+    c->nb = nb;
+    c->tol = tol;
+    c->maxit = maxit;
+    c->kk[0] = 0;
+    c->kk[1] = 0;
+    c->k = 0;
+    c->status = kStOk;
+    c->done = 0;
+    const double rel = (nb > 0.0) ? sqrt(v[1]) / nb : 0.0;
+    c->relres = rel;
+    cb->hist[0] = rel;
+    if (is_bad(v[0]) || is_bad(v[1]) || is_bad(rel)) {
+        c->status = kStNan;
+        c->done = 1;
+    } else if (nb == 0.0 || rel <= tol) {
+        c->done = 1;
+    } else if (maxit <= 0) {
+        c->status = kStNoconv;
+        c->done = 1;
     }
 }
 
 // ---------------------------------------------------------------------------
 // k_refine (mixed outer step): x' = x + e (FP64; e is the FP32 correction, or
-// absent on the first step), r = b - A x' in FP64, r32 = fl32(r).
-// Norms: ||b||^2, ||r||^2, ||r32||^2.  The last workgroup records the outer
-// residual and initialises the inner solve (nb = ||r32||, k = 0, hist[0] = 1).
+// absent on the first step), r = b - A x' in FP64, r32 = fl32(r), with
+// ||b||^2, ||r||^2, ||r32||^2 partials.  Finalised by k_fin_refine, which
+// records the outer residual and initialises the inner solve.
 // ---------------------------------------------------------------------------
 template <bool ADD_E>
-__global__ __launch_bounds__(kBlock) void k_refine(DevOp<double> A, const double *__restrict__ x,
-                                                   const float *__restrict__ e,
-                                                   double *__restrict__ xnew,
-                                                   const double *__restrict__ b,
-                                                   float *__restrict__ r32, CtlBlock *cb,
-                                                   double *partials, int ntiles,
-                                                   double inner_tol, int inner_maxit) {
-    Ctl *c = &cb->c;
+__global__ __launch_bounds__(kBS) void k_refine(DevOp<double> A, const double *__restrict__ x,
+                                                const float *__restrict__ e,
+                                                double *__restrict__ xnew,
+                                                const double *__restrict__ b,
+                                                float *__restrict__ r32, Partials P) {
     const int G = gridDim.x, L = logical_block(blockIdx.x, G);
-    __shared__ double sh[kBlock + 2];
-    auto val = [&](int k) { return ADD_E ? x[k] + (double)e[k] : x[k]; };
+    auto xv = [&](int k) { return ADD_E ? x[k] + (double)e[k] : x[k]; };
     double bb = 0.0, rr = 0.0, r2 = 0.0;
-    int t0, t1;
-    tile_range(L, G, ntiles, t0, t1);
-    for (int t = t0; t < t1; t++) {
-        double own, y;
-        bool valid;
-        stencil_tile(A, t * kBlock, val, sh, own, y, valid);
-        if (valid) {
-            const int k = t * kBlock + threadIdx.x;
-            const double bk = b[k];
-            const double rk = bk - y;
-            const float rf = (float)rk;
-            if (ADD_E) xnew[k] = own;
-            r32[k] = rf;
-            bb += bk * bk;
-            rr += rk * rk;
-            r2 += (double)rf * (double)rf;
+    int c0, c1;
+    range_of(L, G, A.n, c0, c1);
+    for (int base = c0 + threadIdx.x; base < c1 + (int)threadIdx.x; base += kStep) {
+#pragma unroll
+        for (int u = 0; u < kCPT; u++) {
+            const int k = base + u * kBS;
+            if (k < c1) {
+                const Nbr<double> m = neighbours(A, k);
+                const double own = xv(k);
+                const double y = apply_row(m, xv(m.kS), xv(m.kW), own, xv(m.kE), xv(m.kN));
+                const double bk = b[k];
+                const double rk = bk - y;
+                const float rf = (float)rk;
+                if (ADD_E) xnew[k] = own;
+                r32[k] = rf;
+                bb += bk * bk;
+                rr += rk * rk;
+                r2 += (double)rf * (double)rf;
+            }
         }
     }
-    double v[3] = {bb, rr, r2};
-    if (grid_finish<3>(v, partials, G, L, &c->cnt[kCntRefine]) && threadIdx.x == 0) {
-        c->bb = v[0];
-        c->rr_true = v[1];
-        c->inner_nb2 = v[2];
-        c->nb = sqrt(v[2]);
-        c->tol = inner_tol;
-        c->maxit = inner_maxit;
-        c->k = 0;
-        c->status = kStOk;
-        c->beta = 0.0;
-        c->relres = 1.0;
-        cb->hist[0] = 1.0;
-        c->done = (v[2] > 0.0) ? 0 : 1;
-        if (!(v[1] == v[1]) || v[1] == INFINITY) {
-            c->status = kStNan;
-            c->done = 1;
-        }
+    double pv[3] = {bb, rr, r2};
+    put_partials<3>(pv, P.res, L);
+}
+
+static __global__ __launch_bounds__(kBS) void k_fin_refine(CtlBlock *cb, Partials P, int g,
+                                                    double inner_tol, int inner_maxit) {
+    double v[3];
+    sum_partials<3>(P.res, g, v);
+    if (threadIdx.x != 0) return;
+    Ctl *c = &cb->c;
+    c->bb = v[0];
+    c->rr_true = v[1];
+    c->inner_nb2 = v[2];
+    c->nb = sqrt(v[2]);
+    c->tol = inner_tol;
+    c->maxit = inner_maxit;
+    c->kk[0] = 0;
+    c->kk[1] = 0;
+    c->k = 0;
+    c->status = kStOk;
+    c->relres = 1.0;
+    cb->hist[0] = 1.0;
+    c->done = (v[2] > 0.0) ? 0 : 1;
+    if (is_bad(v[0]) || is_bad(v[1]) || is_bad(v[2])) {
+        c->status = kStNan;
+        c->done = 1;
     }
 }
 
 // y = A x in FP64 (single step, for tests).
-__global__ __launch_bounds__(kBlock) void k_apply_a(DevOp<double> A, const double *__restrict__ x,
-                                                    double *__restrict__ y, int ntiles) {
-    __shared__ double sh[kBlock + 2];
-    auto val = [&](int k) { return x[k]; };
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        double own, yy;
-        bool valid;
-        stencil_tile(A, t * kBlock, val, sh, own, yy, valid);
-        if (valid) y[t * kBlock + threadIdx.x] = yy;
+static __global__ __launch_bounds__(kBS) void k_apply_a(DevOp<double> A, const double *__restrict__ x,
+                                                 double *__restrict__ y) {
+    for (int k = blockIdx.x * kBS + threadIdx.x; k < A.n; k += gridDim.x * kBS) {
+        const Nbr<double> m = neighbours(A, k);
+        y[k] = apply_row(m, x[m.kS], x[m.kW], x[k], x[m.kE], x[m.kN]);
     }
 }
 
 template <typename S, typename D>
-__global__ __launch_bounds__(kBlock) void k_convert(int n, const S *__restrict__ in,
-                                                    D *__restrict__ out) {
-    for (int k = blockIdx.x * kBlock + threadIdx.x; k < n; k += gridDim.x * kBlock)
-        out[k] = (D)in[k];
+__global__ __launch_bounds__(kBS) void k_convert(int n, const S *__restrict__ in,
+                                                 D *__restrict__ out) {
+    for (int k = blockIdx.x * kBS + threadIdx.x; k < n; k += gridDim.x * kBS) out[k] = (D)in[k];
 }
 
 }  // namespace pcga

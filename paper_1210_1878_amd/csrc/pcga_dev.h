@@ -8,16 +8,21 @@
 
 namespace pcga {
 
-constexpr int kBlock = 256;        // threads per workgroup (4 wavefronts)
+constexpr int kBS = 256;           // threads per workgroup (4 wavefronts, one per SIMD)
 constexpr int kWave = 64;          // CDNA wavefront
+constexpr int kWavesPerBlock = kBS / kWave;
+constexpr int kCPT = 2;            // stencil cells per thread per step
+constexpr int kStep = kBS * kCPT;  // stencil cells per workgroup step
 constexpr int kHistRing = 4096;    // residual-history ring (entries)
-constexpr int kMaxBlocks = 4096;   // upper bound on partial sums per kernel
+constexpr int kMaxBlocks = 2048;   // workgroups per kernel = partial sums per reduction
 
-// Five-point operator in A5 form, device copy.
+// Five-point operator in A5 form, device copy.  inv_nx = 1/nx (row index by
+// multiplication, corrected to the exact quotient).
 template <typename T>
 struct DevOp {
     const T *diag, *ae, *an;
     int32_t nx, ny, periodic, n;
+    double inv_nx;
 };
 
 // Sliced ELL with per-slice lanes per row (layout described in pcga_host.h).
@@ -30,23 +35,31 @@ struct DevSell {
     int32_t nslices, nrows;
 };
 
+// Per-workgroup partial sums of the three reductions of an iteration and of
+// the residual passes (each kMaxBlocks doubles, one slot per workgroup).
+struct Partials {
+    double *dq, *rr, *sr, *res;   // res: 3 x kMaxBlocks
+};
+
 // Scalars and flags of one solve; lives in device memory, copied to pinned
-// host memory between chunks.
+// host memory between chunks.  Fields that a kernel both reads (all
+// workgroups) and updates (workgroup 0) are double-buffered by iteration
+// parity so that no workgroup can observe the update of the same launch.
 struct Ctl {
-    double rho, alpha, beta, nb, tol, relres;
+    double rho[2];               // rho_k = (s_k, r_k), slot k & 1
+    double nb, tol, relres;
     double bb, rr_true;          // ||b||^2 and ||b - A x||^2 of the last residual pass
     double inner_nb2;            // ||fl32(r)||^2 (mixed: inner right-hand side)
-    int32_t k, maxit, done, status;
-    uint32_t cnt[8];             // last-workgroup counters, one per kernel kind
-    int32_t pad[4];
+    double alpha;                // last alpha (diagnostics)
+    int32_t kk[2];               // iteration count k, slot k & 1 (read by kernels)
+    int32_t maxit, done, status;
+    int32_t k;                   // iteration count for the host (never read by kernels)
+    int32_t pad[5];
 };
 
 struct CtlBlock {
     Ctl c;
     double hist[kHistRing];
 };
-
-// Counter slots
-enum : int { kCntStencil = 0, kCntZt = 1, kCntZ = 2, kCntResid = 3, kCntRefine = 4 };
 
 }  // namespace pcga

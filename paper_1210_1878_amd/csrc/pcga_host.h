@@ -5,7 +5,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/pcgainv.h"
+#include "pcgainv.h"
 
 namespace pcga {
 

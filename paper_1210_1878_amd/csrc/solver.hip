@@ -21,6 +21,7 @@
 
 #include "kernels.h"
 #include "pcga_host.h"
+#include "solver_internal.h"
 
 namespace pcga {
 
@@ -110,56 +111,6 @@ int build_layouts(const AinvFactor &F, int target_width, HostLayouts &H) {
 
 }  // namespace
 
-struct pcga_solver {
-    int precision = PCGA_FP64;
-    int64_t n = 0, nnz_off = 0;
-    int nx = 0, ny = 0, periodic = 0;
-    hipStream_t stream = nullptr;
-    int device = 0;
-    void *ws = nullptr;
-    size_t ws_bytes = 0;
-
-    DevOp<double> A64{};
-    DevOp<float> A32{};
-    DevSell<double> zt64{}, z64{};
-    DevSell<float> zt32{}, z32{};
-    double *dinv64 = nullptr;
-    float *dinv32 = nullptr;
-
-    // FP64 iteration vectors (PCGA_FP64)
-    double *x = nullptr, *r[2] = {nullptr, nullptr}, *s = nullptr, *d[2] = {nullptr, nullptr},
-           *q = nullptr, *t = nullptr;
-    // FP32 inner vectors and FP64 outer solution (PCGA_MIXED)
-    float *e32 = nullptr, *r32[2] = {nullptr, nullptr}, *s32 = nullptr,
-          *d32[2] = {nullptr, nullptr}, *q32 = nullptr, *t32 = nullptr;
-    double *x64[2] = {nullptr, nullptr};
-    float *tmp32 = nullptr;   // apply_prec staging (mixed)
-
-    double *partials = nullptr;
-    CtlBlock *cb = nullptr;
-    CtlBlock *snap[2] = {nullptr, nullptr};   // pinned host
-    hipEvent_t ev[2] = {nullptr, nullptr};
-
-    int ntiles = 0;
-    int g_st = 1, g_zt = 1, g_z = 1;
-    int max_blocks = 2048;
-    int chunk = 32;
-    bool use_graph = true;
-    hipGraphExec_t graph = nullptr;
-    int graph_chunk = 0;
-    int64_t sell_entries = 0;
-    double bytes_per_iter = 0.0;
-
-    void grids() {
-        const int gm = std::max(1, std::min(max_blocks, kMaxBlocks));
-        ntiles = (int)((n + kBlock - 1) / kBlock);
-        g_st = std::max(1, std::min(ntiles, gm));
-        const int nsz = precision == PCGA_FP64 ? zt64.nslices : zt32.nslices;
-        const int nsr = precision == PCGA_FP64 ? z64.nslices : z32.nslices;
-        g_zt = std::max(1, std::min((nsz + 3) / 4, gm));
-        g_z = std::max(1, std::min((nsr + 3) / 4, gm));
-    }
-};
 
 namespace {
 
@@ -212,7 +163,10 @@ size_t carve(pcga_solver &S, void *base, const HostLayouts &H) {
         S.x64[0] = C.take<double>(n);
         S.x64[1] = C.take<double>(n);
     }
-    S.partials = C.take<double>(3 * (size_t)kMaxBlocks);
+    S.P.dq = C.take<double>(kMaxBlocks);
+    S.P.rr = C.take<double>(kMaxBlocks);
+    S.P.sr = C.take<double>(kMaxBlocks);
+    S.P.res = C.take<double>(3 * (size_t)kMaxBlocks);
     S.cb = C.take<CtlBlock>(1);
     return C.off + 256;
 }
@@ -390,16 +344,11 @@ int pcga_solver_create(const pcga_a5_t *A, const pcga_ainv_t *F, int precision, 
     S->ws = ws;
     S->ws_bytes = bytes;
     carve(*S, ws, H);
-    for (auto *dv : {&S->A64}) {
-        dv->nx = A->nx;
-        dv->ny = A->ny;
-        dv->periodic = S->periodic;
-        dv->n = (int32_t)n;
-    }
-    S->A32.nx = A->nx;
-    S->A32.ny = A->ny;
-    S->A32.periodic = S->periodic;
-    S->A32.n = (int32_t)n;
+    S->A64.nx = S->A32.nx = A->nx;
+    S->A64.ny = S->A32.ny = A->ny;
+    S->A64.periodic = S->A32.periodic = S->periodic;
+    S->A64.n = S->A32.n = (int32_t)n;
+    S->A64.inv_nx = S->A32.inv_nx = 1.0 / (double)A->nx;
     S->sell_entries = H.zt.entries() + H.z.entries();
 
     auto fail_free = [&](int code) {
@@ -552,26 +501,59 @@ IterBufs<float> bufs32(pcga_solver &S) {
             {S.d32[0], S.d32[1]}, S.q32, S.t32};
 }
 
+// One kernel of iteration parity p: 0 stencil, 1 axpy + Z^T, 2 Z + dot.
 template <typename T>
-void launch_iters(pcga_solver &S, const IterBufs<T> &B, int count) {
-    for (int it = 0; it < count; it++) {
-        const int p = it & 1;
-        k_stencil<T><<<S.g_st, kBlock, 0, S.stream>>>(B.A, B.s, B.d[p], B.d[p ^ 1], B.q, S.cb,
-                                                      S.partials, S.ntiles);
-        k_zt<T, true><<<S.g_zt, kBlock, 0, S.stream>>>(B.zt, B.dinv, B.r[p], B.q, B.d[p ^ 1],
-                                                       B.r[p ^ 1], B.x, B.t, S.cb, S.partials);
-        k_z<T, true, false><<<S.g_z, kBlock, 0, S.stream>>>(B.z, B.t, B.r[p ^ 1], B.s, S.cb,
-                                                           S.partials);
+void launch_kernel(pcga_solver &S, const IterBufs<T> &B, int p, int which) {
+    switch (which) {
+        case 0:
+            k_stencil<T><<<S.g_st, kBS, 0, S.stream>>>(B.A, B.s, B.d[p], B.d[p ^ 1], B.q, S.cb, S.P,
+                                                       S.g_z, p);
+            break;
+        case 1:
+            k_zt<T, true><<<S.g_zt, kBS, 0, S.stream>>>(B.zt, B.dinv, B.r[p], B.q, B.d[p ^ 1],
+                                                        B.r[p ^ 1], B.x, B.t, S.cb, S.P, S.g_st, p);
+            break;
+        default:
+            k_z<T, true, false><<<S.g_z, kBS, 0, S.stream>>>(B.z, B.t, B.r[p ^ 1], B.s, S.cb, S.P,
+                                                            S.g_zt, p);
+            break;
     }
 }
 
 template <typename T>
+void launch_iters(pcga_solver &S, const IterBufs<T> &B, int count) {
+    for (int it = 0; it < count; it++)
+        for (int w = 0; w < 3; w++) launch_kernel<T>(S, B, it & 1, w);
+}
+
+// r0 = b - A x0 (FP64) and the solve's control state.
+void launch_residual_prologue(pcga_solver &S, const double *x, const double *b, double *r,
+                              double tol, int maxit) {
+    k_residual<true><<<S.g_st, kBS, 0, S.stream>>>(S.A64, x, b, r, S.P);
+    k_fin_residual<0><<<1, kBS, 0, S.stream>>>(S.cb, S.P, S.g_st, tol, maxit);
+}
+
+void launch_true_residual(pcga_solver &S, const double *x, const double *b) {
+    k_residual<false><<<S.g_st, kBS, 0, S.stream>>>(S.A64, x, b, nullptr, S.P);
+    k_fin_residual<1><<<1, kBS, 0, S.stream>>>(S.cb, S.P, S.g_st, 0.0, 0);
+}
+
+void launch_refine(pcga_solver &S, bool add_e, const double *x, double *xnew, const double *b,
+                   double inner_tol, int inner_maxit) {
+    if (add_e)
+        k_refine<true><<<S.g_st, kBS, 0, S.stream>>>(S.A64, x, S.e32, xnew, b, S.r32[0], S.P);
+    else
+        k_refine<false><<<S.g_st, kBS, 0, S.stream>>>(S.A64, x, nullptr, nullptr, b, S.r32[0], S.P);
+    k_fin_refine<<<1, kBS, 0, S.stream>>>(S.cb, S.P, S.g_st, inner_tol, inner_maxit);
+}
+
+// t = D^-1 Z^T r0 ; s0 = Z t ; (s0, r0) partials ; d[0] = 0
+template <typename T>
 int prologue_prec(pcga_solver &S, const IterBufs<T> &B) {
-    // t = D^-1 Z^T r0 ; s0 = Z t ; rho0 = (s0, r0) ; beta = 0 ; d[0] = 0
     HIP_TRY(hipMemsetAsync(B.d[0], 0, S.n * sizeof(T), S.stream));
-    k_zt<T, false><<<S.g_zt, kBlock, 0, S.stream>>>(B.zt, B.dinv, B.r[0], nullptr, nullptr,
-                                                    nullptr, nullptr, B.t, S.cb, S.partials);
-    k_z<T, true, true><<<S.g_z, kBlock, 0, S.stream>>>(B.z, B.t, B.r[0], B.s, S.cb, S.partials);
+    k_zt<T, false><<<S.g_zt, kBS, 0, S.stream>>>(B.zt, B.dinv, B.r[0], nullptr, nullptr, nullptr,
+                                                 nullptr, B.t, S.cb, S.P, 0, 0);
+    k_z<T, true, true><<<S.g_z, kBS, 0, S.stream>>>(B.z, B.t, B.r[0], B.s, S.cb, S.P, 0, 0);
     HIP_TRY(hipGetLastError());
     return PCGA_OK;
 }
@@ -609,8 +591,8 @@ int ensure_graph(pcga_solver &S, const IterBufs<T> &B) {
     return PCGA_OK;
 }
 
-// Run chunks until the device sets `done`.  hist_out receives entries
-// k_first..k (k_first = 1) as they arrive; returns the final snapshot slot.
+// Run chunks until the device sets `done`.  hist_out receives entries 1..k
+// as they arrive; final_slot names the snapshot holding the final state.
 template <typename T>
 int run_chunks(pcga_solver &S, const IterBufs<T> &B, double *hist_out, int64_t hist_cap,
                int64_t maxit, int &final_slot) {
@@ -674,8 +656,7 @@ int pcga_pcg_solve(pcga_solver_t *S, const double *b_dev, double *x_dev, double 
     IterBufs<double> B = bufs64(R);
     const size_t nb8 = R.n * sizeof(double);
     HIP_TRY(hipMemcpyAsync(R.x, x_dev, nb8, hipMemcpyDeviceToDevice, R.stream));
-    k_residual<0><<<R.g_st, kBlock, 0, R.stream>>>(R.A64, R.x, b_dev, R.r[0], R.cb, R.partials,
-                                                   R.ntiles, tol, maxit);
+    launch_residual_prologue(R, R.x, b_dev, R.r[0], tol, maxit);
     int st = prologue_prec<double>(R, B);
     if (st) return st;
     if ((st = snapshot(R, 0))) return st;
@@ -697,8 +678,7 @@ int pcga_pcg_solve(pcga_solver_t *S, const double *b_dev, double *x_dev, double 
     }
     const Ctl cf = R.snap[slot]->c;
     // true residual ||b - A x|| in FP64
-    k_residual<1><<<R.g_st, kBlock, 0, R.stream>>>(R.A64, R.x, b_dev, nullptr, R.cb, R.partials,
-                                                   R.ntiles, 0.0, 0);
+    launch_true_residual(R, R.x, b_dev);
     HIP_TRY(hipMemcpyAsync(x_dev, R.x, nb8, hipMemcpyDeviceToDevice, R.stream));
     if ((st = snapshot(R, 0))) return st;
     if ((st = wait_snap(R, 0))) return st;
@@ -731,17 +711,8 @@ int pcga_pcg_solve_mixed(pcga_solver_t *S, const double *b_dev, double *x_dev, d
     int cur = 0, o = 0, total = 0, st = 0, result = PCGA_OK;
     double rel = 0.0;
     for (;;) {
-        if (o == 0)
-            k_refine<false><<<R.g_st, kBlock, 0, R.stream>>>(R.A64, R.x64[cur], nullptr, nullptr,
-                                                             b_dev, R.r32[0], R.cb, R.partials,
-                                                             R.ntiles, inner_tol, inner_maxit);
-        else {
-            k_refine<true><<<R.g_st, kBlock, 0, R.stream>>>(R.A64, R.x64[cur], R.e32,
-                                                            R.x64[cur ^ 1], b_dev, R.r32[0], R.cb,
-                                                            R.partials, R.ntiles, inner_tol,
-                                                            inner_maxit);
-            cur ^= 1;
-        }
+        launch_refine(R, o > 0, R.x64[cur], R.x64[cur ^ 1], b_dev, inner_tol, inner_maxit);
+        if (o > 0) cur ^= 1;
         HIP_TRY(hipGetLastError());
         if ((st = snapshot(R, 0))) return st;
         if ((st = wait_snap(R, 0))) return st;
@@ -758,7 +729,10 @@ int pcga_pcg_solve_mixed(pcga_solver_t *S, const double *b_dev, double *x_dev, d
         }
         rel = std::sqrt(c.rr_true) / std::sqrt(c.bb);
         if (o < hist_cap) hist_host[o] = rel;
-        if (!(rel == rel) || std::isinf(rel)) { result = fail(PCGA_ENAN, "NaN/Inf in residual"); break; }
+        if (c.status == kStNan || !(rel == rel) || std::isinf(rel)) {
+            result = fail(PCGA_ENAN, "NaN/Inf in residual");
+            break;
+        }
         if (rel <= tol) { result = PCGA_OK; break; }
         if (o == max_outer) { result = PCGA_NOCONV; break; }
         // inner FP32 PCG for A e = r32, e0 = 0
@@ -791,7 +765,8 @@ int pcga_pcg_solve_mixed(pcga_solver_t *S, const double *b_dev, double *x_dev, d
 int pcga_apply_a(pcga_solver_t *S, const double *x_dev, double *y_dev) {
     if (!S || !x_dev || !y_dev) return fail(PCGA_EINVAL, "NULL argument");
     HIP_TRY(hipSetDevice(S->device));
-    k_apply_a<<<S->g_st, kBlock, 0, S->stream>>>(S->A64, x_dev, y_dev, S->ntiles);
+    const int g = (int)std::min<int64_t>(4096, (S->n + kBS - 1) / kBS);
+    k_apply_a<<<g, kBS, 0, S->stream>>>(S->A64, x_dev, y_dev);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(S->stream));
     return PCGA_OK;
@@ -800,22 +775,22 @@ int pcga_apply_a(pcga_solver_t *S, const double *x_dev, double *y_dev) {
 int pcga_apply_prec(pcga_solver_t *S, const double *r_dev, double *t_dev, double *s_dev) {
     if (!S || !r_dev || !t_dev || !s_dev) return fail(PCGA_EINVAL, "NULL argument");
     HIP_TRY(hipSetDevice(S->device));
-    const int gc = std::min(1024, (int)((S->n + kBlock - 1) / kBlock));
+    const int gc = (int)std::min<int64_t>(4096, (S->n + kBS - 1) / kBS);
     if (S->precision == PCGA_FP64) {
-        k_zt<double, false><<<S->g_zt, kBlock, 0, S->stream>>>(S->zt64, S->dinv64, r_dev, nullptr,
-                                                               nullptr, nullptr, nullptr, t_dev,
-                                                               S->cb, S->partials);
-        k_z<double, false, false><<<S->g_z, kBlock, 0, S->stream>>>(S->z64, t_dev, nullptr, s_dev,
-                                                                   S->cb, S->partials);
+        k_zt<double, false><<<S->g_zt, kBS, 0, S->stream>>>(S->zt64, S->dinv64, r_dev, nullptr,
+                                                            nullptr, nullptr, nullptr, t_dev, S->cb,
+                                                            S->P, 0, 0);
+        k_z<double, false, false><<<S->g_z, kBS, 0, S->stream>>>(S->z64, t_dev, nullptr, s_dev,
+                                                                S->cb, S->P, 0, 0);
     } else {
-        k_convert<double, float><<<gc, kBlock, 0, S->stream>>>((int)S->n, r_dev, S->r32[0]);
-        k_zt<float, false><<<S->g_zt, kBlock, 0, S->stream>>>(S->zt32, S->dinv32, S->r32[0],
-                                                              nullptr, nullptr, nullptr, nullptr,
-                                                              S->t32, S->cb, S->partials);
-        k_z<float, false, false><<<S->g_z, kBlock, 0, S->stream>>>(S->z32, S->t32, nullptr,
-                                                                  S->tmp32, S->cb, S->partials);
-        k_convert<float, double><<<gc, kBlock, 0, S->stream>>>((int)S->n, S->t32, t_dev);
-        k_convert<float, double><<<gc, kBlock, 0, S->stream>>>((int)S->n, S->tmp32, s_dev);
+        k_convert<double, float><<<gc, kBS, 0, S->stream>>>((int)S->n, r_dev, S->r32[0]);
+        k_zt<float, false><<<S->g_zt, kBS, 0, S->stream>>>(S->zt32, S->dinv32, S->r32[0], nullptr,
+                                                           nullptr, nullptr, nullptr, S->t32, S->cb,
+                                                           S->P, 0, 0);
+        k_z<float, false, false><<<S->g_z, kBS, 0, S->stream>>>(S->z32, S->t32, nullptr, S->tmp32,
+                                                               S->cb, S->P, 0, 0);
+        k_convert<float, double><<<gc, kBS, 0, S->stream>>>((int)S->n, S->t32, t_dev);
+        k_convert<float, double><<<gc, kBS, 0, S->stream>>>((int)S->n, S->tmp32, s_dev);
     }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(S->stream));
@@ -832,35 +807,25 @@ int pcga_profile_iteration(pcga_solver_t *S, const double *b_dev, int32_t reps, 
     // start state: x0 = 0, tolerance 0 so that no kernel stops early
     if (R.precision == PCGA_FP64) {
         HIP_TRY(hipMemsetAsync(R.x, 0, R.n * sizeof(double), R.stream));
-        k_residual<0><<<R.g_st, kBlock, 0, R.stream>>>(R.A64, R.x, b_dev, R.r[0], R.cb, R.partials,
-                                                       R.ntiles, 0.0, big);
+        launch_residual_prologue(R, R.x, b_dev, R.r[0], 0.0, big);
         if ((st = prologue_prec<double>(R, bufs64(R)))) return st;
     } else {
         HIP_TRY(hipMemsetAsync(R.x64[0], 0, R.n * sizeof(double), R.stream));
-        k_refine<false><<<R.g_st, kBlock, 0, R.stream>>>(R.A64, R.x64[0], nullptr, nullptr, b_dev,
-                                                         R.r32[0], R.cb, R.partials, R.ntiles, 0.0,
-                                                         big);
+        launch_refine(R, false, R.x64[0], nullptr, b_dev, 0.0, big);
         HIP_TRY(hipMemsetAsync(R.e32, 0, R.n * sizeof(float), R.stream));
         if ((st = prologue_prec<float>(R, bufs32(R)))) return st;
     }
-    std::vector<hipEvent_t> ev(3 * (size_t)reps + 1);
+    std::vector<hipEvent_t> ev(3 * (size_t)reps + 1, nullptr);
     for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
     auto cleanup = [&]() { for (auto &e : ev) (void)hipEventDestroy(e); };
     auto run = [&](auto B) -> hipError_t {
         using T = std::remove_pointer_t<decltype(B.x)>;
         hipError_t e = hipEventRecord(ev[0], R.stream);
-        for (int i = 0; i < reps && e == hipSuccess; i++) {
-            const int p = i & 1;
-            k_stencil<T><<<R.g_st, kBlock, 0, R.stream>>>(B.A, B.s, B.d[p], B.d[p ^ 1], B.q, R.cb,
-                                                          R.partials, R.ntiles);
-            e = hipEventRecord(ev[3 * i + 1], R.stream);
-            k_zt<T, true><<<R.g_zt, kBlock, 0, R.stream>>>(B.zt, B.dinv, B.r[p], B.q, B.d[p ^ 1],
-                                                           B.r[p ^ 1], B.x, B.t, R.cb, R.partials);
-            if (e == hipSuccess) e = hipEventRecord(ev[3 * i + 2], R.stream);
-            k_z<T, true, false><<<R.g_z, kBlock, 0, R.stream>>>(B.z, B.t, B.r[p ^ 1], B.s, R.cb,
-                                                               R.partials);
-            if (e == hipSuccess) e = hipEventRecord(ev[3 * i + 3], R.stream);
-        }
+        for (int i = 0; i < reps && e == hipSuccess; i++)
+            for (int w = 0; w < 3 && e == hipSuccess; w++) {
+                launch_kernel<T>(R, B, i & 1, w);
+                e = hipEventRecord(ev[3 * i + w + 1], R.stream);
+            }
         if (e == hipSuccess) e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(R.stream);
         return e;

@@ -1,0 +1,61 @@
+// solver_internal.h -- the device solver object shared by the single-grid
+// driver (solver.hip) and the batched driver (batch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "pcga_dev.h"
+#include "pcgainv.h"
+
+struct pcga_solver {
+    // (all device pointers point into the caller-provided workspace)
+    int precision = PCGA_FP64;
+    int64_t n = 0, nnz_off = 0;
+    int nx = 0, ny = 0, periodic = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+
+    pcga::DevOp<double> A64{};
+    pcga::DevOp<float> A32{};
+    pcga::DevSell<double> zt64{}, z64{};
+    pcga::DevSell<float> zt32{}, z32{};
+    double *dinv64 = nullptr;
+    float *dinv32 = nullptr;
+
+    // FP64 iteration vectors (PCGA_FP64)
+    double *x = nullptr, *r[2] = {nullptr, nullptr}, *s = nullptr, *d[2] = {nullptr, nullptr},
+           *q = nullptr, *t = nullptr;
+    // FP32 inner vectors and FP64 outer solution (PCGA_MIXED)
+    float *e32 = nullptr, *r32[2] = {nullptr, nullptr}, *s32 = nullptr,
+          *d32[2] = {nullptr, nullptr}, *q32 = nullptr, *t32 = nullptr;
+    double *x64[2] = {nullptr, nullptr};
+    float *tmp32 = nullptr;   // apply_prec staging (mixed)
+
+    pcga::Partials P{};
+    pcga::CtlBlock *cb = nullptr;
+    pcga::CtlBlock *snap[2] = {nullptr, nullptr};   // pinned host
+    hipEvent_t ev[2] = {nullptr, nullptr};
+
+    int g_st = 1, g_zt = 1, g_z = 1;
+    int max_blocks = pcga::kMaxBlocks;
+    int chunk = 32;
+    bool use_graph = true;
+    hipGraphExec_t graph = nullptr;
+    int graph_chunk = 0;
+    int64_t sell_entries = 0;
+    double bytes_per_iter = 0.0;
+
+    void grids() {
+        const int gm = std::max(1, std::min(max_blocks, pcga::kMaxBlocks));
+        const int nsteps = (int)((n + pcga::kStep - 1) / pcga::kStep);
+        g_st = std::max(1, std::min(nsteps, gm));
+        const int nsz = precision == PCGA_FP64 ? zt64.nslices : zt32.nslices;
+        const int nsr = precision == PCGA_FP64 ? z64.nslices : z32.nslices;
+        g_zt = std::max(1, std::min((nsz + pcga::kWavesPerBlock - 1) / pcga::kWavesPerBlock, gm));
+        g_z = std::max(1, std::min((nsr + pcga::kWavesPerBlock - 1) / pcga::kWavesPerBlock, gm));
+    }
+};

@@ -1,0 +1,176 @@
+"""Continuous-batching server for the elliptic solve of successive time steps.
+
+Each request is one time step of one grid: a right-hand side and a warm
+start (the grid's previous solution, like the initial guess taken from the
+previous step in Algorithm 1).  Every grid's operator, D^-1 and Z stay
+resident on the device (one PCGA_MIXED solver per grid).  Requests are
+admitted into the running batch as soon as their grid is idle (time steps of
+one grid are sequential) and their vectors fit the device-memory budget; the
+batch advances all admitted requests together, so requests that arrive while
+others are iterating share the device with them.  Latency is measured from
+arrival to the moment the solution is back in the request's output tensor.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+
+import numpy as np
+
+from .api import Batch, Solver, Stencil5, ainv_setup
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    grid: int
+    arrival: float                 # seconds since the start of the run
+    b: object = None               # device tensor [n]
+    x0: object = None              # device tensor [n]
+    admitted: float = -1.0
+    finished: float = -1.0
+    status: int = -99
+    true_relres: float = float("nan")
+    outer: int = 0
+    inner: int = 0
+    x: object = None
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class Server:
+    """Holds resident grids and serves time-step solves by continuous batching."""
+
+    def __init__(self, problems, drop_tol=0.05, device=None, hbm_budget=None, max_slots=64,
+                 tol=1e-10, inner_tol=1e-5, max_outer=30, chunk=16):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda" if device is None else device)
+        self.tol, self.inner_tol, self.max_outer = tol, inner_tol, max_outer
+        self.solvers = []
+        self.resident_bytes = 0
+        for p in problems:
+            A = Stencil5.from_problem(p)
+            S = Solver(A, ainv_setup(A, drop_tol), "mixed", device=self.device)
+            self.solvers.append(S)
+            self.resident_bytes += S.workspace_bytes
+        self.item_bytes = [Batch.item_bytes(S, 1) for S in self.solvers]
+        self.budget = hbm_budget            # bytes for in-flight request vectors (None: no limit)
+        self.batch = Batch(max_slots=max_slots, device=self.device, chunk=chunk)
+        self.in_flight_bytes = 0
+        self.busy = [False] * len(self.solvers)
+
+    def fits(self, grid):
+        return self.budget is None or self.in_flight_bytes + self.item_bytes[grid] <= self.budget
+
+    def admit(self, req, now):
+        slot = self.batch.add(self.solvers[req.grid], req.b.unsqueeze(0), X0=req.x0.unsqueeze(0),
+                              tol=self.tol, inner_tol=self.inner_tol, max_outer=self.max_outer,
+                              tag=req.rid)
+        self.in_flight_bytes += self.item_bytes[req.grid]
+        self.busy[req.grid] = True
+        req.admitted = now
+        return slot
+
+    def run(self, requests, make_rhs, on_done=None, clock=time.perf_counter, poll_chunks=1):
+        """Serve `requests` (sorted by arrival).  make_rhs(req) fills req.b and
+        req.x0 when the request is admitted (it may use the grid's previous
+        solution); on_done(req) is called when a solution is back.
+        Returns the finished requests."""
+        t0 = clock()
+        pending = collections.deque(requests)
+        queue = []
+        slots = {}
+        done = []
+        while pending or queue or slots:
+            now = clock() - t0
+            while pending and pending[0].arrival <= now:
+                queue.append(pending.popleft())
+            # admission: FIFO among requests whose grid is idle and that fit
+            rest = []
+            for req in queue:
+                if not self.busy[req.grid] and len(slots) < self.batch_capacity() and self.fits(req.grid):
+                    make_rhs(req)
+                    slots[self.admit(req, clock() - t0)] = req
+                else:
+                    rest.append(req)
+            queue = rest
+            if not slots:
+                if pending:
+                    wait = pending[0].arrival - (clock() - t0)
+                    if wait > 0:
+                        time.sleep(min(wait, 0.05))
+                continue
+            self.batch.run(poll_chunks)
+            for s in list(slots):
+                q = self.batch.query(s)
+                if not q["done"]:
+                    continue
+                X, q = self.batch.remove(s)
+                req = slots.pop(s)
+                req.finished = clock() - t0
+                req.status = q["status"]
+                req.true_relres = q["true_relres"][0]
+                req.outer, req.inner = q["outer"], q["inner_total"]
+                req.x = X[0]
+                self.busy[req.grid] = False
+                self.in_flight_bytes -= self.item_bytes[req.grid]
+                done.append(req)
+                if on_done:
+                    on_done(req)
+        return done
+
+    def batch_capacity(self):
+        return 64
+
+
+def poisson_arrivals(rate, count, n_grids, seed):
+    """Seeded Poisson process: exponential gaps at `rate` per second, grids
+    drawn uniformly."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    g = rng.integers(0, n_grids, size=count)
+    return [Request(rid=i, grid=int(g[i]), arrival=float(t[i])) for i in range(count)]
+
+
+class TimeStepper:
+    """Per-grid right-hand sides of successive time steps and warm starts:
+    b_t = b_{t-1} + 0.01 rms(b_{t-1}) xi, xi ~ N(0,1) on ocean cells (seeded),
+    x0_t = x_{t-1} (zero for the first step)."""
+
+    def __init__(self, problems, device, seed):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.b = [torch.from_numpy(p.b.copy()).to(device) for p in problems]
+        self.ocean = [torch.from_numpy(p.ocean.astype(np.float64)).to(device) for p in problems]
+        self.x = [torch.zeros(p.n, dtype=torch.float64, device=device) for p in problems]
+        self.gen = torch.Generator(device="cpu").manual_seed(seed)
+        self.steps = [0] * len(problems)
+
+    def __call__(self, req):
+        g = req.grid
+        if self.steps[g] > 0:
+            b = self.b[g]
+            xi = self.torch.randn(b.shape[0], generator=self.gen, dtype=self.torch.float64).to(self.device)
+            rms = self.torch.sqrt((b * b).sum() / self.ocean[g].sum())
+            self.b[g] = b + 0.01 * rms * xi * self.ocean[g]
+        self.steps[g] += 1
+        req.b = self.b[g].clone()
+        req.x0 = self.x[g].clone()
+
+    def done(self, req):
+        self.x[req.grid] = req.x.clone()
+
+
+def latency_stats(done):
+    lat = np.array([r.latency for r in done])
+    span = max(r.finished for r in done) - min(r.arrival for r in done)
+    return {"requests": len(done), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+            "solves_per_s": len(done) / span if span > 0 else float("nan"),
+            "worst_true_relres": float(max(r.true_relres for r in done)),
+            "all_ok": all(r.status == 0 for r in done)}

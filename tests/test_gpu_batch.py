@@ -1,0 +1,136 @@
+"""Batched mixed-precision solves through the C ABI (needs an MI355X).
+
+Each item must reach the FP64 target residual (checked with the oracle's
+product), agree with the single-grid mixed solve and the FP64 oracle within
+the refinement accuracy, and give bitwise the same result alone and in a mix
+(including items added while others are running).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from gen import orca
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-batch]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    if not torch.cuda.is_available():
+        pytest.skip("no ROCm device")
+    import paper_1210_1878_amd as P
+    return P
+
+
+def _members(seeds_shapes, nrhs):
+    out = []
+    for (nx, ny, seed) in seeds_shapes:
+        p = orca.orca_problem(nx, ny, seed, rhs=False)
+        rng = np.random.default_rng(seed + 1)
+        p.B = np.stack([orca.rhs_normal(p.ocean, rng) for _ in range(nrhs)])
+        out.append(p)
+    return out
+
+
+@pytest.fixture(scope="module")
+def ensemble(pkg):
+    say("building small uneven ensemble")
+    ps = _members([(60, 45, 11), (83, 52, 12), (37, 23, 13), (120, 90, 14)], 4)
+    sol = []
+    for p in ps:
+        A = pkg.Stencil5.from_problem(p)
+        sol.append(pkg.Solver(A, pkg.ainv_setup(A, 0.1), "mixed"))
+    return ps, sol
+
+
+def _check_item(ora, p, X, q, nrhs):
+    X = X.cpu().numpy()
+    assert q["status"] == 0 and q["done"]
+    for r in range(nrhs):
+        b = p.B[r]
+        true = np.linalg.norm(b - ora.spmv(p, X[r])) / np.linalg.norm(b)
+        assert true <= 1e-10, (r, true)
+        assert abs(true - q["true_relres"][r]) <= 1e-3 * true + 1e-13
+
+
+def test_batch_r4_and_r1(pkg, ora, ensemble):
+    ps, sol = ensemble
+    say("batch: 4 grids x 4 rhs, plus 1-rhs items")
+    Bt = pkg.Batch(max_slots=16)
+    slots = {}
+    for i, (p, S) in enumerate(zip(ps, sol)):
+        slots[Bt.add(S, torch.from_numpy(p.B).cuda(), tol=1e-10, inner_tol=1e-5)] = (i, 4)
+    for i in (0, 2):
+        p, S = ps[i], sol[i]
+        slots[Bt.add(S, torch.from_numpy(p.B[1:2]).cuda(), tol=1e-10, inner_tol=1e-5)] = (i, 1)
+    res = Bt.solve()
+    for s, (X, q) in res.items():
+        i, nrhs = slots[s]
+        p = ps[i]
+        if nrhs == 1:
+            p1 = orca.Problem(p.nx, p.ny, p.periodic, p.diag, p.ae, p.an, p.ocean, p.B[1], B=p.B[1:2])
+            _check_item(ora, p1, X, q, 1)
+        else:
+            _check_item(ora, p, X, q, 4)
+        say(f"  slot {s} grid {i} nrhs {nrhs}: outer {q['outer']} inner {q['inner_total']}")
+
+
+def test_batch_matches_single_solver_and_oracle(pkg, ora, ensemble):
+    ps, sol = ensemble
+    p, S = ps[0], sol[0]
+    say("batch vs single-grid mixed solve vs FP64 oracle")
+    Bt = pkg.Batch(max_slots=4)
+    s = Bt.add(S, torch.from_numpy(p.B).cuda(), tol=1e-10, inner_tol=1e-5)
+    X, q = Bt.solve()[s]
+    F = ora.ainv_setup(p, 0.1)
+    for r in range(4):
+        m = S.solve_mixed(torch.from_numpy(p.B[r]).cuda(), tol=1e-10, inner_tol=1e-5)
+        xo = ora.pcg(p, F, b=p.B[r], tol=1e-13).x
+        xb = X[r].cpu().numpy()
+        lam = np.linalg.eigvalsh(p.dense())
+        bound = lam[-1] / lam[0] * 2e-10
+        assert np.linalg.norm(xb - xo) <= bound * np.linalg.norm(xo)
+        assert np.linalg.norm(m.x.cpu().numpy() - xo) <= bound * np.linalg.norm(xo)
+
+
+def test_batch_alone_equals_in_mix(pkg, ensemble):
+    ps, sol = ensemble
+    say("alone vs in the mix (bitwise)")
+    alone = {}
+    for i in range(len(ps)):
+        Bt = pkg.Batch(max_slots=4)
+        s = Bt.add(sol[i], torch.from_numpy(ps[i].B).cuda())
+        alone[i] = Bt.solve()[s][0]
+    Bt = pkg.Batch(max_slots=8)
+    order = [2, 0, 3, 1]
+    slot_of = {}
+    for i in order[:2]:
+        slot_of[Bt.add(sol[i], torch.from_numpy(ps[i].B).cuda())] = i
+    Bt.run(2)                       # the first two are already iterating ...
+    for i in order[2:]:             # ... when the others arrive
+        slot_of[Bt.add(sol[i], torch.from_numpy(ps[i].B).cuda())] = i
+    res = Bt.solve()
+    for s, (X, q) in res.items():
+        assert torch.equal(X, alone[slot_of[s]]), slot_of[s]
+
+
+def test_batch_zero_rhs_and_limits(pkg, ora, ensemble):
+    ps, sol = ensemble
+    p, S = ps[2], sol[2]
+    say("zero right-hand side, outer limit")
+    Bt = pkg.Batch(max_slots=4)
+    Bz = np.stack([np.zeros(p.n), p.B[0]])
+    s = Bt.add(S, torch.from_numpy(Bz).cuda(), X0=torch.ones(2, p.n, dtype=torch.float64).cuda())
+    X, q = Bt.solve()[s]
+    assert q["status"] == 0
+    assert float(X[0].abs().max()) <= 1e-6
+    s2 = Bt.add(S, torch.from_numpy(p.B[:1]).cuda(), max_outer=1)
+    X2, q2 = Bt.solve()[s2]
+    assert q2["status"] == 1 and q2["outer"] == 1

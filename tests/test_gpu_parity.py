@@ -134,7 +134,7 @@ def test_pcg_natural_stop(pkg, ora, name):
     x = g.x.cpu().numpy()
     true = np.linalg.norm(p.b - ora.spmv(p, x)) / np.linalg.norm(p.b)
     assert true <= 1.05e-10
-    assert abs(true - g.true_relres) <= 1e-3 * true + 1e-15
+    assert abs(true - g.true_relres) <= 1e-3 * true + 1e-13
 
 
 @pytest.mark.parametrize("name", ["box64x48", "orca182x149", "orca37x23_ragged"])
@@ -148,7 +148,8 @@ def test_mixed_reaches_fp64_residual(pkg, ora, name):
     x = m.x.cpu().numpy()
     true = np.linalg.norm(p.b - ora.spmv(p, x)) / np.linalg.norm(p.b)
     assert true <= 1e-10
-    assert abs(true - m.true_relres) <= 1e-3 * true + 1e-15
+    # the same residual summed in two orders: equal to rounding level
+    assert abs(true - m.true_relres) <= 1e-3 * true + 1e-13
     xo = ora.pcg(p, ora.ainv_setup(p, tau), tol=1e-12).x
     err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
     say("  mixed outer", m.outer, "inner", m.inner_total, "rel err vs FP64 oracle", err)
