@@ -108,6 +108,38 @@ def bench_batch(P, torch, dev, log, members=64, nrhs=4):
             "speedup_vs_sequential": round(dts / dt, 2)}
 
 
+def bench_serve(P, torch, dev, log, count=40, rate=8.0):
+    """Poisson arrivals of time-step solves on a catalogue of resident grids
+    from 182x149 to 4322x3059; mixed precision to 1e-10, warm starts,
+    continuous batching."""
+    from gen import orca
+    from paper_1210_1878_amd import serve
+    shapes = [(182, 149), (182, 149), (362, 292), (362, 292), (721, 510), (721, 510),
+              (1442, 1021), (4322, 3059)]
+    t0 = time.perf_counter()
+    probs = [orca.orca_problem(nx, ny, orca.CONFIG_SEED_BASE + 40 + i) for i, (nx, ny) in enumerate(shapes)]
+    srv = serve.Server(probs, drop_tol=0.05, device=dev, chunk=16)
+    log(f"serving: {len(probs)} resident grids ({srv.resident_bytes / 2**30:.2f} GiB), "
+        f"setup {time.perf_counter() - t0:.1f}s")
+    # warm-up: one step per grid (graph capture, first-touch)
+    warm = [serve.Request(rid=-1 - g, grid=g, arrival=0.0) for g in range(len(probs))]
+    stepper = serve.TimeStepper(probs, dev, seed=CONFIG_SERVE_SEED)
+    srv.run(warm, make_rhs=stepper, on_done=stepper.done)
+    reqs = serve.poisson_arrivals(rate=rate, count=count, n_grids=len(probs), seed=CONFIG_SERVE_SEED)
+    done = srv.run(reqs, make_rhs=stepper, on_done=stepper.done)
+    st = serve.latency_stats(done)
+    log(f"served {st['requests']} requests: p50 {st['p50_ms']:.1f} ms, p99 {st['p99_ms']:.1f} ms, "
+        f"{st['solves_per_s']:.2f} solves/s, worst true relres {st['worst_true_relres']:.2e}")
+    st.update({"workload": "Poisson arrivals (seeded) of warm-started time steps (b_t = b_{t-1} + "
+                           "1% noise) on 8 resident ORCA-shaped grids 182x149 .. 4322x3059, mixed "
+                           "precision to 1e-10, continuous batching",
+               "arrival_rate_per_s": rate, "grids": [f"{a}x{b}" for a, b in shapes]})
+    return st
+
+
+CONFIG_SERVE_SEED = 1878 + 4
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +151,11 @@ def main():
     ap.add_argument("--max-blocks", type=int, default=2048)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched ensemble")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="profiling driver: a 256 MiB device copy (counter calibration), then the "
+                         "three FP64 and FP32 iteration kernels, --reps launches each")
+    ap.add_argument("--reps", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
@@ -148,6 +185,23 @@ def main():
         S.tune(chunk=args.chunk, use_graph=not args.no_graph, max_blocks=args.max_blocks)
     b = torch.from_numpy(p.b).to(dev)
     torch.cuda.synchronize()
+
+    if args.kernels_only:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        ms = S64.profile_iteration(b, reps=args.reps)
+        ms32 = Smx.profile_iteration(b, reps=args.reps)
+        kb = kernel_bytes(p.n, G.nnz_off, 8)
+        kb32 = kernel_bytes(p.n, G.nnz_off, 4)
+        for tag, t, byt in (("fp64", ms, kb), ("fp32", ms32, kb32)):
+            log(tag + " " + ", ".join(f"{k}={t[i] * 1e3:.2f} us ({byt[k] / (t[i] * 1e-3) / 1e9:.0f} GB/s)"
+                                      for i, k in enumerate(byt)))
+        print(json.dumps({"kernels_only": True, "fp64_ms": ms, "fp32_ms": ms32, "bytes_fp64": kb,
+                          "bytes_fp32": kb32, "n": p.n, "nnz_off": G.nnz_off}), flush=True)
+        return
 
     for _ in range(args.warmup):
         S64.solve(b, tol=TOL)
@@ -213,6 +267,7 @@ def main():
             "bytes_per_launch": kb[names[dom]], "ms_per_launch": ms[dom]}
 
     batched = None if args.no_batch else bench_batch(P, torch, dev, log)
+    served = None if args.no_serve else bench_serve(P, torch, dev, log)
 
     cpu = None
     if not args.no_cpu:
@@ -244,6 +299,7 @@ def main():
         "jacobi": {"iters": rj.iters, "ms_per_solve": round(dtj * 1e3, 3),
                    "true_relres": rj.true_relres},
         "batched": batched,
+        "served": served,
         "setup_s": round(setup_s, 3),
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -89,6 +89,16 @@ const char *pcga_last_error(void);
  */
 int pcga_ainv_setup(const pcga_a5_t *A, double drop_tol, pcga_ainv_t **out);
 
+/* pcga_fsai_band_setup: the paper's own preconditioner (Sec. 3, six-step
+ * scheme; Propositions 2-3): the factored approximate inverse of T, the part
+ * of A with |col - row| <= 1 in natural ordering (east-west couplings inside
+ * each grid row), with band q: column z_j keeps rows j-q .. j (entries with
+ * j > i + q are the negligible set) and is computed by T-orthogonalisation on
+ * that pattern; D = diag(p).  The result is used like an AINV factor
+ * (P = Z D^-1 Z^T).  q = 0 gives Jacobi.  Errors: EINVAL (A5 rules, q outside
+ * 0..4096), EBREAKDOWN (a pivot <= 0), ENOMEM. */
+int pcga_fsai_band_setup(const pcga_a5_t *A, int32_t q, pcga_ainv_t **out);
+
 /* Sizes of a setup result: n and the number of stored off-diagonal entries
  * of Z (the unit diagonal is implicit). */
 int pcga_ainv_info(const pcga_ainv_t *F, int64_t *n, int64_t *nnz_off);

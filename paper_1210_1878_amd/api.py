@@ -112,6 +112,15 @@ def ainv_setup(A: Stencil5, drop_tol: float) -> AInv:
     return AInv(h)
 
 
+def fsai_band_setup(A: Stencil5, q: int) -> AInv:
+    """The paper's banded factor of T (Sec. 3 scheme), band q."""
+    L = _lib.load()
+    h = ctypes.c_void_p()
+    a5 = A.c_struct()
+    check(L.pcga_fsai_band_setup(ctypes.byref(a5), int(q), ctypes.byref(h)), "pcga_fsai_band_setup")
+    return AInv(h)
+
+
 def _dev_ptr(t, dtype, n):
     import torch
     if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()

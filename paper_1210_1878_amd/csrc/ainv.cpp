@@ -183,4 +183,87 @@ int ainv_build(const A5View &A, double tau, AinvFactor &F, int64_t *bad_row) {
     return PCGA_OK;
 }
 
+// The paper's banded factor of T (Sec. 3, six-step pattern scheme).  T keeps
+// the entries of A with |col - row| <= 1 in natural ordering: the east-west
+// couplings inside each grid row (the periodic wrap lies outside the band).
+// Column z_j of the unit upper factor is restricted to rows j-q .. j (the
+// dropped set is {(i, j): j > i + q}) and computed by T-orthogonalisation on
+// that pattern: for i = j-q .. j-1 in increasing order,
+//   c = t_i^T z_j (columns i-1, i, i+1 of row i that lie in the band of z_j,
+//   ascending, absent/zero entries skipped), and if c != 0:
+//   z_j[r] <- z_j[r] - (c / p_i) z_i[r] for the rows r of z_i inside the band;
+// then p_j = t_j^T z_j.  Unfused FP64 in this order.
+int fsai_band_build(const A5View &A, int64_t q, AinvFactor &F, int64_t *bad_row) {
+    if (bad_row) *bad_row = -1;
+    int st = A.validate();
+    if (st) return st;
+    if (q < 0 || q > 4096) return PCGA_EINVAL;
+    const int64_t n = A.n(), nx = A.nx;
+    auto t_at = [&](int64_t row, int64_t col) -> double {   // entry of T
+        if (col == row) return A.diag[row];
+        if (col == row + 1) return (row % nx != nx - 1) ? A.ae[row] : 0.0;
+        if (col == row - 1) return (col % nx != nx - 1) ? A.ae[col] : 0.0;
+        return 0.0;
+    };
+    try {
+        // band storage: band[j*(q+1) + m] = z_j[j - q + m], m = 0..q (m = q is the unit diagonal)
+        std::vector<double> band((size_t)n * (q + 1), 0.0);
+        F.n = n;
+        F.D.assign(n, 0.0);
+        for (int64_t j = 0; j < n; j++) {
+            double *zj = &band[(size_t)j * (q + 1)];
+            zj[q] = 1.0;
+            const int64_t top = j - q;               // row held in zj[0]
+            const int64_t lo = top < 0 ? 0 : top;
+            for (int64_t i = lo; i < j; i++) {
+                double c = 0.0;
+                for (int64_t col = i - 1; col <= i + 1; col++) {
+                    if (col < 0 || col >= n || col < top || col > j) continue;
+                    const double z = zj[col - top];
+                    if (z == 0.0) continue;
+                    const double pr = t_at(i, col) * z;
+                    c = c + pr;
+                }
+                if (c == 0.0) continue;
+                const double mult = c / F.D[i];
+                const double *zi = &band[(size_t)i * (q + 1)];   // zi[m] = z_i[i - q + m]
+                for (int64_t r = (i - q > lo ? i - q : lo); r <= i; r++) {
+                    const double pr = mult * zi[r - (i - q)];
+                    zj[r - top] = zj[r - top] - pr;
+                }
+            }
+            double p = 0.0;
+            for (int64_t col = j - 1; col <= j + 1; col++) {
+                if (col < 0 || col >= n || col < top || col > j) continue;
+                const double z = zj[col - top];
+                if (z == 0.0) continue;
+                const double pr = t_at(j, col) * z;
+                p = p + pr;
+            }
+            if (!(p > 0.0)) {
+                if (bad_row) *bad_row = j;
+                return PCGA_EBREAKDOWN;
+            }
+            F.D[j] = p;
+        }
+        F.colptr.assign(1, 0);
+        F.rowidx.clear();
+        F.val.clear();
+        for (int64_t j = 0; j < n; j++) {
+            const double *zj = &band[(size_t)j * (q + 1)];
+            for (int64_t m = 0; m < q; m++) {
+                const int64_t r = j - q + m;
+                if (r >= 0 && zj[m] != 0.0) {
+                    F.rowidx.push_back((int32_t)r);
+                    F.val.push_back(zj[m]);
+                }
+            }
+            F.colptr.push_back((int64_t)F.rowidx.size());
+        }
+    } catch (const std::bad_alloc &) {
+        return PCGA_ENOMEM;
+    }
+    return PCGA_OK;
+}
+
 }  // namespace pcga

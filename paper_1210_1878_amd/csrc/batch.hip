@@ -34,9 +34,11 @@
 // Workgroups reach slots through a table of logical blocks.  A slot's block
 // count depends only on its grid, so each of its reductions is summed in the
 // same order whatever else is in the batch: a solve gives bitwise the same
-// result alone or in any mix.  The host places all blocks of a slot on one XCD
+// result alone or in any mix.  The host places all blocks of a small slot on
+// one XCD and splits a large one into eight contiguous ranges, one per XCD
 // (table index congruent to the XCD mod 8; the launch has a multiple of 8
-// workgroups and workgroup b serves table entries b, b + grid, ...).
+// workgroups and workgroup b serves table entries b, b + grid, ...).  Slice
+// ranges of a slot's workgroups are balanced by Z entries (host-computed).
 
 #include <hip/hip_runtime.h>
 
@@ -55,7 +57,7 @@ namespace pcga {
 
 constexpr int kMaxR = 4;
 constexpr int kBatchGrid = 2048;     // workgroups per batched launch (multiple of 8)
-constexpr int kSlotCells = 4096;     // cells per logical block of a slot (target)
+constexpr int kSpreadBlocks = 128;   // slots with at least this many blocks use all XCDs
 
 enum : int { kActSkip = 0, kActCG = 1, kActResid = 2, kActDecide = 3, kActFirst = 4 };
 
@@ -291,7 +293,8 @@ __device__ void zt_apply(const SlotDesc &D, int L, const float (&al)[R], const f
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     int s0, s1;
-    range_of(L, D.G, M.nslices, s0, s1);
+    s0 = M.bounds_b[L];
+    s1 = M.bounds_b[L + 1];
     const int nsw = (s1 - s0 - w + kWavesPerBlock - 1) / kWavesPerBlock;
     for (int i0 = 0; i0 < nsw; i0 += kWave) {
         const int cnt = nsw - i0 < kWave ? nsw - i0 : kWave;
@@ -491,7 +494,8 @@ __device__ void z_apply(const SlotDesc &D, int L, const float *r, double (&sr)[1
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     int s0, s1;
-    range_of(L, D.G, M.nslices, s0, s1);
+    s0 = M.bounds_b[L];
+    s1 = M.bounds_b[L + 1];
     const int nsw = (s1 - s0 - w + kWavesPerBlock - 1) / kWavesPerBlock;
     for (int i0 = 0; i0 < nsw; i0 += kWave) {
         const int cnt = nsw - i0 < kWave ? nsw - i0 : kWave;
@@ -703,10 +707,6 @@ ItemLayout item_layout(int64_t n, int R, int G) {
     return L;
 }
 
-int slot_blocks(int64_t n) {
-    const int64_t g = (n + kSlotCells - 1) / kSlotCells;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(g, kMaxBlocks));
-}
 
 }  // namespace
 
@@ -768,12 +768,23 @@ int rebuild_table(pcga_batch &B) {
     int load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     std::vector<std::vector<BlkEnt>> per(8);
     for (int s : order) {
+        const int G = B.desc[s].G;
+        if (G >= kSpreadBlocks) {
+            // large grid: eight contiguous block ranges, one per XCD
+            for (int x = 0; x < 8; x++) {
+                const int a = (int)((int64_t)G * x / 8), e = (int)((int64_t)G * (x + 1) / 8);
+                for (int L = a; L < e; L++) per[x].push_back({s, L});
+                load[x] += e - a;
+            }
+            B.xcd_of[s] = -1;
+            continue;
+        }
         int x = 0;
         for (int i = 1; i < 8; i++)
             if (load[i] < load[x]) x = i;
         B.xcd_of[s] = x;
-        for (int L = 0; L < B.desc[s].G; L++) per[x].push_back({s, L});
-        load[x] += B.desc[s].G;
+        for (int L = 0; L < G; L++) per[x].push_back({s, L});
+        load[x] += G;
     }
     int depth = 0;
     for (int x = 0; x < 8; x++) depth = std::max<int>(depth, (int)per[x].size());

@@ -23,7 +23,8 @@
 // while others write new ones.
 //
 // Work split: a launch of G workgroups gives each workgroup one contiguous
-// range of cells or sliced-ELL slices.  Workgroups are dispatched
+// range of cells, or of sliced-ELL slices balanced by their entry count (the
+// polar slices are much heavier than ocean-interior ones).  Workgroups are dispatched
 // round-robin over the 8 XCDs, so the hardware index is remapped to make the
 // ranges of one XCD contiguous: grid neighbours (rows above and below, rows a
 // Z column reaches) are then read from the same L2.
@@ -345,7 +346,8 @@ __global__ __launch_bounds__(kBS) void k_zt(DevSell<T> Zt, const T *__restrict__
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
     int s0, s1;
-    range_of(L, G, Zt.nslices, s0, s1);
+    s0 = Zt.bounds[L];
+    s1 = Zt.bounds[L + 1];
     double rr = 0.0;
     auto g = [&](int kk) { return FUSED ? fma(-at, q[kk], rcur[kk]) : rcur[kk]; };
     const int nsw = (s1 - s0 - w + kWavesPerBlock - 1) / kWavesPerBlock;   // this wave's slices
@@ -416,7 +418,8 @@ __global__ __launch_bounds__(kBS) void k_z(DevSell<T> Z, const T *__restrict__ t
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
     int s0, s1;
-    range_of(L, G, Z.nslices, s0, s1);
+    s0 = Z.bounds[L];
+    s1 = Z.bounds[L + 1];
     double sr = 0.0;
     auto g = [&](int jj) { return t[jj]; };
     const int nsw = (s1 - s0 - w + kWavesPerBlock - 1) / kWavesPerBlock;   // this wave's slices

@@ -15,6 +15,14 @@ constexpr int kCPT = 2;            // stencil cells per thread per step
 constexpr int kStep = kBS * kCPT;  // stencil cells per workgroup step
 constexpr int kHistRing = 4096;    // residual-history ring (entries)
 constexpr int kMaxBlocks = 2048;   // workgroups per kernel = partial sums per reduction
+constexpr int kSlotCells = 4096;   // cells per workgroup of a batch slot (target)
+
+// Workgroups of a batch slot: a function of the grid alone, so that a slot's
+// reductions do not depend on the rest of the batch.
+inline int slot_blocks(int64_t n) {
+    const int64_t g = (n + kSlotCells - 1) / kSlotCells;
+    return (int)(g < 1 ? 1 : (g > kMaxBlocks ? kMaxBlocks : g));
+}
 
 // Five-point operator in A5 form, device copy.  inv_nx = 1/nx (row index by
 // multiplication, corrected to the exact quotient).
@@ -32,6 +40,8 @@ struct DevSell {
     const int64_t *off;
     const int32_t *idx;
     const T *val;
+    const int32_t *bounds;   // slice range of workgroup L: [bounds[L], bounds[L+1])
+    const int32_t *bounds_b; // the same for the block count of a batch slot
     int32_t nslices, nrows;
 };
 

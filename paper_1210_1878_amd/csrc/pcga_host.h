@@ -31,6 +31,7 @@ struct AinvFactor {
 };
 
 int ainv_build(const A5View &A, double tau, AinvFactor &F, int64_t *bad_row);
+int fsai_band_build(const A5View &A, int64_t q, AinvFactor &F, int64_t *bad_row);
 
 // Sliced ELL with a per-slice number of lanes per row ("SELL-L").
 //   A slice is one 64-lane wavefront.  It covers `nrows = 64 >> lpr_log2`

@@ -163,6 +163,10 @@ size_t carve(pcga_solver &S, void *base, const HostLayouts &H) {
         S.x64[0] = C.take<double>(n);
         S.x64[1] = C.take<double>(n);
     }
+    S.bnd_zt = C.take<int32_t>(kMaxBlocks + 1);
+    S.bnd_z = C.take<int32_t>(kMaxBlocks + 1);
+    S.bnd_zt_b = C.take<int32_t>(kMaxBlocks + 1);
+    S.bnd_z_b = C.take<int32_t>(kMaxBlocks + 1);
     S.P.dq = C.take<double>(kMaxBlocks);
     S.P.rr = C.take<double>(kMaxBlocks);
     S.P.sr = C.take<double>(kMaxBlocks);
@@ -194,6 +198,46 @@ int check_a5(const pcga_a5_t *A) {
 }
 
 constexpr int kTargetWidth = 16;
+
+// Per-slice work estimate: its stored entries plus one row's worth of
+// own-row loads and stores.
+std::vector<int32_t> slice_costs(const SellLayout &L) {
+    std::vector<int32_t> c(L.nslices());
+    for (int64_t s = 0; s < L.nslices(); s++) c[s] = ((L.meta[s] >> 8) + 1) * 64;
+    return c;
+}
+
+// Contiguous slice ranges for G workgroups with equal estimated work.
+std::vector<int32_t> balanced_bounds(const std::vector<int32_t> &cost, int G) {
+    const int64_t ns = (int64_t)cost.size();
+    std::vector<int32_t> b(G + 1, 0);
+    int64_t total = 0;
+    for (int32_t c : cost) total += c;
+    int64_t acc = 0, s = 0;
+    for (int L = 1; L < G; L++) {
+        const int64_t target = (total * L) / G;
+        while (s < ns && acc + cost[s] / 2 < target) acc += cost[s++];
+        b[L] = (int32_t)s;
+    }
+    b[G] = (int32_t)ns;
+    for (int L = 1; L <= G; L++) b[L] = std::max(b[L], b[L - 1]);
+    return b;
+}
+
+int upload_bounds(pcga_solver &S) {
+    const std::vector<int32_t> bz = balanced_bounds(S.cost_zt, S.g_zt);
+    const std::vector<int32_t> b = balanced_bounds(S.cost_z, S.g_z);
+    const int gb = slot_blocks(S.n);
+    const std::vector<int32_t> bzb = balanced_bounds(S.cost_zt, gb);
+    const std::vector<int32_t> bb = balanced_bounds(S.cost_z, gb);
+    hipError_t e = hipMemcpyAsync(S.bnd_zt, bz.data(), bz.size() * 4, hipMemcpyHostToDevice, S.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(S.bnd_z, b.data(), b.size() * 4, hipMemcpyHostToDevice, S.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(S.bnd_zt_b, bzb.data(), bzb.size() * 4, hipMemcpyHostToDevice, S.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(S.bnd_z_b, bb.data(), bb.size() * 4, hipMemcpyHostToDevice, S.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(S.stream);
+    if (e != hipSuccess) return fail(PCGA_EHIP, std::string("bounds upload: ") + hipGetErrorString(e));
+    return PCGA_OK;
+}
 
 }  // namespace
 
@@ -232,6 +276,26 @@ int pcga_ainv_setup(const pcga_a5_t *A, double drop_tol, pcga_ainv_t **out) {
         if (st == PCGA_EBREAKDOWN)
             return fail(st, "AINV breakdown: pivot p_i <= 0 at row " + std::to_string(bad));
         return fail(st, "AINV setup failed");
+    }
+    *out = h;
+    return PCGA_OK;
+}
+
+int pcga_fsai_band_setup(const pcga_a5_t *A, int32_t q, pcga_ainv_t **out) {
+    if (!out) return fail(PCGA_EINVAL, "out is NULL");
+    *out = nullptr;
+    int st = check_a5(A);
+    if (st) return st;
+    if (q < 0 || q > 4096) return fail(PCGA_EINVAL, "band q must be 0..4096");
+    pcga_ainv *h = new (std::nothrow) pcga_ainv;
+    if (!h) return fail(PCGA_ENOMEM, "host allocation failed");
+    int64_t bad = -1;
+    st = fsai_band_build(view_of(A), q, h->F, &bad);
+    if (st) {
+        delete h;
+        if (st == PCGA_EBREAKDOWN)
+            return fail(st, "banded factor breakdown: pivot <= 0 at row " + std::to_string(bad));
+        return fail(st, "banded factor setup failed");
     }
     *out = h;
     return PCGA_OK;
@@ -426,7 +490,18 @@ int pcga_solver_create(const pcga_a5_t *A, const pcga_ainv_t *F, int precision, 
     CR(hipMemsetAsync(S->cb, 0, sizeof(CtlBlock), sm));
     CR(hipStreamSynchronize(sm));
 #undef CR
+    S->cost_zt = slice_costs(H.zt);
+    S->cost_z = slice_costs(H.z);
+    S->zt64.bounds = S->zt32.bounds = S->bnd_zt;
+    S->z64.bounds = S->z32.bounds = S->bnd_z;
+    S->zt64.bounds_b = S->zt32.bounds_b = S->bnd_zt_b;
+    S->z64.bounds_b = S->z32.bounds_b = S->bnd_z_b;
     S->grids();
+    st = upload_bounds(*S);
+    if (st) {
+        pcga_solver_destroy(S);
+        return st;
+    }
     // modelled compulsory bytes per iteration (see kernels.h):
     //   stencil: s, d_old, diag, ae, an read; d_new, q written       7 n words
     //   zt: r, q, d, x, dinv read; r', x, t written; Z^T entries     8 n words + E_zt
@@ -475,7 +550,7 @@ int pcga_solver_tune(pcga_solver_t *S, int32_t chunk, int32_t use_graph, int32_t
     S->use_graph = use_graph != 0;
     S->max_blocks = max_blocks;
     S->grids();
-    return PCGA_OK;
+    return upload_bounds(*S);
 }
 
 }  // extern "C"

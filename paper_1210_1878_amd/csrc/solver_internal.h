@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "pcga_dev.h"
 #include "pcgainv.h"
@@ -47,6 +48,9 @@ struct pcga_solver {
     hipGraphExec_t graph = nullptr;
     int graph_chunk = 0;
     int64_t sell_entries = 0;
+    std::vector<int32_t> cost_zt, cost_z;    // per-slice work estimates (host)
+    int32_t *bnd_zt = nullptr, *bnd_z = nullptr;   // device: workgroup slice ranges
+    int32_t *bnd_zt_b = nullptr, *bnd_z_b = nullptr;   // device: ranges for a batch slot
     double bytes_per_iter = 0.0;
 
     void grids() {

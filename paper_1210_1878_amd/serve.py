@@ -59,6 +59,7 @@ class Server:
             self.resident_bytes += S.workspace_bytes
         self.item_bytes = [Batch.item_bytes(S, 1) for S in self.solvers]
         self.budget = hbm_budget            # bytes for in-flight request vectors (None: no limit)
+        self.max_slots = max_slots
         self.batch = Batch(max_slots=max_slots, device=self.device, chunk=chunk)
         self.in_flight_bytes = 0
         self.busy = [False] * len(self.solvers)
@@ -124,7 +125,7 @@ class Server:
         return done
 
     def batch_capacity(self):
-        return 64
+        return self.max_slots
 
 
 def poisson_arrivals(rate, count, n_grids, seed):
@@ -148,14 +149,15 @@ class TimeStepper:
         self.b = [torch.from_numpy(p.b.copy()).to(device) for p in problems]
         self.ocean = [torch.from_numpy(p.ocean.astype(np.float64)).to(device) for p in problems]
         self.x = [torch.zeros(p.n, dtype=torch.float64, device=device) for p in problems]
-        self.gen = torch.Generator(device="cpu").manual_seed(seed)
+        self.gen = torch.Generator(device=device).manual_seed(seed)
         self.steps = [0] * len(problems)
 
     def __call__(self, req):
         g = req.grid
         if self.steps[g] > 0:
             b = self.b[g]
-            xi = self.torch.randn(b.shape[0], generator=self.gen, dtype=self.torch.float64).to(self.device)
+            xi = self.torch.randn(b.shape[0], generator=self.gen, dtype=self.torch.float64,
+                                  device=self.device)
             rms = self.torch.sqrt((b * b).sum() / self.ocean[g].sum())
             self.b[g] = b + 0.01 * rms * xi * self.ocean[g]
         self.steps[g] += 1

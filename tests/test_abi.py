@@ -133,3 +133,19 @@ def test_workspace_bytes_query():
     assert sizes[_lib.MIXED] < sizes[_lib.FP64] * 1.1
     nb = ctypes.c_size_t()
     assert L.pcga_workspace_bytes(ctypes.byref(a5), G.handle, 7, ctypes.byref(nb)) == _lib.EINVAL
+
+
+@pytest.mark.parametrize("q", [0, 1, 2, 4, 8])
+def test_fsai_band_bitwise_equal_to_oracle(ora, q):
+    """The paper's banded factor of T: library setup equals the oracle's."""
+    from paper_1210_1878_amd.api import fsai_band_setup
+    for p in (orca.orca_problem(37, 23, 5), orca.box_problem(20, 9, seed=2)):
+        F, _ = ora.fsai_band(p, q)
+        G = fsai_band_setup(Stencil5.from_problem(p), q)
+        colptr, rowidx, val, D = G.export()
+        assert np.array_equal(colptr, F.colptr)
+        assert np.array_equal(rowidx.astype(np.int64), F.rowidx)
+        assert np.array_equal(val.view(np.uint64), F.val.view(np.uint64))
+        assert np.array_equal(D.view(np.uint64), F.D.view(np.uint64))
+    with pytest.raises(_lib.PcgaError):
+        fsai_band_setup(Stencil5.from_problem(orca.box_problem(5, 4)), -1)

@@ -272,3 +272,26 @@ def test_full_size_mixed(pkg, ora, orca025):
     x = m.x.cpu().numpy()
     true = np.linalg.norm(p.b - ora.spmv(p, x)) / np.linalg.norm(p.b)
     assert true <= 1e-10
+
+
+@pytest.mark.parametrize("q", [1, 4])
+def test_pcg_paper_band_preconditioner(pkg, ora, q):
+    """Algorithm 1 with the paper's own banded factor of T (Sec. 3 scheme):
+    device and oracle iterates match; AINV needs fewer iterations than the
+    banded factor of T, which needs no more than Jacobi (Table 2's ordering)."""
+    p, _ = case("orca182x149")
+    say("band preconditioner q =", q)
+    A = pkg.Stencil5.from_problem(p)
+    G = pkg.fsai_band_setup(A, q)
+    F, _ = ora.fsai_band(p, q)
+    K = ora.pcg(p, F, tol=1e-10).iters
+    S = pkg.Solver(A, G, "fp64")
+    g = S.solve(dev(p.b), tol=0.0, maxit=K)
+    o = ora.pcg(p, F, tol=0.0, maxit=K)
+    assert np.linalg.norm(g.x.cpu().numpy() - o.x) <= 1e-9 * np.linalg.norm(o.x)
+    nat = S.solve(dev(p.b), tol=1e-10)
+    assert nat.status == 0 and abs(nat.iters - K) <= 2
+    kj = ora.pcg(p, ora.ainv_setup(p, np.inf), tol=1e-10).iters
+    ka = ora.pcg(p, ora.ainv_setup(p, 0.1), tol=1e-10).iters
+    say(f"  iterations: jacobi {kj}, band q={q} {K}, ainv {ka}")
+    assert K <= kj and ka < K

@@ -1,0 +1,82 @@
+"""Continuous-batching server (needs an MI355X): every served time step meets
+the FP64 target, equals the same solve run alone, and admission respects the
+device-memory budget."""
+import sys
+
+import numpy as np
+import pytest
+
+from gen import orca
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-serve]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no ROCm device")
+    import paper_1210_1878_amd as P
+    from paper_1210_1878_amd import serve
+    probs = [orca.orca_problem(nx, ny, 100 + i) for i, (nx, ny) in
+             enumerate([(60, 45), (91, 62), (37, 23)])]
+    return P, serve, probs
+
+
+def test_served_steps_correct_and_equal_alone(setup, ora):
+    P, serve, probs = setup
+    say("serving 12 time steps on 3 grids")
+    srv = serve.Server(probs, drop_tol=0.1, device="cuda", chunk=8)
+    reqs = serve.poisson_arrivals(rate=400.0, count=12, n_grids=len(probs), seed=7)
+    stepper = serve.TimeStepper(probs, torch.device("cuda"), seed=3)
+    done = srv.run(reqs, make_rhs=stepper, on_done=stepper.done)
+    assert len(done) == 12
+    overlapped = 0
+    for r in done:
+        p = probs[r.grid]
+        b = r.b.cpu().numpy()
+        x = r.x.cpu().numpy()
+        true = np.linalg.norm(b - ora.spmv(p, x)) / np.linalg.norm(b)
+        assert r.status == 0 and true <= 1e-10
+        # the same solve alone in a fresh batch gives bitwise the same x
+        Bt = P.Batch(max_slots=2, chunk=8)
+        s = Bt.add(srv.solvers[r.grid], r.b.unsqueeze(0), X0=r.x0.unsqueeze(0), tol=1e-10,
+                   inner_tol=1e-5, max_outer=30)
+        X, q = Bt.solve()[s]
+        assert torch.equal(X[0], r.x)
+        overlapped += any(o is not r and o.admitted < r.finished and o.finished > r.admitted
+                          for o in done)
+    stats = serve.latency_stats(done)
+    say("  stats", stats, "overlapping requests", overlapped)
+    assert overlapped > 0         # requests did share the device
+    # warm starts: later steps of a grid need fewer inner iterations than its first
+    firsts = {}
+    for r in sorted(done, key=lambda r: r.arrival):
+        firsts.setdefault(r.grid, r)
+    later = [r for r in done if firsts[r.grid] is not r]
+    assert later and np.mean([r.inner for r in later]) < np.mean([r.inner for r in firsts.values()])
+
+
+def test_admission_by_footprint(setup):
+    P, serve, probs = setup
+    say("admission under a tight memory budget")
+    srv = serve.Server(probs, drop_tol=0.1, device="cuda", chunk=8)
+    srv.budget = max(srv.item_bytes)      # room for one request at a time
+    reqs = serve.poisson_arrivals(rate=1000.0, count=6, n_grids=len(probs), seed=9)
+    stepper = serve.TimeStepper(probs, torch.device("cuda"), seed=4)
+    peak = [0]
+    orig_admit = srv.admit
+
+    def admit(req, now):
+        s = orig_admit(req, now)
+        peak[0] = max(peak[0], srv.in_flight_bytes)
+        return s
+    srv.admit = admit
+    done = srv.run(reqs, make_rhs=stepper, on_done=stepper.done)
+    assert len(done) == 6 and all(r.status == 0 for r in done)
+    assert peak[0] <= srv.budget
