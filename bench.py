@@ -31,6 +31,11 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+# kernel names as rocprofv3 reports them (FP64 iteration kernels)
+KERNEL_NAMES = {"stencil": "k_stencil<double>", "axpy_zt": "k_zt<double, true>",
+                "z_dot": "k_z<double, true, false>"}
+
+
 def kernel_bytes(n, nnz_off, word):
     """Algorithmic bytes per launch of the three iteration kernels (each array
     once; Z entries = value + 4-byte index).  word = 8 (FP64) or 4 (FP32)."""
@@ -39,6 +44,39 @@ def kernel_bytes(n, nnz_off, word):
         "axpy_zt": 8 * word * n + (word + 4) * nnz_off,  # r, q, d, x, D^-1 in; r', x, t out; Z^T
         "z_dot": 3 * word * n + (word + 4) * nnz_off,    # t, r' in; s out; Z
     }
+
+
+COUNTER_FILE = os.path.join(ROOT, "profiles", "pcg_iteration_kernels_1442x1021_hbm_traffic.json")
+KERNEL_SOURCES = ["paper_1210_1878_amd/csrc/kernels.h", "paper_1210_1878_amd/csrc/pcga_dev.h",
+                  "paper_1210_1878_amd/csrc/solver.hip"]
+
+
+def kernel_source_hash():
+    """SHA-256 over the sources that define the iteration kernels and their launch."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by its reading on a plain
+    device copy), or None when there is none or the kernel sources changed
+    since the counters were taken."""
+    try:
+        with open(COUNTER_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None, "no counter summary"
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None, "kernel sources changed since the counters were taken"
+    k = rec.get("kernels", {}).get(kernel)
+    if k is None:
+        return None, "kernel not in the counter summary"
+    return k["hbm_bytes_per_launch"], rec.get("profile", "")
 
 
 def cpu_baseline(p, seconds=15.0):
@@ -148,7 +186,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--chunk", type=int, default=32)
-    ap.add_argument("--max-blocks", type=int, default=2048)
+    ap.add_argument("--max-blocks", type=int, default=1280)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched ensemble")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
@@ -261,9 +299,12 @@ def main():
     b_iter = sum(kb.values())
     b_iter32 = sum(kb32.values())
     it_time = sum(ms) * 1e-3
-    roof = {"bound": "hbm", "kernel": f"k_{names[dom]}<double>",
+    kname = KERNEL_NAMES[names[dom]]
+    traffic, tnote = measured_traffic(kname)
+    roof = {"bound": "hbm", "kernel": kname,
             "achieved": round(gbs[names[dom]], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(gbs[names[dom]] / PEAK_HBM_GBS, 4), "traffic": None,
+            "frac": round(gbs[names[dom]] / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "traffic_source": tnote,
             "bytes_per_launch": kb[names[dom]], "ms_per_launch": ms[dom]}
 
     batched = None if args.no_batch else bench_batch(P, torch, dev, log)

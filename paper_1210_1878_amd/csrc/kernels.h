@@ -29,10 +29,14 @@
 // ranges of one XCD contiguous: grid neighbours (rows above and below, rows a
 // Z column reaches) are then read from the same L2.
 //
-// Memory-level parallelism: the stencil issues every load of its 2 cells per
-// thread before any arithmetic (branch-free neighbour indices); the sliced-ELL
-// kernels load 8 index/value pairs, then their 8 gathers, per step, and fetch
-// the headers of all of a wavefront's slices with one load.
+// Memory-level parallelism: every kernel issues its first loads before it
+// reduces the previous launch's partial sums, so that round trip overlaps
+// them.  The stencil issues every load of a step before any arithmetic
+// (branch-free neighbour indices).  The sliced-ELL kernels are software
+// pipelined: while one unit of a slice is gathered and accumulated, the
+// index/value loads of the next unit (and the next slice's own-row operands)
+// are in flight; the headers of all of a wavefront's slices come with one
+// load.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -51,10 +55,40 @@ __device__ __forceinline__ int logical_block(int b, int G) {
 __device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v < INFINITY; }
 __device__ __forceinline__ bool is_bad(double v) { return !(v == v) || v == INFINITY || v == -INFINITY; }
 
+#ifndef PCGA_DPP_SUM
+#define PCGA_DPP_SUM 1
+#endif
+
+// v from another lane by a DPP pattern (both 32-bit halves); lanes whose row
+// is masked off, or whose source lies outside the row, read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes of a wavefront, the same value returned to every lane.
+// Fixed order: scans within rows of 16 lanes (row_shr 1, 2, 4, 8), then rows
+// combined by row broadcasts; lane 63 ends with the total.
 __device__ __forceinline__ double wave_sum(double v) {
+#if PCGA_DPP_SUM
+    v += dpp_d<0x111, 0xf>(v);   // row_shr:1
+    v += dpp_d<0x112, 0xf>(v);   // row_shr:2
+    v += dpp_d<0x114, 0xf>(v);   // row_shr:4
+    v += dpp_d<0x118, 0xf>(v);   // row_shr:8
+    v += dpp_d<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_d<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+#else
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
     return v;
+#endif
 }
 
 // Sum NV values over the workgroup in a fixed order; result in every thread.
@@ -82,28 +116,45 @@ __device__ __forceinline__ void block_sum_all(double (&v)[NV]) {
 }
 
 // Total of G per-workgroup partials (stride kMaxBlocks between the NV
-// quantities), identical in every workgroup and thread.
-// All loads are issued before any is consumed (fixed trip count, predicated),
-// so the whole read costs one memory round trip.
+// quantities), identical in every workgroup and thread.  Split in two so that
+// a kernel can issue its own first loads between them: load_partials issues
+// every load (fixed trip count, predicated), reduce_partials consumes them,
+// so the read costs one memory round trip, overlapped with the caller's.
 template <int NV>
-__device__ __forceinline__ void sum_partials(const double *part, int G, double (&out)[NV]) {
-    constexpr int R = kMaxBlocks / kBS;
+struct PartialsLoad {
+    static constexpr int R = kMaxBlocks / kBS;
     double v[NV][R];
+};
+
+template <int NV>
+__device__ __forceinline__ PartialsLoad<NV> load_partials(const double *part, int G) {
+    PartialsLoad<NV> pl;
 #pragma unroll
-    for (int i = 0; i < R; i++) {
+    for (int i = 0; i < PartialsLoad<NV>::R; i++) {
         const int b = threadIdx.x + i * kBS;
         const int bb = b < G ? b : 0;
 #pragma unroll
-        for (int q = 0; q < NV; q++) v[q][i] = part[q * kMaxBlocks + bb];
+        for (int q = 0; q < NV; q++) pl.v[q][i] = part[q * kMaxBlocks + bb];
     }
+    return pl;
+}
+
+template <int NV>
+__device__ __forceinline__ void reduce_partials(const PartialsLoad<NV> &pl, int G, double (&out)[NV]) {
 #pragma unroll
     for (int q = 0; q < NV; q++) {
         out[q] = 0.0;
 #pragma unroll
-        for (int i = 0; i < R; i++)
-            if (threadIdx.x + i * kBS < G) out[q] += v[q][i];
+        for (int i = 0; i < PartialsLoad<NV>::R; i++)
+            if (threadIdx.x + i * kBS < G) out[q] += pl.v[q][i];
     }
     block_sum_all<NV>(out);
+}
+
+template <int NV>
+__device__ __forceinline__ void sum_partials(const double *part, int G, double (&out)[NV]) {
+    const PartialsLoad<NV> pl = load_partials<NV>(part, G);
+    reduce_partials<NV>(pl, G, out);
 }
 
 // Publish this workgroup's NV partial sums.
@@ -202,9 +253,8 @@ __device__ __forceinline__ SliceMeta header_of(const SliceHeaders &h, int i) {
     return m;
 }
 
-// This lane's sum over its entries of one slice, acc = sum_c val[c] * g(idx[c])
-// in increasing c.  Batches of U: U index/value loads (streamed once, not kept
-// in cache), then U gathers, then U fused multiply-adds.
+// Index/value streams of Z are read once per launch: non-temporal loads keep
+// them from evicting the gathered vectors.
 #ifndef PCGA_SELL_NT
 #define PCGA_SELL_NT 1
 #endif
@@ -217,40 +267,118 @@ __device__ __forceinline__ P stream_load(const P *p) {
 #endif
 }
 
-template <typename T, int U, typename Gth>
-__device__ __forceinline__ T lane_sum(const DevSell<T> &M, const SliceMeta &m, int lane,
-                                      const Gth &g) {
+// Index/value loads of one unit (U consecutive entry steps of a slice, from
+// step cc); past the slice width the last entry is re-read and ignored.
+template <typename T, int U>
+__device__ __forceinline__ void load_unit(const DevSell<T> &M, const SliceMeta &m, int cc, int lane,
+                                          int (&kk)[U], T (&zv)[U]) {
+    const int last = m.width - 1;
     const int32_t *ip = M.idx + m.off + lane;
     const T *vp = M.val + m.off + lane;
-    T acc = T(0);
-    const int last = m.width - 1;
-    for (int cc = 0; cc < m.width; cc += U) {
-        // Past the slice width the last entry is re-read (an L1 hit) and its
-        // value replaced by zero: no branches, so every load of the batch is
-        // in flight at once.
-        int kk[U];
-        T zv[U];
+    if (last >= 0) {
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int c = cc + u <= last ? cc + u : last;
             kk[u] = stream_load(ip + (int64_t)c * kWave);
             zv[u] = stream_load(vp + (int64_t)c * kWave);
         }
-        T gv[U];
+    } else {
 #pragma unroll
-        for (int u = 0; u < U; u++) gv[u] = g(kk[u]);
-#pragma unroll
-        for (int u = 0; u < U; u++) acc = fma(cc + u <= last ? zv[u] : T(0), gv[u], acc);
+        for (int u = 0; u < U; u++) {
+            kk[u] = m.row0;
+            zv[u] = T(0);
+        }
     }
-    return acc;
 }
 
-// Gather unroll per precision (register budget: all workgroups resident).
-#ifndef PCGA_SELL_U
-#define PCGA_SELL_U 8
+// Software-pipelined pass over a wavefront's slices.  Work is a stream of
+// units; while the gathers and multiply-adds of unit u run, the index/value
+// loads of unit u+1 (and, at a slice boundary, the next slice's own-row
+// operands via ownf) are already in flight.  pre() runs once, after the
+// first unit's loads are issued and before any gather (the kernels reduce
+// the previous launch's partial sums there); it is called by every wave,
+// also one without slices, and the pass ends early when it returns false.
+// epi(m, acc, own) finishes a slice (called by all lanes; acc is this lane's
+// partial row sum, entries in increasing order).
+template <typename T, int U, typename Gth, typename OwnF, typename EpiF, typename PreF>
+__device__ __forceinline__ bool sell_stream(const DevSell<T> &M, int first, int nsw, int lane,
+                                            const Gth &g, const OwnF &ownf, const EpiF &epi,
+                                            const PreF &pre) {
+    using Own = decltype(ownf(SliceMeta{}));
+    SliceHeaders hd{0, 0, 0, 0};
+    SliceMeta m{0, 0, 0, 0};
+    int kk[U];
+    T zv[U];
+    Own own{};
+    int cnt = nsw < kWave ? nsw : kWave;
+    auto start_batch = [&](int i0) {
+        hd = load_headers(M, first + i0 * kWavesPerBlock, kWavesPerBlock, cnt, lane);
+        m = header_of(hd, 0);
+        load_unit<T, U>(M, m, 0, lane, kk, zv);
+        own = ownf(m);
+    };
+    if (nsw > 0) start_batch(0);
+    __builtin_amdgcn_sched_barrier(0);   // the loads above stay ahead of pre()
+    if (!pre()) return false;
+    for (int i0 = 0; i0 < nsw;) {
+        int i = 0, cc = 0;
+        T acc = T(0);
+        for (;;) {
+            int ni = i, ncc = cc + U;
+            SliceMeta nm = m;
+            const bool slice_end = ncc >= m.width;
+            if (slice_end) {
+                ni = i + 1;
+                ncc = 0;
+                if (ni < cnt) nm = header_of(hd, ni);
+            }
+            const bool more = ni < cnt;
+            int kk2[U];
+            T zv2[U];
+            Own own2 = own;
+            if (more) {
+                load_unit<T, U>(M, nm, ncc, lane, kk2, zv2);
+                if (slice_end) own2 = ownf(nm);
+            }
+            T gv[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) gv[u] = g(kk[u]);
+#pragma unroll
+            for (int u = 0; u < U; u++) acc = fma(cc + u < m.width ? zv[u] : T(0), gv[u], acc);
+            if (slice_end) {
+                epi(m, acc, own);
+                acc = T(0);
+            }
+            if (!more) break;
+            i = ni;
+            cc = ncc;
+            m = nm;
+            own = own2;
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                kk[u] = kk2[u];
+                zv[u] = zv2[u];
+            }
+        }
+        i0 += kWave;
+        if (i0 < nsw) {
+            cnt = nsw - i0 < kWave ? nsw - i0 : kWave;
+            start_batch(i0);
+        }
+    }
+    return true;
+}
+
+// Entry steps per unit: 2 (FP64) and 4 (FP32) keep the fused kernels at 7-8
+// wavefronts per SIMD; wider units measured slower (fewer waves in flight).
+#ifndef PCGA_PIPE_UD
+#define PCGA_PIPE_UD 2
+#endif
+#ifndef PCGA_PIPE_UF
+#define PCGA_PIPE_UF 4
 #endif
 template <typename T>
-struct SellUnroll { static constexpr int U = PCGA_SELL_U; };
+struct PipeUnroll { static constexpr int U = sizeof(T) == 8 ? PCGA_PIPE_UD : PCGA_PIPE_UF; };
 
 // ---------------------------------------------------------------------------
 // k_stencil: rho_k, beta; d_new = s + beta d_old; q = A d_new; (d_new,q) partials
@@ -264,8 +392,36 @@ __global__ __launch_bounds__(kBS) void k_stencil(DevOp<T> A, const T *__restrict
     Ctl *c = &cb->c;
     if (c->done) return;
     const int G = gridDim.x, L = logical_block(blockIdx.x, G);
+    // Operands of kCPT cells per thread per step: every load of a step is issued
+    // before any arithmetic (branch-free neighbour indices, clamped cells).
+    struct Step {
+        T sv[kCPT][5], dv[kCPT][5];
+        Nbr<T> m[kCPT];
+        int kc[kCPT];
+    };
+    int c0, c1;
+    range_of(L, G, A.n, c0, c1);
+    auto load_step = [&](int base, Step &st) {
+#pragma unroll
+        for (int u = 0; u < kCPT; u++) {
+            st.kc[u] = base + u * kBS;
+            const int kk = st.kc[u] < c1 ? st.kc[u] : (c1 > 0 ? c1 - 1 : 0);
+            st.m[u] = neighbours(A, kk);
+            const int idx[5] = {st.m[u].kS, st.m[u].kW, kk, st.m[u].kE, st.m[u].kN};
+#pragma unroll
+            for (int e = 0; e < 5; e++) {
+                st.sv[u][e] = s[idx[e]];
+                st.dv[u][e] = dold[idx[e]];
+            }
+        }
+    };
+    const PartialsLoad<1> pl = load_partials<1>(P.sr, g_sr);
+    int base = c0 + threadIdx.x;
+    Step st;
+    load_step(base, st);   // in flight during the reduction (clamped, also for an empty range)
+    __builtin_amdgcn_sched_barrier(0);   // keep every load above the partials' first use
     double rs[1];
-    sum_partials<1>(P.sr, g_sr, rs);
+    reduce_partials<1>(pl, g_sr, rs);
     const double rho = rs[0];
     const int k = c->kk[par];
     if (!finite_pos(rho)) {
@@ -279,36 +435,21 @@ __global__ __launch_bounds__(kBS) void k_stencil(DevOp<T> A, const T *__restrict
     if (blockIdx.x == 0 && threadIdx.x == 0) c->rho[par] = rho;
     const T bt = (T)beta;
     double acc = 0.0;
-    int c0, c1;
-    range_of(L, G, A.n, c0, c1);
-    for (int base = c0 + threadIdx.x; base < c1 + (int)threadIdx.x; base += kStep) {
-        T sv[kCPT][5], dv[kCPT][5];
-        Nbr<T> m[kCPT];
-        int kc[kCPT];
+    while (base < c1 + (int)threadIdx.x) {
 #pragma unroll
         for (int u = 0; u < kCPT; u++) {
-            kc[u] = base + u * kBS;
-            const int kk = kc[u] < c1 ? kc[u] : c1 - 1;
-            m[u] = neighbours(A, kk);
-            const int idx[5] = {m[u].kS, m[u].kW, kk, m[u].kE, m[u].kN};
-#pragma unroll
-            for (int e = 0; e < 5; e++) {
-                sv[u][e] = s[idx[e]];
-                dv[u][e] = dold[idx[e]];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kCPT; u++) {
-            if (kc[u] < c1) {
+            if (st.kc[u] < c1) {
                 T v[5];
 #pragma unroll
-                for (int e = 0; e < 5; e++) v[e] = fma(bt, dv[u][e], sv[u][e]);
-                const T y = apply_row(m[u], v[0], v[1], v[2], v[3], v[4]);
-                dnew[kc[u]] = v[2];
-                q[kc[u]] = y;
+                for (int e = 0; e < 5; e++) v[e] = fma(bt, st.dv[u][e], st.sv[u][e]);
+                const T y = apply_row(st.m[u], v[0], v[1], v[2], v[3], v[4]);
+                dnew[st.kc[u]] = v[2];
+                q[st.kc[u]] = y;
                 acc += (double)v[2] * (double)y;
             }
         }
+        base += kStep;
+        if (base < c1 + (int)threadIdx.x) load_step(base, st);
     }
     double pv[1] = {acc};
     put_partials<1>(pv, P.dq, L);
@@ -326,56 +467,61 @@ __global__ __launch_bounds__(kBS) void k_zt(DevSell<T> Zt, const T *__restrict__
                                             T *__restrict__ x, T *__restrict__ t, CtlBlock *cb,
                                             Partials P, int g_dq, int par) {
     Ctl *c = &cb->c;
+    if (FUSED && c->done) return;
+    const PartialsLoad<1> pl = load_partials<1>(P.dq, FUSED ? g_dq : 0);
+    const int G = gridDim.x, L = logical_block(blockIdx.x, G);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
+    const int s0 = Zt.bounds[L], s1 = Zt.bounds[L + 1];
+    double rr = 0.0;
     T at = T(0);
-    if (FUSED) {
-        if (c->done) return;
+    auto g = [&](int kk) { return FUSED ? fma(-at, q[kk], rcur[kk]) : rcur[kk]; };
+    // own-row operands of a slice, raw (alpha is not known when the first is loaded)
+    struct OwnZt {
+        T rj, qj, dj, xj, ij;
+    };
+    auto ownf = [&](const SliceMeta &m) {
+        const int row = m.row0 + (lane >> m.lg);
+        const int rw = row < Zt.nrows ? row : Zt.nrows - 1;
+        OwnZt o;
+        o.rj = rcur[rw];
+        o.qj = FUSED ? q[rw] : T(0);
+        o.dj = FUSED ? dcur[rw] : T(0);
+        o.xj = FUSED ? x[rw] : T(0);
+        o.ij = dinv[rw];
+        return o;
+    };
+    auto epi = [&](const SliceMeta &m, T acc, const OwnZt &o) {
+        for (int sh = (1 << m.lg) >> 1; sh > 0; sh >>= 1) acc += __shfl_xor(acc, sh, kWave);
+        const int row = m.row0 + (lane >> m.lg);
+        if ((lane & ((1 << m.lg) - 1)) == 0 && row < Zt.nrows) {
+            const T rj = FUSED ? fma(-at, o.qj, o.rj) : o.rj;
+            if (FUSED) {
+                rnext[row] = rj;
+                x[row] = fma(at, o.dj, o.xj);
+                rr += (double)rj * (double)rj;
+            }
+            t[row] = (acc + rj) * o.ij;
+        }
+    };
+    auto pre = [&]() {
+        if (!FUSED) return true;
         double dq[1];
-        sum_partials<1>(P.dq, g_dq, dq);
+        reduce_partials<1>(pl, g_dq, dq);
         if (!finite_pos(dq[0])) {
             if (blockIdx.x == 0 && threadIdx.x == 0) {
                 c->status = is_bad(dq[0]) ? kStNan : kStBreak;
                 c->done = 1;
             }
-            return;
+            return false;
         }
         const double alpha = c->rho[par] / dq[0];
         if (blockIdx.x == 0 && threadIdx.x == 0) c->alpha = alpha;
         at = (T)alpha;
-    }
-    const int G = gridDim.x, L = logical_block(blockIdx.x, G);
-    const int lane = threadIdx.x & (kWave - 1);
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
-    int s0, s1;
-    s0 = Zt.bounds[L];
-    s1 = Zt.bounds[L + 1];
-    double rr = 0.0;
-    auto g = [&](int kk) { return FUSED ? fma(-at, q[kk], rcur[kk]) : rcur[kk]; };
+        return true;
+    };
     const int nsw = (s1 - s0 - w + kWavesPerBlock - 1) / kWavesPerBlock;   // this wave's slices
-    for (int i0 = 0; i0 < nsw; i0 += kWave) {
-      const int cnt = nsw - i0 < kWave ? nsw - i0 : kWave;
-      const SliceHeaders hd = load_headers(Zt, s0 + w + i0 * kWavesPerBlock, kWavesPerBlock, cnt, lane);
-      for (int i = 0; i < cnt; i++) {
-        const SliceMeta m = header_of(hd, i);
-        // own-row operands first, so their latency overlaps the slice's loads
-        const int row = m.row0 + (lane >> m.lg);
-        const bool lead = (lane & ((1 << m.lg) - 1)) == 0 && row < Zt.nrows;
-        const int rw = row < Zt.nrows ? row : Zt.nrows - 1;
-        const T rj = g(rw);
-        const T dj = FUSED ? dcur[rw] : T(0);
-        const T xj = FUSED ? x[rw] : T(0);
-        const T ij = dinv[rw];
-        T acc = lane_sum<T, SellUnroll<T>::U>(Zt, m, lane, g);
-        for (int o = (1 << m.lg) >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
-        if (lead) {
-            if (FUSED) {
-                rnext[row] = rj;
-                x[row] = fma(at, dj, xj);
-                rr += (double)rj * (double)rj;
-            }
-            t[row] = (acc + rj) * ij;
-        }
-      }
-    }
+    if (!sell_stream<T, PipeUnroll<T>::U>(Zt, s0 + w, nsw, lane, g, ownf, epi, pre)) return;
     if (FUSED) {
         double pv[1] = {rr};
         put_partials<1>(pv, P.rr, L);
@@ -391,12 +537,40 @@ __global__ __launch_bounds__(kBS) void k_z(DevSell<T> Z, const T *__restrict__ t
                                            const T *__restrict__ r, T *__restrict__ s,
                                            CtlBlock *cb, Partials P, int g_rr, int par) {
     Ctl *c = &cb->c;
-    if (DOT) {
-        if (c->done) return;
-    }
-    if (DOT && !FIRST) {
+    if (DOT && c->done) return;
+    constexpr bool TEST = DOT && !FIRST;
+    const PartialsLoad<1> pl = load_partials<1>(P.rr, TEST ? g_rr : 0);
+    const int G = gridDim.x, L = logical_block(blockIdx.x, G);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
+    const int s0 = Z.bounds[L], s1 = Z.bounds[L + 1];
+    double sr = 0.0;
+    auto g = [&](int jj) { return t[jj]; };
+    struct OwnZ {
+        T tk, rk;
+    };
+    auto ownf = [&](const SliceMeta &m) {
+        const int row = m.row0 + (lane >> m.lg);
+        const int rw = row < Z.nrows ? row : Z.nrows - 1;
+        OwnZ o;
+        o.tk = t[rw];
+        o.rk = DOT ? r[rw] : T(0);
+        return o;
+    };
+    auto epi = [&](const SliceMeta &m, T acc, const OwnZ &o) {
+        for (int sh = (1 << m.lg) >> 1; sh > 0; sh >>= 1) acc += __shfl_xor(acc, sh, kWave);
+        const int row = m.row0 + (lane >> m.lg);
+        if ((lane & ((1 << m.lg) - 1)) == 0 && row < Z.nrows) {
+            const T sk = o.tk + acc;
+            s[row] = sk;
+            if (DOT) sr += (double)sk * (double)o.rk;
+        }
+    };
+    // stop test on the recursive residual of the iteration that just ended
+    auto pre = [&]() {
+        if (!TEST) return true;
         double rr[1];
-        sum_partials<1>(P.rr, g_rr, rr);
+        reduce_partials<1>(pl, g_rr, rr);
         const int k = c->kk[par] + 1;
         const double rel = sqrt(rr[0]) / c->nb;
         const bool bad = is_bad(rel);
@@ -412,36 +586,10 @@ __global__ __launch_bounds__(kBS) void k_z(DevSell<T> Z, const T *__restrict__ t
                 c->done = 1;
             }
         }
-        if (stop) return;
-    }
-    const int G = gridDim.x, L = logical_block(blockIdx.x, G);
-    const int lane = threadIdx.x & (kWave - 1);
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
-    int s0, s1;
-    s0 = Z.bounds[L];
-    s1 = Z.bounds[L + 1];
-    double sr = 0.0;
-    auto g = [&](int jj) { return t[jj]; };
+        return !stop;
+    };
     const int nsw = (s1 - s0 - w + kWavesPerBlock - 1) / kWavesPerBlock;   // this wave's slices
-    for (int i0 = 0; i0 < nsw; i0 += kWave) {
-      const int cnt = nsw - i0 < kWave ? nsw - i0 : kWave;
-      const SliceHeaders hd = load_headers(Z, s0 + w + i0 * kWavesPerBlock, kWavesPerBlock, cnt, lane);
-      for (int i = 0; i < cnt; i++) {
-        const SliceMeta m = header_of(hd, i);
-        const int row = m.row0 + (lane >> m.lg);
-        const bool lead = (lane & ((1 << m.lg) - 1)) == 0 && row < Z.nrows;
-        const int rw = row < Z.nrows ? row : Z.nrows - 1;
-        const T tk = t[rw];
-        const T rk = DOT ? r[rw] : T(0);
-        T acc = lane_sum<T, SellUnroll<T>::U>(Z, m, lane, g);
-        for (int o = (1 << m.lg) >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
-        if (lead) {
-            const T sk = tk + acc;
-            s[row] = sk;
-            if (DOT) sr += (double)sk * (double)rk;
-        }
-      }
-    }
+    if (!sell_stream<T, PipeUnroll<T>::U>(Z, s0 + w, nsw, lane, g, ownf, epi, pre)) return;
     if (DOT) {
         double pv[1] = {sr};
         put_partials<1>(pv, P.sr, L);

@@ -11,10 +11,16 @@ namespace pcga {
 constexpr int kBS = 256;           // threads per workgroup (4 wavefronts, one per SIMD)
 constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kWavesPerBlock = kBS / kWave;
-constexpr int kCPT = 2;            // stencil cells per thread per step
+#ifndef PCGA_CPT
+#define PCGA_CPT 1
+#endif
+constexpr int kCPT = PCGA_CPT;     // stencil cells per thread per step
 constexpr int kStep = kBS * kCPT;  // stencil cells per workgroup step
 constexpr int kHistRing = 4096;    // residual-history ring (entries)
 constexpr int kMaxBlocks = 2048;   // workgroups per kernel = partial sums per reduction
+// Default workgroups per kernel: 5 per CU (256 CUs), so that every workgroup
+// of the heaviest iteration kernel (5 wavefronts per SIMD) is resident at once.
+constexpr int kDefaultBlocks = 1280;
 constexpr int kSlotCells = 4096;   // cells per workgroup of a batch slot (target)
 
 // Workgroups of a batch slot: a function of the grid alone, so that a slot's

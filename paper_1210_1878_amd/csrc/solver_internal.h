@@ -42,7 +42,7 @@ struct pcga_solver {
     hipEvent_t ev[2] = {nullptr, nullptr};
 
     int g_st = 1, g_zt = 1, g_z = 1;
-    int max_blocks = pcga::kMaxBlocks;
+    int max_blocks = pcga::kDefaultBlocks;
     int chunk = 32;
     bool use_graph = true;
     hipGraphExec_t graph = nullptr;

@@ -207,7 +207,7 @@ def test_determinism_and_launch_modes(pkg):
     S = pkg.Solver(A, pkg.ainv_setup(A, tau))
     ref = S.solve(dev(p.b), tol=1e-10)
     for chunk, graph in ((32, True), (32, False), (2, True), (128, True)):
-        S.tune(chunk=chunk, use_graph=graph, max_blocks=2048)
+        S.tune(chunk=chunk, use_graph=graph)
         r = S.solve(dev(p.b), tol=1e-10)
         assert r.iters == ref.iters and torch.equal(r.x, ref.x)
         assert np.array_equal(r.hist, ref.hist)
@@ -274,6 +274,20 @@ def test_full_size_mixed(pkg, ora, orca025):
     assert true <= 1e-10
 
 
+def oracle_stop_window(ora, p, F, tol, K, seeds=6):
+    """Range of stop iterations the oracle itself reaches when b is perturbed
+    at the rounding level (relative 1e-15, seeded), together with K.  Where the
+    recursive residual is flat and non-monotone around tol (the banded factor
+    of T at q = 4), any other correct FP64 evaluation order stops somewhere
+    in this range; for AINV it is the single iteration K."""
+    rng = np.random.default_rng(1878)
+    ks = [K]
+    for _ in range(seeds):
+        b = p.b * (1.0 + 1e-15 * rng.standard_normal(p.n))
+        ks.append(ora.pcg(p, F, b=b, tol=tol).iters)
+    return min(ks), max(ks)
+
+
 @pytest.mark.parametrize("q", [1, 4])
 def test_pcg_paper_band_preconditioner(pkg, ora, q):
     """Algorithm 1 with the paper's own banded factor of T (Sec. 3 scheme):
@@ -290,7 +304,10 @@ def test_pcg_paper_band_preconditioner(pkg, ora, q):
     o = ora.pcg(p, F, tol=0.0, maxit=K)
     assert np.linalg.norm(g.x.cpu().numpy() - o.x) <= 1e-9 * np.linalg.norm(o.x)
     nat = S.solve(dev(p.b), tol=1e-10)
-    assert nat.status == 0 and abs(nat.iters - K) <= 2
+    lo, hi = oracle_stop_window(ora, p, F, 1e-10, K)
+    say(f"  natural stop: device {nat.iters}, oracle {K}, oracle under rounding-level "
+        f"perturbation {lo}..{hi}")
+    assert nat.status == 0 and lo - 2 <= nat.iters <= hi + 2
     kj = ora.pcg(p, ora.ainv_setup(p, np.inf), tol=1e-10).iters
     ka = ora.pcg(p, ora.ainv_setup(p, 0.1), tol=1e-10).iters
     say(f"  iterations: jacobi {kj}, band q={q} {K}, ainv {ka}")
