@@ -31,18 +31,23 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-# kernel names as rocprofv3 reports them (FP64 iteration kernels)
-KERNEL_NAMES = {"stencil": "k_stencil<double>", "axpy_zt": "k_zt<double, true>",
-                "z_dot": "k_z<double, true, false>"}
+def kernel_names(word, formats):
+    """Iteration kernels as rocprofv3 names them (template arguments: value
+    type, fused/dot flags, storage/read format of Z^T and Z)."""
+    t = "double" if word == 8 else "float"
+    return {"stencil": f"k_stencil<{t}>", "axpy_zt": f"k_zt<{t}, true, {formats[0]}>",
+            "z_dot": f"k_z<{t}, true, false, {formats[1]}>"}
 
 
-def kernel_bytes(n, nnz_off, word):
+def kernel_bytes(n, nnz_off, word, index_bytes=4):
     """Algorithmic bytes per launch of the three iteration kernels (each array
-    once; Z entries = value + 4-byte index).  word = 8 (FP64) or 4 (FP32)."""
+    once; a Z entry = its value + its index: a 4-byte column or a 2-byte
+    distance).  word = 8 (FP64) or 4 (FP32)."""
+    e = word + index_bytes
     return {
-        "stencil": 7 * word * n,                       # s, d_old, diag, ae, an in; d, q out
-        "axpy_zt": 8 * word * n + (word + 4) * nnz_off,  # r, q, d, x, D^-1 in; r', x, t out; Z^T
-        "z_dot": 3 * word * n + (word + 4) * nnz_off,    # t, r' in; s out; Z
+        "stencil": 7 * word * n,               # s, d_old, diag, ae, an in; d, q out
+        "axpy_zt": 8 * word * n + e * nnz_off,  # r, q, d, x, D^-1 in; r', x, t out; Z^T
+        "z_dot": 3 * word * n + e * nnz_off,    # t, r' in; s out; Z
     }
 
 
@@ -146,10 +151,14 @@ def bench_batch(P, torch, dev, log, members=64, nrhs=4):
             "speedup_vs_sequential": round(dts / dt, 2)}
 
 
-def bench_serve(P, torch, dev, log, count=40, rate=8.0):
-    """Poisson arrivals of time-step solves on a catalogue of resident grids
-    from 182x149 to 4322x3059; mixed precision to 1e-10, warm starts,
-    continuous batching."""
+def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=10.0):
+    """Time-step solves on a catalogue of resident grids from 182x149 to
+    4322x3059 (mixed precision to 1e-10, warm starts, continuous batching).
+    Capacity first: a closed loop keeps every grid busy and gives each grid's
+    saturated throughput c_g.  Then, per load factor L, independent Poisson
+    arrivals per grid at rate L * c_g over a fixed horizon; latency is arrival
+    to solution."""
+    import numpy as np
     from gen import orca
     from paper_1210_1878_amd import serve
     shapes = [(182, 149), (182, 149), (362, 292), (362, 292), (721, 510), (721, 510),
@@ -159,20 +168,35 @@ def bench_serve(P, torch, dev, log, count=40, rate=8.0):
     srv = serve.Server(probs, drop_tol=0.05, device=dev, chunk=16)
     log(f"serving: {len(probs)} resident grids ({srv.resident_bytes / 2**30:.2f} GiB), "
         f"setup {time.perf_counter() - t0:.1f}s")
-    # warm-up: one step per grid (graph capture, first-touch)
-    warm = [serve.Request(rid=-1 - g, grid=g, arrival=0.0) for g in range(len(probs))]
     stepper = serve.TimeStepper(probs, dev, seed=CONFIG_SERVE_SEED)
+    # warm-up: one step per grid (graph capture, first touch)
+    warm = [serve.Request(rid=-1 - g, grid=g, arrival=0.0) for g in range(len(probs))]
     srv.run(warm, make_rhs=stepper, on_done=stepper.done)
-    reqs = serve.poisson_arrivals(rate=rate, count=count, n_grids=len(probs), seed=CONFIG_SERVE_SEED)
-    done = srv.run(reqs, make_rhs=stepper, on_done=stepper.done)
-    st = serve.latency_stats(done)
-    log(f"served {st['requests']} requests: p50 {st['p50_ms']:.1f} ms, p99 {st['p99_ms']:.1f} ms, "
-        f"{st['solves_per_s']:.2f} solves/s, worst true relres {st['worst_true_relres']:.2e}")
-    st.update({"workload": "Poisson arrivals (seeded) of warm-started time steps (b_t = b_{t-1} + "
-                           "1% noise) on 8 resident ORCA-shaped grids 182x149 .. 4322x3059, mixed "
-                           "precision to 1e-10, continuous batching",
-               "arrival_rate_per_s": rate, "grids": [f"{a}x{b}" for a, b in shapes]})
-    return st
+    done, el = srv.saturate(saturate_s, make_rhs=stepper, on_done=stepper.done)
+    cap = [sum(1 for r in done if r.grid == g) / el for g in range(len(probs))]
+    log(f"capacity (closed loop, {el:.1f}s): {sum(cap):.1f} solves/s; per grid "
+        + ", ".join(f"{a}x{b}: {c:.2f}" for (a, b), c in zip(shapes, cap)))
+    out = {"workload": "warm-started time steps (b_t = b_{t-1} + 1% noise) on 8 resident "
+                       "ORCA-shaped grids 182x149 .. 4322x3059, mixed precision to 1e-10, "
+                       "continuous batching; per-grid Poisson arrivals at a load factor of "
+                       "each grid's closed-loop throughput",
+           "grids": [f"{a}x{b}" for a, b in shapes],
+           "capacity_solves_per_s": round(sum(cap), 2),
+           "capacity_per_grid": [round(c, 3) for c in cap],
+           "capacity_worst_true_relres": float(max(r.true_relres for r in done)),
+           "loads": {}}
+    for i, L in enumerate(loads):
+        reqs = serve.poisson_arrivals_per_grid([L * c for c in cap], horizon_s,
+                                               seed=CONFIG_SERVE_SEED + 1 + i)
+        res = srv.run(reqs, make_rhs=stepper, on_done=stepper.done)
+        st = serve.latency_stats(res)
+        big = [r.latency * 1e3 for r in res if r.grid == len(shapes) - 1]
+        st["p50_ms_largest_grid"] = float(np.median(big)) if big else None
+        log(f"load {L:.2f}: {st['requests']} requests, p50 {st['p50_ms']:.1f} ms, "
+            f"p99 {st['p99_ms']:.1f} ms, {st['solves_per_s']:.2f} solves/s, "
+            f"worst true relres {st['worst_true_relres']:.2e}")
+        out["loads"][str(L)] = st
+    return out
 
 
 CONFIG_SERVE_SEED = 1878 + 4
@@ -230,15 +254,18 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        ms = S64.profile_iteration(b, reps=args.reps)
-        ms32 = Smx.profile_iteration(b, reps=args.reps)
-        kb = kernel_bytes(p.n, G.nnz_off, 8)
-        kb32 = kernel_bytes(p.n, G.nnz_off, 4)
+        ms = S64.profile_iteration(b, reps=args.reps, mode=1)
+        ms32 = Smx.profile_iteration(b, reps=args.reps, mode=1)
+        kb = kernel_bytes(p.n, G.nnz_off, 8, S64.index_bytes)
+        kb32 = kernel_bytes(p.n, G.nnz_off, 4, Smx.index_bytes)
         for tag, t, byt in (("fp64", ms, kb), ("fp32", ms32, kb32)):
             log(tag + " " + ", ".join(f"{k}={t[i] * 1e3:.2f} us ({byt[k] / (t[i] * 1e-3) / 1e9:.0f} GB/s)"
-                                      for i, k in enumerate(byt)))
+                                      for i, k in enumerate(byt))
+                + f", iteration={t[3] * 1e3:.2f} us")
         print(json.dumps({"kernels_only": True, "fp64_ms": ms, "fp32_ms": ms32, "bytes_fp64": kb,
-                          "bytes_fp32": kb32, "n": p.n, "nnz_off": G.nnz_off}), flush=True)
+                          "bytes_fp32": kb32, "n": p.n, "nnz_off": G.nnz_off,
+                          "index_bytes": S64.index_bytes, "formats_fp64": S64.formats,
+                          "formats_fp32": Smx.formats}), flush=True)
         return
 
     for _ in range(args.warmup):
@@ -286,20 +313,22 @@ def main():
     log(f"jacobi: {rj.iters} iterations, {dtj * 1e3:.2f} ms/solve")
 
     # ---- roofline of the dominant kernel (HIP events on the solver stream) --
-    ms = S64.profile_iteration(b, reps=100)
-    ms32 = Smx.profile_iteration(b, reps=100)
-    kb = kernel_bytes(p.n, G.nnz_off, 8)
-    kb32 = kernel_bytes(p.n, G.nnz_off, 4)
+    ms = S64.profile_iteration(b, reps=100, mode=1)
+    ms32 = Smx.profile_iteration(b, reps=100, mode=1)
+    kb = kernel_bytes(p.n, G.nnz_off, 8, S64.index_bytes)
+    kb32 = kernel_bytes(p.n, G.nnz_off, 4, Smx.index_bytes)
     names = list(kb)
     gbs = {k: kb[k] / (ms[i] * 1e-3) / 1e9 for i, k in enumerate(names)}
     gbs32 = {k: kb32[k] / (ms32[i] * 1e-3) / 1e9 for i, k in enumerate(names)}
     dom = max(range(3), key=lambda i: ms[i])
-    log("fp64 kernels ms: " + ", ".join(f"{k}={ms[i]:.4f} ({gbs[k]:.0f} GB/s)" for i, k in enumerate(names)))
-    log("fp32 kernels ms: " + ", ".join(f"{k}={ms32[i]:.4f} ({gbs32[k]:.0f} GB/s)" for i, k in enumerate(names)))
+    log("fp64 kernels ms: " + ", ".join(f"{k}={ms[i]:.4f} ({gbs[k]:.0f} GB/s)" for i, k in enumerate(names))
+        + f", iteration={ms[3]:.4f}")
+    log("fp32 kernels ms: " + ", ".join(f"{k}={ms32[i]:.4f} ({gbs32[k]:.0f} GB/s)" for i, k in enumerate(names))
+        + f", iteration={ms32[3]:.4f}")
     b_iter = sum(kb.values())
     b_iter32 = sum(kb32.values())
-    it_time = sum(ms) * 1e-3
-    kname = KERNEL_NAMES[names[dom]]
+    it_time = ms[3] * 1e-3
+    kname = kernel_names(8, S64.formats)[names[dom]]
     traffic, tnote = measured_traffic(kname)
     roof = {"bound": "hbm", "kernel": kname,
             "achieved": round(gbs[names[dom]], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -324,19 +353,21 @@ def main():
         "config": {"workload": "ORCA025-shaped 1442x1021 lat-lon grid (lat -78..90, EW periodic, "
                                "35% land, seeded depth 500-5500 m), AINV drop tol 0.05, FP64 "
                                "PCG to relres 1e-10 from x0=0",
-                   "nx": NX, "ny": NY, "n": p.n, "nnz_off": G.nnz_off, "tol": TOL,
+                   "nx": NX, "ny": NY, "n": p.n, "nnz_off": G.nnz_off, "index_bytes": S64.index_bytes, "formats": {"fp64": S64.formats, "mixed": Smx.formats}, "tol": TOL,
                    "drop_tol": TAU, "iters_per_solve": fp64_iters, "chunk": args.chunk,
                    "graph": not args.no_graph, "max_blocks": args.max_blocks},
         "fp64": {"iters": fp64_iters, "ms_per_solve": round(dt * 1e3 / args.steps, 3),
                  "true_relres": fp64_true, "model_bytes_per_iter": b_iter,
                  "model_gbs_per_iter_kernels": round(b_iter / it_time / 1e9, 1),
                  "model_gbs_whole_solve": round(b_iter * it_s / 1e9, 1),
-                 "kernel_ms": dict(zip(names, [round(v, 5) for v in ms]))},
+                 "kernel_ms": dict(zip(names, [round(v, 5) for v in ms[:3]])),
+                 "iteration_ms": round(ms[3], 5)},
         "mixed": {"ms_per_solve": round(dtm * 1e3, 3), "outer": m.outer, "inner_iters": m.inner_total,
                   "inner_it_s": round(m.inner_total / dtm, 1), "true_relres": m.true_relres,
                   "rel_err_vs_fp64": err_mx, "speedup_vs_fp64": round(dt / args.steps / dtm, 3),
                   "model_bytes_per_inner_iter": b_iter32,
-                  "kernel_ms": dict(zip(names, [round(v, 5) for v in ms32]))},
+                  "kernel_ms": dict(zip(names, [round(v, 5) for v in ms32[:3]])),
+                  "iteration_ms": round(ms32[3], 5)},
         "jacobi": {"iters": rj.iters, "ms_per_solve": round(dtj * 1e3, 3),
                    "true_relres": rj.true_relres},
         "batched": batched,

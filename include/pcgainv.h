@@ -131,12 +131,18 @@ int pcga_solver_create(const pcga_a5_t *A, const pcga_ainv_t *F, int precision,
                        pcga_solver_t **out);
 int pcga_solver_destroy(pcga_solver_t *S);
 
-/* Solver facts: n, nnz_off, precision, and the modelled device bytes one PCG
- * iteration must move (each array once; FP64: 144 n + 24 nnz_pad, mixed inner:
- * 72 n + 16 nnz_pad, nnz_pad = stored sliced-ELL entries of Z^T plus Z
- * divided by 2). */
+/* Solver facts: n, nnz_off, precision, the modelled device bytes one PCG
+ * iteration must move (each array once; FP64: 144 n + (8 + b) nnz_pad, mixed
+ * inner: 72 n + (4 + b) nnz_pad, nnz_pad = stored sliced-ELL entries of Z^T
+ * plus Z, b = index bytes) and b itself: 2 when every stored entry of Z lies
+ * within 65535 rows of its row (16-bit distances), else 4 (32-bit columns);
+ * formats[0], formats[1]: how Z^T and Z are stored and read (bit 0: 16-bit
+ * distances; bit 1: indices, bit 2: values read with non-temporal loads,
+ * chosen so that the rest of an iteration's data fits the 256 MiB
+ * memory-side cache).  Any output pointer may be NULL. */
 int pcga_solver_info(const pcga_solver_t *S, int64_t *n, int64_t *nnz_off,
-                     int32_t *precision, double *bytes_per_iter);
+                     int32_t *precision, double *bytes_per_iter, int32_t *index_bytes,
+                     int32_t *formats);
 
 /* Launch tuning (used by the autotuner): iterations per chunk (even,
  * 2..512), whether chunks are replayed through a captured HIP graph (1) or
@@ -185,11 +191,20 @@ int pcga_apply_prec(pcga_solver_t *S, const double *r_dev, double *t_dev, double
 
 /* Average device time in milliseconds of each kernel of one PCG iteration,
  * ms_out[0] = d-update + five-point product + (d,q); ms_out[1] = residual and
- * solution update + D^-1 Z^T r; ms_out[2] = Z t + (s,r).  Measured with HIP
- * events on the solver's stream over `reps` (1..100000) iterations started
- * from x0 = 0 with no stopping test (FP64 kernels for PCGA_FP64, the FP32
- * inner kernels for PCGA_MIXED).  For benchmarks; the solver stays usable. */
-int pcga_profile_iteration(pcga_solver_t *S, const double *b_dev, int32_t reps, double *ms_out);
+ * solution update + D^-1 Z^T r; ms_out[2] = Z t + (s,r); ms_out[3] = one
+ * whole iteration.  Starts from the prologue of a solve from x0 = 0; no
+ * stopping test fires.  mode 0: each kernel launched `reps` (1..100000)
+ * times back to back between two HIP events (data a kernel re-reads may stay
+ * cached between its launches).  mode 1: `reps` whole iterations with a HIP
+ * event between every two kernels, so that each kernel meets the cache state
+ * of a solve (the times include the events' own cost, a few microseconds).
+ * ms_out[3]: `reps` whole iterations between two events, launched as a solve
+ * launches them (from a captured graph when the solver uses graphs).  FP64
+ * kernels for PCGA_FP64, the FP32 inner kernels for PCGA_MIXED.  For
+ * benchmarks: the solver's vectors are left in an unspecified state, the
+ * solver stays usable. */
+int pcga_profile_iteration(pcga_solver_t *S, const double *b_dev, int32_t reps, int32_t mode,
+                           double *ms_out);
 
 /* ---- batched solves (ensembles and continuous batching) -------------------
  * A batch advances many independent solves with one launch of each iteration

@@ -52,14 +52,14 @@ _SIGS = {
     "pcga_solver_create": ([ctypes.POINTER(A5), _p, ctypes.c_int, _p, _sz, _p, _pp],
                            ctypes.c_int),
     "pcga_solver_destroy": ([_p], ctypes.c_int),
-    "pcga_solver_info": ([_p, _pi64, _pi64, _pi32, _pdbl], ctypes.c_int),
+    "pcga_solver_info": ([_p, _pi64, _pi64, _pi32, _pdbl, _pi32, _pi32], ctypes.c_int),
     "pcga_solver_tune": ([_p, _i32, _i32, _i32], ctypes.c_int),
     "pcga_pcg_solve": ([_p, _p, _p, _dbl, _i32, _pi32, _p, _i32, _pi32, _pdbl], ctypes.c_int),
     "pcga_pcg_solve_mixed": ([_p, _p, _p, _dbl, _dbl, _i32, _i32, _pi32, _pi32, _p, _i32,
                               _pi32, _pdbl], ctypes.c_int),
     "pcga_apply_a": ([_p, _p, _p], ctypes.c_int),
     "pcga_apply_prec": ([_p, _p, _p, _p], ctypes.c_int),
-    "pcga_profile_iteration": ([_p, _p, _i32, _pdbl], ctypes.c_int),
+    "pcga_profile_iteration": ([_p, _p, _i32, _i32, _pdbl], ctypes.c_int),
     "pcga_batch_scratch_bytes": ([_i32, ctypes.POINTER(_sz)], ctypes.c_int),
     "pcga_batch_item_bytes": ([_p, _i32, ctypes.POINTER(_sz)], ctypes.c_int),
     "pcga_batch_create": ([_i32, _p, _sz, _p, _pp], ctypes.c_int),

@@ -173,11 +173,15 @@ class Solver:
         nnz = ctypes.c_int64()
         prec = ctypes.c_int32()
         bpi = ctypes.c_double()
+        ib = ctypes.c_int32()
+        fm = (ctypes.c_int32 * 2)()
         check(L.pcga_solver_info(self._h, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(prec),
-                                 ctypes.byref(bpi)), "pcga_solver_info")
+                                 ctypes.byref(bpi), ctypes.byref(ib), fm), "pcga_solver_info")
+        self.formats = (fm[0], fm[1])     # Z^T, Z: bit 0 16-bit index, bit 1/2 streamed idx/val
         self.n = n.value
         self.nnz_off = nnz.value
         self.bytes_per_iter = bpi.value
+        self.index_bytes = ib.value
 
     @property
     def handle(self):
@@ -247,13 +251,17 @@ class Solver:
                                           _dev_ptr(s, torch.float64, self.n)), "pcga_apply_prec")
         return t, s
 
-    def profile_iteration(self, b, reps=50):
-        """Average ms of the three iteration kernels (HIP events, solver stream)."""
+    def profile_iteration(self, b, reps=50, mode=1):
+        """Average ms of the three iteration kernels and of a whole iteration
+        (HIP events on the solver stream).  mode 1: kernels timed inside whole
+        iterations (the cache state of a solve); mode 0: each kernel repeated
+        alone."""
         import torch
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
-        ms = (ctypes.c_double * 3)()
+        ms = (ctypes.c_double * 4)()
         check(_lib.load().pcga_profile_iteration(self._h, _dev_ptr(b, torch.float64, self.n),
-                                                 int(reps), ms), "pcga_profile_iteration")
+                                                 int(reps), int(mode), ms),
+              "pcga_profile_iteration")
         return list(ms)
 
     def close(self):

@@ -284,9 +284,9 @@ __global__ __launch_bounds__(kBS) void kb_stencil(const BlkEnt *tab, int ntab, c
 // ---------------------------------------------------------------------------
 // t = D^-1 Z^T r' with r' = r - alpha q per right-hand side (FUSED) or r' = r.
 // FUSED also writes r', updates e += alpha d and returns ||r'||^2.
-template <int R, bool FUSED>
-__device__ void zt_apply(const SlotDesc &D, int L, const float (&al)[R], const float *rcur,
-                         float *rnext, const float *dcur, double (&rr)[1][R]) {
+template <int R, bool FUSED, bool NARROW>
+__device__ void zt_apply_f(const SlotDesc &D, int L, const float (&al)[R], const float *rcur,
+                           float *rnext, const float *dcur, double (&rr)[1][R]) {
     const DevSell<float> &M = D.zt;
     const float *q = D.q;
     float *e = D.e, *t = D.t;
@@ -315,7 +315,6 @@ __device__ void zt_apply(const SlotDesc &D, int L, const float (&al)[R], const f
             float acc[R];
 #pragma unroll
             for (int r = 0; r < R; r++) acc[r] = 0.f;
-            const int32_t *ip = M.idx + m.off + lane;
             const float *vp = M.val + m.off + lane;
             const int last = m.width - 1;
             constexpr int U = 4;
@@ -325,8 +324,8 @@ __device__ void zt_apply(const SlotDesc &D, int L, const float (&al)[R], const f
 #pragma unroll
                 for (int u = 0; u < U; u++) {
                     const int ci = cc + u <= last ? cc + u : last;
-                    kk[u] = stream_load(ip + (int64_t)ci * kWave);
-                    zv[u] = stream_load(vp + (int64_t)ci * kWave);
+                    kk[u] = entry_col<float, NARROW ? kFmtNarrow : 0, true>(M, m.off + (int64_t)ci * kWave + lane, rw);
+                    zv[u] = vp[(int64_t)ci * kWave];
                 }
                 float gr[U][R], gq[U][R];
 #pragma unroll
@@ -368,6 +367,17 @@ __device__ void zt_apply(const SlotDesc &D, int L, const float (&al)[R], const f
             }
         }
     }
+}
+
+// the slot's index format (uniform over the workgroup)
+template <int R, bool FUSED>
+__device__ __forceinline__ void zt_apply(const SlotDesc &D, int L, const float (&al)[R],
+                                         const float *rcur, float *rnext, const float *dcur,
+                                         double (&rr)[1][R]) {
+    if (D.zt.dist)
+        zt_apply_f<R, FUSED, true>(D, L, al, rcur, rnext, dcur, rr);
+    else
+        zt_apply_f<R, FUSED, false>(D, L, al, rcur, rnext, dcur, rr);
 }
 
 template <int R>
@@ -486,8 +496,8 @@ __global__ __launch_bounds__(kBS) void kb_zt(const BlkEnt *tab, int ntab, const 
 // kb_z
 // ---------------------------------------------------------------------------
 // s = Z t and (s, r) partials for R right-hand sides.
-template <int R>
-__device__ void z_apply(const SlotDesc &D, int L, const float *r, double (&sr)[1][R]) {
+template <int R, bool NARROW>
+__device__ void z_apply_f(const SlotDesc &D, int L, const float *r, double (&sr)[1][R]) {
     const DevSell<float> &M = D.z;
     const float *t = D.t;
     float *s = D.s;
@@ -511,7 +521,6 @@ __device__ void z_apply(const SlotDesc &D, int L, const float *r, double (&sr)[1
             float acc[R];
 #pragma unroll
             for (int q = 0; q < R; q++) acc[q] = 0.f;
-            const int32_t *ip = M.idx + m.off + lane;
             const float *vp = M.val + m.off + lane;
             const int last = m.width - 1;
             constexpr int U = 8;
@@ -521,8 +530,8 @@ __device__ void z_apply(const SlotDesc &D, int L, const float *r, double (&sr)[1
 #pragma unroll
                 for (int u = 0; u < U; u++) {
                     const int ci = cc + u <= last ? cc + u : last;
-                    jj[u] = stream_load(ip + (int64_t)ci * kWave);
-                    zv[u] = stream_load(vp + (int64_t)ci * kWave);
+                    jj[u] = entry_col<float, NARROW ? kFmtNarrow : 0, false>(M, m.off + (int64_t)ci * kWave + lane, rw);
+                    zv[u] = vp[(int64_t)ci * kWave];
                 }
                 float tv[U][R];
 #pragma unroll
@@ -548,6 +557,14 @@ __device__ void z_apply(const SlotDesc &D, int L, const float *r, double (&sr)[1
             }
         }
     }
+}
+
+template <int R>
+__device__ __forceinline__ void z_apply(const SlotDesc &D, int L, const float *r, double (&sr)[1][R]) {
+    if (D.z.dist)
+        z_apply_f<R, true>(D, L, r, sr);
+    else
+        z_apply_f<R, false>(D, L, r, sr);
 }
 
 template <int R>

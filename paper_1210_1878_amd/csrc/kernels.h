@@ -253,39 +253,54 @@ __device__ __forceinline__ SliceMeta header_of(const SliceHeaders &h, int i) {
     return m;
 }
 
-// Index/value streams of Z are read once per launch: non-temporal loads keep
-// them from evicting the gathered vectors.
-#ifndef PCGA_SELL_NT
-#define PCGA_SELL_NT 1
-#endif
-template <typename P>
+// Storage and read format of a sliced-ELL matrix, a kernel template argument:
+//   bit 0: 16-bit distances instead of 32-bit columns;
+//   bit 1: indices read with non-temporal loads;
+//   bit 2: values read with non-temporal loads.
+// Non-temporal reads keep a stream out of the caches, so that the data the
+// host chose to keep resident in the 256 MB memory-side cache (the vectors,
+// then as much of Z as fits) is not evicted by a stream that cannot fit.
+constexpr int kFmtNarrow = 1, kFmtNtIdx = 2, kFmtNtVal = 4;
+
+template <bool NT, typename P>
 __device__ __forceinline__ P stream_load(const P *p) {
-#if PCGA_SELL_NT
-    return __builtin_nontemporal_load(p);
-#else
+    if (NT) return __builtin_nontemporal_load(p);
     return *p;
-#endif
+}
+
+// Column of entry step c of this lane: the stored 32-bit column, or (narrow)
+// the lane's row (clamped to the matrix) minus (LOWER, Z^T) or plus (Z) the
+// stored 16-bit distance.
+template <typename T, int FMT, bool LOWER>
+__device__ __forceinline__ int entry_col(const DevSell<T> &M, int64_t pos, int rowc) {
+    constexpr bool nt = (FMT & kFmtNtIdx) != 0;
+    if (FMT & kFmtNarrow) {
+        const int d = stream_load<nt>(M.dist + pos);
+        return LOWER ? rowc - d : rowc + d;
+    }
+    return stream_load<nt>(M.idx + pos);
 }
 
 // Index/value loads of one unit (U consecutive entry steps of a slice, from
 // step cc); past the slice width the last entry is re-read and ignored.
-template <typename T, int U>
+template <typename T, int U, int FMT, bool LOWER>
 __device__ __forceinline__ void load_unit(const DevSell<T> &M, const SliceMeta &m, int cc, int lane,
                                           int (&kk)[U], T (&zv)[U]) {
     const int last = m.width - 1;
-    const int32_t *ip = M.idx + m.off + lane;
+    const int row = m.row0 + (lane >> m.lg);
+    const int rowc = row < M.nrows ? row : M.nrows - 1;
     const T *vp = M.val + m.off + lane;
     if (last >= 0) {
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int c = cc + u <= last ? cc + u : last;
-            kk[u] = stream_load(ip + (int64_t)c * kWave);
-            zv[u] = stream_load(vp + (int64_t)c * kWave);
+            kk[u] = entry_col<T, FMT, LOWER>(M, m.off + (int64_t)c * kWave + lane, rowc);
+            zv[u] = stream_load<(FMT & kFmtNtVal) != 0>(vp + (int64_t)c * kWave);
         }
     } else {
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            kk[u] = m.row0;
+            kk[u] = rowc;
             zv[u] = T(0);
         }
     }
@@ -300,7 +315,8 @@ __device__ __forceinline__ void load_unit(const DevSell<T> &M, const SliceMeta &
 // also one without slices, and the pass ends early when it returns false.
 // epi(m, acc, own) finishes a slice (called by all lanes; acc is this lane's
 // partial row sum, entries in increasing order).
-template <typename T, int U, typename Gth, typename OwnF, typename EpiF, typename PreF>
+template <typename T, int U, int FMT, bool LOWER, typename Gth, typename OwnF, typename EpiF,
+          typename PreF>
 __device__ __forceinline__ bool sell_stream(const DevSell<T> &M, int first, int nsw, int lane,
                                             const Gth &g, const OwnF &ownf, const EpiF &epi,
                                             const PreF &pre) {
@@ -314,7 +330,7 @@ __device__ __forceinline__ bool sell_stream(const DevSell<T> &M, int first, int 
     auto start_batch = [&](int i0) {
         hd = load_headers(M, first + i0 * kWavesPerBlock, kWavesPerBlock, cnt, lane);
         m = header_of(hd, 0);
-        load_unit<T, U>(M, m, 0, lane, kk, zv);
+        load_unit<T, U, FMT, LOWER>(M, m, 0, lane, kk, zv);
         own = ownf(m);
     };
     if (nsw > 0) start_batch(0);
@@ -337,7 +353,7 @@ __device__ __forceinline__ bool sell_stream(const DevSell<T> &M, int first, int 
             T zv2[U];
             Own own2 = own;
             if (more) {
-                load_unit<T, U>(M, nm, ncc, lane, kk2, zv2);
+                load_unit<T, U, FMT, LOWER>(M, nm, ncc, lane, kk2, zv2);
                 if (slice_end) own2 = ownf(nm);
             }
             T gv[U];
@@ -460,7 +476,7 @@ __global__ __launch_bounds__(kBS) void k_stencil(DevOp<T> A, const T *__restrict
 // (written to rnext), x += alpha d, ||r'||^2 partials.  Not fused: r' = r.
 // Rows of Z^T are the columns of Z; the unit diagonal is added last.
 // ---------------------------------------------------------------------------
-template <typename T, bool FUSED>
+template <typename T, bool FUSED, int FMT>
 __global__ __launch_bounds__(kBS) void k_zt(DevSell<T> Zt, const T *__restrict__ dinv,
                                             const T *__restrict__ rcur, const T *__restrict__ q,
                                             const T *__restrict__ dcur, T *__restrict__ rnext,
@@ -521,7 +537,8 @@ __global__ __launch_bounds__(kBS) void k_zt(DevSell<T> Zt, const T *__restrict__
         return true;
     };
     const int nsw = (s1 - s0 - w + kWavesPerBlock - 1) / kWavesPerBlock;   // this wave's slices
-    if (!sell_stream<T, PipeUnroll<T>::U>(Zt, s0 + w, nsw, lane, g, ownf, epi, pre)) return;
+    if (!sell_stream<T, PipeUnroll<T>::U, FMT, true>(Zt, s0 + w, nsw, lane, g, ownf, epi, pre))
+        return;
     if (FUSED) {
         double pv[1] = {rr};
         put_partials<1>(pv, P.rr, L);
@@ -532,7 +549,7 @@ __global__ __launch_bounds__(kBS) void k_zt(DevSell<T> Zt, const T *__restrict__
 // k_z: (DOT, not FIRST) stop test from the ||r'||^2 partials, then s = Z t and
 // (s, r') partials.  FIRST: prologue (no stop test).  Neither: s = Z t only.
 // ---------------------------------------------------------------------------
-template <typename T, bool DOT, bool FIRST>
+template <typename T, bool DOT, bool FIRST, int FMT>
 __global__ __launch_bounds__(kBS) void k_z(DevSell<T> Z, const T *__restrict__ t,
                                            const T *__restrict__ r, T *__restrict__ s,
                                            CtlBlock *cb, Partials P, int g_rr, int par) {
@@ -589,7 +606,8 @@ __global__ __launch_bounds__(kBS) void k_z(DevSell<T> Z, const T *__restrict__ t
         return !stop;
     };
     const int nsw = (s1 - s0 - w + kWavesPerBlock - 1) / kWavesPerBlock;   // this wave's slices
-    if (!sell_stream<T, PipeUnroll<T>::U>(Z, s0 + w, nsw, lane, g, ownf, epi, pre)) return;
+    if (!sell_stream<T, PipeUnroll<T>::U, FMT, false>(Z, s0 + w, nsw, lane, g, ownf, epi, pre))
+        return;
     if (DOT) {
         double pv[1] = {sr};
         put_partials<1>(pv, P.sr, L);

@@ -63,4 +63,25 @@ void sell_build(int64_t m, const int64_t *rowptr, const int32_t *col, const doub
     }
 }
 
+bool sell_narrow(SellLayout &L, bool lower) {
+    const int64_t m = L.nrows_total;
+    std::vector<uint16_t> d(L.idx.size());
+    for (int64_t s = 0; s < L.nslices(); s++) {
+        const int lg = L.meta[s] & 255;
+        for (int64_t pos = L.off[s]; pos < L.off[s + 1]; pos++) {
+            const int l = (int)((pos - L.off[s]) % 64);
+            const int64_t r = std::min<int64_t>(L.row0[s] + (l >> lg), m - 1);
+            const int64_t c = L.idx[pos];
+            const int64_t dist = lower ? r - c : c - r;
+            if (dist < 0 || dist > 65535) return false;
+            d[pos] = (uint16_t)dist;
+        }
+    }
+    L.dist.swap(d);
+    L.idx.clear();
+    L.idx.shrink_to_fit();
+    L.narrow = true;
+    return true;
+}
+
 }  // namespace pcga

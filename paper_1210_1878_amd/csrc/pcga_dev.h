@@ -21,6 +21,10 @@ constexpr int kMaxBlocks = 2048;   // workgroups per kernel = partial sums per r
 // Default workgroups per kernel: 5 per CU (256 CUs), so that every workgroup
 // of the heaviest iteration kernel (5 wavefronts per SIMD) is resident at once.
 constexpr int kDefaultBlocks = 1280;
+// Memory-side cache (Infinity Cache) of one MI355X: 256 MiB.  The streams an
+// iteration reads are kept resident up to 95% of it (see cache_plan).
+constexpr double kMallBytes = 268435456.0;
+constexpr double kResidentBudget = 0.95 * kMallBytes;
 constexpr int kSlotCells = 4096;   // cells per workgroup of a batch slot (target)
 
 // Workgroups of a batch slot: a function of the grid alone, so that a slot's
@@ -44,7 +48,8 @@ template <typename T>
 struct DevSell {
     const int32_t *row0, *meta;
     const int64_t *off;
-    const int32_t *idx;
+    const int32_t *idx;      // columns, or null in the narrow form
+    const uint16_t *dist;    // narrow form: |column - row| (direction fixed per matrix)
     const T *val;
     const int32_t *bounds;   // slice range of workgroup L: [bounds[L], bounds[L+1])
     const int32_t *bounds_b; // the same for the block count of a batch slot

@@ -41,13 +41,20 @@ int fsai_band_build(const A5View &A, int64_t q, AinvFactor &F, int64_t *bad_row)
 //   off[s] + c*64 + l (column-major in the slice, so each step c is one
 //   coalesced 64-wide load).  Padding entries have value 0 and point to the
 //   lane's own row.
+//   Narrow form: when every entry lies within 65535 rows of its lane's row
+//   (rows past the matrix count as its last row), the column is stored as
+//   the 16-bit distance |col - row| instead (dist, same positions; idx is
+//   then empty); the direction is fixed per matrix (Z^T: col <= row, Z:
+//   col >= row).
 struct SellLayout {
     int64_t nrows_total = 0;
     std::vector<int32_t> row0;      // [nslices]
     std::vector<int32_t> meta;      // [nslices]: lpr_log2 | (width << 8)
     std::vector<int64_t> off;       // [nslices + 1] entry offsets
-    std::vector<int32_t> idx;       // [off.back()]
+    std::vector<int32_t> idx;       // [off.back()] (empty in the narrow form)
+    std::vector<uint16_t> dist;     // [off.back()] (narrow form only)
     std::vector<double> val;        // [off.back()]
+    bool narrow = false;
     int64_t nslices() const { return (int64_t)row0.size(); }
     int64_t entries() const { return off.empty() ? 0 : off.back(); }
 };
@@ -55,6 +62,10 @@ struct SellLayout {
 // rows given as CSR (rowptr[m+1], col, val with columns ascending per row).
 void sell_build(int64_t m, const int64_t *rowptr, const int32_t *col, const double *val,
                 int target_width, SellLayout &L);
+
+// Switch L to the narrow form when it fits (lower: every column <= its row,
+// else every column >= its row).  Returns whether it did.
+bool sell_narrow(SellLayout &L, bool lower);
 
 std::string &last_error();
 int fail(int code, const std::string &msg);

@@ -103,6 +103,12 @@ int build_layouts(const AinvFactor &F, int target_width, HostLayouts &H) {
                 val[p] = F.val[a];
             }
         sell_build(n, rp.data(), col.data(), val.data(), target_width, H.z);
+        // 16-bit distances when both fit (one format per solver)
+        if (sell_narrow(H.zt, true) && !sell_narrow(H.z, false)) {
+            // Z^T fits but Z does not (cannot happen for a transpose pair of
+            // the same pattern; kept consistent anyway): rebuild Z^T wide
+            sell_build(n, F.colptr.data(), F.rowidx.data(), F.val.data(), target_width, H.zt);
+        }
     } catch (const std::bad_alloc &) {
         return fail(PCGA_ENOMEM, "host allocation failed while building sliced-ELL layouts");
     }
@@ -127,7 +133,13 @@ size_t carve(pcga_solver &S, void *base, const HostLayouts &H) {
         dst.row0 = C.take<int32_t>(L.nslices());
         dst.meta = C.take<int32_t>(L.nslices());
         dst.off = C.take<int64_t>(L.nslices() + 1);
-        dst.idx = C.take<int32_t>(std::max<int64_t>(L.entries(), 1));
+        if (L.narrow) {
+            dst.idx = nullptr;
+            dst.dist = C.take<uint16_t>(std::max<int64_t>(L.entries(), 1));
+        } else {
+            dst.idx = C.take<int32_t>(std::max<int64_t>(L.entries(), 1));
+            dst.dist = nullptr;
+        }
         dst.val = C.take<T>(std::max<int64_t>(L.entries(), 1));
         dst.nslices = (int32_t)L.nslices();
         dst.nrows = (int32_t)L.nrows_total;
@@ -222,6 +234,29 @@ std::vector<int32_t> balanced_bounds(const std::vector<int32_t> &cost, int G) {
     b[G] = (int32_t)ns;
     for (int L = 1; L <= G; L++) b[L] = std::max(b[L], b[L - 1]);
     return b;
+}
+
+// Which streams of an iteration stay resident in the memory-side cache.  The
+// iteration kernels read, per iteration, the vectors and operator arrays
+// (12 of n words: x or e, r[2], s, d[2], q, t, diag, ae, an, D^-1) and the
+// values and indices of Z^T and Z.  The vectors are kept first (each is read
+// by two or three kernels), then Z^T values, Z values, Z^T indices, Z
+// indices, as long as the total fits the budget; the streams left over are
+// read with non-temporal loads so that they do not evict the resident ones
+// (cycling a working set larger than the cache through it would evict
+// everything before its reuse).
+void cache_plan(pcga_solver &S, const HostLayouts &H) {
+    const double w = S.precision == PCGA_FP64 ? 8.0 : 4.0;
+    const double ib = H.zt.narrow ? 2.0 : 4.0;
+    const double ezt = (double)H.zt.entries(), ez = (double)H.z.entries();
+    const double streams[4] = {w * ezt, w * ez, ib * ezt, ib * ez};   // kept in this order
+    double used = 12.0 * w * (double)S.n;
+    int kept = 0;
+    while (kept < 4 && used + streams[kept] <= kResidentBudget) used += streams[kept++];
+    // streams not kept: Z idx (kept < 4), Z^T idx (< 3), Z val (< 2), Z^T val (< 1)
+    const int nar = H.zt.narrow ? kFmtNarrow : 0;
+    S.fmt_zt = nar | (kept < 3 ? kFmtNtIdx : 0) | (kept < 1 ? kFmtNtVal : 0);
+    S.fmt_z = nar | (kept < 4 ? kFmtNtIdx : 0) | (kept < 2 ? kFmtNtVal : 0);
 }
 
 int upload_bounds(pcga_solver &S) {
@@ -454,7 +489,10 @@ int pcga_solver_create(const pcga_a5_t *A, const pcga_ainv_t *F, int precision, 
         e = hipMemcpyAsync((void *)dst.off, L.off.data(), L.off.size() * 8, hipMemcpyHostToDevice, sm);
         if (e) return e;
         if (L.entries() == 0) return hipSuccess;
-        e = hipMemcpyAsync((void *)dst.idx, L.idx.data(), L.idx.size() * 4, hipMemcpyHostToDevice, sm);
+        if (L.narrow)
+            e = hipMemcpyAsync((void *)dst.dist, L.dist.data(), L.dist.size() * 2, hipMemcpyHostToDevice, sm);
+        else
+            e = hipMemcpyAsync((void *)dst.idx, L.idx.data(), L.idx.size() * 4, hipMemcpyHostToDevice, sm);
         if (e) return e;
         if constexpr (std::is_same_v<T, double>) {
             return hipMemcpyAsync((void *)dst.val, L.val.data(), L.val.size() * 8,
@@ -506,11 +544,14 @@ int pcga_solver_create(const pcga_a5_t *A, const pcga_ainv_t *F, int precision, 
     //   stencil: s, d_old, diag, ae, an read; d_new, q written       7 n words
     //   zt: r, q, d, x, dinv read; r', x, t written; Z^T entries     8 n words + E_zt
     //   z:  t, r' read; s written; Z entries                         3 n words + E_z
+    //   (an entry: its value and a 4-byte column or 2-byte distance)
     const double E = (double)S->sell_entries;
+    S->index_bytes = H.zt.narrow ? 2 : 4;
+    cache_plan(*S, H);
     if (precision == PCGA_FP64)
-        S->bytes_per_iter = 8.0 * 18.0 * n + 12.0 * E;
+        S->bytes_per_iter = 8.0 * 18.0 * n + (8.0 + S->index_bytes) * E;
     else
-        S->bytes_per_iter = 4.0 * 18.0 * n + 8.0 * E;
+        S->bytes_per_iter = 4.0 * 18.0 * n + (4.0 + S->index_bytes) * E;
     *out = S;
     return PCGA_OK;
 }
@@ -527,8 +568,13 @@ int pcga_solver_destroy(pcga_solver_t *S) {
 }
 
 int pcga_solver_info(const pcga_solver_t *S, int64_t *n, int64_t *nnz_off, int32_t *precision,
-                     double *bytes_per_iter) {
+                     double *bytes_per_iter, int32_t *index_bytes, int32_t *formats) {
     if (!S) return fail(PCGA_EINVAL, "S is NULL");
+    if (index_bytes) *index_bytes = S->index_bytes;
+    if (formats) {
+        formats[0] = S->fmt_zt;
+        formats[1] = S->fmt_z;
+    }
     if (n) *n = S->n;
     if (nnz_off) *nnz_off = S->nnz_off;
     if (precision) *precision = S->precision;
@@ -576,6 +622,32 @@ IterBufs<float> bufs32(pcga_solver &S) {
             {S.d32[0], S.d32[1]}, S.q32, S.t32};
 }
 
+// Launch k_zt / k_z in a matrix's storage and read format (kFmt* bits).
+#define PCGA_FMT_CASES(KERNEL, ...)                                      \
+    switch (fmt) {                                                       \
+        case 0: KERNEL(0)<<<grid, kBS, 0, st>>>(__VA_ARGS__); break;     \
+        case 1: KERNEL(1)<<<grid, kBS, 0, st>>>(__VA_ARGS__); break;     \
+        case 2: KERNEL(2)<<<grid, kBS, 0, st>>>(__VA_ARGS__); break;     \
+        case 3: KERNEL(3)<<<grid, kBS, 0, st>>>(__VA_ARGS__); break;     \
+        case 6: KERNEL(6)<<<grid, kBS, 0, st>>>(__VA_ARGS__); break;     \
+        default: KERNEL(7)<<<grid, kBS, 0, st>>>(__VA_ARGS__); break;    \
+    }
+
+template <typename T, bool FUSED, typename... Args>
+void launch_zt(const DevSell<T> &M, int fmt, int grid, hipStream_t st, Args... args) {
+#define PCGA_K(F) k_zt<T, FUSED, F>
+    PCGA_FMT_CASES(PCGA_K, M, args...)
+#undef PCGA_K
+}
+
+template <typename T, bool DOT, bool FIRST, typename... Args>
+void launch_z(const DevSell<T> &M, int fmt, int grid, hipStream_t st, Args... args) {
+#define PCGA_K(F) k_z<T, DOT, FIRST, F>
+    PCGA_FMT_CASES(PCGA_K, M, args...)
+#undef PCGA_K
+}
+#undef PCGA_FMT_CASES
+
 // One kernel of iteration parity p: 0 stencil, 1 axpy + Z^T, 2 Z + dot.
 template <typename T>
 void launch_kernel(pcga_solver &S, const IterBufs<T> &B, int p, int which) {
@@ -585,12 +657,12 @@ void launch_kernel(pcga_solver &S, const IterBufs<T> &B, int p, int which) {
                                                        S.g_z, p);
             break;
         case 1:
-            k_zt<T, true><<<S.g_zt, kBS, 0, S.stream>>>(B.zt, B.dinv, B.r[p], B.q, B.d[p ^ 1],
-                                                        B.r[p ^ 1], B.x, B.t, S.cb, S.P, S.g_st, p);
+            launch_zt<T, true>(B.zt, S.fmt_zt, S.g_zt, S.stream, B.dinv, (const T *)B.r[p], (const T *)B.q,
+                               (const T *)B.d[p ^ 1], B.r[p ^ 1], B.x, B.t, S.cb, S.P, S.g_st, p);
             break;
         default:
-            k_z<T, true, false><<<S.g_z, kBS, 0, S.stream>>>(B.z, B.t, B.r[p ^ 1], B.s, S.cb, S.P,
-                                                            S.g_zt, p);
+            launch_z<T, true, false>(B.z, S.fmt_z, S.g_z, S.stream, (const T *)B.t, (const T *)B.r[p ^ 1],
+                                     B.s, S.cb, S.P, S.g_zt, p);
             break;
     }
 }
@@ -626,9 +698,10 @@ void launch_refine(pcga_solver &S, bool add_e, const double *x, double *xnew, co
 template <typename T>
 int prologue_prec(pcga_solver &S, const IterBufs<T> &B) {
     HIP_TRY(hipMemsetAsync(B.d[0], 0, S.n * sizeof(T), S.stream));
-    k_zt<T, false><<<S.g_zt, kBS, 0, S.stream>>>(B.zt, B.dinv, B.r[0], nullptr, nullptr, nullptr,
-                                                 nullptr, B.t, S.cb, S.P, 0, 0);
-    k_z<T, true, true><<<S.g_z, kBS, 0, S.stream>>>(B.z, B.t, B.r[0], B.s, S.cb, S.P, 0, 0);
+    launch_zt<T, false>(B.zt, S.fmt_zt, S.g_zt, S.stream, B.dinv, (const T *)B.r[0], (const T *)nullptr,
+                        (const T *)nullptr, (T *)nullptr, (T *)nullptr, B.t, S.cb, S.P, 0, 0);
+    launch_z<T, true, true>(B.z, S.fmt_z, S.g_z, S.stream, (const T *)B.t, (const T *)B.r[0], B.s, S.cb,
+                            S.P, 0, 0);
     HIP_TRY(hipGetLastError());
     return PCGA_OK;
 }
@@ -852,18 +925,19 @@ int pcga_apply_prec(pcga_solver_t *S, const double *r_dev, double *t_dev, double
     HIP_TRY(hipSetDevice(S->device));
     const int gc = (int)std::min<int64_t>(4096, (S->n + kBS - 1) / kBS);
     if (S->precision == PCGA_FP64) {
-        k_zt<double, false><<<S->g_zt, kBS, 0, S->stream>>>(S->zt64, S->dinv64, r_dev, nullptr,
-                                                            nullptr, nullptr, nullptr, t_dev, S->cb,
-                                                            S->P, 0, 0);
-        k_z<double, false, false><<<S->g_z, kBS, 0, S->stream>>>(S->z64, t_dev, nullptr, s_dev,
-                                                                S->cb, S->P, 0, 0);
+        launch_zt<double, false>(S->zt64, S->fmt_zt, S->g_zt, S->stream, (const double *)S->dinv64, r_dev,
+                                 (const double *)nullptr, (const double *)nullptr, (double *)nullptr,
+                                 (double *)nullptr, t_dev, S->cb, S->P, 0, 0);
+        launch_z<double, false, false>(S->z64, S->fmt_z, S->g_z, S->stream, (const double *)t_dev,
+                                       (const double *)nullptr, s_dev, S->cb, S->P, 0, 0);
     } else {
         k_convert<double, float><<<gc, kBS, 0, S->stream>>>((int)S->n, r_dev, S->r32[0]);
-        k_zt<float, false><<<S->g_zt, kBS, 0, S->stream>>>(S->zt32, S->dinv32, S->r32[0], nullptr,
-                                                           nullptr, nullptr, nullptr, S->t32, S->cb,
-                                                           S->P, 0, 0);
-        k_z<float, false, false><<<S->g_z, kBS, 0, S->stream>>>(S->z32, S->t32, nullptr, S->tmp32,
-                                                               S->cb, S->P, 0, 0);
+        launch_zt<float, false>(S->zt32, S->fmt_zt, S->g_zt, S->stream, (const float *)S->dinv32,
+                                (const float *)S->r32[0], (const float *)nullptr,
+                                (const float *)nullptr, (float *)nullptr, (float *)nullptr, S->t32,
+                                S->cb, S->P, 0, 0);
+        launch_z<float, false, false>(S->z32, S->fmt_z, S->g_z, S->stream, (const float *)S->t32,
+                                      (const float *)nullptr, S->tmp32, S->cb, S->P, 0, 0);
         k_convert<float, double><<<gc, kBS, 0, S->stream>>>((int)S->n, S->t32, t_dev);
         k_convert<float, double><<<gc, kBS, 0, S->stream>>>((int)S->n, S->tmp32, s_dev);
     }
@@ -872,57 +946,118 @@ int pcga_apply_prec(pcga_solver_t *S, const double *r_dev, double *t_dev, double
     return PCGA_OK;
 }
 
-int pcga_profile_iteration(pcga_solver_t *S, const double *b_dev, int32_t reps, double *ms_out) {
-    if (!S || !b_dev || !ms_out || reps < 1 || reps > 100000)
+int pcga_profile_iteration(pcga_solver_t *S, const double *b_dev, int32_t reps, int32_t mode,
+                           double *ms_out) {
+    if (!S || !b_dev || !ms_out || reps < 1 || reps > 100000 || (mode != 0 && mode != 1))
         return fail(PCGA_EINVAL, "bad profile arguments");
     HIP_TRY(hipSetDevice(S->device));
     pcga_solver &R = *S;
     const int big = INT32_MAX;
     int st;
     // start state: x0 = 0, tolerance 0 so that no kernel stops early
-    if (R.precision == PCGA_FP64) {
-        HIP_TRY(hipMemsetAsync(R.x, 0, R.n * sizeof(double), R.stream));
-        launch_residual_prologue(R, R.x, b_dev, R.r[0], 0.0, big);
-        if ((st = prologue_prec<double>(R, bufs64(R)))) return st;
-    } else {
+    auto prologue = [&]() -> int {
+        if (R.precision == PCGA_FP64) {
+            HIP_TRY(hipMemsetAsync(R.x, 0, R.n * sizeof(double), R.stream));
+            launch_residual_prologue(R, R.x, b_dev, R.r[0], 0.0, big);
+            return prologue_prec<double>(R, bufs64(R));
+        }
         HIP_TRY(hipMemsetAsync(R.x64[0], 0, R.n * sizeof(double), R.stream));
         launch_refine(R, false, R.x64[0], nullptr, b_dev, 0.0, big);
         HIP_TRY(hipMemsetAsync(R.e32, 0, R.n * sizeof(float), R.stream));
-        if ((st = prologue_prec<float>(R, bufs32(R)))) return st;
-    }
-    std::vector<hipEvent_t> ev(3 * (size_t)reps + 1, nullptr);
+        return prologue_prec<float>(R, bufs32(R));
+    };
+    if ((st = prologue())) return st;
+    const int nev = mode == 0 ? 2 : 3 * reps + 1;
+    std::vector<hipEvent_t> ev(nev, nullptr);
     for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
-    auto cleanup = [&]() { for (auto &e : ev) (void)hipEventDestroy(e); };
-    auto run = [&](auto B) -> hipError_t {
-        using T = std::remove_pointer_t<decltype(B.x)>;
-        hipError_t e = hipEventRecord(ev[0], R.stream);
-        for (int i = 0; i < reps && e == hipSuccess; i++)
-            for (int w = 0; w < 3 && e == hipSuccess; w++) {
-                launch_kernel<T>(R, B, i & 1, w);
-                e = hipEventRecord(ev[3 * i + w + 1], R.stream);
-            }
-        if (e == hipSuccess) e = hipGetLastError();
-        if (e == hipSuccess) e = hipStreamSynchronize(R.stream);
+    hipGraphExec_t gx = nullptr;
+    auto cleanup = [&]() {
+        if (gx) (void)hipGraphExecDestroy(gx);
+        gx = nullptr;
+        for (auto &e : ev) (void)hipEventDestroy(e);
+    };
+    // Run `body` once to warm up and once between events ev[first], ev[last];
+    // from a captured graph when the solver replays its chunks that way.
+    // With `inner`, body records its own events (direct launches only).
+    auto timed = [&](auto body, bool inner) -> hipError_t {
+        hipError_t e = hipSuccess;
+        if (R.use_graph && !inner) {
+            hipGraph_t g = nullptr;
+            if ((e = hipStreamBeginCapture(R.stream, hipStreamCaptureModeThreadLocal))) return e;
+            body(false);
+            if ((e = hipStreamEndCapture(R.stream, &g))) return e;
+            e = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e) return e;
+            if ((e = hipGraphLaunch(gx, R.stream))) return e;   // warm
+            if ((e = hipEventRecord(ev.front(), R.stream))) return e;
+            if ((e = hipGraphLaunch(gx, R.stream))) return e;
+            if ((e = hipEventRecord(ev.back(), R.stream))) return e;
+        } else {
+            body(false);   // warm
+            if (!inner && (e = hipEventRecord(ev.front(), R.stream))) return e;
+            body(inner);
+            if (!inner && (e = hipEventRecord(ev.back(), R.stream))) return e;
+        }
+        if ((e = hipGetLastError())) return e;
+        if ((e = hipStreamSynchronize(R.stream))) return e;
+        if (gx) {
+            (void)hipGraphExecDestroy(gx);
+            gx = nullptr;
+        }
+        return hipSuccess;
+    };
+    auto elapsed = [&](int a, int b, double &ms) -> hipError_t {
+        float f = 0.f;
+        const hipError_t e = hipEventElapsedTime(&f, ev[a], ev[b]);
+        ms = f;
         return e;
     };
-    hipError_t e = (R.precision == PCGA_FP64) ? run(bufs64(R)) : run(bufs32(R));
-    if (e != hipSuccess) {
-        cleanup();
-        return fail(PCGA_EHIP, std::string("profile: ") + hipGetErrorString(e));
-    }
-    double acc[3] = {0, 0, 0};
-    for (int i = 0; i < reps; i++)
-        for (int kk = 0; kk < 3; kk++) {
-            float ms = 0.f;
-            e = hipEventElapsedTime(&ms, ev[3 * i + kk], ev[3 * i + kk + 1]);
-            if (e != hipSuccess) {
-                cleanup();
-                return fail(PCGA_EHIP, std::string("profile: ") + hipGetErrorString(e));
+    auto run = [&](auto B) -> hipError_t {
+        using T = std::remove_pointer_t<decltype(B.x)>;
+        hipError_t e;
+        double ms = 0.0;
+        if (mode == 0) {
+            // each kernel alone, `reps` launches back to back (inputs stay
+            // valid for every repetition: the stencil reads the prologue's
+            // (s,r) partials, the residual update the last stencil's (d,q)
+            // partials, and no stopping test can fire at tol 0)
+            for (int w = 0; w < 3; w++) {
+                e = timed([&](bool) { for (int i = 0; i < reps; i++) launch_kernel<T>(R, B, i & 1, w); },
+                          false);
+                if (e || (e = elapsed(0, 1, ms))) return e;
+                ms_out[w] = ms / reps;
             }
-            acc[kk] += ms;
+        } else {
+            // `reps` whole iterations with an event between every two kernels
+            // (direct launches): each kernel sees the cache state of a solve
+            e = timed([&](bool rec) {
+                for (int i = 0; i < reps; i++)
+                    for (int w = 0; w < 3; w++) {
+                        if (rec) (void)hipEventRecord(ev[3 * i + w], R.stream);
+                        launch_kernel<T>(R, B, i & 1, w);
+                    }
+                if (rec) (void)hipEventRecord(ev[3 * reps], R.stream);
+            }, true);
+            if (e) return e;
+            double acc[3] = {0, 0, 0};
+            for (int i = 0; i < reps; i++)
+                for (int w = 0; w < 3; w++) {
+                    if ((e = elapsed(3 * i + w, 3 * i + w + 1, ms))) return e;
+                    acc[w] += ms;
+                }
+            for (int w = 0; w < 3; w++) ms_out[w] = acc[w] / reps;
         }
+        // whole iterations without events, launched as in a solve
+        if (prologue()) return hipErrorUnknown;
+        e = timed([&](bool) { launch_iters<T>(R, B, reps); }, false);
+        if (e || (e = elapsed(0, nev - 1, ms))) return e;
+        ms_out[3] = ms / reps;
+        return hipSuccess;
+    };
+    const hipError_t e = (R.precision == PCGA_FP64) ? run(bufs64(R)) : run(bufs32(R));
     cleanup();
-    for (int kk = 0; kk < 3; kk++) ms_out[kk] = acc[kk] / reps;
+    if (e != hipSuccess) return fail(PCGA_EHIP, std::string("profile: ") + hipGetErrorString(e));
     return PCGA_OK;
 }
 

@@ -127,6 +127,47 @@ class Server:
     def batch_capacity(self):
         return self.max_slots
 
+    def saturate(self, seconds, make_rhs, on_done=None, clock=time.perf_counter, poll_chunks=1):
+        """Closed loop: every grid always has one time step in flight (the next
+        is submitted as soon as the previous is back) until `seconds` have
+        passed; then the steps in flight are drained.  Returns the finished
+        requests and the elapsed time; completions per grid over the elapsed
+        time are the grids' saturated throughputs."""
+        t0 = clock()
+        slots = {}
+        done = []
+        rid = [0]
+
+        def submit(g):
+            now = clock() - t0
+            req = Request(rid=rid[0], grid=g, arrival=now)
+            rid[0] += 1
+            make_rhs(req)
+            slots[self.admit(req, clock() - t0)] = req
+
+        for g in range(len(self.solvers)):
+            submit(g)
+        while slots:
+            self.batch.run(poll_chunks)
+            for s in list(slots):
+                if not self.batch.query(s)["done"]:
+                    continue
+                X, q = self.batch.remove(s)
+                req = slots.pop(s)
+                req.finished = clock() - t0
+                req.status = q["status"]
+                req.true_relres = q["true_relres"][0]
+                req.outer, req.inner = q["outer"], q["inner_total"]
+                req.x = X[0]
+                self.busy[req.grid] = False
+                self.in_flight_bytes -= self.item_bytes[req.grid]
+                done.append(req)
+                if on_done:
+                    on_done(req)
+                if req.finished < seconds:
+                    submit(req.grid)
+        return done, clock() - t0
+
 
 def poisson_arrivals(rate, count, n_grids, seed):
     """Seeded Poisson process: exponential gaps at `rate` per second, grids
@@ -135,6 +176,22 @@ def poisson_arrivals(rate, count, n_grids, seed):
     t = np.cumsum(rng.exponential(1.0 / rate, size=count))
     g = rng.integers(0, n_grids, size=count)
     return [Request(rid=i, grid=int(g[i]), arrival=float(t[i])) for i in range(count)]
+
+
+def poisson_arrivals_per_grid(rates, horizon, seed):
+    """Independent seeded Poisson processes, one per grid (rates[g] per
+    second), over [0, horizon) seconds; merged in arrival order."""
+    rng = np.random.default_rng(seed)
+    ev = []
+    for g, lam in enumerate(rates):
+        t = 0.0
+        while lam > 0:
+            t += rng.exponential(1.0 / lam)
+            if t >= horizon:
+                break
+            ev.append((t, g))
+    ev.sort()
+    return [Request(rid=i, grid=g, arrival=t) for i, (t, g) in enumerate(ev)]
 
 
 class TimeStepper:

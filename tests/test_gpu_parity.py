@@ -97,6 +97,45 @@ def test_apply_prec(pkg, ora, name, prec):
     assert np.all(np.abs(s - s_ref) <= 2 * width * u * s_mag + 1e-300)
 
 
+def test_wide_index_fallback(pkg, ora):
+    """Grid rows longer than 65535 cells put Z entries beyond a 16-bit
+    distance from their row: the solver keeps 32-bit columns there (and
+    16-bit distances on ordinary grids); both formats match the oracle."""
+    p = orca.box_problem(70000, 3, seed=5)
+    q, tau = case("orca182x149")
+    A = pkg.Stencil5.from_problem(p)
+    G = pkg.ainv_setup(A, 0.1)
+    F = ora.ainv_setup(p, 0.1)
+    assert int(np.max(np.arange(p.n).repeat(np.diff(F.colptr)) - F.rowidx)) > 65535
+    S = pkg.Solver(A, G, "fp64")
+    say("wide index fallback: index bytes", S.index_bytes)
+    assert S.index_bytes == 4
+    Aq = pkg.Stencil5.from_problem(q)
+    assert pkg.Solver(Aq, pkg.ainv_setup(Aq, tau), "fp64").index_bytes == 2
+    assert pkg.Solver(Aq, pkg.ainv_setup(Aq, tau), "mixed").index_bytes == 2
+    r = np.random.default_rng(13).standard_normal(p.n)
+    t, s = S.apply_prec(dev(r))
+    t_ref = ora.zt_apply(F, r)
+    s_ref = ora.z_apply(F, t_ref)
+    Fa = ora.AInv(F.n, F.colptr, F.rowidx, np.abs(F.val), F.D)
+    t_mag = ora.zt_apply(Fa, np.abs(r))
+    s_mag = ora.z_apply(Fa, t_mag)
+    width = max(8, int(np.diff(F.colptr).max()) + 2)
+    assert np.all(np.abs(t.cpu().numpy() - t_ref) <= width * 4 * EPS * t_mag + 1e-300)
+    assert np.all(np.abs(s.cpu().numpy() - s_ref) <= 2 * width * 4 * EPS * s_mag + 1e-300)
+    K = 30
+    g = S.solve(dev(p.b), tol=0.0, maxit=K)
+    o = ora.pcg(p, F, tol=0.0, maxit=K)
+    assert g.iters == o.iters == K
+    assert np.linalg.norm(g.x.cpu().numpy() - o.x) <= 1e-9 * np.linalg.norm(o.x)
+    Sm = pkg.Solver(A, G, "mixed")
+    assert Sm.index_bytes == 4
+    tm, sm = Sm.apply_prec(dev(r))
+    u32 = 4 * np.finfo(np.float32).eps
+    assert np.all(np.abs(tm.cpu().numpy() - t_ref) <= width * u32 * t_mag + 1e-300)
+    assert np.all(np.abs(sm.cpu().numpy() - s_ref) <= 2 * width * u32 * s_mag + 1e-300)
+
+
 def _solve_pair(pkg, ora, p, tau, tol, maxit=None, x0=None, b=None):
     A = pkg.Stencil5.from_problem(p)
     G = pkg.ainv_setup(A, tau)

@@ -80,3 +80,24 @@ def test_admission_by_footprint(setup):
     done = srv.run(reqs, make_rhs=stepper, on_done=stepper.done)
     assert len(done) == 6 and all(r.status == 0 for r in done)
     assert peak[0] <= srv.budget
+
+
+def test_saturate_closed_loop(setup, ora):
+    P, serve, probs = setup
+    say("closed loop: every grid keeps one step in flight")
+    srv = serve.Server(probs, drop_tol=0.1, device="cuda", chunk=8)
+    stepper = serve.TimeStepper(probs, torch.device("cuda"), seed=5)
+    done, el = srv.saturate(0.3, make_rhs=stepper, on_done=stepper.done)
+    per = [sum(1 for r in done if r.grid == g) for g in range(len(probs))]
+    say("  completions per grid", per, "in", round(el, 3), "s")
+    assert all(c >= 1 for c in per)
+    assert not srv.busy.count(True) and srv.in_flight_bytes == 0
+    for r in done:
+        p = probs[r.grid]
+        b, x = r.b.cpu().numpy(), r.x.cpu().numpy()
+        assert r.status == 0
+        assert np.linalg.norm(b - ora.spmv(p, x)) / np.linalg.norm(b) <= 1e-10
+    # steps of one grid never overlap
+    for g in range(len(probs)):
+        rs = sorted((r for r in done if r.grid == g), key=lambda r: r.admitted)
+        assert all(a.finished <= b.admitted for a, b in zip(rs, rs[1:]))
