@@ -191,8 +191,9 @@ int pcga_apply_prec(pcga_solver_t *S, const double *r_dev, double *t_dev, double
 
 /* Average device time in milliseconds of each kernel of one PCG iteration,
  * ms_out[0] = d-update + five-point product + (d,q); ms_out[1] = residual and
- * solution update + D^-1 Z^T r; ms_out[2] = Z t + (s,r); ms_out[3] = one
- * whole iteration.  Starts from the prologue of a solve from x0 = 0; no
+ * solution update + D^-1 Z^T r; ms_out[2] = Z t + (s,r) (0 with the
+ * diagonal preconditioner, whose second kernel also applies D^-1); ms_out[3]
+ * = one whole iteration.  Starts from the prologue of a solve from x0 = 0; no
  * stopping test fires.  mode 0: each kernel launched `reps` (1..100000)
  * times back to back between two HIP events (data a kernel re-reads may stay
  * cached between its launches).  mode 1: `reps` whole iterations with a HIP

@@ -396,17 +396,41 @@ __device__ __forceinline__ bool sell_stream(const DevSell<T> &M, int first, int 
 template <typename T>
 struct PipeUnroll { static constexpr int U = sizeof(T) == 8 ? PCGA_PIPE_UD : PCGA_PIPE_UF; };
 
+// Stopping test of Algorithm 1 on ||r_k||^2 = rr (every workgroup computes
+// the same): history entry k, and the solve ends when ||r_k|| / ||b|| <= tol,
+// k reaches maxit, or the norm is not finite.  Returns whether it stopped.
+__device__ __forceinline__ bool stop_test(CtlBlock *cb, double rr, int k) {
+    Ctl *c = &cb->c;
+    const double rel = sqrt(rr) / c->nb;
+    const bool bad = is_bad(rel);
+    const bool conv = !bad && rel <= c->tol;
+    const bool stop = bad || conv || k >= c->maxit;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        c->k = k;
+        c->relres = rel;
+        cb->hist[k & (kHistRing - 1)] = rel;
+        if (stop) {
+            c->status = bad ? kStNan : (conv ? kStOk : kStNoconv);
+            c->done = 1;
+        }
+    }
+    return stop;
+}
+
 // ---------------------------------------------------------------------------
 // k_stencil: rho_k, beta; d_new = s + beta d_old; q = A d_new; (d_new,q) partials
 // par = k & 1 (fixed per position in a captured chunk; chunks are even).
 // ---------------------------------------------------------------------------
-template <typename T>
+// STOP (diagonal preconditioner path, two launches per iteration): the stop
+// test on ||r_k|| from the previous k_jacobi's partials runs here first.
+template <typename T, bool STOP>
 __global__ __launch_bounds__(kBS) void k_stencil(DevOp<T> A, const T *__restrict__ s,
                                                  const T *__restrict__ dold,
                                                  T *__restrict__ dnew, T *__restrict__ q,
                                                  CtlBlock *cb, Partials P, int g_sr, int par) {
     Ctl *c = &cb->c;
     if (c->done) return;
+    const PartialsLoad<1> pr = load_partials<1>(P.rr, STOP ? g_sr : 0);
     const int G = gridDim.x, L = logical_block(blockIdx.x, G);
     // Operands of kCPT cells per thread per step: every load of a step is issued
     // before any arithmetic (branch-free neighbour indices, clamped cells).
@@ -436,10 +460,15 @@ __global__ __launch_bounds__(kBS) void k_stencil(DevOp<T> A, const T *__restrict
     Step st;
     load_step(base, st);   // in flight during the reduction (clamped, also for an empty range)
     __builtin_amdgcn_sched_barrier(0);   // keep every load above the partials' first use
+    const int k = c->kk[par];
+    if (STOP && k > 0) {
+        double rr[1];
+        reduce_partials<1>(pr, g_sr, rr);
+        if (stop_test(cb, rr[0], k)) return;
+    }
     double rs[1];
     reduce_partials<1>(pl, g_sr, rs);
     const double rho = rs[0];
-    const int k = c->kk[par];
     if (!finite_pos(rho)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             c->status = is_bad(rho) ? kStNan : kStBreak;
@@ -589,21 +618,8 @@ __global__ __launch_bounds__(kBS) void k_z(DevSell<T> Z, const T *__restrict__ t
         double rr[1];
         reduce_partials<1>(pl, g_rr, rr);
         const int k = c->kk[par] + 1;
-        const double rel = sqrt(rr[0]) / c->nb;
-        const bool bad = is_bad(rel);
-        const bool conv = !bad && rel <= c->tol;
-        const bool stop = bad || conv || k >= c->maxit;
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            c->kk[par ^ 1] = k;
-            c->k = k;
-            c->relres = rel;
-            cb->hist[k & (kHistRing - 1)] = rel;
-            if (stop) {
-                c->status = bad ? kStNan : (conv ? kStOk : kStNoconv);
-                c->done = 1;
-            }
-        }
-        return !stop;
+        if (blockIdx.x == 0 && threadIdx.x == 0) c->kk[par ^ 1] = k;
+        return !stop_test(cb, rr[0], k);
     };
     const int nsw = (s1 - s0 - w + kWavesPerBlock - 1) / kWavesPerBlock;   // this wave's slices
     if (!sell_stream<T, PipeUnroll<T>::U, FMT, false>(Z, s0 + w, nsw, lane, g, ownf, epi, pre))
@@ -611,6 +627,79 @@ __global__ __launch_bounds__(kBS) void k_z(DevSell<T> Z, const T *__restrict__ t
     if (DOT) {
         double pv[1] = {sr};
         put_partials<1>(pv, P.sr, L);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_jacobi (diagonal preconditioner, Z = I): alpha = rho_k / (d,q);
+// r' = r - alpha q; x += alpha d; s = D^-1 r'; ||r'||^2 and (s, r') partials;
+// iteration count k + 1.  With k_stencil<STOP> it makes a two-launch
+// iteration of the same Algorithm 1 (t = s needs no separate pass).
+// FIRST (prologue): s0 = D^-1 r0 and the (s0, r0) partials only.
+// ---------------------------------------------------------------------------
+template <typename T, bool FIRST>
+__global__ __launch_bounds__(kBS) void k_jacobi(const T *__restrict__ dinv,
+                                                const T *__restrict__ rcur,
+                                                const T *__restrict__ q,
+                                                const T *__restrict__ dcur, T *__restrict__ rnext,
+                                                T *__restrict__ x, T *__restrict__ s, int n,
+                                                CtlBlock *cb, Partials P, int g_dq, int par) {
+    Ctl *c = &cb->c;
+    if (!FIRST && c->done) return;
+    const PartialsLoad<1> pl = load_partials<1>(P.dq, FIRST ? 0 : g_dq);
+    const int G = gridDim.x, L = logical_block(blockIdx.x, G);
+    int c0, c1;
+    range_of(L, G, n, c0, c1);
+    int k0 = c0 + threadIdx.x;
+    const int kc = k0 < c1 ? k0 : (c1 > 0 ? c1 - 1 : 0);
+    T rv = rcur[kc], iv = dinv[kc];
+    T qv = FIRST ? T(0) : q[kc], dv = FIRST ? T(0) : dcur[kc], xv = FIRST ? T(0) : x[kc];
+    __builtin_amdgcn_sched_barrier(0);   // the loads above stay ahead of the reduction
+    T at = T(0);
+    if (!FIRST) {
+        double dq[1];
+        reduce_partials<1>(pl, g_dq, dq);
+        if (!finite_pos(dq[0])) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                c->status = is_bad(dq[0]) ? kStNan : kStBreak;
+                c->done = 1;
+            }
+            return;
+        }
+        const double alpha = c->rho[par] / dq[0];
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            c->alpha = alpha;
+            c->kk[par ^ 1] = c->kk[par] + 1;
+        }
+        at = (T)alpha;
+    }
+    double rr = 0.0, sr = 0.0;
+    for (; k0 < c1; k0 += kBS) {
+        const T rj = FIRST ? rv : fma(-at, qv, rv);
+        const T sj = rj * iv;
+        if (!FIRST) {
+            rnext[k0] = rj;
+            x[k0] = fma(at, dv, xv);
+        }
+        s[k0] = sj;
+        rr += (double)rj * (double)rj;
+        sr += (double)sj * (double)rj;
+        const int kn = k0 + kBS;
+        if (kn < c1) {
+            rv = rcur[kn];
+            iv = dinv[kn];
+            if (!FIRST) {
+                qv = q[kn];
+                dv = dcur[kn];
+                xv = x[kn];
+            }
+        }
+    }
+    double pv[2] = {rr, sr};
+    block_sum_all<2>(pv);
+    if (threadIdx.x == 0) {
+        P.rr[L] = pv[0];
+        P.sr[L] = pv[1];
     }
 }
 

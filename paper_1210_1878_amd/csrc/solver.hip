@@ -431,6 +431,7 @@ int pcga_solver_create(const pcga_a5_t *A, const pcga_ainv_t *F, int precision, 
     S->precision = precision;
     S->n = n;
     S->nnz_off = F->F.nnz_off();
+    S->jacobi = S->nnz_off == 0;
     S->nx = A->nx;
     S->ny = A->ny;
     S->periodic = (A->flags & PCGA_PERIODIC_X) ? 1 : 0;
@@ -653,10 +654,20 @@ template <typename T>
 void launch_kernel(pcga_solver &S, const IterBufs<T> &B, int p, int which) {
     switch (which) {
         case 0:
-            k_stencil<T><<<S.g_st, kBS, 0, S.stream>>>(B.A, B.s, B.d[p], B.d[p ^ 1], B.q, S.cb, S.P,
-                                                       S.g_z, p);
+            if (S.jacobi)
+                k_stencil<T, true><<<S.g_st, kBS, 0, S.stream>>>(B.A, B.s, B.d[p], B.d[p ^ 1], B.q,
+                                                                 S.cb, S.P, S.g_st, p);
+            else
+                k_stencil<T, false><<<S.g_st, kBS, 0, S.stream>>>(B.A, B.s, B.d[p], B.d[p ^ 1], B.q,
+                                                                  S.cb, S.P, S.g_z, p);
             break;
         case 1:
+            if (S.jacobi) {
+                k_jacobi<T, false><<<S.g_st, kBS, 0, S.stream>>>(
+                    B.dinv, B.r[p], B.q, B.d[p ^ 1], B.r[p ^ 1], B.x, B.s, (int)S.n, S.cb, S.P,
+                    S.g_st, p);
+                break;
+            }
             launch_zt<T, true>(B.zt, S.fmt_zt, S.g_zt, S.stream, B.dinv, (const T *)B.r[p], (const T *)B.q,
                                (const T *)B.d[p ^ 1], B.r[p ^ 1], B.x, B.t, S.cb, S.P, S.g_st, p);
             break;
@@ -670,7 +681,7 @@ void launch_kernel(pcga_solver &S, const IterBufs<T> &B, int p, int which) {
 template <typename T>
 void launch_iters(pcga_solver &S, const IterBufs<T> &B, int count) {
     for (int it = 0; it < count; it++)
-        for (int w = 0; w < 3; w++) launch_kernel<T>(S, B, it & 1, w);
+        for (int w = 0; w < S.kernels_per_iter(); w++) launch_kernel<T>(S, B, it & 1, w);
 }
 
 // r0 = b - A x0 (FP64) and the solve's control state.
@@ -698,6 +709,12 @@ void launch_refine(pcga_solver &S, bool add_e, const double *x, double *xnew, co
 template <typename T>
 int prologue_prec(pcga_solver &S, const IterBufs<T> &B) {
     HIP_TRY(hipMemsetAsync(B.d[0], 0, S.n * sizeof(T), S.stream));
+    if (S.jacobi) {
+        k_jacobi<T, true><<<S.g_st, kBS, 0, S.stream>>>(B.dinv, B.r[0], nullptr, nullptr, nullptr,
+                                                        nullptr, B.s, (int)S.n, S.cb, S.P, 0, 0);
+        HIP_TRY(hipGetLastError());
+        return PCGA_OK;
+    }
     launch_zt<T, false>(B.zt, S.fmt_zt, S.g_zt, S.stream, B.dinv, (const T *)B.r[0], (const T *)nullptr,
                         (const T *)nullptr, (T *)nullptr, (T *)nullptr, B.t, S.cb, S.P, 0, 0);
     launch_z<T, true, true>(B.z, S.fmt_z, S.g_z, S.stream, (const T *)B.t, (const T *)B.r[0], B.s, S.cb,
@@ -967,7 +984,9 @@ int pcga_profile_iteration(pcga_solver_t *S, const double *b_dev, int32_t reps, 
         return prologue_prec<float>(R, bufs32(R));
     };
     if ((st = prologue())) return st;
-    const int nev = mode == 0 ? 2 : 3 * reps + 1;
+    const int nk = R.kernels_per_iter();   // 2 with the diagonal preconditioner
+    const int nev = mode == 0 ? 2 : nk * reps + 1;
+    ms_out[2] = 0.0;
     std::vector<hipEvent_t> ev(nev, nullptr);
     for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
     hipGraphExec_t gx = nullptr;
@@ -1022,7 +1041,7 @@ int pcga_profile_iteration(pcga_solver_t *S, const double *b_dev, int32_t reps, 
             // valid for every repetition: the stencil reads the prologue's
             // (s,r) partials, the residual update the last stencil's (d,q)
             // partials, and no stopping test can fire at tol 0)
-            for (int w = 0; w < 3; w++) {
+            for (int w = 0; w < nk; w++) {
                 e = timed([&](bool) { for (int i = 0; i < reps; i++) launch_kernel<T>(R, B, i & 1, w); },
                           false);
                 if (e || (e = elapsed(0, 1, ms))) return e;
@@ -1033,20 +1052,20 @@ int pcga_profile_iteration(pcga_solver_t *S, const double *b_dev, int32_t reps, 
             // (direct launches): each kernel sees the cache state of a solve
             e = timed([&](bool rec) {
                 for (int i = 0; i < reps; i++)
-                    for (int w = 0; w < 3; w++) {
-                        if (rec) (void)hipEventRecord(ev[3 * i + w], R.stream);
+                    for (int w = 0; w < nk; w++) {
+                        if (rec) (void)hipEventRecord(ev[nk * i + w], R.stream);
                         launch_kernel<T>(R, B, i & 1, w);
                     }
-                if (rec) (void)hipEventRecord(ev[3 * reps], R.stream);
+                if (rec) (void)hipEventRecord(ev[nk * reps], R.stream);
             }, true);
             if (e) return e;
             double acc[3] = {0, 0, 0};
             for (int i = 0; i < reps; i++)
-                for (int w = 0; w < 3; w++) {
-                    if ((e = elapsed(3 * i + w, 3 * i + w + 1, ms))) return e;
+                for (int w = 0; w < nk; w++) {
+                    if ((e = elapsed(nk * i + w, nk * i + w + 1, ms))) return e;
                     acc[w] += ms;
                 }
-            for (int w = 0; w < 3; w++) ms_out[w] = acc[w] / reps;
+            for (int w = 0; w < nk; w++) ms_out[w] = acc[w] / reps;
         }
         // whole iterations without events, launched as in a solve
         if (prologue()) return hipErrorUnknown;

@@ -50,6 +50,10 @@ struct pcga_solver {
     int64_t sell_entries = 0;
     int index_bytes = 4;   // 2 when Z^T and Z use 16-bit distances
     int fmt_zt = 0, fmt_z = 0;   // storage/read format of Z^T and Z (kFmt* bits)
+    // Z = I (no stored off-diagonal entries: the diagonal preconditioner):
+    // two launches per iteration (k_stencil<STOP>, k_jacobi) instead of three
+    bool jacobi = false;
+    int kernels_per_iter() const { return jacobi ? 2 : 3; }
     std::vector<int32_t> cost_zt, cost_z;    // per-slice work estimates (host)
     int32_t *bnd_zt = nullptr, *bnd_z = nullptr;   // device: workgroup slice ranges
     int32_t *bnd_zt_b = nullptr, *bnd_z_b = nullptr;   // device: ranges for a batch slot

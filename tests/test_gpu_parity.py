@@ -301,6 +301,32 @@ def test_full_size_pcg(pkg, ora, orca025):
     assert true <= 1.05e-10
 
 
+def test_full_size_jacobi_two_launch_path(pkg, ora, orca025):
+    """The diagonal preconditioner (Z = I) runs two launches per iteration
+    (stencil with the stop test, fused update + D^-1): iterates match the
+    oracle's Algorithm 1 with (Z, D) = ainv_setup(A, inf), in FP64 and as the
+    FP32 inner solve of the mixed form."""
+    p, F, A, G = orca025
+    say("full size: diagonal preconditioner, 40 iterations matched")
+    Gj = pkg.ainv_setup(A, np.inf)
+    Fj = ora.ainv_setup(p, np.inf)
+    assert Gj.nnz_off == 0
+    S = pkg.Solver(A, Gj, "fp64")
+    g = S.solve(dev(p.b), tol=0.0, maxit=40)
+    o = ora.pcg(p, Fj, tol=0.0, maxit=40)
+    assert g.iters == o.iters == 40
+    assert np.linalg.norm(g.x.cpu().numpy() - o.x) <= 1e-9 * np.linalg.norm(o.x)
+    assert np.allclose(g.hist, o.hist, rtol=1e-9)
+    ms = S.profile_iteration(dev(p.b), reps=4)
+    assert ms[2] == 0.0 and ms[0] > 0 and ms[1] > 0 and ms[3] > 0
+    Sm = pkg.Solver(A, Gj, "mixed")
+    m = Sm.solve_mixed(dev(p.b), tol=1e-8, inner_tol=1e-3, max_outer=20)
+    say("  mixed: outer", m.outer, "inner", m.inner_total, "true", m.true_relres)
+    assert m.status == 0
+    x = m.x.cpu().numpy()
+    assert np.linalg.norm(p.b - ora.spmv(p, x)) / np.linalg.norm(p.b) <= 1e-8
+
+
 def test_full_size_mixed(pkg, ora, orca025):
     p, F, A, G = orca025
     say("full size: mixed precision")
