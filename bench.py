@@ -35,7 +35,7 @@ def kernel_names(word, formats):
     """Iteration kernels as rocprofv3 names them (template arguments: value
     type, fused/dot flags, storage/read format of Z^T and Z)."""
     t = "double" if word == 8 else "float"
-    return {"stencil": f"k_stencil<{t}>", "axpy_zt": f"k_zt<{t}, true, {formats[0]}>",
+    return {"stencil": f"k_stencil<{t}, false>", "axpy_zt": f"k_zt<{t}, true, {formats[0]}>",
             "z_dot": f"k_z<{t}, true, false, {formats[1]}>"}
 
 
@@ -158,7 +158,6 @@ def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=
     saturated throughput c_g.  Then, per load factor L, independent Poisson
     arrivals per grid at rate L * c_g over a fixed horizon; latency is arrival
     to solution."""
-    import numpy as np
     from gen import orca
     from paper_1210_1878_amd import serve
     shapes = [(182, 149), (182, 149), (362, 292), (362, 292), (721, 510), (721, 510),
@@ -181,6 +180,9 @@ def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=
                        "continuous batching; per-grid Poisson arrivals at a load factor of "
                        "each grid's closed-loop throughput",
            "grids": [f"{a}x{b}" for a, b in shapes],
+           "size_classes": "class 0: grids under 2M cells, class 1: the 4322x3059 grid; one "
+                           "batch per class, each on its own stream, running concurrently",
+           "grid_class": srv.klass,
            "capacity_solves_per_s": round(sum(cap), 2),
            "capacity_per_grid": [round(c, 3) for c in cap],
            "capacity_worst_true_relres": float(max(r.true_relres for r in done)),
@@ -189,12 +191,12 @@ def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=
         reqs = serve.poisson_arrivals_per_grid([L * c for c in cap], horizon_s,
                                                seed=CONFIG_SERVE_SEED + 1 + i)
         res = srv.run(reqs, make_rhs=stepper, on_done=stepper.done)
-        st = serve.latency_stats(res)
-        big = [r.latency * 1e3 for r in res if r.grid == len(shapes) - 1]
-        st["p50_ms_largest_grid"] = float(np.median(big)) if big else None
+        st = serve.latency_stats(res, srv.klass)
         log(f"load {L:.2f}: {st['requests']} requests, p50 {st['p50_ms']:.1f} ms, "
             f"p99 {st['p99_ms']:.1f} ms, {st['solves_per_s']:.2f} solves/s, "
-            f"worst true relres {st['worst_true_relres']:.2e}")
+            f"worst true relres {st['worst_true_relres']:.2e}; per size class "
+            + ", ".join(f"{k}: {v['requests']} req p50 {v['p50_ms']:.0f} p99 {v['p99_ms']:.0f} ms"
+                        for k, v in st["per_class"].items()))
         out["loads"][str(L)] = st
     return out
 

@@ -245,6 +245,18 @@ int pcga_batch_add(pcga_batch_t *B, pcga_solver_t *S, int32_t nrhs, const double
  * done); *active receives the number of items not yet done. */
 int pcga_batch_run(pcga_batch_t *B, int32_t chunks, int32_t *active);
 
+/* Asynchronous form of pcga_batch_run, for callers that advance several
+ * batches (each on its own stream) from one thread.  pcga_batch_launch
+ * enqueues `chunks` chunks and the control-block snapshot on the batch's
+ * stream and returns at once.  pcga_batch_wait then waits for them (block =
+ * 1) or only checks (block = 0): *ready = 1 once they have finished (then
+ * *active is set as by pcga_batch_run and the snapshot that pcga_batch_query
+ * reads is current), 0 while they run.  While a launch is in flight,
+ * pcga_batch_launch, _add, _remove, _query and _set_chunk on that batch
+ * return PCGA_EINVAL.  Errors: EINVAL, EHIP. */
+int pcga_batch_launch(pcga_batch_t *B, int32_t chunks);
+int pcga_batch_wait(pcga_batch_t *B, int32_t block, int32_t *ready, int32_t *active);
+
 /* Item results as of the last pcga_batch_run: done flag, status (PCGA_OK,
  * PCGA_NOCONV, PCGA_EBREAKDOWN, PCGA_ENAN), outer steps, inner iterations,
  * and true_relres[r] = ||b_r - A x_r|| / ||b_r|| (FP64) for r < nrhs. */

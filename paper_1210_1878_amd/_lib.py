@@ -67,6 +67,8 @@ _SIGS = {
     "pcga_batch_add": ([_p, _p, _i32, _p, _p, _p, _p, _sz, _dbl, _dbl, _i32, _i32, _pi32],
                        ctypes.c_int),
     "pcga_batch_run": ([_p, _i32, _pi32], ctypes.c_int),
+    "pcga_batch_launch": ([_p, _i32], ctypes.c_int),
+    "pcga_batch_wait": ([_p, _i32, _pi32, _pi32], ctypes.c_int),
     "pcga_batch_query": ([_p, _i32, _pi32, _pi32, _pi32, _pi32, _pdbl], ctypes.c_int),
     "pcga_batch_remove": ([_p, _i32], ctypes.c_int),
     "pcga_batch_set_chunk": ([_p, _i32], ctypes.c_int),

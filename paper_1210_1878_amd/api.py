@@ -351,6 +351,18 @@ class Batch:
         check(_lib.load().pcga_batch_run(self._h, int(chunks), ctypes.byref(active)), "pcga_batch_run")
         return active.value
 
+    def launch(self, chunks=1):
+        """Enqueue `chunks` chunks on the batch's stream without waiting."""
+        check(_lib.load().pcga_batch_launch(self._h, int(chunks)), "pcga_batch_launch")
+
+    def wait(self, block=True):
+        """Wait for (block) or check on the last launch: (ready, active items)."""
+        ready = ctypes.c_int32()
+        active = ctypes.c_int32()
+        check(_lib.load().pcga_batch_wait(self._h, int(bool(block)), ctypes.byref(ready),
+                                          ctypes.byref(active)), "pcga_batch_wait")
+        return bool(ready.value), active.value
+
     def query(self, slot):
         it = self.items[slot]
         done, st, outer, inner = (ctypes.c_int32() for _ in range(4))

@@ -749,6 +749,7 @@ struct pcga_batch {
     hipGraphExec_t graph = nullptr;
     int graph_chunk = 0;
     int64_t iterations = 0;
+    bool in_flight = false;           // chunks launched, snapshot not yet consumed
 };
 
 namespace {
@@ -905,6 +906,7 @@ int pcga_batch_add(pcga_batch_t *B, pcga_solver_t *S, int32_t nrhs, const double
                    const double *const *x0_dev, double *const *x_out_dev, void *item_ws,
                    size_t item_bytes, double tol, double inner_tol, int32_t max_outer,
                    int32_t inner_maxit, int32_t *slot) {
+    if (B && B->in_flight) return fail(PCGA_EINVAL, "a launch of this batch is still in flight");
     if (!B || !S || !b_dev || !x0_dev || !x_out_dev || !item_ws || !slot)
         return fail(PCGA_EINVAL, "NULL argument");
     if (S->precision != PCGA_MIXED) return fail(PCGA_EINVAL, "batch items need PCGA_MIXED solvers");
@@ -982,8 +984,9 @@ int pcga_batch_add(pcga_batch_t *B, pcga_solver_t *S, int32_t nrhs, const double
 // Run `chunks` chunks of `chunk` graph iterations (or until every slot is
 // done), then snapshot every slot's control block.  *active receives the
 // number of slots still running.
-int pcga_batch_run(pcga_batch_t *B, int32_t chunks, int32_t *active) {
+int pcga_batch_launch(pcga_batch_t *B, int32_t chunks) {
     if (!B || chunks < 1) return fail(PCGA_EINVAL, "bad arguments");
+    if (B->in_flight) return fail(PCGA_EINVAL, "a launch of this batch is still in flight");
     int st;
     if (B->table_dirty && (st = rebuild_table(*B))) return st;
     if (!B->graph || B->graph_chunk != B->chunk) {
@@ -1003,22 +1006,47 @@ int pcga_batch_run(pcga_batch_t *B, int32_t chunks, int32_t *active) {
         }
         B->graph_chunk = B->chunk;
     }
-    int n_active = 0;
     for (int c = 0; c < chunks; c++) {
-        hipError_t e = hipGraphLaunch(B->graph, B->stream);
+        const hipError_t e = hipGraphLaunch(B->graph, B->stream);
         if (e != hipSuccess) return fail(PCGA_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
         B->iterations += B->chunk;
-        kb_gather_ctl<<<16, 256, 0, B->stream>>>(B->d_desc, B->max_slots, B->d_ctl);
-        e = hipGetLastError();
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(B->snap, B->d_ctl, B->max_slots * sizeof(SlotCtl), hipMemcpyDeviceToHost,
-                               B->stream);
-        if (e != hipSuccess) return fail(PCGA_EHIP, std::string("snapshot: ") + hipGetErrorString(e));
-        e = hipStreamSynchronize(B->stream);
-        if (e != hipSuccess) return fail(PCGA_EHIP, std::string("batch run: ") + hipGetErrorString(e));
-        n_active = 0;
-        for (int s = 0; s < B->max_slots; s++)
-            if (B->used[s] && !B->snap[s].done) n_active++;
+    }
+    kb_gather_ctl<<<16, 256, 0, B->stream>>>(B->d_desc, B->max_slots, B->d_ctl);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(B->snap, B->d_ctl, B->max_slots * sizeof(SlotCtl), hipMemcpyDeviceToHost,
+                           B->stream);
+    if (e == hipSuccess) e = hipEventRecord(B->ev, B->stream);
+    if (e != hipSuccess) return fail(PCGA_EHIP, std::string("snapshot: ") + hipGetErrorString(e));
+    B->in_flight = true;
+    return PCGA_OK;
+}
+
+int pcga_batch_wait(pcga_batch_t *B, int32_t block, int32_t *ready, int32_t *active) {
+    if (!B) return fail(PCGA_EINVAL, "B is NULL");
+    if (B->in_flight) {
+        const hipError_t e = block ? hipEventSynchronize(B->ev) : hipEventQuery(B->ev);
+        if (!block && e == hipErrorNotReady) {
+            if (ready) *ready = 0;
+            return PCGA_OK;
+        }
+        if (e != hipSuccess) return fail(PCGA_EHIP, std::string("batch wait: ") + hipGetErrorString(e));
+        B->in_flight = false;
+    }
+    int n_active = 0;
+    for (int s = 0; s < B->max_slots; s++)
+        if (B->used[s] && !B->snap[s].done) n_active++;
+    if (ready) *ready = 1;
+    if (active) *active = n_active;
+    return PCGA_OK;
+}
+
+int pcga_batch_run(pcga_batch_t *B, int32_t chunks, int32_t *active) {
+    if (!B || chunks < 1) return fail(PCGA_EINVAL, "bad arguments");
+    int n_active = 0, st;
+    for (int c = 0; c < chunks; c++) {
+        if ((st = pcga_batch_launch(B, 1))) return st;
+        if ((st = pcga_batch_wait(B, 1, nullptr, &n_active))) return st;
         if (n_active == 0) break;
     }
     if (active) *active = n_active;
@@ -1029,6 +1057,7 @@ int pcga_batch_run(pcga_batch_t *B, int32_t chunks, int32_t *active) {
 // and the per-right-hand-side relative true residuals.  done = 0 if running.
 int pcga_batch_query(pcga_batch_t *B, int32_t slot, int32_t *done, int32_t *status, int32_t *outer,
                      int32_t *inner_total, double *true_relres) {
+    if (B && B->in_flight) return fail(PCGA_EINVAL, "a launch of this batch is still in flight");
     if (!B || slot < 0 || slot >= B->max_slots || !B->used[slot]) return fail(PCGA_EINVAL, "bad slot");
     const SlotCtl &c = B->snap[slot];
     if (done) *done = c.done;
@@ -1049,6 +1078,7 @@ int pcga_batch_query(pcga_batch_t *B, int32_t slot, int32_t *done, int32_t *stat
 
 // Copy a slot's solution to its output vectors and free the slot.
 int pcga_batch_remove(pcga_batch_t *B, int32_t slot) {
+    if (B && B->in_flight) return fail(PCGA_EINVAL, "a launch of this batch is still in flight");
     if (!B || slot < 0 || slot >= B->max_slots || !B->used[slot]) return fail(PCGA_EINVAL, "bad slot");
     const SlotDesc &D = B->desc[slot];
     const int64_t n = D.A64.n;
@@ -1071,6 +1101,7 @@ int pcga_batch_remove(pcga_batch_t *B, int32_t slot) {
 }
 
 int pcga_batch_set_chunk(pcga_batch_t *B, int32_t chunk) {
+    if (B && B->in_flight) return fail(PCGA_EINVAL, "a launch of this batch is still in flight");
     if (!B || chunk < 2 || chunk > 512 || (chunk & 1)) return fail(PCGA_EINVAL, "chunk must be even, 2..512");
     B->chunk = chunk;
     return PCGA_OK;

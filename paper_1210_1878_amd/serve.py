@@ -4,11 +4,14 @@ Each request is one time step of one grid: a right-hand side and a warm
 start (the grid's previous solution, like the initial guess taken from the
 previous step in Algorithm 1).  Every grid's operator, D^-1 and Z stay
 resident on the device (one PCGA_MIXED solver per grid).  Requests are
-admitted into the running batch as soon as their grid is idle (time steps of
-one grid are sequential) and their vectors fit the device-memory budget; the
-batch advances all admitted requests together, so requests that arrive while
-others are iterating share the device with them.  Latency is measured from
-arrival to the moment the solution is back in the request's output tensor.
+admitted as soon as their grid is idle (time steps of one grid are
+sequential) and their vectors fit the device-memory budget.  Grids are split
+into size classes, each with its own batch on its own HIP stream: a batch
+advances all of its admitted requests together (one launch per kernel per
+step), and the classes run concurrently, so that steps of a very large grid
+do not hold back the many steps a small grid's solve needs.  Latency is
+measured from arrival to the moment the solution is back in the request's
+output tensor.
 """
 from __future__ import annotations
 
@@ -45,7 +48,7 @@ class Server:
     """Holds resident grids and serves time-step solves by continuous batching."""
 
     def __init__(self, problems, drop_tol=0.05, device=None, hbm_budget=None, max_slots=64,
-                 tol=1e-10, inner_tol=1e-5, max_outer=30, chunk=16):
+                 tol=1e-10, inner_tol=1e-5, max_outer=30, chunk=16, class_cells=(2_000_000,)):
         import torch
         self.torch = torch
         self.device = torch.device("cuda" if device is None else device)
@@ -60,7 +63,11 @@ class Server:
         self.item_bytes = [Batch.item_bytes(S, 1) for S in self.solvers]
         self.budget = hbm_budget            # bytes for in-flight request vectors (None: no limit)
         self.max_slots = max_slots
-        self.batch = Batch(max_slots=max_slots, device=self.device, chunk=chunk)
+        # size class of each grid: index of the first bound above its cell count
+        bounds = sorted(class_cells)
+        self.klass = [sum(1 for c in bounds if p.nx * p.ny >= c) for p in problems]
+        used = sorted(set(self.klass))
+        self.batches = {k: Batch(max_slots=max_slots, device=self.device, chunk=chunk) for k in used}
         self.in_flight_bytes = 0
         self.busy = [False] * len(self.solvers)
 
@@ -68,13 +75,45 @@ class Server:
         return self.budget is None or self.in_flight_bytes + self.item_bytes[grid] <= self.budget
 
     def admit(self, req, now):
-        slot = self.batch.add(self.solvers[req.grid], req.b.unsqueeze(0), X0=req.x0.unsqueeze(0),
-                              tol=self.tol, inner_tol=self.inner_tol, max_outer=self.max_outer,
-                              tag=req.rid)
+        k = self.klass[req.grid]
+        slot = self.batches[k].add(self.solvers[req.grid], req.b.unsqueeze(0),
+                                   X0=req.x0.unsqueeze(0), tol=self.tol,
+                                   inner_tol=self.inner_tol, max_outer=self.max_outer, tag=req.rid)
         self.in_flight_bytes += self.item_bytes[req.grid]
         self.busy[req.grid] = True
         req.admitted = now
-        return slot
+        return (k, slot)
+
+    def _advance(self, slots, poll_chunks):
+        """Launch every class batch that has work and no launch in flight, then
+        collect one that finished.  Returns the finished (key, req, X, q)."""
+        for k, B in self.batches.items():
+            if k not in self._flying and any(key[0] == k for key in slots):
+                B.launch(poll_chunks)
+                self._flying.add(k)
+        while True:
+            for k in list(self._flying):
+                ready, _ = self.batches[k].wait(block=False)
+                if not ready:
+                    continue
+                self._flying.discard(k)
+                out = []
+                for key in [key for key in slots if key[0] == k]:
+                    q = self.batches[k].query(key[1])
+                    if q["done"]:
+                        X, q = self.batches[k].remove(key[1])
+                        out.append((key, X, q))
+                return out
+            time.sleep(20e-6)
+
+    def _finish(self, req, X, q, now):
+        req.finished = now
+        req.status = q["status"]
+        req.true_relres = q["true_relres"][0]
+        req.outer, req.inner = q["outer"], q["inner_total"]
+        req.x = X[0]
+        self.busy[req.grid] = False
+        self.in_flight_bytes -= self.item_bytes[req.grid]
 
     def run(self, requests, make_rhs, on_done=None, clock=time.perf_counter, poll_chunks=1):
         """Serve `requests` (sorted by arrival).  make_rhs(req) fills req.b and
@@ -86,14 +125,19 @@ class Server:
         queue = []
         slots = {}
         done = []
+        self._flying = set()
         while pending or queue or slots:
             now = clock() - t0
             while pending and pending[0].arrival <= now:
                 queue.append(pending.popleft())
-            # admission: FIFO among requests whose grid is idle and that fit
+            # admission: FIFO among requests whose grid is idle and that fit;
+            # a class batch takes new items only between its launches
             rest = []
             for req in queue:
-                if not self.busy[req.grid] and len(slots) < self.batch_capacity() and self.fits(req.grid):
+                k = self.klass[req.grid]
+                if (not self.busy[req.grid] and k not in self._flying
+                        and sum(1 for key in slots if key[0] == k) < self.batch_capacity()
+                        and self.fits(req.grid)):
                     make_rhs(req)
                     slots[self.admit(req, clock() - t0)] = req
                 else:
@@ -105,24 +149,19 @@ class Server:
                     if wait > 0:
                         time.sleep(min(wait, 0.05))
                 continue
-            self.batch.run(poll_chunks)
-            for s in list(slots):
-                q = self.batch.query(s)
-                if not q["done"]:
-                    continue
-                X, q = self.batch.remove(s)
-                req = slots.pop(s)
-                req.finished = clock() - t0
-                req.status = q["status"]
-                req.true_relres = q["true_relres"][0]
-                req.outer, req.inner = q["outer"], q["inner_total"]
-                req.x = X[0]
-                self.busy[req.grid] = False
-                self.in_flight_bytes -= self.item_bytes[req.grid]
+            for key, X, q in self._advance(slots, poll_chunks):
+                req = slots.pop(key)
+                self._finish(req, X, q, clock() - t0)
                 done.append(req)
                 if on_done:
                     on_done(req)
+        self._drain()
         return done
+
+    def _drain(self):
+        for k in list(self._flying):
+            self.batches[k].wait(block=True)
+        self._flying = set()
 
     def batch_capacity(self):
         return self.max_slots
@@ -137,6 +176,8 @@ class Server:
         slots = {}
         done = []
         rid = [0]
+        self._flying = set()
+        waiting = list(range(len(self.solvers)))   # grids whose next step is due
 
         def submit(g):
             now = clock() - t0
@@ -145,27 +186,21 @@ class Server:
             make_rhs(req)
             slots[self.admit(req, clock() - t0)] = req
 
-        for g in range(len(self.solvers)):
-            submit(g)
-        while slots:
-            self.batch.run(poll_chunks)
-            for s in list(slots):
-                if not self.batch.query(s)["done"]:
-                    continue
-                X, q = self.batch.remove(s)
-                req = slots.pop(s)
-                req.finished = clock() - t0
-                req.status = q["status"]
-                req.true_relres = q["true_relres"][0]
-                req.outer, req.inner = q["outer"], q["inner_total"]
-                req.x = X[0]
-                self.busy[req.grid] = False
-                self.in_flight_bytes -= self.item_bytes[req.grid]
+        while slots or waiting:
+            for g in [g for g in waiting if self.klass[g] not in self._flying]:
+                waiting.remove(g)
+                submit(g)
+            if not slots:
+                continue
+            for key, X, q in self._advance(slots, poll_chunks):
+                req = slots.pop(key)
+                self._finish(req, X, q, clock() - t0)
                 done.append(req)
                 if on_done:
                     on_done(req)
                 if req.finished < seconds:
-                    submit(req.grid)
+                    waiting.append(req.grid)
+        self._drain()
         return done, clock() - t0
 
 
@@ -225,11 +260,22 @@ class TimeStepper:
         self.x[req.grid] = req.x.clone()
 
 
-def latency_stats(done):
+def latency_stats(done, klass=None):
+    """Latency percentiles (arrival to solution) and throughput; with
+    klass[grid] also per size class."""
     lat = np.array([r.latency for r in done])
     span = max(r.finished for r in done) - min(r.arrival for r in done)
-    return {"requests": len(done), "p50_ms": float(np.percentile(lat, 50) * 1e3),
-            "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
-            "solves_per_s": len(done) / span if span > 0 else float("nan"),
-            "worst_true_relres": float(max(r.true_relres for r in done)),
-            "all_ok": all(r.status == 0 for r in done)}
+    out = {"requests": len(done), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+           "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+           "solves_per_s": len(done) / span if span > 0 else float("nan"),
+           "worst_true_relres": float(max(r.true_relres for r in done)),
+           "all_ok": all(r.status == 0 for r in done)}
+    if klass is not None:
+        per = {}
+        for k in sorted(set(klass)):
+            lk = np.array([r.latency for r in done if klass[r.grid] == k])
+            if len(lk):
+                per[str(k)] = {"requests": int(len(lk)), "p50_ms": float(np.percentile(lk, 50) * 1e3),
+                               "p99_ms": float(np.percentile(lk, 99) * 1e3)}
+        out["per_class"] = per
+    return out

@@ -1,5 +1,6 @@
 """Host logic of the serving layer (no GPU): seeded arrival processes."""
 import numpy as np
+import pytest
 
 from paper_1210_1878_amd import serve
 
@@ -28,3 +29,18 @@ def test_poisson_uniform_grids():
     assert abs(t[-1] / 2000 * 100.0 - 1.0) < 0.1
     counts = np.bincount([r.grid for r in a], minlength=4)
     assert counts.min() > 400
+
+
+def test_latency_stats_per_class():
+    reqs = []
+    for i in range(100):
+        r = serve.Request(rid=i, grid=i % 3, arrival=0.01 * i)
+        r.finished = r.arrival + (1.0 if r.grid == 2 else 0.01 * (1 + i % 7))
+        r.status, r.true_relres = 0, 1e-11
+        reqs.append(r)
+    st = serve.latency_stats(reqs, klass=[0, 0, 1])
+    assert st["requests"] == 100 and st["all_ok"]
+    per = st["per_class"]
+    assert per["0"]["requests"] + per["1"]["requests"] == 100
+    assert abs(per["1"]["p50_ms"] - 1000.0) < 1e-6 and per["0"]["p99_ms"] <= 70.0 + 1e-9
+    assert st["p99_ms"] == pytest.approx(1000.0)
