@@ -45,7 +45,7 @@ def kernel_bytes(n, nnz_off, word, index_bytes=4):
     distance).  word = 8 (FP64) or 4 (FP32)."""
     e = word + index_bytes
     return {
-        "stencil": 7 * word * n,               # s, d_old, diag, ae, an in; d, q out
+        "stencil": 4 * word * n + 24 * n,      # s, d_old in; d, q out; FP64 diag, ae, an in
         "axpy_zt": 8 * word * n + e * nnz_off,  # r, q, d, x, D^-1 in; r', x, t out; Z^T
         "z_dot": 3 * word * n + e * nnz_off,    # t, r' in; s out; Z
     }

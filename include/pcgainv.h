@@ -59,8 +59,9 @@ extern "C" {
 
 /* precision of a solver */
 #define PCGA_FP64 0         /* A, Z, vectors and scalars in FP64              */
-#define PCGA_MIXED 1        /* FP32 inner PCG (A, Z, vectors), FP64 scalars,  */
-                            /* FP64 residual, solution and outer refinement   */
+#define PCGA_MIXED 1        /* FP32 inner PCG (Z, D^-1, vectors; the FP64     */
+                            /* operator applied to FP32 vectors), FP64        */
+                            /* scalars, residual, solution and refinement     */
 
 typedef struct pcga_a5 {
     int32_t nx, ny;
@@ -133,7 +134,8 @@ int pcga_solver_destroy(pcga_solver_t *S);
 
 /* Solver facts: n, nnz_off, precision, the modelled device bytes one PCG
  * iteration must move (each array once; FP64: 144 n + (8 + b) nnz_pad, mixed
- * inner: 72 n + (4 + b) nnz_pad, nnz_pad = stored sliced-ELL entries of Z^T
+ * inner: 84 n + (4 + b) nnz_pad, with the FP64 coefficients read by the
+ * stencil; nnz_pad = stored sliced-ELL entries of Z^T
  * plus Z, b = index bytes) and b itself: 2 when every stored entry of Z lies
  * within 65535 rows of its row (16-bit distances), else 4 (32-bit columns);
  * formats[0], formats[1]: how Z^T and Z are stored and read (bit 0: 16-bit
@@ -171,7 +173,8 @@ int pcga_pcg_solve(pcga_solver_t *S, const double *b_dev, double *x_dev, double 
 
 /* pcga_pcg_solve_mixed: FP64 iterative refinement.  Outer step o: r = b - A x
  * in FP64; stop if ||r||/||b|| <= tol; else solve A e = r with the FP32
- * inner PCG (FP32 A, Z, D^-1 and vectors; FP64 alpha/beta/rho and dot sums)
+ * inner PCG (FP32 Z, D^-1 and vectors; q = A d with the FP64 coefficients,
+ * rounded to FP32; FP64 alpha/beta/rho and dot sums)
  * to relative residual inner_tol (at most inner_maxit iterations, < 0: n),
  * then x += e in FP64.  At most max_outer corrections.  hist_host receives
  * the outer true residuals ||b - A x_o||/||b||, o = 0..*outer.

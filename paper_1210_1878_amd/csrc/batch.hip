@@ -77,8 +77,7 @@ struct SlotCtl {
 };
 
 struct SlotDesc {
-    DevOp<double> A64;
-    DevOp<float> A32;
+    DevOp<double> A64;   // FP64 coefficients, also for the FP32 inner steps
     DevSell<float> zt, z;
     const float *dinv;
     float *e, *r[2], *s, *d[2], *q, *t;   // [n][R]
@@ -186,7 +185,7 @@ __device__ void stencil_cg(const SlotDesc &D, int L, int par) {
         for (int r = 0; r < R; r++) c->rho[par][r] = rs[0][r];
         c->st[1] = kActCG;
     }
-    const DevOp<float> &A = D.A32;
+    const DevOp<double> &A = D.A64;
     const float *s = D.s, *dold = D.d[par];
     float *dnew = D.d[par ^ 1], *q = D.q;
     double acc[1][R];
@@ -195,7 +194,7 @@ __device__ void stencil_cg(const SlotDesc &D, int L, int par) {
     int c0, c1;
     range_of(L, D.G, A.n, c0, c1);
     for (int kc = c0 + threadIdx.x; kc < c1; kc += kBS) {
-        const Nbr<float> m = neighbours(A, kc);
+        const Nbr<double> m = neighbours(A, kc);
         const int idx[5] = {m.kS, m.kW, kc, m.kE, m.kN};
         float sv[5][R], dv[5][R];
 #pragma unroll
@@ -210,7 +209,8 @@ __device__ void stencil_cg(const SlotDesc &D, int L, int par) {
 #pragma unroll
             for (int e = 0; e < 5; e++) v[e] = (k == 0) ? sv[e][r] : fmaf(bt[r], dv[e][r], sv[e][r]);
             dn[r] = v[2];
-            qn[r] = apply_row(m, v[0], v[1], v[2], v[3], v[4]);
+            qn[r] = (float)apply_row(m, (double)v[0], (double)v[1], (double)v[2], (double)v[3],
+                                     (double)v[4]);
             acc[0][r] += (double)dn[r] * (double)qn[r];
         }
         stv<R>(dnew, kc, dn);
@@ -456,7 +456,7 @@ __device__ void zt_decide(const SlotDesc &D, int L, int par) {
     if (finished) return;
     // e = 0 on this block's cells, then t = D^-1 Z^T r32
     int c0, c1;
-    range_of(L, D.G, D.A32.n, c0, c1);
+    range_of(L, D.G, D.A64.n, c0, c1);
     for (int kc = c0 + threadIdx.x; kc < c1; kc += kBS) {
         float z[R];
 #pragma unroll
@@ -602,7 +602,7 @@ __device__ void z_cg(const SlotDesc &D, int L, int par) {
     if (inner_done) {
         // x += e (FP64) on this block's cells; the next step recomputes r
         int c0, c1;
-        range_of(L, D.G, D.A32.n, c0, c1);
+        range_of(L, D.G, D.A64.n, c0, c1);
         for (int kc = c0 + threadIdx.x; kc < c1; kc += kBS) {
             float ev[R];
             double xv[R];
@@ -927,7 +927,6 @@ int pcga_batch_add(pcga_batch_t *B, pcga_solver_t *S, int32_t nrhs, const double
     char *w = (char *)item_ws;
     SlotDesc D{};
     D.A64 = S->A64;
-    D.A32 = S->A32;
     D.zt = S->zt32;
     D.z = S->z32;
     D.dinv = S->dinv32;

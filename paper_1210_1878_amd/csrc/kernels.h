@@ -424,7 +424,7 @@ __device__ __forceinline__ bool stop_test(CtlBlock *cb, double rr, int k) {
 // STOP (diagonal preconditioner path, two launches per iteration): the stop
 // test on ||r_k|| from the previous k_jacobi's partials runs here first.
 template <typename T, bool STOP>
-__global__ __launch_bounds__(kBS) void k_stencil(DevOp<T> A, const T *__restrict__ s,
+__global__ __launch_bounds__(kBS) void k_stencil(DevOp<double> A, const T *__restrict__ s,
                                                  const T *__restrict__ dold,
                                                  T *__restrict__ dnew, T *__restrict__ q,
                                                  CtlBlock *cb, Partials P, int g_sr, int par) {
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(kBS) void k_stencil(DevOp<T> A, const T *__restrict
     // before any arithmetic (branch-free neighbour indices, clamped cells).
     struct Step {
         T sv[kCPT][5], dv[kCPT][5];
-        Nbr<T> m[kCPT];
+        Nbr<double> m[kCPT];
         int kc[kCPT];
     };
     int c0, c1;
@@ -487,7 +487,10 @@ __global__ __launch_bounds__(kBS) void k_stencil(DevOp<T> A, const T *__restrict
                 T v[5];
 #pragma unroll
                 for (int e = 0; e < 5; e++) v[e] = fma(bt, st.dv[u][e], st.sv[u][e]);
-                const T y = apply_row(st.m[u], v[0], v[1], v[2], v[3], v[4]);
+                // the operator is applied in FP64 (exact coefficients) also to
+                // FP32 vectors; q is rounded to T
+                const T y = (T)apply_row(st.m[u], (double)v[0], (double)v[1], (double)v[2],
+                                         (double)v[3], (double)v[4]);
                 dnew[st.kc[u]] = v[2];
                 q[st.kc[u]] = y;
                 acc += (double)v[2] * (double)y;

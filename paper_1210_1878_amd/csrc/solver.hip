@@ -157,9 +157,6 @@ size_t carve(pcga_solver &S, void *base, const HostLayouts &H) {
         S.q = C.take<double>(n);
         S.t = C.take<double>(n);
     } else {
-        S.A32.diag = C.take<float>(n);
-        S.A32.ae = C.take<float>(n);
-        S.A32.an = C.take<float>(n);
         S.dinv32 = C.take<float>(n);
         sell(H.zt, S.zt32, float());
         sell(H.z, S.z32, float());
@@ -237,8 +234,8 @@ std::vector<int32_t> balanced_bounds(const std::vector<int32_t> &cost, int G) {
 }
 
 // Which streams of an iteration stay resident in the memory-side cache.  The
-// iteration kernels read, per iteration, the vectors and operator arrays
-// (12 of n words: x or e, r[2], s, d[2], q, t, diag, ae, an, D^-1) and the
+// iteration kernels read, per iteration, the vectors (9 of n words: x or e,
+// r[2], s, d[2], q, t, D^-1), the FP64 operator arrays diag, ae, an, and the
 // values and indices of Z^T and Z.  The vectors are kept first (each is read
 // by two or three kernels), then Z^T values, Z values, Z^T indices, Z
 // indices, as long as the total fits the budget; the streams left over are
@@ -250,7 +247,7 @@ void cache_plan(pcga_solver &S, const HostLayouts &H) {
     const double ib = H.zt.narrow ? 2.0 : 4.0;
     const double ezt = (double)H.zt.entries(), ez = (double)H.z.entries();
     const double streams[4] = {w * ezt, w * ez, ib * ezt, ib * ez};   // kept in this order
-    double used = 12.0 * w * (double)S.n;
+    double used = (9.0 * w + 24.0) * (double)S.n;
     int kept = 0;
     while (kept < 4 && used + streams[kept] <= kResidentBudget) used += streams[kept++];
     // streams not kept: Z idx (kept < 4), Z^T idx (< 3), Z val (< 2), Z^T val (< 1)
@@ -444,11 +441,11 @@ int pcga_solver_create(const pcga_a5_t *A, const pcga_ainv_t *F, int precision, 
     S->ws = ws;
     S->ws_bytes = bytes;
     carve(*S, ws, H);
-    S->A64.nx = S->A32.nx = A->nx;
-    S->A64.ny = S->A32.ny = A->ny;
-    S->A64.periodic = S->A32.periodic = S->periodic;
-    S->A64.n = S->A32.n = (int32_t)n;
-    S->A64.inv_nx = S->A32.inv_nx = 1.0 / (double)A->nx;
+    S->A64.nx = A->nx;
+    S->A64.ny = A->ny;
+    S->A64.periodic = S->periodic;
+    S->A64.n = (int32_t)n;
+    S->A64.inv_nx = 1.0 / (double)A->nx;
     S->sell_entries = H.zt.entries() + H.z.entries();
 
     auto fail_free = [&](int code) {
@@ -511,15 +508,6 @@ int pcga_solver_create(const pcga_a5_t *A, const pcga_ainv_t *F, int precision, 
         CR(up_sell(H.z, S->z64));
     } else {
         std::vector<float> f(n);
-        for (int64_t k = 0; k < n; k++) f[k] = (float)A->diag[k];
-        CR(hipMemcpyAsync((void *)S->A32.diag, f.data(), n * 4, hipMemcpyHostToDevice, sm));
-        CR(hipStreamSynchronize(sm));
-        for (int64_t k = 0; k < n; k++) f[k] = (float)A->ae[k];
-        CR(hipMemcpyAsync((void *)S->A32.ae, f.data(), n * 4, hipMemcpyHostToDevice, sm));
-        CR(hipStreamSynchronize(sm));
-        for (int64_t k = 0; k < n; k++) f[k] = (float)A->an[k];
-        CR(hipMemcpyAsync((void *)S->A32.an, f.data(), n * 4, hipMemcpyHostToDevice, sm));
-        CR(hipStreamSynchronize(sm));
         for (int64_t k = 0; k < n; k++) f[k] = (float)dinv[k];
         CR(hipMemcpyAsync(S->dinv32, f.data(), n * 4, hipMemcpyHostToDevice, sm));
         CR(hipStreamSynchronize(sm));
@@ -542,17 +530,19 @@ int pcga_solver_create(const pcga_a5_t *A, const pcga_ainv_t *F, int precision, 
         return st;
     }
     // modelled compulsory bytes per iteration (see kernels.h):
-    //   stencil: s, d_old, diag, ae, an read; d_new, q written       7 n words
+    //   stencil: s, d_old read; d_new, q written       4 n words + FP64 diag, ae, an
     //   zt: r, q, d, x, dinv read; r', x, t written; Z^T entries     8 n words + E_zt
     //   z:  t, r' read; s written; Z entries                         3 n words + E_z
     //   (an entry: its value and a 4-byte column or 2-byte distance)
     const double E = (double)S->sell_entries;
     S->index_bytes = H.zt.narrow ? 2 : 4;
     cache_plan(*S, H);
+    //   (the stencil reads the FP64 coefficients diag, ae, an also for the
+    //   FP32 inner iteration: 24 n bytes)
     if (precision == PCGA_FP64)
         S->bytes_per_iter = 8.0 * 18.0 * n + (8.0 + S->index_bytes) * E;
     else
-        S->bytes_per_iter = 4.0 * 18.0 * n + (4.0 + S->index_bytes) * E;
+        S->bytes_per_iter = 4.0 * 15.0 * n + 24.0 * n + (4.0 + S->index_bytes) * E;
     *out = S;
     return PCGA_OK;
 }
@@ -609,7 +599,7 @@ namespace {
 
 template <typename T>
 struct IterBufs {
-    DevOp<T> A;
+    DevOp<double> A;   // FP64 coefficients for both the FP64 and the FP32 inner iteration
     DevSell<T> zt, z;
     const T *dinv;
     T *x, *r[2], *s, *d[2], *q, *t;
@@ -619,7 +609,7 @@ IterBufs<double> bufs64(pcga_solver &S) {
     return {S.A64, S.zt64, S.z64, S.dinv64, S.x, {S.r[0], S.r[1]}, S.s, {S.d[0], S.d[1]}, S.q, S.t};
 }
 IterBufs<float> bufs32(pcga_solver &S) {
-    return {S.A32, S.zt32, S.z32, S.dinv32, S.e32, {S.r32[0], S.r32[1]}, S.s32,
+    return {S.A64, S.zt32, S.z32, S.dinv32, S.e32, {S.r32[0], S.r32[1]}, S.s32,
             {S.d32[0], S.d32[1]}, S.q32, S.t32};
 }
 

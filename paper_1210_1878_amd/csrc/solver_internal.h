@@ -21,7 +21,6 @@ struct pcga_solver {
     size_t ws_bytes = 0;
 
     pcga::DevOp<double> A64{};
-    pcga::DevOp<float> A32{};
     pcga::DevSell<double> zt64{}, z64{};
     pcga::DevSell<float> zt32{}, z32{};
     double *dinv64 = nullptr;
