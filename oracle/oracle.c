@@ -456,9 +456,12 @@ out:
 /* ------------------------------------------------------------------------ */
 /* Mixed precision: FP64 outer refinement around an FP32 inner PCG.          */
 /*   outer: r = b - A x (FP64); stop if ||r||/||b|| <= tol;                  */
-/*          solve A e = r with FP32 data (A, Z, D and vectors rounded to      */
-/*          float) to relative tolerance inner_tol; x += e in FP64.          */
-/*   inner: CG scalars and dot sums in FP64, vector updates in FP32.          */
+/*          solve A e = r with FP32 data (Z, D and vectors rounded to float)  */
+/*          to relative tolerance inner_tol; x += e in FP64.                 */
+/*   inner: CG scalars and dot sums in FP64, vector updates in FP32; q = A d  */
+/*          sums the FP64 coefficients times the FP32 d in FP64 and rounds   */
+/*          q to float (rounded coefficients would cap each outer step's     */
+/*          reduction on fine grids).                                         */
 /* outer_hist[o] = ||b - A x_o||/||b|| (capacity max_outer+1).               */
 /* ------------------------------------------------------------------------ */
 static void spmv32(int64_t nx, int64_t ny, int periodic, const double *diag,
@@ -468,12 +471,12 @@ static void spmv32(int64_t nx, int64_t ny, int periodic, const double *diag,
     double vals[5];
     for (int64_t k = 0; k < n; k++) {
         int m = a_row(nx, ny, periodic, diag, ae, an, k, cols, vals);
-        float s = 0.0f;
+        double s = 0.0;
         for (int t = 0; t < m; t++) {
-            float p = (float)vals[t] * x[cols[t]];
+            double p = vals[t] * (double)x[cols[t]];
             s = s + p;
         }
-        y[k] = s;
+        y[k] = (float)s;
     }
 }
 
