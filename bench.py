@@ -6,7 +6,7 @@ tolerance 0.05) of the synthetic 1442x1021 problem from x0 = 0 to relative
 residual 1e-10, inputs resident in HBM.  `value` = iterations per second over
 the K timed steps.  The same JSON line carries the mixed-precision solve (FP32
 inner PCG + FP64 refinement) on the same GPU, the diagonal (Jacobi)
-preconditioner baseline, the roofline of the dominant kernel (HIP-event
+preconditioner baseline, the paper's banded factor of T (q = 4), the roofline of the dominant kernel (HIP-event
 timing on the solver stream), and the FP64 oracle timed on the host.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -314,6 +314,18 @@ def main():
     dtj = time.perf_counter() - t0
     log(f"jacobi: {rj.iters} iterations, {dtj * 1e3:.2f} ms/solve")
 
+    # ---- the paper's own preconditioner: banded factor of T, q = 4 ---------
+    Gb = P.fsai_band_setup(A, 4)
+    Sb = P.Solver(A, Gb, "fp64", device=dev)
+    Sb.tune(chunk=args.chunk, use_graph=not args.no_graph, max_blocks=args.max_blocks)
+    Sb.solve(b, tol=TOL)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rb = Sb.solve(b, tol=TOL)
+    torch.cuda.synchronize()
+    dtb = time.perf_counter() - t0
+    log(f"banded factor of T (q=4, diagonal storage): {rb.iters} iterations, {dtb * 1e3:.2f} ms/solve")
+
     # ---- roofline of the dominant kernel (HIP events on the solver stream) --
     ms = S64.profile_iteration(b, reps=100, mode=1)
     ms32 = Smx.profile_iteration(b, reps=100, mode=1)
@@ -372,6 +384,8 @@ def main():
                   "iteration_ms": round(ms32[3], 5)},
         "jacobi": {"iters": rj.iters, "ms_per_solve": round(dtj * 1e3, 3),
                    "true_relres": rj.true_relres},
+        "band_factor_q4": {"iters": rb.iters, "ms_per_solve": round(dtb * 1e3, 3),
+                           "true_relres": rb.true_relres, "band_q": Sb.band_q},
         "batched": batched,
         "served": served,
         "setup_s": round(setup_s, 3),

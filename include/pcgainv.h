@@ -141,7 +141,10 @@ int pcga_solver_destroy(pcga_solver_t *S);
  * formats[0], formats[1]: how Z^T and Z are stored and read (bit 0: 16-bit
  * distances; bit 1: indices, bit 2: values read with non-temporal loads,
  * chosen so that the rest of an iteration's data fits the 256 MiB
- * memory-side cache).  Any output pointer may be NULL. */
+ * memory-side cache); formats[2]: q when every entry of Z lies within q <= 8
+ * rows above the diagonal (e.g. the banded factor of T), which the solve
+ * then applies from diagonals (no index arrays, no gathers), else 0.  Any
+ * output pointer may be NULL. */
 int pcga_solver_info(const pcga_solver_t *S, int64_t *n, int64_t *nnz_off,
                      int32_t *precision, double *bytes_per_iter, int32_t *index_bytes,
                      int32_t *formats);

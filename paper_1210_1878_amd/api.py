@@ -174,10 +174,11 @@ class Solver:
         prec = ctypes.c_int32()
         bpi = ctypes.c_double()
         ib = ctypes.c_int32()
-        fm = (ctypes.c_int32 * 2)()
+        fm = (ctypes.c_int32 * 3)()
         check(L.pcga_solver_info(self._h, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(prec),
                                  ctypes.byref(bpi), ctypes.byref(ib), fm), "pcga_solver_info")
         self.formats = (fm[0], fm[1])     # Z^T, Z: bit 0 16-bit index, bit 1/2 streamed idx/val
+        self.band_q = fm[2]               # > 0: Z applied from its diagonals
         self.n = n.value
         self.nnz_off = nnz.value
         self.bytes_per_iter = bpi.value

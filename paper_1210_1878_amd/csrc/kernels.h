@@ -634,6 +634,101 @@ __global__ __launch_bounds__(kBS) void k_z(DevSell<T> Z, const T *__restrict__ t
 }
 
 // ---------------------------------------------------------------------------
+// Banded factor (the paper's factor of T with band q, Sec. 3): Z has entries
+// only at Z[j-m, j], m = 1..q, stored by diagonals, zb[(m-1) n + j] (0 where
+// absent).  Z^T row j then reads r at j-q..j-1 and Z row i reads t at
+// i+1..i+q: shifted, coalesced reads of the vectors instead of index-driven
+// gathers, and no index arrays.  Entries are summed in increasing column
+// order, the unit diagonal last, as in the sliced-ELL kernels.
+// ---------------------------------------------------------------------------
+template <typename T, bool FUSED>
+__global__ __launch_bounds__(kBS) void k_zt_band(const T *__restrict__ zb, int qb,
+                                                 const T *__restrict__ dinv,
+                                                 const T *__restrict__ rcur,
+                                                 const T *__restrict__ q,
+                                                 const T *__restrict__ dcur, T *__restrict__ rnext,
+                                                 T *__restrict__ x, T *__restrict__ t, int n,
+                                                 CtlBlock *cb, Partials P, int g_dq, int par) {
+    Ctl *c = &cb->c;
+    if (FUSED && c->done) return;
+    const PartialsLoad<1> pl = load_partials<1>(P.dq, FUSED ? g_dq : 0);
+    const int G = gridDim.x, L = logical_block(blockIdx.x, G);
+    int c0, c1;
+    range_of(L, G, n, c0, c1);
+    __builtin_amdgcn_sched_barrier(0);
+    T at = T(0);
+    if (FUSED) {
+        double dq[1];
+        reduce_partials<1>(pl, g_dq, dq);
+        if (!finite_pos(dq[0])) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                c->status = is_bad(dq[0]) ? kStNan : kStBreak;
+                c->done = 1;
+            }
+            return;
+        }
+        const double alpha = c->rho[par] / dq[0];
+        if (blockIdx.x == 0 && threadIdx.x == 0) c->alpha = alpha;
+        at = (T)alpha;
+    }
+    auto rp = [&](int k) { return FUSED ? fma(-at, q[k], rcur[k]) : rcur[k]; };
+    double rr = 0.0;
+    for (int j = c0 + threadIdx.x; j < c1; j += kBS) {
+        T acc = T(0);
+        for (int m = qb; m >= 1; m--) {
+            if (j - m >= 0) acc = fma(zb[(int64_t)(m - 1) * n + j], rp(j - m), acc);
+        }
+        const T rj = rp(j);
+        t[j] = (acc + rj) * dinv[j];
+        if (FUSED) {
+            rnext[j] = rj;
+            x[j] = fma(at, dcur[j], x[j]);
+            rr += (double)rj * (double)rj;
+        }
+    }
+    if (FUSED) {
+        double pv[1] = {rr};
+        put_partials<1>(pv, P.rr, L);
+    }
+}
+
+template <typename T, bool DOT, bool FIRST>
+__global__ __launch_bounds__(kBS) void k_z_band(const T *__restrict__ zb, int qb,
+                                                const T *__restrict__ t,
+                                                const T *__restrict__ r, T *__restrict__ s, int n,
+                                                CtlBlock *cb, Partials P, int g_rr, int par) {
+    Ctl *c = &cb->c;
+    if (DOT && c->done) return;
+    constexpr bool TEST = DOT && !FIRST;
+    const PartialsLoad<1> pl = load_partials<1>(P.rr, TEST ? g_rr : 0);
+    const int G = gridDim.x, L = logical_block(blockIdx.x, G);
+    int c0, c1;
+    range_of(L, G, n, c0, c1);
+    __builtin_amdgcn_sched_barrier(0);
+    if (TEST) {
+        double rr[1];
+        reduce_partials<1>(pl, g_rr, rr);
+        const int k = c->kk[par] + 1;
+        if (blockIdx.x == 0 && threadIdx.x == 0) c->kk[par ^ 1] = k;
+        if (stop_test(cb, rr[0], k)) return;
+    }
+    double sr = 0.0;
+    for (int i = c0 + threadIdx.x; i < c1; i += kBS) {
+        T acc = T(0);
+        for (int m = 1; m <= qb; m++) {
+            if (i + m < n) acc = fma(zb[(int64_t)(m - 1) * n + i + m], t[i + m], acc);
+        }
+        const T si = t[i] + acc;
+        s[i] = si;
+        if (DOT) sr += (double)si * (double)r[i];
+    }
+    if (DOT) {
+        double pv[1] = {sr};
+        put_partials<1>(pv, P.sr, L);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // k_jacobi (diagonal preconditioner, Z = I): alpha = rho_k / (d,q);
 // r' = r - alpha q; x += alpha d; s = D^-1 r'; ||r'||^2 and (s, r') partials;
 // iteration count k + 1.  With k_stencil<STOP> it makes a two-launch

@@ -21,6 +21,7 @@ constexpr int kMaxBlocks = 2048;   // workgroups per kernel = partial sums per r
 // Default workgroups per kernel: 5 per CU (256 CUs), so that every workgroup
 // of the heaviest iteration kernel (5 wavefronts per SIMD) is resident at once.
 constexpr int kDefaultBlocks = 1280;
+constexpr int kMaxBand = 8;          // widest band stored by diagonals
 // Memory-side cache (Infinity Cache) of one MI355X: 256 MiB.  The streams an
 // iteration reads are kept resident up to 95% of it (see cache_plan).
 constexpr double kMallBytes = 268435456.0;

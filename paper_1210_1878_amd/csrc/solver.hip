@@ -144,6 +144,12 @@ size_t carve(pcga_solver &S, void *base, const HostLayouts &H) {
         dst.nslices = (int32_t)L.nslices();
         dst.nrows = (int32_t)L.nrows_total;
     };
+    if (S.band_q > 0) {
+        if (f64)
+            S.zb64 = C.take<double>((size_t)S.band_q * n);
+        else
+            S.zb32 = C.take<float>((size_t)S.band_q * n);
+    }
     if (f64) {
         S.dinv64 = C.take<double>(n);
         sell(H.zt, S.zt64, double());
@@ -389,6 +395,27 @@ int pcga_ainv_free(pcga_ainv_t *F) {
     return PCGA_OK;
 }
 
+// Width q of Z's band (largest j - i over stored entries Z[i, j]) when it is
+// at most kMaxBand, else 0 (also 0 for Z = I).
+static int band_width(const AinvFactor &F) {
+    int64_t q = 0;
+    for (int64_t j = 0; j < F.n; j++)
+        for (int64_t a = F.colptr[j]; a < F.colptr[j + 1]; a++) {
+            q = std::max<int64_t>(q, j - F.rowidx[a]);
+            if (q > kMaxBand) return 0;
+        }
+    return (int)q;
+}
+
+// Z by diagonals: zb[(m-1) n + j] = Z[j-m, j], m = 1..q (0 where not stored).
+static std::vector<double> band_diagonals(const AinvFactor &F, int q) {
+    std::vector<double> zb((size_t)q * F.n, 0.0);
+    for (int64_t j = 0; j < F.n; j++)
+        for (int64_t a = F.colptr[j]; a < F.colptr[j + 1]; a++)
+            zb[(size_t)(j - F.rowidx[a] - 1) * F.n + j] = F.val[a];
+    return zb;
+}
+
 int pcga_workspace_bytes(const pcga_a5_t *A, const pcga_ainv_t *F, int precision,
                          size_t *bytes) {
     if (!bytes || !F) return fail(PCGA_EINVAL, "NULL argument");
@@ -403,6 +430,7 @@ int pcga_workspace_bytes(const pcga_a5_t *A, const pcga_ainv_t *F, int precision
     pcga_solver S;
     S.precision = precision;
     S.n = F->F.n;
+    S.band_q = band_width(F->F);
     *bytes = carve(S, nullptr, H);
     return PCGA_OK;
 }
@@ -429,6 +457,7 @@ int pcga_solver_create(const pcga_a5_t *A, const pcga_ainv_t *F, int precision, 
     S->n = n;
     S->nnz_off = F->F.nnz_off();
     S->jacobi = S->nnz_off == 0;
+    S->band_q = band_width(F->F);
     S->nx = A->nx;
     S->ny = A->ny;
     S->periodic = (A->flags & PCGA_PERIODIC_X) ? 1 : 0;
@@ -502,6 +531,16 @@ int pcga_solver_create(const pcga_a5_t *A, const pcga_ainv_t *F, int precision, 
             return hipStreamSynchronize(sm);   // v32 is a temporary
         }
     };
+    if (S->band_q > 0) {
+        const std::vector<double> zb = band_diagonals(F->F, S->band_q);
+        if (precision == PCGA_FP64) {
+            CR(hipMemcpyAsync(S->zb64, zb.data(), zb.size() * 8, hipMemcpyHostToDevice, sm));
+        } else {
+            const std::vector<float> zf(zb.begin(), zb.end());
+            CR(hipMemcpyAsync(S->zb32, zf.data(), zf.size() * 4, hipMemcpyHostToDevice, sm));
+        }
+        CR(hipStreamSynchronize(sm));   // zb / zf are temporaries
+    }
     if (precision == PCGA_FP64) {
         CR(hipMemcpyAsync(S->dinv64, dinv.data(), nb8, hipMemcpyHostToDevice, sm));
         CR(up_sell(H.zt, S->zt64));
@@ -565,6 +604,7 @@ int pcga_solver_info(const pcga_solver_t *S, int64_t *n, int64_t *nnz_off, int32
     if (formats) {
         formats[0] = S->fmt_zt;
         formats[1] = S->fmt_z;
+        formats[2] = S->band_q;
     }
     if (n) *n = S->n;
     if (nnz_off) *nnz_off = S->nnz_off;
@@ -601,15 +641,17 @@ template <typename T>
 struct IterBufs {
     DevOp<double> A;   // FP64 coefficients for both the FP64 and the FP32 inner iteration
     DevSell<T> zt, z;
+    const T *zb;       // banded Z by diagonals (band_q > 0)
     const T *dinv;
     T *x, *r[2], *s, *d[2], *q, *t;
 };
 
 IterBufs<double> bufs64(pcga_solver &S) {
-    return {S.A64, S.zt64, S.z64, S.dinv64, S.x, {S.r[0], S.r[1]}, S.s, {S.d[0], S.d[1]}, S.q, S.t};
+    return {S.A64, S.zt64, S.z64, S.zb64, S.dinv64, S.x, {S.r[0], S.r[1]}, S.s, {S.d[0], S.d[1]},
+            S.q, S.t};
 }
 IterBufs<float> bufs32(pcga_solver &S) {
-    return {S.A64, S.zt32, S.z32, S.dinv32, S.e32, {S.r32[0], S.r32[1]}, S.s32,
+    return {S.A64, S.zt32, S.z32, S.zb32, S.dinv32, S.e32, {S.r32[0], S.r32[1]}, S.s32,
             {S.d32[0], S.d32[1]}, S.q32, S.t32};
 }
 
@@ -649,7 +691,7 @@ void launch_kernel(pcga_solver &S, const IterBufs<T> &B, int p, int which) {
                                                                  S.cb, S.P, S.g_st, p);
             else
                 k_stencil<T, false><<<S.g_st, kBS, 0, S.stream>>>(B.A, B.s, B.d[p], B.d[p ^ 1], B.q,
-                                                                  S.cb, S.P, S.g_z, p);
+                                                                  S.cb, S.P, S.g_prec(), p);
             break;
         case 1:
             if (S.jacobi) {
@@ -658,10 +700,21 @@ void launch_kernel(pcga_solver &S, const IterBufs<T> &B, int p, int which) {
                     S.g_st, p);
                 break;
             }
+            if (S.band_q > 0) {
+                k_zt_band<T, true><<<S.g_st, kBS, 0, S.stream>>>(
+                    B.zb, S.band_q, B.dinv, B.r[p], B.q, B.d[p ^ 1], B.r[p ^ 1], B.x, B.t, (int)S.n,
+                    S.cb, S.P, S.g_st, p);
+                break;
+            }
             launch_zt<T, true>(B.zt, S.fmt_zt, S.g_zt, S.stream, B.dinv, (const T *)B.r[p], (const T *)B.q,
                                (const T *)B.d[p ^ 1], B.r[p ^ 1], B.x, B.t, S.cb, S.P, S.g_st, p);
             break;
         default:
+            if (S.band_q > 0) {
+                k_z_band<T, true, false><<<S.g_st, kBS, 0, S.stream>>>(
+                    B.zb, S.band_q, B.t, B.r[p ^ 1], B.s, (int)S.n, S.cb, S.P, S.g_st, p);
+                break;
+            }
             launch_z<T, true, false>(B.z, S.fmt_z, S.g_z, S.stream, (const T *)B.t, (const T *)B.r[p ^ 1],
                                      B.s, S.cb, S.P, S.g_zt, p);
             break;
@@ -702,6 +755,15 @@ int prologue_prec(pcga_solver &S, const IterBufs<T> &B) {
     if (S.jacobi) {
         k_jacobi<T, true><<<S.g_st, kBS, 0, S.stream>>>(B.dinv, B.r[0], nullptr, nullptr, nullptr,
                                                         nullptr, B.s, (int)S.n, S.cb, S.P, 0, 0);
+        HIP_TRY(hipGetLastError());
+        return PCGA_OK;
+    }
+    if (S.band_q > 0) {
+        k_zt_band<T, false><<<S.g_st, kBS, 0, S.stream>>>(B.zb, S.band_q, B.dinv, B.r[0], nullptr,
+                                                          nullptr, nullptr, nullptr, B.t, (int)S.n,
+                                                          S.cb, S.P, 0, 0);
+        k_z_band<T, true, true><<<S.g_st, kBS, 0, S.stream>>>(B.zb, S.band_q, B.t, B.r[0], B.s,
+                                                              (int)S.n, S.cb, S.P, 0, 0);
         HIP_TRY(hipGetLastError());
         return PCGA_OK;
     }
@@ -931,7 +993,22 @@ int pcga_apply_prec(pcga_solver_t *S, const double *r_dev, double *t_dev, double
     if (!S || !r_dev || !t_dev || !s_dev) return fail(PCGA_EINVAL, "NULL argument");
     HIP_TRY(hipSetDevice(S->device));
     const int gc = (int)std::min<int64_t>(4096, (S->n + kBS - 1) / kBS);
-    if (S->precision == PCGA_FP64) {
+    if (S->band_q > 0 && S->precision == PCGA_FP64) {
+        k_zt_band<double, false><<<S->g_st, kBS, 0, S->stream>>>(
+            S->zb64, S->band_q, S->dinv64, r_dev, nullptr, nullptr, nullptr, nullptr, t_dev,
+            (int)S->n, S->cb, S->P, 0, 0);
+        k_z_band<double, false, false><<<S->g_st, kBS, 0, S->stream>>>(
+            S->zb64, S->band_q, t_dev, nullptr, s_dev, (int)S->n, S->cb, S->P, 0, 0);
+    } else if (S->band_q > 0) {
+        k_convert<double, float><<<gc, kBS, 0, S->stream>>>((int)S->n, r_dev, S->r32[0]);
+        k_zt_band<float, false><<<S->g_st, kBS, 0, S->stream>>>(
+            S->zb32, S->band_q, S->dinv32, S->r32[0], nullptr, nullptr, nullptr, nullptr, S->t32,
+            (int)S->n, S->cb, S->P, 0, 0);
+        k_z_band<float, false, false><<<S->g_st, kBS, 0, S->stream>>>(
+            S->zb32, S->band_q, S->t32, nullptr, S->tmp32, (int)S->n, S->cb, S->P, 0, 0);
+        k_convert<float, double><<<gc, kBS, 0, S->stream>>>((int)S->n, S->t32, t_dev);
+        k_convert<float, double><<<gc, kBS, 0, S->stream>>>((int)S->n, S->tmp32, s_dev);
+    } else if (S->precision == PCGA_FP64) {
         launch_zt<double, false>(S->zt64, S->fmt_zt, S->g_zt, S->stream, (const double *)S->dinv64, r_dev,
                                  (const double *)nullptr, (const double *)nullptr, (double *)nullptr,
                                  (double *)nullptr, t_dev, S->cb, S->P, 0, 0);

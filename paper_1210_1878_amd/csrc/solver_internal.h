@@ -53,6 +53,13 @@ struct pcga_solver {
     // two launches per iteration (k_stencil<STOP>, k_jacobi) instead of three
     bool jacobi = false;
     int kernels_per_iter() const { return jacobi ? 2 : 3; }
+    // Banded Z (every entry within band_q <= kMaxBand rows above the
+    // diagonal, e.g. the banded factor of T): stored by diagonals, applied by
+    // k_zt_band / k_z_band (elementwise launches of g_st workgroups)
+    int band_q = 0;
+    double *zb64 = nullptr;
+    float *zb32 = nullptr;
+    int g_prec() const { return band_q > 0 ? g_st : g_z; }   // workgroups writing (s,r) partials
     std::vector<int32_t> cost_zt, cost_z;    // per-slice work estimates (host)
     int32_t *bnd_zt = nullptr, *bnd_z = nullptr;   // device: workgroup slice ranges
     int32_t *bnd_zt_b = nullptr, *bnd_z_b = nullptr;   // device: ranges for a batch slot
