@@ -324,7 +324,8 @@ __device__ void zt_apply_f(const SlotDesc &D, int L, const float (&al)[R], const
 #pragma unroll
                 for (int u = 0; u < U; u++) {
                     const int ci = cc + u <= last ? cc + u : last;
-                    kk[u] = entry_col<float, NARROW ? kFmtNarrow : 0, true>(M, m.off + (int64_t)ci * kWave + lane, rw);
+                    kk[u] = entry_col<NARROW ? kFmtNarrow : 0, true>(
+                        load_idx<float, NARROW ? kFmtNarrow : 0>(M, m.off + (int64_t)ci * kWave + lane), rw);
                     zv[u] = vp[(int64_t)ci * kWave];
                 }
                 float gr[U][R], gq[U][R];
@@ -530,7 +531,8 @@ __device__ void z_apply_f(const SlotDesc &D, int L, const float *r, double (&sr)
 #pragma unroll
                 for (int u = 0; u < U; u++) {
                     const int ci = cc + u <= last ? cc + u : last;
-                    jj[u] = entry_col<float, NARROW ? kFmtNarrow : 0, false>(M, m.off + (int64_t)ci * kWave + lane, rw);
+                    jj[u] = entry_col<NARROW ? kFmtNarrow : 0, false>(
+                        load_idx<float, NARROW ? kFmtNarrow : 0>(M, m.off + (int64_t)ci * kWave + lane), rw);
                     zv[u] = vp[(int64_t)ci * kWave];
                 }
                 float tv[U][R];

@@ -216,7 +216,7 @@ __device__ __forceinline__ T apply_row(const Nbr<T> &m, T vS, T vW, T vC, T vE, 
 
 // Slice header of the sliced-ELL layout (wave-uniform, scalar loads).
 struct SliceMeta {
-    int row0, lg, width;
+    int row0, lg, width, toff;
     int64_t off;
 };
 
@@ -224,13 +224,13 @@ struct SliceMeta {
 // coalesced load), handed out with readlane: the wave pays one memory round
 // trip for all its headers.
 struct SliceHeaders {
-    int row0, meta, off_lo, off_hi;
+    int row0, meta, off_lo, off_hi, toff;
 };
 
 template <typename T>
 __device__ __forceinline__ SliceHeaders load_headers(const DevSell<T> &M, int first, int stride,
                                                      int count, int lane) {
-    SliceHeaders h{0, 0, 0, 0};
+    SliceHeaders h{0, 0, 0, 0, -1};
     if (lane < count) {
         const int sl = first + lane * stride;
         h.row0 = M.row0[sl];
@@ -238,6 +238,7 @@ __device__ __forceinline__ SliceHeaders load_headers(const DevSell<T> &M, int fi
         const int64_t o = M.off[sl];
         h.off_lo = (int)(o & 0xffffffff);
         h.off_hi = (int)(o >> 32);
+        h.toff = M.toff[sl];
     }
     return h;
 }
@@ -250,6 +251,7 @@ __device__ __forceinline__ SliceMeta header_of(const SliceHeaders &h, int i) {
     m.width = mt >> 8;
     m.off = ((int64_t)__builtin_amdgcn_readlane(h.off_hi, i) << 32) |
             (uint32_t)__builtin_amdgcn_readlane(h.off_lo, i);
+    m.toff = __builtin_amdgcn_readlane(h.toff, i);
     return m;
 }
 
@@ -268,127 +270,161 @@ __device__ __forceinline__ P stream_load(const P *p) {
     return *p;
 }
 
-// Column of entry step c of this lane: the stored 32-bit column, or (narrow)
-// the lane's row (clamped to the matrix) minus (LOWER, Z^T) or plus (Z) the
-// stored 16-bit distance.
-template <typename T, int FMT, bool LOWER>
-__device__ __forceinline__ int entry_col(const DevSell<T> &M, int64_t pos, int rowc) {
+// One per-lane index (32-bit column or 16-bit distance), undecoded.
+template <typename T, int FMT>
+__device__ __forceinline__ int load_idx(const DevSell<T> &M, int64_t pos) {
     constexpr bool nt = (FMT & kFmtNtIdx) != 0;
-    if (FMT & kFmtNarrow) {
-        const int d = stream_load<nt>(M.dist + pos);
-        return LOWER ? rowc - d : rowc + d;
-    }
+    if (FMT & kFmtNarrow) return stream_load<nt>(M.dist + pos);
     return stream_load<nt>(M.idx + pos);
 }
 
-// Index/value loads of one unit (U consecutive entry steps of a slice, from
-// step cc); past the slice width the last entry is re-read and ignored.
-template <typename T, int U, int FMT, bool LOWER>
-__device__ __forceinline__ void load_unit(const DevSell<T> &M, const SliceMeta &m, int cc, int lane,
-                                          int (&kk)[U], T (&zv)[U]) {
-    const int last = m.width - 1;
-    const int row = m.row0 + (lane >> m.lg);
-    const int rowc = row < M.nrows ? row : M.nrows - 1;
-    const T *vp = M.val + m.off + lane;
-    if (last >= 0) {
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            const int c = cc + u <= last ? cc + u : last;
-            kk[u] = entry_col<T, FMT, LOWER>(M, m.off + (int64_t)c * kWave + lane, rowc);
-            zv[u] = stream_load<(FMT & kFmtNtVal) != 0>(vp + (int64_t)c * kWave);
-        }
-    } else {
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            kk[u] = rowc;
-            zv[u] = T(0);
-        }
-    }
+// Column of a per-lane index for a lane whose row (clamped to the matrix) is
+// rowc: Z^T (LOWER) stores row - col, Z stores col - row.
+template <int FMT, bool LOWER>
+__device__ __forceinline__ int entry_col(int kr, int rowc) {
+    if (FMT & kFmtNarrow) return LOWER ? rowc - kr : rowc + kr;
+    return kr;
 }
 
-// Software-pipelined pass over a wavefront's slices.  Work is a stream of
-// units; while the gathers and multiply-adds of unit u run, the index/value
-// loads of unit u+1 (and, at a slice boundary, the next slice's own-row
-// operands via ownf) are already in flight.  pre() runs once, after the
-// first unit's loads are issued and before any gather (the kernels reduce
-// the previous launch's partial sums there); it is called by every wave,
-// also one without slices, and the pass ends early when it returns false.
-// epi(m, acc, own) finishes a slice (called by all lanes; acc is this lane's
-// partial row sum, entries in increasing order).
+// Pass over a wavefront's slices (nsw of them: first, first + 4, ...; the
+// workgroup's waves interleave), slice by slice.
+//   Table slices (one lane per row, column offsets from the slice's table):
+//   the gathered column of step c is row + table[c], known as soon as the
+//   table (one load per slice, fetched while the previous slice runs) is in,
+//   so values and gathers of a chunk of U steps are issued together, the
+//   next chunk's loads in flight while the current one is accumulated.
+//   Other slices (several lanes per row, or rows too unlike each other): a
+//   per-lane column index is loaded first, then gathered, one chunk ahead.
+// ownf(m) loads a slice's own-row operands (issued one slice ahead); pre()
+// runs once, after the first slice's loads are issued and before any gather
+// (the kernels reduce the previous launch's partial sums there); it is called
+// by every wave, also one without slices, and the pass ends early when it
+// returns false.  epi(m, acc, own) finishes a slice (called by all lanes; acc
+// is this lane's partial row sum, entries in increasing column order).
 template <typename T, int U, int FMT, bool LOWER, typename Gth, typename OwnF, typename EpiF,
           typename PreF>
 __device__ __forceinline__ bool sell_stream(const DevSell<T> &M, int first, int nsw, int lane,
                                             const Gth &g, const OwnF &ownf, const EpiF &epi,
                                             const PreF &pre) {
     using Own = decltype(ownf(SliceMeta{}));
-    SliceHeaders hd{0, 0, 0, 0};
-    SliceMeta m{0, 0, 0, 0};
-    int kk[U];
-    T zv[U];
-    Own own{};
+    constexpr bool ntv = (FMT & kFmtNtVal) != 0;
+    const int nlast = M.nrows - 1;
+    SliceHeaders hd{0, 0, 0, 0, -1};
     int cnt = nsw < kWave ? nsw : kWave;
-    auto start_batch = [&](int i0) {
-        hd = load_headers(M, first + i0 * kWavesPerBlock, kWavesPerBlock, cnt, lane);
-        m = header_of(hd, 0);
-        load_unit<T, U, FMT, LOWER>(M, m, 0, lane, kk, zv);
-        own = ownf(m);
+    auto rowc_of = [&](const SliceMeta &m) {
+        const int row = m.row0 + (lane >> m.lg);
+        return row < M.nrows ? row : nlast;
     };
-    if (nsw > 0) start_batch(0);
+    // offset table of a table slice: lane c holds table[min(c, width - 1)]
+    auto load_tab = [&](const SliceMeta &m) {
+        int v = 0;
+        if (m.toff >= 0 && m.width > 0) v = M.tab[m.toff + (lane < m.width ? lane : m.width - 1)];
+        return v;
+    };
+    // values of steps c0..c0+U-1 (clamped to the last step; masked when summed)
+    auto load_vals = [&](const SliceMeta &m, int c0, T (&zv)[U]) {
+        const int last = m.width > 0 ? m.width - 1 : 0;
+        const int64_t base = m.width > 0 ? m.off + lane : 0;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int c = c0 + u <= last ? c0 + u : last;
+            zv[u] = stream_load<ntv>(M.val + base + (m.width > 0 ? (int64_t)c * kWave : 0));
+        }
+    };
+    // gathers of a table slice's steps c0..c0+U-1 for a lane whose row is rowc
+    auto gather_tab = [&](const SliceMeta &m, int tabv, int rowc, int c0, T (&gv)[U]) {
+        const int last = m.width > 0 ? m.width - 1 : 0;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int c = c0 + u <= last ? c0 + u : last;
+            const int o = __builtin_amdgcn_readlane(tabv, c);
+            int k = rowc + o;
+            k = k < 0 ? 0 : (k > nlast ? nlast : k);
+            gv[u] = g(k);
+        }
+    };
+    T acc = T(0);
+    auto accumulate = [&](const SliceMeta &m, int c0, const T (&zv)[U], const T (&gv)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; u++) acc = fma(c0 + u < m.width ? zv[u] : T(0), gv[u], acc);
+    };
+    // next slice's header, table and own-row operands (prefetched)
+    SliceMeta mn{0, 0, 0, -1, 0};
+    int tabn = 0;
+    Own ownn{};
+    auto prefetch = [&](int i) {
+        mn = header_of(hd, i);
+        tabn = load_tab(mn);
+        ownn = ownf(mn);
+    };
+    if (nsw > 0) {
+        hd = load_headers(M, first, kWavesPerBlock, cnt, lane);
+        prefetch(0);
+    }
     __builtin_amdgcn_sched_barrier(0);   // the loads above stay ahead of pre()
     if (!pre()) return false;
     for (int i0 = 0; i0 < nsw;) {
-        int i = 0, cc = 0;
-        T acc = T(0);
-        for (;;) {
-            int ni = i, ncc = cc + U;
-            SliceMeta nm = m;
-            const bool slice_end = ncc >= m.width;
-            if (slice_end) {
-                ni = i + 1;
-                ncc = 0;
-                if (ni < cnt) nm = header_of(hd, ni);
-            }
-            const bool more = ni < cnt;
-            int kk2[U];
-            T zv2[U];
-            Own own2 = own;
-            if (more) {
-                load_unit<T, U, FMT, LOWER>(M, nm, ncc, lane, kk2, zv2);
-                if (slice_end) own2 = ownf(nm);
-            }
-            T gv[U];
+        for (int i = 0; i < cnt; i++) {
+            const SliceMeta m = mn;
+            const int tabv = tabn;
+            const Own own = ownn;
+            if (i + 1 < cnt) prefetch(i + 1);
+            const int rowc = rowc_of(m);
+            if (m.toff >= 0) {
+                T za[U], ga[U], zb[U], gb[U];
+                load_vals(m, 0, za);
+                gather_tab(m, tabv, rowc, 0, ga);
+                int c0 = 0;
+                for (;;) {
+                    const bool more = c0 + U < m.width;
+                    if (more) {
+                        load_vals(m, c0 + U, zb);
+                        gather_tab(m, tabv, rowc, c0 + U, gb);
+                    }
+                    accumulate(m, c0, za, ga);
+                    if (!more) break;
+                    c0 += U;
+                    const bool more2 = c0 + U < m.width;
+                    if (more2) {
+                        load_vals(m, c0 + U, za);
+                        gather_tab(m, tabv, rowc, c0 + U, ga);
+                    }
+                    accumulate(m, c0, zb, gb);
+                    if (!more2) break;
+                    c0 += U;
+                }
+            } else {
+                for (int c0 = 0; c0 < m.width; c0 += U) {
+                    int kr[U];
+                    T zv[U], gv[U];
+                    const int last = m.width - 1;
 #pragma unroll
-            for (int u = 0; u < U; u++) gv[u] = g(kk[u]);
+                    for (int u = 0; u < U; u++) {
+                        const int c = c0 + u <= last ? c0 + u : last;
+                        kr[u] = load_idx<T, FMT>(M, m.off + (int64_t)c * kWave + lane);
+                    }
+                    load_vals(m, c0, zv);
 #pragma unroll
-            for (int u = 0; u < U; u++) acc = fma(cc + u < m.width ? zv[u] : T(0), gv[u], acc);
-            if (slice_end) {
-                epi(m, acc, own);
-                acc = T(0);
+                    for (int u = 0; u < U; u++) gv[u] = g(entry_col<FMT, LOWER>(kr[u], rowc));
+                    accumulate(m, c0, zv, gv);
+                }
             }
-            if (!more) break;
-            i = ni;
-            cc = ncc;
-            m = nm;
-            own = own2;
-#pragma unroll
-            for (int u = 0; u < U; u++) {
-                kk[u] = kk2[u];
-                zv[u] = zv2[u];
-            }
+            epi(m, acc, own);
+            acc = T(0);
         }
         i0 += kWave;
         if (i0 < nsw) {
             cnt = nsw - i0 < kWave ? nsw - i0 : kWave;
-            start_batch(i0);
+            hd = load_headers(M, first + i0 * kWavesPerBlock, kWavesPerBlock, cnt, lane);
+            prefetch(0);
         }
     }
     return true;
 }
 
-// Entry steps per unit: 2 (FP64) and 4 (FP32) keep the fused kernels at 7-8
-// wavefronts per SIMD; wider units measured slower (fewer waves in flight).
+// Entry steps per chunk (FP64 / FP32).
 #ifndef PCGA_PIPE_UD
-#define PCGA_PIPE_UD 2
+#define PCGA_PIPE_UD 4
 #endif
 #ifndef PCGA_PIPE_UF
 #define PCGA_PIPE_UF 4

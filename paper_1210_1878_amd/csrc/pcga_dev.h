@@ -52,6 +52,8 @@ struct DevSell {
     const int32_t *idx;      // columns, or null in the narrow form
     const uint16_t *dist;    // narrow form: |column - row| (direction fixed per matrix)
     const T *val;
+    const int32_t *toff;     // per slice: start of its offset table in tab, -1: per-lane indices
+    const int32_t *tab;      // offset tables (col - row, ascending)
     const int32_t *bounds;   // slice range of workgroup L: [bounds[L], bounds[L+1])
     const int32_t *bounds_b; // the same for the block count of a batch slot
     int32_t nslices, nrows;

@@ -51,6 +51,8 @@ struct SellLayout {
     std::vector<int32_t> row0;      // [nslices]
     std::vector<int32_t> meta;      // [nslices]: lpr_log2 | (width << 8)
     std::vector<int64_t> off;       // [nslices + 1] entry offsets
+    std::vector<int32_t> toff;      // [nslices] start of the slice's offset table in tab, -1: none
+    std::vector<int32_t> tab;       // offset tables (col - row, ascending) of table slices
     std::vector<int32_t> idx;       // [off.back()] (empty in the narrow form)
     std::vector<uint16_t> dist;     // [off.back()] (narrow form only)
     std::vector<double> val;        // [off.back()]

@@ -133,6 +133,8 @@ size_t carve(pcga_solver &S, void *base, const HostLayouts &H) {
         dst.row0 = C.take<int32_t>(L.nslices());
         dst.meta = C.take<int32_t>(L.nslices());
         dst.off = C.take<int64_t>(L.nslices() + 1);
+        dst.toff = C.take<int32_t>(std::max<int64_t>(L.nslices(), 1));
+        dst.tab = C.take<int32_t>(std::max<int64_t>((int64_t)L.tab.size(), 1));
         if (L.narrow) {
             dst.idx = nullptr;
             dst.dist = C.take<uint16_t>(std::max<int64_t>(L.entries(), 1));
@@ -515,6 +517,16 @@ int pcga_solver_create(const pcga_a5_t *A, const pcga_ainv_t *F, int precision, 
         if (e) return e;
         e = hipMemcpyAsync((void *)dst.off, L.off.data(), L.off.size() * 8, hipMemcpyHostToDevice, sm);
         if (e) return e;
+        if (!L.toff.empty()) {
+            e = hipMemcpyAsync((void *)dst.toff, L.toff.data(), L.toff.size() * 4,
+                               hipMemcpyHostToDevice, sm);
+            if (e) return e;
+        }
+        if (!L.tab.empty()) {
+            e = hipMemcpyAsync((void *)dst.tab, L.tab.data(), L.tab.size() * 4,
+                               hipMemcpyHostToDevice, sm);
+            if (e) return e;
+        }
         if (L.entries() == 0) return hipSuccess;
         if (L.narrow)
             e = hipMemcpyAsync((void *)dst.dist, L.dist.data(), L.dist.size() * 2, hipMemcpyHostToDevice, sm);
