@@ -212,7 +212,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--chunk", type=int, default=32)
-    ap.add_argument("--max-blocks", type=int, default=1280)
+    ap.add_argument("--max-blocks", type=int, default=0,
+                    help="workgroups per kernel; 0 = the solver's default (FP64 1280, mixed 1792)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched ensemble")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
@@ -369,7 +370,7 @@ def main():
                                "PCG to relres 1e-10 from x0=0",
                    "nx": NX, "ny": NY, "n": p.n, "nnz_off": G.nnz_off, "index_bytes": S64.index_bytes, "formats": {"fp64": S64.formats, "mixed": Smx.formats}, "tol": TOL,
                    "drop_tol": TAU, "iters_per_solve": fp64_iters, "chunk": args.chunk,
-                   "graph": not args.no_graph, "max_blocks": args.max_blocks},
+                   "graph": not args.no_graph, "max_blocks": args.max_blocks or "default: fp64 1280, mixed 1792"},
         "fp64": {"iters": fp64_iters, "ms_per_solve": round(dt * 1e3 / args.steps, 3),
                  "true_relres": fp64_true, "model_bytes_per_iter": b_iter,
                  "model_gbs_per_iter_kernels": round(b_iter / it_time / 1e9, 1),

@@ -152,8 +152,8 @@ int pcga_solver_info(const pcga_solver_t *S, int64_t *n, int64_t *nnz_off,
 /* Launch tuning (used by the autotuner): iterations per chunk (even,
  * 2..512), whether chunks are replayed through a captured HIP graph (1) or
  * launched directly (0), and the maximum number of workgroups per kernel
- * (8..2048, default 1280; each workgroup streams one contiguous range of the
- * grid).
+ * (8..2048; 0 selects the default, 1280 for PCGA_FP64 and 1792 for
+ * PCGA_MIXED; each workgroup streams one contiguous range of the grid).
  * Takes effect at the next solve.  Results of a solve are bitwise
  * reproducible for fixed settings. */
 int pcga_solver_tune(pcga_solver_t *S, int32_t chunk, int32_t use_graph, int32_t max_blocks);

@@ -188,7 +188,7 @@ class Solver:
     def handle(self):
         return self._h
 
-    def tune(self, chunk=32, use_graph=True, max_blocks=1280):
+    def tune(self, chunk=32, use_graph=True, max_blocks=0):
         check(_lib.load().pcga_solver_tune(self._h, int(chunk), int(bool(use_graph)),
                                            int(max_blocks)), "pcga_solver_tune")
 

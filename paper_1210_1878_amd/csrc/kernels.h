@@ -422,15 +422,21 @@ __device__ __forceinline__ bool sell_stream(const DevSell<T> &M, int first, int 
     return true;
 }
 
-// Entry steps per chunk (FP64 / FP32).
-#ifndef PCGA_PIPE_UD
-#define PCGA_PIPE_UD 4
+// Entry steps per chunk: FP64 for the Z^T sweep / the Z sweep, FP32 for both
+// (measured at 1442 x 1021: the FP64 Z^T sweep is fastest at 2, Z at 3).
+#ifndef PCGA_PIPE_UD_ZT
+#define PCGA_PIPE_UD_ZT 2
+#endif
+#ifndef PCGA_PIPE_UD_Z
+#define PCGA_PIPE_UD_Z 3
 #endif
 #ifndef PCGA_PIPE_UF
 #define PCGA_PIPE_UF 4
 #endif
-template <typename T>
-struct PipeUnroll { static constexpr int U = sizeof(T) == 8 ? PCGA_PIPE_UD : PCGA_PIPE_UF; };
+template <typename T, bool LOWER>
+struct PipeUnroll {
+    static constexpr int U = sizeof(T) == 8 ? (LOWER ? PCGA_PIPE_UD_ZT : PCGA_PIPE_UD_Z) : PCGA_PIPE_UF;
+};
 
 // Stopping test of Algorithm 1 on ||r_k||^2 = rr (every workgroup computes
 // the same): history entry k, and the solve ends when ||r_k|| / ||b|| <= tol,
@@ -605,7 +611,7 @@ __global__ __launch_bounds__(kBS) void k_zt(DevSell<T> Zt, const T *__restrict__
         return true;
     };
     const int nsw = (s1 - s0 - w + kWavesPerBlock - 1) / kWavesPerBlock;   // this wave's slices
-    if (!sell_stream<T, PipeUnroll<T>::U, FMT, true>(Zt, s0 + w, nsw, lane, g, ownf, epi, pre))
+    if (!sell_stream<T, PipeUnroll<T, true>::U, FMT, true>(Zt, s0 + w, nsw, lane, g, ownf, epi, pre))
         return;
     if (FUSED) {
         double pv[1] = {rr};
@@ -661,7 +667,7 @@ __global__ __launch_bounds__(kBS) void k_z(DevSell<T> Z, const T *__restrict__ t
         return !stop_test(cb, rr[0], k);
     };
     const int nsw = (s1 - s0 - w + kWavesPerBlock - 1) / kWavesPerBlock;   // this wave's slices
-    if (!sell_stream<T, PipeUnroll<T>::U, FMT, false>(Z, s0 + w, nsw, lane, g, ownf, epi, pre))
+    if (!sell_stream<T, PipeUnroll<T, false>::U, FMT, false>(Z, s0 + w, nsw, lane, g, ownf, epi, pre))
         return;
     if (DOT) {
         double pv[1] = {sr};

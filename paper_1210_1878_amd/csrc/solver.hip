@@ -456,6 +456,7 @@ int pcga_solver_create(const pcga_a5_t *A, const pcga_ainv_t *F, int precision, 
     pcga_solver *S = new (std::nothrow) pcga_solver;
     if (!S) return fail(PCGA_ENOMEM, "host allocation failed");
     S->precision = precision;
+    S->max_blocks = precision == PCGA_MIXED ? kDefaultBlocksMixed : kDefaultBlocks;
     S->n = n;
     S->nnz_off = F->F.nnz_off();
     S->jacobi = S->nnz_off == 0;
@@ -629,8 +630,9 @@ int pcga_solver_tune(pcga_solver_t *S, int32_t chunk, int32_t use_graph, int32_t
     if (!S) return fail(PCGA_EINVAL, "S is NULL");
     if (chunk < 2 || chunk > 512 || (chunk & 1))
         return fail(PCGA_EINVAL, "chunk must be even, 2..512");
+    if (max_blocks == 0) max_blocks = S->precision == PCGA_MIXED ? kDefaultBlocksMixed : kDefaultBlocks;
     if (max_blocks < 8 || max_blocks > kMaxBlocks)
-        return fail(PCGA_EINVAL, "max_blocks must be 8.." + std::to_string(kMaxBlocks));
+        return fail(PCGA_EINVAL, "max_blocks must be 0 or 8.." + std::to_string(kMaxBlocks));
     if (S->graph && (chunk != S->graph_chunk || max_blocks != S->max_blocks)) {
         (void)hipGraphExecDestroy(S->graph);
         S->graph = nullptr;
