@@ -57,12 +57,18 @@ KERNEL_SOURCES = ["paper_1210_1878_amd/csrc/kernels.h", "paper_1210_1878_amd/csr
 
 
 def kernel_source_hash():
-    """SHA-256 over the sources that define the iteration kernels and their launch."""
+    """SHA-256 over the code of the sources that define the iteration kernels
+    and their launch: comments and whitespace are removed first, so that an
+    edit of a comment does not void counters taken on the same code."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)   # block comments
+        text = re.sub(r"//[^\n]*", " ", text)                 # line comments
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

@@ -23,8 +23,9 @@
 // while others write new ones.
 //
 // Work split: a launch of G workgroups gives each workgroup one contiguous
-// range of cells, or of sliced-ELL slices balanced by their entry count (the
-// polar slices are much heavier than ocean-interior ones).  Workgroups are dispatched
+// range of cells, and each wavefront of the sliced-ELL kernels one contiguous
+// range of slices, balanced by a per-slice cost estimate (the polar slices
+// are much heavier than ocean-interior ones).  Workgroups are dispatched
 // round-robin over the 8 XCDs, so the hardware index is remapped to make the
 // ranges of one XCD contiguous: grid neighbours (rows above and below, rows a
 // Z column reaches) are then read from the same L2.
@@ -33,10 +34,9 @@
 // reduces the previous launch's partial sums, so that round trip overlaps
 // them.  The stencil issues every load of a step before any arithmetic
 // (branch-free neighbour indices).  The sliced-ELL kernels are software
-// pipelined: while one unit of a slice is gathered and accumulated, the
-// index/value loads of the next unit (and the next slice's own-row operands)
-// are in flight; the headers of all of a wavefront's slices come with one
-// load.
+// pipelined: while one chunk of a slice is accumulated, the value and gather
+// loads of the next chunk (and the next slice's own-row operands) are in
+// flight; the headers of all of a wavefront's slices come with one load.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -286,8 +286,7 @@ __device__ __forceinline__ int entry_col(int kr, int rowc) {
     return kr;
 }
 
-// Pass over a wavefront's slices (nsw of them: first, first + 4, ...; the
-// workgroup's waves interleave), slice by slice.
+// Pass over a wavefront's slices first .. first + nsw - 1, slice by slice.
 //   Table slices (one lane per row, column offsets from the slice's table):
 //   the gathered column of step c is row + table[c], known as soon as the
 //   table (one load per slice, fetched while the previous slice runs) is in,
@@ -295,6 +294,8 @@ __device__ __forceinline__ int entry_col(int kr, int rowc) {
 //   next chunk's loads in flight while the current one is accumulated.
 //   Other slices (several lanes per row, or rows too unlike each other): a
 //   per-lane column index is loaded first, then gathered, one chunk ahead.
+// g(k) loads the operands gathered at column k, raw; g.fin(v) makes the
+// vector value from them when the chunk is summed.
 // ownf(m) loads a slice's own-row operands (issued one slice ahead); pre()
 // runs once, after the first slice's loads are issued and before any gather
 // (the kernels reduce the previous launch's partial sums there); it is called
@@ -307,6 +308,7 @@ __device__ __forceinline__ bool sell_stream(const DevSell<T> &M, int first, int 
                                             const Gth &g, const OwnF &ownf, const EpiF &epi,
                                             const PreF &pre) {
     using Own = decltype(ownf(SliceMeta{}));
+    using GR = decltype(g(0));   // raw gathered operands; g.fin() makes the vector value
     constexpr bool ntv = (FMT & kFmtNtVal) != 0;
     const int nlast = M.nrows - 1;
     SliceHeaders hd{0, 0, 0, 0, -1};
@@ -332,7 +334,7 @@ __device__ __forceinline__ bool sell_stream(const DevSell<T> &M, int first, int 
         }
     };
     // gathers of a table slice's steps c0..c0+U-1 for a lane whose row is rowc
-    auto gather_tab = [&](const SliceMeta &m, int tabv, int rowc, int c0, T (&gv)[U]) {
+    auto gather_tab = [&](const SliceMeta &m, int tabv, int rowc, int c0, GR (&gv)[U]) {
         const int last = m.width > 0 ? m.width - 1 : 0;
 #pragma unroll
         for (int u = 0; u < U; u++) {
@@ -344,9 +346,9 @@ __device__ __forceinline__ bool sell_stream(const DevSell<T> &M, int first, int 
         }
     };
     T acc = T(0);
-    auto accumulate = [&](const SliceMeta &m, int c0, const T (&zv)[U], const T (&gv)[U]) {
+    auto accumulate = [&](const SliceMeta &m, int c0, const T (&zv)[U], const GR (&gv)[U]) {
 #pragma unroll
-        for (int u = 0; u < U; u++) acc = fma(c0 + u < m.width ? zv[u] : T(0), gv[u], acc);
+        for (int u = 0; u < U; u++) acc = fma(c0 + u < m.width ? zv[u] : T(0), g.fin(gv[u]), acc);
     };
     // next slice's header, table and own-row operands (prefetched)
     SliceMeta mn{0, 0, 0, -1, 0};
@@ -358,7 +360,7 @@ __device__ __forceinline__ bool sell_stream(const DevSell<T> &M, int first, int 
         ownn = ownf(mn);
     };
     if (nsw > 0) {
-        hd = load_headers(M, first, kWavesPerBlock, cnt, lane);
+        hd = load_headers(M, first, 1, cnt, lane);
         prefetch(0);
     }
     __builtin_amdgcn_sched_barrier(0);   // the loads above stay ahead of pre()
@@ -371,32 +373,37 @@ __device__ __forceinline__ bool sell_stream(const DevSell<T> &M, int first, int 
             if (i + 1 < cnt) prefetch(i + 1);
             const int rowc = rowc_of(m);
             if (m.toff >= 0) {
-                T za[U], ga[U], zb[U], gb[U];
+                T za[U], zb[U];
+                GR ga[U], gb[U];
                 load_vals(m, 0, za);
                 gather_tab(m, tabv, rowc, 0, ga);
+                // the last chunk is summed on its own exit path, so that a chunk
+                // summed inside the loop has the next chunk's loads issued on
+                // every path that reaches it
                 int c0 = 0;
                 for (;;) {
-                    const bool more = c0 + U < m.width;
-                    if (more) {
-                        load_vals(m, c0 + U, zb);
-                        gather_tab(m, tabv, rowc, c0 + U, gb);
+                    if (c0 + U >= m.width) {
+                        accumulate(m, c0, za, ga);
+                        break;
                     }
+                    load_vals(m, c0 + U, zb);
+                    gather_tab(m, tabv, rowc, c0 + U, gb);
                     accumulate(m, c0, za, ga);
-                    if (!more) break;
                     c0 += U;
-                    const bool more2 = c0 + U < m.width;
-                    if (more2) {
-                        load_vals(m, c0 + U, za);
-                        gather_tab(m, tabv, rowc, c0 + U, ga);
+                    if (c0 + U >= m.width) {
+                        accumulate(m, c0, zb, gb);
+                        break;
                     }
+                    load_vals(m, c0 + U, za);
+                    gather_tab(m, tabv, rowc, c0 + U, ga);
                     accumulate(m, c0, zb, gb);
-                    if (!more2) break;
                     c0 += U;
                 }
             } else {
                 for (int c0 = 0; c0 < m.width; c0 += U) {
                     int kr[U];
-                    T zv[U], gv[U];
+                    T zv[U];
+                    GR gv[U];
                     const int last = m.width - 1;
 #pragma unroll
                     for (int u = 0; u < U; u++) {
@@ -415,7 +422,7 @@ __device__ __forceinline__ bool sell_stream(const DevSell<T> &M, int first, int 
         i0 += kWave;
         if (i0 < nsw) {
             cnt = nsw - i0 < kWave ? nsw - i0 : kWave;
-            hd = load_headers(M, first + i0 * kWavesPerBlock, kWavesPerBlock, cnt, lane);
+            hd = load_headers(M, first + i0, 1, cnt, lane);
             prefetch(0);
         }
     }
@@ -423,9 +430,9 @@ __device__ __forceinline__ bool sell_stream(const DevSell<T> &M, int first, int 
 }
 
 // Entry steps per chunk: FP64 for the Z^T sweep / the Z sweep, FP32 for both
-// (measured at 1442 x 1021: the FP64 Z^T sweep is fastest at 2, Z at 3).
+// (measured at 1442 x 1021 over 2..4).
 #ifndef PCGA_PIPE_UD_ZT
-#define PCGA_PIPE_UD_ZT 2
+#define PCGA_PIPE_UD_ZT 3
 #endif
 #ifndef PCGA_PIPE_UD_Z
 #define PCGA_PIPE_UD_Z 3
@@ -562,10 +569,21 @@ __global__ __launch_bounds__(kBS) void k_zt(DevSell<T> Zt, const T *__restrict__
     const int G = gridDim.x, L = logical_block(blockIdx.x, G);
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
-    const int s0 = Zt.bounds[L], s1 = Zt.bounds[L + 1];
+    const int v = L * kWavesPerBlock + w;   // this wave's contiguous slice range
+    const int s0 = Zt.bounds[v], s1 = Zt.bounds[v + 1];
     double rr = 0.0;
     T at = T(0);
-    auto g = [&](int kk) { return FUSED ? fma(-at, q[kk], rcur[kk]) : rcur[kk]; };
+    // gathered r' = r - alpha q: loaded raw, combined only when summed (an
+    // operation on a load right after it is issued would wait for it)
+    struct GZt {
+        T r, q;
+    };
+    struct {
+        const T *rc, *qq;
+        const T *pat;
+        __device__ GZt operator()(int kk) const { return GZt{rc[kk], FUSED ? qq[kk] : T(0)}; }
+        __device__ T fin(const GZt &v) const { return FUSED ? fma(-*pat, v.q, v.r) : v.r; }
+    } g{rcur, q, &at};
     // own-row operands of a slice, raw (alpha is not known when the first is loaded)
     struct OwnZt {
         T rj, qj, dj, xj, ij;
@@ -610,8 +628,7 @@ __global__ __launch_bounds__(kBS) void k_zt(DevSell<T> Zt, const T *__restrict__
         at = (T)alpha;
         return true;
     };
-    const int nsw = (s1 - s0 - w + kWavesPerBlock - 1) / kWavesPerBlock;   // this wave's slices
-    if (!sell_stream<T, PipeUnroll<T, true>::U, FMT, true>(Zt, s0 + w, nsw, lane, g, ownf, epi, pre))
+    if (!sell_stream<T, PipeUnroll<T, true>::U, FMT, true>(Zt, s0, s1 - s0, lane, g, ownf, epi, pre))
         return;
     if (FUSED) {
         double pv[1] = {rr};
@@ -634,9 +651,14 @@ __global__ __launch_bounds__(kBS) void k_z(DevSell<T> Z, const T *__restrict__ t
     const int G = gridDim.x, L = logical_block(blockIdx.x, G);
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
-    const int s0 = Z.bounds[L], s1 = Z.bounds[L + 1];
+    const int v = L * kWavesPerBlock + w;   // this wave's contiguous slice range
+    const int s0 = Z.bounds[v], s1 = Z.bounds[v + 1];
     double sr = 0.0;
-    auto g = [&](int jj) { return t[jj]; };
+    struct {
+        const T *tt;
+        __device__ T operator()(int jj) const { return tt[jj]; }
+        __device__ T fin(T v) const { return v; }
+    } g{t};
     struct OwnZ {
         T tk, rk;
     };
@@ -666,8 +688,7 @@ __global__ __launch_bounds__(kBS) void k_z(DevSell<T> Z, const T *__restrict__ t
         if (blockIdx.x == 0 && threadIdx.x == 0) c->kk[par ^ 1] = k;
         return !stop_test(cb, rr[0], k);
     };
-    const int nsw = (s1 - s0 - w + kWavesPerBlock - 1) / kWavesPerBlock;   // this wave's slices
-    if (!sell_stream<T, PipeUnroll<T, false>::U, FMT, false>(Z, s0 + w, nsw, lane, g, ownf, epi, pre))
+    if (!sell_stream<T, PipeUnroll<T, false>::U, FMT, false>(Z, s0, s1 - s0, lane, g, ownf, epi, pre))
         return;
     if (DOT) {
         double pv[1] = {sr};

@@ -56,7 +56,7 @@ struct DevSell {
     const T *val;
     const int32_t *toff;     // per slice: start of its offset table in tab, -1: per-lane indices
     const int32_t *tab;      // offset tables (col - row, ascending)
-    const int32_t *bounds;   // slice range of workgroup L: [bounds[L], bounds[L+1])
+    const int32_t *bounds;   // slice range of wave v = L * kWavesPerBlock + w: [bounds[v], bounds[v+1])
     const int32_t *bounds_b; // the same for the block count of a batch slot
     int32_t nslices, nrows;
 };

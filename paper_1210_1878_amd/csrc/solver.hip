@@ -180,8 +180,8 @@ size_t carve(pcga_solver &S, void *base, const HostLayouts &H) {
         S.x64[0] = C.take<double>(n);
         S.x64[1] = C.take<double>(n);
     }
-    S.bnd_zt = C.take<int32_t>(kMaxBlocks + 1);
-    S.bnd_z = C.take<int32_t>(kMaxBlocks + 1);
+    S.bnd_zt = C.take<int32_t>(kWavesPerBlock * kMaxBlocks + 1);
+    S.bnd_z = C.take<int32_t>(kWavesPerBlock * kMaxBlocks + 1);
     S.bnd_zt_b = C.take<int32_t>(kMaxBlocks + 1);
     S.bnd_z_b = C.take<int32_t>(kMaxBlocks + 1);
     S.P.dq = C.take<double>(kMaxBlocks);
@@ -216,15 +216,24 @@ int check_a5(const pcga_a5_t *A) {
 
 constexpr int kTargetWidth = 16;
 
-// Per-slice work estimate: its stored entries plus one row's worth of
-// own-row loads and stores.
+// Per-slice work estimate, in units of about 10 ns of one wavefront's time:
+// a fixed part (headers, own-row operands, the pipeline's drain at the end of
+// the slice) plus a part per entry step, which costs a slice with per-lane
+// indices (index load, then gather) more than twice what it costs a table
+// slice.  Fitted to per-wavefront timings of the FP64 Z^T and Z sweeps at
+// 1442 x 1021 (table: 1.6 us + 0.14-0.20 us per step; per-lane: 0.6-1.2 us
+// + 0.37-0.44 us per step).
 std::vector<int32_t> slice_costs(const SellLayout &L) {
     std::vector<int32_t> c(L.nslices());
-    for (int64_t s = 0; s < L.nslices(); s++) c[s] = ((L.meta[s] >> 8) + 1) * 64;
+    for (int64_t s = 0; s < L.nslices(); s++) {
+        const int32_t width = L.meta[s] >> 8;
+        c[s] = L.toff[s] >= 0 ? 160 + 17 * width : 90 + 40 * width;
+    }
     return c;
 }
 
-// Contiguous slice ranges for G workgroups with equal estimated work.
+// Contiguous slice ranges for G parts (wavefronts, or workgroups of a batch
+// slot) with equal estimated work.
 std::vector<int32_t> balanced_bounds(const std::vector<int32_t> &cost, int G) {
     const int64_t ns = (int64_t)cost.size();
     std::vector<int32_t> b(G + 1, 0);
@@ -265,8 +274,8 @@ void cache_plan(pcga_solver &S, const HostLayouts &H) {
 }
 
 int upload_bounds(pcga_solver &S) {
-    const std::vector<int32_t> bz = balanced_bounds(S.cost_zt, S.g_zt);
-    const std::vector<int32_t> b = balanced_bounds(S.cost_z, S.g_z);
+    const std::vector<int32_t> bz = balanced_bounds(S.cost_zt, S.g_zt * kWavesPerBlock);
+    const std::vector<int32_t> b = balanced_bounds(S.cost_z, S.g_z * kWavesPerBlock);
     const int gb = slot_blocks(S.n);
     const std::vector<int32_t> bzb = balanced_bounds(S.cost_zt, gb);
     const std::vector<int32_t> bb = balanced_bounds(S.cost_z, gb);

@@ -61,7 +61,7 @@ struct pcga_solver {
     float *zb32 = nullptr;
     int g_prec() const { return band_q > 0 ? g_st : g_z; }   // workgroups writing (s,r) partials
     std::vector<int32_t> cost_zt, cost_z;    // per-slice work estimates (host)
-    int32_t *bnd_zt = nullptr, *bnd_z = nullptr;   // device: workgroup slice ranges
+    int32_t *bnd_zt = nullptr, *bnd_z = nullptr;   // device: wavefront slice ranges
     int32_t *bnd_zt_b = nullptr, *bnd_z_b = nullptr;   // device: ranges for a batch slot
     double bytes_per_iter = 0.0;
 
