@@ -157,7 +157,11 @@ def bench_batch(P, torch, dev, log, members=64, nrhs=4):
             "speedup_vs_sequential": round(dts / dt, 2)}
 
 
-def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=10.0):
+SERVE_CLASS_CELLS = (2_000_000,)
+
+
+def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=10.0,
+                class_cells=SERVE_CLASS_CELLS):
     """Time-step solves on a catalogue of resident grids from 182x149 to
     4322x3059 (mixed precision to 1e-10, warm starts, continuous batching).
     Capacity first: a closed loop keeps every grid busy and gives each grid's
@@ -170,7 +174,7 @@ def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=
               (1442, 1021), (4322, 3059)]
     t0 = time.perf_counter()
     probs = [orca.orca_problem(nx, ny, orca.CONFIG_SEED_BASE + 40 + i) for i, (nx, ny) in enumerate(shapes)]
-    srv = serve.Server(probs, drop_tol=0.05, device=dev, chunk=16)
+    srv = serve.Server(probs, drop_tol=0.05, device=dev, chunk=16, class_cells=class_cells)
     log(f"serving: {len(probs)} resident grids ({srv.resident_bytes / 2**30:.2f} GiB), "
         f"setup {time.perf_counter() - t0:.1f}s")
     stepper = serve.TimeStepper(probs, dev, seed=CONFIG_SERVE_SEED)
@@ -186,8 +190,8 @@ def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=
                        "continuous batching; per-grid Poisson arrivals at a load factor of "
                        "each grid's closed-loop throughput",
            "grids": [f"{a}x{b}" for a, b in shapes],
-           "size_classes": "class 0: grids under 2M cells, class 1: the 4322x3059 grid; one "
-                           "batch per class, each on its own stream, running concurrently",
+           "size_classes": "grids split at " + ", ".join(f"{c:,} cells" for c in sorted(class_cells))
+                           + "; one batch per class, each on its own stream, running concurrently",
            "grid_class": srv.klass,
            "capacity_solves_per_s": round(sum(cap), 2),
            "capacity_per_grid": [round(c, 3) for c in cap],
