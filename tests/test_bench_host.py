@@ -1,0 +1,79 @@
+"""Host logic of bench.py (no GPU): the algorithmic byte model of the
+iteration kernels, the guard that ties committed counter readings to the
+kernel code they were taken on, and the single-GPU refusal of --gpus N."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+@pytest.mark.parametrize("word,b", [(8, 2), (8, 4), (4, 2)])
+def test_kernel_bytes_model(word, b):
+    # each array once: stencil reads s, d_old and the FP64 operator (24 B per
+    # cell) and writes d, q; the Z^T pass reads r, q, d, x, D^-1 and writes
+    # r', x, t; the Z pass reads t, r' and writes s; every nonzero of Z is read
+    # once per pass as a value and an index
+    n, E = 1000, 7777
+    kb = bench.kernel_bytes(n, E, word, b)
+    assert kb["stencil"] == 4 * word * n + 24 * n
+    assert kb["axpy_zt"] == 8 * word * n + (word + b) * E
+    assert kb["z_dot"] == 3 * word * n + (word + b) * E
+    if word == 8:
+        assert sum(kb.values()) == 144 * n + 2 * (8 + b) * E
+
+
+def test_kernel_names_carry_formats():
+    k = bench.kernel_names(8, (3, 7))
+    assert k == {"stencil": "k_stencil<double, false>", "axpy_zt": "k_zt<double, true, 3>",
+                 "z_dot": "k_z<double, true, false, 7>"}
+    assert bench.kernel_names(4, (1, 1))["z_dot"] == "k_z<float, true, false, 1>"
+
+
+def _hash_of(monkeypatch, tmp_path, texts):
+    files = []
+    for i, t in enumerate(texts):
+        f = tmp_path / f"src{i}.h"
+        f.write_text(t)
+        files.append(str(f))
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", files)
+    return bench.kernel_source_hash()
+
+
+def test_source_hash_ignores_comments_not_code(monkeypatch, tmp_path):
+    base = _hash_of(monkeypatch, tmp_path, ["int f(int a) {\n    return a + 1;\n}\n"])
+    commented = _hash_of(monkeypatch, tmp_path, [
+        "// the successor\n/* of a,\n   in int */\nint f(int a) {   // one more\n\n    return a + 1;\n}\n"])
+    changed = _hash_of(monkeypatch, tmp_path, ["int f(int a) {\n    return a + 2;\n}\n"])
+    assert commented == base
+    assert changed != base
+
+
+def test_measured_traffic_only_for_matching_code(monkeypatch, tmp_path):
+    h = _hash_of(monkeypatch, tmp_path, ["int g;\n"])
+    rec = {"source_sha256": h, "profile": "profiles/x.md",
+           "kernels": {"k_zt<double, true, 3>": {"hbm_bytes_per_launch": 123456}}}
+    cf = tmp_path / "counters.json"
+    cf.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "COUNTER_FILE", str(cf))
+    assert bench.measured_traffic("k_zt<double, true, 3>") == (123456, "profiles/x.md")
+    assert bench.measured_traffic("k_z<double, true, false, 7>")[0] is None
+    rec["source_sha256"] = "0" * 64
+    cf.write_text(json.dumps(rec))
+    val, why = bench.measured_traffic("k_zt<double, true, 3>")
+    assert val is None and "changed" in why
+    monkeypatch.setattr(bench, "COUNTER_FILE", str(tmp_path / "missing.json"))
+    assert bench.measured_traffic("k_zt<double, true, 3>")[0] is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
