@@ -53,7 +53,11 @@ def kernel_bytes(n, nnz_off, word, index_bytes=4):
 
 COUNTER_FILE = os.path.join(ROOT, "profiles", "pcg_iteration_kernels_1442x1021_hbm_traffic.json")
 KERNEL_SOURCES = ["paper_1210_1878_amd/csrc/kernels.h", "paper_1210_1878_amd/csrc/pcga_dev.h",
-                  "paper_1210_1878_amd/csrc/solver.hip"]
+                  "paper_1210_1878_amd/csrc/solver.hip", "paper_1210_1878_amd/csrc/timestep.hip"]
+# Time-step passes around the solve: algorithmic bytes per cell (each array once)
+TS_KERNEL_BYTES = {"k_ts_rhs": 40,          # e2u, Mu, e1v, Mv in; b out
+                   "k_ts_guess<true>": 24,  # D^{t-1}, D^{t-2} in; x0 out
+                   "k_ts_eta": 24}          # eta^{n-1}, D^n in; eta^{n+1} out
 
 
 def kernel_source_hash():
@@ -158,6 +162,7 @@ def bench_batch(P, torch, dev, log, members=64, nrhs=4):
 
 
 SERVE_CLASS_CELLS = (2_000_000,)
+SERVE_GUESS = (2.0, -1.0)      # x0 = 2 D^{t-1} - D^{t-2}
 
 
 def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=10.0,
@@ -177,7 +182,8 @@ def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=
     srv = serve.Server(probs, drop_tol=0.05, device=dev, chunk=16, class_cells=class_cells)
     log(f"serving: {len(probs)} resident grids ({srv.resident_bytes / 2**30:.2f} GiB), "
         f"setup {time.perf_counter() - t0:.1f}s")
-    stepper = serve.TimeStepper(probs, dev, seed=CONFIG_SERVE_SEED)
+    stepper = serve.CoupledTimeStepper(probs, srv.solvers, dev, seed=CONFIG_SERVE_SEED,
+                                       guess=SERVE_GUESS)
     # warm-up: one step per grid (graph capture, first touch)
     warm = [serve.Request(rid=-1 - g, grid=g, arrival=0.0) for g in range(len(probs))]
     srv.run(warm, make_rhs=stepper, on_done=stepper.done)
@@ -185,10 +191,11 @@ def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=
     cap = [sum(1 for r in done if r.grid == g) / el for g in range(len(probs))]
     log(f"capacity (closed loop, {el:.1f}s): {sum(cap):.1f} solves/s; per grid "
         + ", ".join(f"{a}x{b}: {c:.2f}" for (a, b), c in zip(shapes, cap)))
-    out = {"workload": "warm-started time steps (b_t = b_{t-1} + 1% noise) on 8 resident "
-                       "ORCA-shaped grids 182x149 .. 4322x3059, mixed precision to 1e-10, "
-                       "continuous batching; per-grid Poisson arrivals at a load factor of "
-                       "each grid's closed-loop throughput",
+    out = {"workload": "coupled time steps (right-hand side of eq. (8) from seeded, slowly "
+                       "varying face transports; first guess x0 = 2 D^{t-1} - D^{t-2}; "
+                       "eq. (1) height update) on 8 resident ORCA-shaped grids 182x149 .. "
+                       "4322x3059, mixed precision to 1e-10, continuous batching; per-grid "
+                       "Poisson arrivals at a load factor of each grid's closed-loop throughput",
            "grids": [f"{a}x{b}" for a, b in shapes],
            "size_classes": "grids split at " + ", ".join(f"{c:,} cells" for c in sorted(class_cells))
                            + "; one batch per class, each on its own stream, running concurrently",
@@ -212,6 +219,54 @@ def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=
 
 
 CONFIG_SERVE_SEED = 1878 + 4
+CONFIG_TS_SEED = 1878 + 5
+
+
+def bench_timestep(P, torch, S, p, log, steps=10, dt_step=0.5):
+    """Coupled time steps around the FP64 solve on the benchmark grid: per step
+    the right-hand side of eq. (8) from that step's face transports (seeded,
+    slowly varying), the first guess of Algorithm 1 from earlier solutions,
+    the solve to 1e-10 and the sea-surface update of eq. (1).  Run once per
+    reading of the first guess (the paper writes x0 = 2 D^{t-1}); iterations
+    and time per step are averaged over the steps after the first two."""
+    import numpy as np
+    from gen import orca
+    dev = torch.device("cuda:0")
+    faces = [[torch.from_numpy(f).to(dev) for f in orca.orca_transports(p, t, CONFIG_TS_SEED)]
+             for t in range(steps)]
+    readings = {"zero": None, "previous": (1.0, 0.0), "printed_2D": (2.0, 0.0),
+                "extrapolated": (2.0, -1.0)}
+    res = {}
+    for name, g in readings.items():
+        zero = torch.zeros(p.n, dtype=torch.float64, device=dev)
+        eta = [zero, zero.clone()]
+        D, iters, times = [], [], []
+        for t in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b = S.ts_rhs(*faces[t])
+            if g is None or not D:
+                x0 = None
+            elif g[1] == 0.0:
+                x0 = S.ts_guess(D[-1], None, g[0], 0.0)
+            elif len(D) == 1:
+                x0 = S.ts_guess(D[-1], None, 1.0, 0.0)
+            else:
+                x0 = S.ts_guess(D[-1], D[-2], g[0], g[1])
+            r = S.solve(b, x0, tol=TOL)
+            eta = [eta[1], S.ts_eta(eta[0], r.x, dt_step)]
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            iters.append(r.iters)
+            D = (D + [r.x])[-2:]
+        res[name] = {"iters_per_step": iters, "mean_iters": round(float(np.mean(iters[2:])), 1),
+                     "ms_per_step": round(float(np.mean(times[2:])) * 1e3, 2)}
+    log(f"time steps ({steps}, 1442x1021, FP64): "
+        + ", ".join(f"x0 {k}: {v['mean_iters']} it, {v['ms_per_step']} ms/step" for k, v in res.items()))
+    return {"workload": f"{steps} coupled time steps on the 1442x1021 grid: b from seeded, slowly "
+                        "varying face transports (eq. (8)), FP64 solve to 1e-10 from the first "
+                        "guess of each reading, eta update (eq. (1)); means over steps 3..",
+            "readings": res}
 
 
 def main():
@@ -227,6 +282,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched ensemble")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-timestep", action="store_true", help="skip the coupled time steps")
     ap.add_argument("--kernels-only", action="store_true",
                     help="profiling driver: a 256 MiB device copy (counter calibration), then the "
                          "three FP64 and FP32 iteration kernels, --reps launches each")
@@ -269,6 +325,14 @@ def main():
         torch.cuda.synchronize()
         ms = S64.profile_iteration(b, reps=args.reps, mode=1)
         ms32 = Smx.profile_iteration(b, reps=args.reps, mode=1)
+        # the time-step passes around the solve, for the kernel trace
+        from gen import orca
+        faces = [torch.from_numpy(f).to(dev) for f in orca.orca_transports(p, 0, CONFIG_TS_SEED)]
+        for _ in range(20):
+            S64.ts_rhs(*faces)
+            S64.ts_guess(faces[1], faces[3], 2.0, -1.0)
+            S64.ts_eta(faces[1], faces[3], 0.5)
+        torch.cuda.synchronize()
         kb = kernel_bytes(p.n, G.nnz_off, 8, S64.index_bytes)
         kb32 = kernel_bytes(p.n, G.nnz_off, 4, Smx.index_bytes)
         for tag, t, byt in (("fp64", ms, kb), ("fp32", ms32, kb32)):
@@ -337,6 +401,9 @@ def main():
     dtb = time.perf_counter() - t0
     log(f"banded factor of T (q=4, diagonal storage): {rb.iters} iterations, {dtb * 1e3:.2f} ms/solve")
 
+    # ---- the time step around the solve (eq. (1), eq. (8), first guess) ----
+    tstep = None if args.no_timestep else bench_timestep(P, torch, S64, p, log)
+
     # ---- roofline of the dominant kernel (HIP events on the solver stream) --
     ms = S64.profile_iteration(b, reps=100, mode=1)
     ms32 = Smx.profile_iteration(b, reps=100, mode=1)
@@ -397,6 +464,7 @@ def main():
                    "true_relres": rj.true_relres},
         "band_factor_q4": {"iters": rb.iters, "ms_per_solve": round(dtb * 1e3, 3),
                            "true_relres": rb.true_relres, "band_q": Sb.band_q},
+        "timestep": tstep,
         "batched": batched,
         "served": served,
         "setup_s": round(setup_s, 3),

@@ -202,9 +202,19 @@ def _land_mask(nx, ny, lam, phi, rng, land_frac=0.35, blobs=12):
     return f < thr
 
 
-def orca_problem(nx, ny, seed, land_frac=0.35, rhs=True):
-    """ORCA-shaped lon/lat grid: phi in [-78, 90] degrees, EW periodic."""
-    rng = np.random.default_rng(seed)
+@dataclasses.dataclass
+class Geometry:
+    """Lon/lat geometry of the ORCA-shaped grid (radians)."""
+    lam: np.ndarray      # [nx] cell-centre longitudes
+    phi_c: np.ndarray    # [ny] cell-centre latitudes
+    phi_f: np.ndarray    # [ny+1] face latitudes (j-1/2 for j = 0..ny)
+    cos_f: np.ndarray    # [ny+1] cos of the face latitudes (0 at the pole)
+    dlam: float
+    dphi: float
+
+
+def orca_geometry(nx, ny) -> Geometry:
+    """phi in [-78, 90] degrees, EW periodic, uniform spacings."""
     dphi_deg = 168.0 / ny
     dlam = 2.0 * np.pi / nx
     dphi = math.radians(dphi_deg)
@@ -214,6 +224,14 @@ def orca_problem(nx, ny, seed, land_frac=0.35, rhs=True):
     phi_f = np.radians(-78.0 + np.arange(ny + 1) * dphi_deg)
     cos_f = np.cos(phi_f)
     cos_f[-1] = 0.0        # fl(cos(pi/2)) != 0: the polar face carries nothing
+    return Geometry(lam, phi_c, phi_f, cos_f, dlam, dphi)
+
+
+def orca_problem(nx, ny, seed, land_frac=0.35, rhs=True):
+    """ORCA-shaped lon/lat grid: phi in [-78, 90] degrees, EW periodic."""
+    rng = np.random.default_rng(seed)
+    geo = orca_geometry(nx, ny)
+    dlam, dphi, lam, phi_c, cos_f = geo.dlam, geo.dphi, geo.lam, geo.phi_c, geo.cos_f
 
     H = _bathymetry(nx, ny, lam, phi_c, rng)
     ocean = _land_mask(nx, ny, lam, phi_c, rng, land_frac=land_frac)
@@ -253,3 +271,79 @@ def ensemble_problems(count=64, seed=CONFIG_SEED_BASE + 3, nrhs=4,
         p.B = np.stack([rhs_normal(p.ocean, rr) for _ in range(nrhs)])
         out.append(p)
     return out
+
+
+@dataclasses.dataclass
+class TransportModes:
+    """Face transports of an ORCA-shaped grid as fixed spatial fields and time
+    factors: Mu(t) = base_u + sum_m (cos(w_m t) cu_m + sin(w_m t) su_m) on open
+    east faces (likewise Mv on open north faces, base_v = 0), zero on faces
+    that touch land or close the domain.  Fields are [n], stored at the cell
+    west (east faces) or south (north faces) of the face."""
+    w: list
+    base_u: np.ndarray
+    cu: list
+    su: list
+    cv: list
+    sv: list
+    e2u: np.ndarray           # east-face metric factor e2 = dphi (radius dropped)
+    e1v: np.ndarray           # north-face metric factor e1 = cos(phi) dlam
+
+
+def orca_transport_modes(p: Problem, seed: int) -> TransportModes:
+    """A zonal band flow plus four planetary-scale modes travelling slowly in
+    time (periods of 150-400 steps), seeded; see TransportModes."""
+    nx, ny = p.nx, p.ny
+    geo = orca_geometry(nx, ny)
+    rng = np.random.default_rng(seed)
+    ocean = p.ocean.reshape(ny, nx)
+    open_e = (ocean & np.roll(ocean, -1, axis=1)).ravel()       # periodic in longitude
+    open_n = np.zeros_like(ocean)
+    open_n[:-1, :] = ocean[:-1, :] & ocean[1:, :]
+    open_n = open_n.ravel()
+    lam_e = geo.lam + 0.5 * geo.dlam                           # east-face longitudes
+    phi_n = geo.phi_f[1:]                                      # north-face latitudes
+    base_u = np.where(open_e, (0.8 * np.cos(3.0 * geo.phi_c)[:, None] * np.ones((1, nx))).ravel(), 0.0)
+    w, cu, su, cv, sv = [], [], [], [], []
+    for _ in range(4):
+        k = int(rng.integers(1, 6))
+        l = int(rng.integers(1, 5))
+        amp = rng.uniform(0.2, 0.6)
+        w.append(2.0 * np.pi / rng.uniform(150.0, 400.0))
+        ps = rng.uniform(0.0, 2.0 * np.pi)
+        # cos(k lam - w t + ps) = cos(w t) cos(k lam + ps) + sin(w t) sin(k lam + ps)
+        # sin(k lam - w t + ps) = cos(w t) sin(k lam + ps) - sin(w t) cos(k lam + ps)
+        su_amp = amp * np.sin(l * geo.phi_c)[:, None]
+        sv_amp = amp * np.cos(l * phi_n)[:, None]
+        ce, se = np.cos(k * lam_e + ps)[None, :], np.sin(k * lam_e + ps)[None, :]
+        cc, sc = np.cos(k * geo.lam + ps)[None, :], np.sin(k * geo.lam + ps)[None, :]
+        cu.append(np.where(open_e, (su_amp * ce).ravel(), 0.0))
+        su.append(np.where(open_e, (su_amp * se).ravel(), 0.0))
+        cv.append(np.where(open_n, (sv_amp * sc).ravel(), 0.0))
+        sv.append(np.where(open_n, (-sv_amp * cc).ravel(), 0.0))
+    e2u = np.full(nx * ny, geo.dphi)
+    e1v = np.repeat(geo.cos_f[1:] * geo.dlam, nx)
+    return TransportModes(w, base_u, cu, su, cv, sv, e2u, e1v)
+
+
+def combine_transports(m: TransportModes, t: int):
+    """(Mu, Mv) of time step t from the modes."""
+    mu = m.base_u.copy()
+    mv = np.zeros_like(m.base_u)
+    for w, cu, su, cv, sv in zip(m.w, m.cu, m.su, m.cv, m.sv):
+        c, s = math.cos(w * t), math.sin(w * t)
+        mu += c * cu + s * su
+        mv += c * cv + s * sv
+    return mu, mv
+
+
+def orca_transports(p: Problem, t: int, seed: int):
+    """Synthetic face transports of time step t for the right-hand side of
+    eq. (8) (see orca_transport_modes).  Returns (e2u, mu, e1v, mv), each
+    [nx*ny]: east-face metric factor e2 = dphi and transport Mu (at the cell
+    west of the face), north-face metric factor e1 = cos(phi) dlam and
+    transport Mv (at the cell south of the face); the radius is dropped as in
+    the operator's coefficients."""
+    m = orca_transport_modes(p, seed)
+    mu, mv = combine_transports(m, t)
+    return m.e2u, mu, m.e1v, mv

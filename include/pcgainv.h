@@ -213,6 +213,38 @@ int pcga_apply_prec(pcga_solver_t *S, const double *r_dev, double *t_dev, double
 int pcga_profile_iteration(pcga_solver_t *S, const double *b_dev, int32_t reps, int32_t mode,
                            double *ms_out);
 
+/* ---- the time step around the solve ----------------------------------------
+ * The elliptic solve is one stage of the sea-surface time step (Sec. 2,
+ * eq. (1)-(2)).  These passes produce a step's right-hand side and first
+ * guess and advance the sea-surface height, on the solver's grid (nx, ny,
+ * periodicity) and stream; all pointers are device arrays of n = nx*ny FP64
+ * values owned by the caller.  They are queued on the solver's stream and
+ * return without waiting for it.  Errors: EINVAL (NULL pointer, bad dt),
+ * EHIP.
+ *
+ * pcga_ts_rhs: the right-hand side of eq. (8),
+ *   b = -(delta_i(e2 Mu) - delta_j(e1 Mv)),
+ * negated like the operator (the system solved is the negation of
+ * eq. (10)).  delta_i f(i,j) = f(i+1/2,j) - f(i-1/2,j) and likewise delta_j.
+ * e2u[k], mu[k]: metric factor e2 and transport Mu on the east face of cell
+ * k; e1v[k], mv[k]: e1 and Mv on its north face.  Closed faces (zero flux):
+ * the west face of i = 0 and the east face of i = nx-1 unless the grid is
+ * periodic (then they are one face, stored at i = nx-1), the south face of
+ * j = 0 and the north face of j = ny-1 (values stored there are ignored).
+ * Transports on faces that touch land must be zero (land rows then get
+ * b = 0, as the solve requires). */
+int pcga_ts_rhs(pcga_solver_t *S, const double *e2u, const double *mu, const double *e1v,
+                const double *mv, double *b);
+/* pcga_ts_eta: eq. (1), eta_next = eta_prev - 2 dt D cell by cell (eta_prev
+ * = eta^{n-1}, D = D^n; eta_next may alias eta_prev).  dt >= 0. */
+int pcga_ts_eta(pcga_solver_t *S, const double *eta_prev, const double *D, double dt,
+                double *eta_next);
+/* pcga_ts_guess: the first guess x0 of Algorithm 1 from the solutions of the
+ * two previous steps, x0 = a D1 + c D2 (D2 is not read, and may be NULL,
+ * when c = 0); x0 may alias D1 or D2.  The paper writes x0 = 2 D^{t-1}. */
+int pcga_ts_guess(pcga_solver_t *S, const double *D1, const double *D2, double a, double c,
+                  double *x0);
+
 /* ---- batched solves (ensembles and continuous batching) -------------------
  * A batch advances many independent solves with one launch of each iteration
  * kernel for all of them.  An item (slot) is a PCGA_MIXED solver (its resident

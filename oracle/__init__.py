@@ -72,6 +72,12 @@ def lib():
         L.ora_pcg_mixed.restype = _int
         L.ora_fsai_band.argtypes = [_i64, _i64, _int, _p, _p, _p, _i64, _p, _p]
         L.ora_fsai_band.restype = _int
+        L.ora_ts_rhs.argtypes = [_i64, _i64, _int, _p, _p, _p, _p, _p]
+        L.ora_ts_rhs.restype = None
+        L.ora_ts_eta.argtypes = [_i64, _p, _p, _dbl, _p]
+        L.ora_ts_eta.restype = None
+        L.ora_ts_guess.argtypes = [_i64, _p, _p, _dbl, _dbl, _p]
+        L.ora_ts_guess.restype = None
         _lib = L
     return _lib
 
@@ -250,3 +256,36 @@ def fsai_band(p, q):
                     vals.append(v)
         colptr[j + 1] = len(rows)
     return AInv(n, colptr, np.array(rows, dtype=np.int64), np.array(vals), D), zb
+
+
+# --- the time step around the solve (eq. (1), eq. (8), Algorithm 1's first guess)
+
+def ts_rhs(nx, ny, periodic, e2u, mu, e1v, mv):
+    """b = -(delta_i(e2 Mu) - delta_j(e1 Mv)) (eq. (8); the solved system is the
+    negation of eq. (10)).  Face arrays are indexed by the cell west / south of
+    the face; see oracle.c for the closed faces."""
+    n = nx * ny
+    arrs = [_f64(a) for a in (e2u, mu, e1v, mv)]
+    for a in arrs:
+        if a.shape != (n,):
+            raise ValueError("face arrays must have shape (nx*ny,)")
+    b = np.empty(n)
+    lib().ora_ts_rhs(nx, ny, int(bool(periodic)), *[_ptr(a) for a in arrs], _ptr(b))
+    return b
+
+
+def ts_eta(eta_prev, D, dt):
+    """eta^{n+1} = eta^{n-1} - 2 dt D^n (eq. (1))."""
+    e, d = _f64(eta_prev), _f64(D)
+    out = np.empty_like(e)
+    lib().ora_ts_eta(e.shape[0], _ptr(e), _ptr(d), float(dt), _ptr(out))
+    return out
+
+
+def ts_guess(D1, D2, a, c):
+    """x0 = a D^{t-1} + c D^{t-2} (the second term left out when c = 0)."""
+    d1 = _f64(D1)
+    d2 = _f64(D2) if D2 is not None else np.zeros_like(d1)
+    out = np.empty_like(d1)
+    lib().ora_ts_guess(d1.shape[0], _ptr(d1), _ptr(d2), float(a), float(c), _ptr(out))
+    return out

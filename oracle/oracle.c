@@ -20,6 +20,9 @@
  *   ora_pcg_mixed   FP64 iterative refinement around an FP32 inner PCG.
  *   ora_fsai_band   the paper's own banded factor of T (Sec. 3, six-step
  *                   pattern scheme, Propositions 2-3).
+ *   ora_ts_*        the surrounding time step: the right-hand side of eq. (8)
+ *                   from face transports, the sea-surface update of eq. (1),
+ *                   and the first guess of Algorithm 1 from earlier solutions.
  *
  * Operator storage ("A5", all row-major over the nx*ny grid, k = j*nx + i):
  *   diag[k] = A[k,k], ae[k] = A[k,east(k)], an[k] = A[k,k+nx];
@@ -656,4 +659,57 @@ int ora_fsai_band(int64_t nx, int64_t ny, int periodic, const double *diag,
     (void)periodic;
     free(zj);
     return st;
+}
+
+/* ------------------------------------------------------------------------
+ * The time step around the solve (Sec. 2 eq. (1); Sec. 3 eq. (8); the first
+ * guess of Algorithm 1).
+ *
+ * Right-hand side, eq. (8): b_paper(i,j) = delta_i(e2 Mu) - delta_j(e1 Mv),
+ * with delta_i f(i,j) = f(i+1/2,j) - f(i-1/2,j) over the cell's faces
+ * (likewise delta_j).  Face values are stored at the cell to their west
+ * (east faces: e2u[k], mu[k]) or south (north faces: e1v[k], mv[k]).  The
+ * west face of i = 0 is the east face of i = nx-1 on a periodic grid and a
+ * closed face (zero flux) otherwise; the east face of i = nx-1 on a
+ * non-periodic grid, the south face of j = 0 and the north face of
+ * j = ny-1 are closed.  The system solved is the negation of eq. (10)
+ * (symmetric positive definite), so the stored right-hand side is
+ * b = -b_paper.  Transports on faces that touch land are the caller's to
+ * set to zero; land cells then get b = 0.
+ * ------------------------------------------------------------------------ */
+void ora_ts_rhs(int64_t nx, int64_t ny, int periodic, const double *e2u, const double *mu,
+                const double *e1v, const double *mv, double *b) {
+    for (int64_t j = 0; j < ny; j++) {
+        for (int64_t i = 0; i < nx; i++) {
+            const int64_t k = j * nx + i;
+            double fe = 0.0, fw = 0.0, fn = 0.0, fs = 0.0;
+            if (i < nx - 1 || periodic) fe = e2u[k] * mu[k];
+            if (i > 0) {
+                fw = e2u[k - 1] * mu[k - 1];
+            } else if (periodic) {
+                fw = e2u[k + nx - 1] * mu[k + nx - 1];
+            }
+            if (j < ny - 1) fn = e1v[k] * mv[k];
+            if (j > 0) fs = e1v[k - nx] * mv[k - nx];
+            const double bp = (fe - fw) - (fn - fs);
+            b[k] = -bp;
+        }
+    }
+}
+
+/* Eq. (1): eta^{n+1} = eta^{n-1} - 2 dt D^n, cell by cell. */
+void ora_ts_eta(int64_t n, const double *eta_prev, const double *D, double dt, double *eta_next) {
+    const double s = 2.0 * dt;
+    for (int64_t k = 0; k < n; k++) eta_next[k] = eta_prev[k] - s * D[k];
+}
+
+/* First guess of Algorithm 1 from the two previous solutions:
+ * x0 = a D^{t-1} + c D^{t-2} (the second term left out when c = 0). */
+void ora_ts_guess(int64_t n, const double *D1, const double *D2, double a, double c, double *x0) {
+    for (int64_t k = 0; k < n; k++) {
+        if (c == 0.0)
+            x0[k] = a * D1[k];
+        else
+            x0[k] = a * D1[k] + c * D2[k];
+    }
 }

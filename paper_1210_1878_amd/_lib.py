@@ -60,6 +60,9 @@ _SIGS = {
     "pcga_apply_a": ([_p, _p, _p], ctypes.c_int),
     "pcga_apply_prec": ([_p, _p, _p, _p], ctypes.c_int),
     "pcga_profile_iteration": ([_p, _p, _i32, _i32, _pdbl], ctypes.c_int),
+    "pcga_ts_rhs": ([_p, _p, _p, _p, _p, _p], ctypes.c_int),
+    "pcga_ts_eta": ([_p, _p, _p, _dbl, _p], ctypes.c_int),
+    "pcga_ts_guess": ([_p, _p, _p, _dbl, _dbl, _p], ctypes.c_int),
     "pcga_batch_scratch_bytes": ([_i32, ctypes.POINTER(_sz)], ctypes.c_int),
     "pcga_batch_item_bytes": ([_p, _i32, ctypes.POINTER(_sz)], ctypes.c_int),
     "pcga_batch_create": ([_i32, _p, _sz, _p, _pp], ctypes.c_int),

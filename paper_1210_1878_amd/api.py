@@ -252,6 +252,46 @@ class Solver:
                                           _dev_ptr(s, torch.float64, self.n)), "pcga_apply_prec")
         return t, s
 
+    # --- the time step around the solve (eq. (1), eq. (8), the first guess) ---
+    def _on_stream(self, fn):
+        import torch
+        cur = torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)       # inputs written by the caller's stream
+        fn()
+        cur.wait_stream(self.stream)       # outputs visible to the caller's stream
+
+    def ts_rhs(self, e2u, mu, e1v, mv):
+        """Right-hand side of eq. (8) from face transports (see pcga_ts_rhs):
+        b = -(delta_i(e2 Mu) - delta_j(e1 Mv))."""
+        import torch
+        ptrs = [_dev_ptr(t, torch.float64, self.n) for t in (e2u, mu, e1v, mv)]
+        b = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        self._on_stream(lambda: check(_lib.load().pcga_ts_rhs(
+            self._h, *ptrs, _dev_ptr(b, torch.float64, self.n)), "pcga_ts_rhs"))
+        return b
+
+    def ts_eta(self, eta_prev, D, dt):
+        """eta^{n+1} = eta^{n-1} - 2 dt D^n (eq. (1))."""
+        import torch
+        out = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        ep, dp = _dev_ptr(eta_prev, torch.float64, self.n), _dev_ptr(D, torch.float64, self.n)
+        self._on_stream(lambda: check(_lib.load().pcga_ts_eta(
+            self._h, ep, dp, float(dt), _dev_ptr(out, torch.float64, self.n)), "pcga_ts_eta"))
+        return out
+
+    def ts_guess(self, D1, D2=None, a=2.0, c=0.0):
+        """First guess x0 = a D^{t-1} + c D^{t-2} (D2 unused when c = 0)."""
+        import torch
+        if c != 0.0 and D2 is None:
+            raise ValueError("D2 is needed when c != 0")
+        out = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        p1 = _dev_ptr(D1, torch.float64, self.n)
+        p2 = _dev_ptr(D2, torch.float64, self.n) if D2 is not None else None
+        self._on_stream(lambda: check(_lib.load().pcga_ts_guess(
+            self._h, p1, p2, float(a), float(c), _dev_ptr(out, torch.float64, self.n)),
+            "pcga_ts_guess"))
+        return out
+
     def profile_iteration(self, b, reps=50, mode=1):
         """Average ms of the three iteration kernels and of a whole iteration
         (HIP events on the solver stream).  mode 1: kernels timed inside whole

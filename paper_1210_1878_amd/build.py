@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libpcgainv.so")
 BUILD = os.path.join(HERE, "_build")
 
 HOST_SOURCES = ["ainv.cpp", "layout.cpp"]
-HIP_SOURCES = ["solver.hip", "batch.hip"]
+HIP_SOURCES = ["solver.hip", "batch.hip", "timestep.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

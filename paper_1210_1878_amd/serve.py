@@ -1,8 +1,10 @@
 """Continuous-batching server for the elliptic solve of successive time steps.
 
 Each request is one time step of one grid: a right-hand side and a warm
-start (the grid's previous solution, like the initial guess taken from the
-previous step in Algorithm 1).  Every grid's operator, D^-1 and Z stay
+start from the grid's previous solutions (the initial guess of Algorithm 1).
+CoupledTimeStepper produces them as the model's sea-surface step does
+(eq. (8) right-hand side from face transports, eq. (1) height update);
+TimeStepper is a lighter stand-in (noise on the previous right-hand side).  Every grid's operator, D^-1 and Z stay
 resident on the device (one PCGA_MIXED solver per grid).  Requests are
 admitted as soon as their grid is idle (time steps of one grid are
 sequential) and their vectors fit the device-memory budget.  Grids are split
@@ -258,6 +260,73 @@ class TimeStepper:
 
     def done(self, req):
         self.x[req.grid] = req.x.clone()
+
+
+class CoupledTimeStepper:
+    """Successive time steps coupled as in the model's sea-surface step: the
+    right-hand side of step t is eq. (8)'s, from that step's face transports
+    (seeded, slowly varying; gen.orca.orca_transport_modes), the first guess is
+    x0 = a D^{t-1} + c D^{t-2} from the grid's two previous solutions (the
+    paper writes x0 = 2 D^{t-1}; with one previous solution x0 = D^{t-1}, with
+    none x0 = 0), and each solution advances the sea-surface height by
+    eq. (1), eta^{n+1} = eta^{n-1} - 2 dt D^n.  The right-hand side, the first
+    guess and the height update run in the library's time-step passes on the
+    grid's solver; the transports of a step are formed on the device from the
+    modes (input synthesis)."""
+
+    def __init__(self, problems, solvers, device, seed, guess=(2.0, -1.0), dt=0.5):
+        import torch
+        from gen import orca
+        self.torch = torch
+        self.device = device
+        self.solvers = solvers
+        self.guess = guess
+        self.dt = dt
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+        self.modes = []
+        for p in problems:
+            m = orca.orca_transport_modes(p, seed)
+            self.modes.append({"w": list(m.w), "base_u": dev(m.base_u), "cu": [dev(a) for a in m.cu],
+                               "su": [dev(a) for a in m.su], "cv": [dev(a) for a in m.cv],
+                               "sv": [dev(a) for a in m.sv], "e2u": dev(m.e2u), "e1v": dev(m.e1v)})
+        self.D = [[] for _ in problems]
+        self.eta = [[torch.zeros(p.n, dtype=torch.float64, device=device) for _ in range(2)]
+                    for p in problems]
+        self.steps = [0] * len(problems)
+
+    def transports(self, g, t):
+        m = self.modes[g]
+        mu = m["base_u"].clone()
+        mv = self.torch.zeros_like(mu)
+        for w, cu, su, cv, sv in zip(m["w"], m["cu"], m["su"], m["cv"], m["sv"]):
+            c, s = np.cos(w * t), np.sin(w * t)
+            mu += c * cu + s * su
+            mv += c * cv + s * sv
+        return mu, mv
+
+    def __call__(self, req):
+        g = req.grid
+        S = self.solvers[g]
+        req.step = self.steps[g]
+        mu, mv = self.transports(g, self.steps[g])
+        m = self.modes[g]
+        req.b = S.ts_rhs(m["e2u"], mu, m["e1v"], mv)
+        D = self.D[g]
+        a, c = self.guess
+        if not D:
+            req.x0 = self.torch.zeros_like(req.b)
+        elif len(D) == 1 or c == 0.0:
+            req.x0 = S.ts_guess(D[-1], None, a if c == 0.0 else 1.0, 0.0)
+        else:
+            req.x0 = S.ts_guess(D[-1], D[-2], a, c)
+        self.steps[g] += 1
+
+    def done(self, req):
+        g = req.grid
+        x = req.x.clone()
+        self.D[g] = (self.D[g] + [x])[-2:]
+        e = self.eta[g]
+        self.eta[g] = [e[1], self.solvers[g].ts_eta(e[0], x, self.dt)]
 
 
 def latency_stats(done, klass=None):

@@ -101,3 +101,40 @@ def test_saturate_closed_loop(setup, ora):
     for g in range(len(probs)):
         rs = sorted((r for r in done if r.grid == g), key=lambda r: r.admitted)
         assert all(a.finished <= b.admitted for a, b in zip(rs, rs[1:]))
+
+
+def test_coupled_time_steps(setup, ora):
+    """Served steps coupled as the model's sea-surface step: each request's
+    right-hand side is eq. (8)'s from that step's transports, its first guess
+    2 D^{t-1} - D^{t-2} from the grid's previous solutions, and the heights
+    follow eq. (1); checked against the oracle's passes on the host."""
+    P, serve, probs = setup
+    say("coupled time steps: 15 requests on 3 grids")
+    srv = serve.Server(probs, drop_tol=0.1, device="cuda", chunk=8)
+    reqs = serve.poisson_arrivals(rate=400.0, count=15, n_grids=len(probs), seed=11)
+    stepper = serve.CoupledTimeStepper(probs, srv.solvers, torch.device("cuda"), seed=5,
+                                       guess=(2.0, -1.0), dt=0.5)
+    done = srv.run(reqs, make_rhs=stepper, on_done=stepper.done)
+    assert len(done) == 15
+    by_grid = {}
+    for r in sorted(done, key=lambda r: r.step):
+        by_grid.setdefault(r.grid, []).append(r)
+    for g, rs in by_grid.items():
+        p = probs[g]
+        assert [r.step for r in rs] == list(range(len(rs)))
+        eta = [np.zeros(p.n), np.zeros(p.n)]
+        for r in rs:
+            e2u, mu, e1v, mv = orca.orca_transports(p, r.step, seed=5)
+            want_b = ora.ts_rhs(p.nx, p.ny, p.periodic, e2u, mu, e1v, mv)
+            b = r.b.cpu().numpy()
+            assert np.allclose(b, want_b, rtol=0, atol=1e-15 * np.abs(want_b).max())
+            x = r.x.cpu().numpy()
+            assert r.status == 0
+            assert np.linalg.norm(b - ora.spmv(p, x)) <= 1e-10 * np.linalg.norm(b)
+            if r.step >= 2:
+                x1, x2 = rs[r.step - 1].x.cpu().numpy(), rs[r.step - 2].x.cpu().numpy()
+                assert np.array_equal(r.x0.cpu().numpy(), ora.ts_guess(x1, x2, 2.0, -1.0))
+            eta = [eta[1], ora.ts_eta(eta[0], x, 0.5)]
+        got = stepper.eta[g][1].cpu().numpy()
+        assert np.array_equal(got, eta[1])
+        say("  grid", g, "steps", len(rs), "inner iterations", [r.inner for r in rs])
