@@ -306,6 +306,12 @@ int pcga_batch_remove(pcga_batch_t *B, int32_t slot);
 
 /* Iterations per captured chunk (even, 2..512). */
 int pcga_batch_set_chunk(pcga_batch_t *B, int32_t chunk);
+/* Workgroups per launch of the batch's kernels: a multiple of 8 in 8..2048
+ * (default 2048; each workgroup takes the batch's logical blocks in turn).
+ * A smaller grid leaves CUs to other streams' kernels (e.g. another batch on
+ * the same device).  Results do not depend on it.  EINVAL while a launch is
+ * in flight or for a bad value.  Takes effect at the next launch. */
+int pcga_batch_set_grid(pcga_batch_t *B, int32_t grid);
 
 #ifdef __cplusplus
 }

@@ -75,6 +75,7 @@ _SIGS = {
     "pcga_batch_query": ([_p, _i32, _pi32, _pi32, _pi32, _pi32, _pdbl], ctypes.c_int),
     "pcga_batch_remove": ([_p, _i32], ctypes.c_int),
     "pcga_batch_set_chunk": ([_p, _i32], ctypes.c_int),
+    "pcga_batch_set_grid": ([_p, _i32], ctypes.c_int),
 }
 
 _lib = None

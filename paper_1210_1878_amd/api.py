@@ -337,7 +337,7 @@ class Batch:
     """Many mixed-precision solves advanced together (one launch per kernel per
     iteration for all items); items can be added and removed between runs."""
 
-    def __init__(self, max_slots=64, device=None, stream=None, chunk=16):
+    def __init__(self, max_slots=64, device=None, stream=None, chunk=16, grid=None):
         import torch
         L = _lib.load()
         self.device = torch.device("cuda" if device is None else device)
@@ -353,6 +353,12 @@ class Batch:
         self._h = h
         self.items = {}
         check(L.pcga_batch_set_chunk(self._h, int(chunk)), "pcga_batch_set_chunk")
+        if grid is not None:
+            self.set_grid(grid)
+
+    def set_grid(self, grid):
+        """Workgroups per launch (multiple of 8, 8..2048; results do not depend on it)."""
+        check(_lib.load().pcga_batch_set_grid(self._h, int(grid)), "pcga_batch_set_grid")
 
     @staticmethod
     def item_bytes(solver, nrhs):

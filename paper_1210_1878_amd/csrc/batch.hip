@@ -748,8 +748,9 @@ struct pcga_batch {
     SlotCtl *snap = nullptr;          // pinned host, max_slots entries
     hipEvent_t ev = nullptr;
     int chunk = 16;
+    int grid = kBatchGrid;            // workgroups per launch (multiple of 8)
     hipGraphExec_t graph = nullptr;
-    int graph_chunk = 0;
+    int graph_chunk = 0, graph_grid = 0;
     int64_t iterations = 0;
     bool in_flight = false;           // chunks launched, snapshot not yet consumed
 };
@@ -829,9 +830,9 @@ void launch_batch_iters(pcga_batch &B, int count) {
     // table capacity and let empty entries be skipped.
     for (int it = 0; it < count; it++) {
         const int p = it & 1;
-        kb_stencil<<<kBatchGrid, kBS, 0, B.stream>>>(B.d_tab, B.tab_cap, B.d_desc, p);
-        kb_zt<<<kBatchGrid, kBS, 0, B.stream>>>(B.d_tab, B.tab_cap, B.d_desc, p);
-        kb_z<<<kBatchGrid, kBS, 0, B.stream>>>(B.d_tab, B.tab_cap, B.d_desc, p);
+        kb_stencil<<<B.grid, kBS, 0, B.stream>>>(B.d_tab, B.tab_cap, B.d_desc, p);
+        kb_zt<<<B.grid, kBS, 0, B.stream>>>(B.d_tab, B.tab_cap, B.d_desc, p);
+        kb_z<<<B.grid, kBS, 0, B.stream>>>(B.d_tab, B.tab_cap, B.d_desc, p);
     }
 }
 
@@ -990,7 +991,7 @@ int pcga_batch_launch(pcga_batch_t *B, int32_t chunks) {
     if (B->in_flight) return fail(PCGA_EINVAL, "a launch of this batch is still in flight");
     int st;
     if (B->table_dirty && (st = rebuild_table(*B))) return st;
-    if (!B->graph || B->graph_chunk != B->chunk) {
+    if (!B->graph || B->graph_chunk != B->chunk || B->graph_grid != B->grid) {
         if (B->graph) (void)hipGraphExecDestroy(B->graph);
         B->graph = nullptr;
         hipGraph_t g = nullptr;
@@ -1006,6 +1007,7 @@ int pcga_batch_launch(pcga_batch_t *B, int32_t chunks) {
             return fail(PCGA_EHIP, std::string("instantiate: ") + hipGetErrorString(e));
         }
         B->graph_chunk = B->chunk;
+        B->graph_grid = B->grid;
     }
     for (int c = 0; c < chunks; c++) {
         const hipError_t e = hipGraphLaunch(B->graph, B->stream);
@@ -1105,6 +1107,14 @@ int pcga_batch_set_chunk(pcga_batch_t *B, int32_t chunk) {
     if (B && B->in_flight) return fail(PCGA_EINVAL, "a launch of this batch is still in flight");
     if (!B || chunk < 2 || chunk > 512 || (chunk & 1)) return fail(PCGA_EINVAL, "chunk must be even, 2..512");
     B->chunk = chunk;
+    return PCGA_OK;
+}
+
+int pcga_batch_set_grid(pcga_batch_t *B, int32_t grid) {
+    if (B && B->in_flight) return fail(PCGA_EINVAL, "a launch of this batch is still in flight");
+    if (!B || grid < 8 || grid > kBatchGrid || (grid & 7))
+        return fail(PCGA_EINVAL, "grid must be a multiple of 8, 8.." + std::to_string(kBatchGrid));
+    B->grid = grid;
     return PCGA_OK;
 }
 

@@ -50,7 +50,8 @@ class Server:
     """Holds resident grids and serves time-step solves by continuous batching."""
 
     def __init__(self, problems, drop_tol=0.05, device=None, hbm_budget=None, max_slots=64,
-                 tol=1e-10, inner_tol=1e-5, max_outer=30, chunk=16, class_cells=(2_000_000,)):
+                 tol=1e-10, inner_tol=1e-5, max_outer=30, chunk=16, class_cells=(2_000_000,),
+                 class_grid=None):
         import torch
         self.torch = torch
         self.device = torch.device("cuda" if device is None else device)
@@ -69,7 +70,11 @@ class Server:
         bounds = sorted(class_cells)
         self.klass = [sum(1 for c in bounds if p.nx * p.ny >= c) for p in problems]
         used = sorted(set(self.klass))
-        self.batches = {k: Batch(max_slots=max_slots, device=self.device, chunk=chunk) for k in used}
+        # class_grid: workgroups per launch of each class's batch (None: 2048),
+        # so that a large grid's kernels can leave CUs to the other classes
+        grids = class_grid or {}
+        self.batches = {k: Batch(max_slots=max_slots, device=self.device, chunk=chunk,
+                                 grid=grids.get(k)) for k in used}
         self.in_flight_bytes = 0
         self.busy = [False] * len(self.solvers)
 

@@ -121,6 +121,23 @@ def test_batch_alone_equals_in_mix(pkg, ensemble):
         assert torch.equal(X, alone[slot_of[s]]), slot_of[s]
 
 
+def test_batch_launch_grid_does_not_change_results(pkg, ensemble):
+    ps, sol = ensemble
+    say("launch grids 2048 / 64 / 8 (bitwise)")
+    res = []
+    for grid in (None, 64, 8):
+        Bt = pkg.Batch(max_slots=8, grid=grid)
+        slot_of = {Bt.add(sol[i], torch.from_numpy(ps[i].B).cuda()): i for i in range(len(ps))}
+        out = Bt.solve()
+        res.append({slot_of[s]: X for s, (X, q) in out.items()})
+    for i in range(len(ps)):
+        assert torch.equal(res[0][i], res[1][i]) and torch.equal(res[0][i], res[2][i]), i
+    Bt = pkg.Batch(max_slots=2)
+    for bad in (0, 12, 4096):
+        with pytest.raises(Exception):
+            Bt.set_grid(bad)
+
+
 def test_batch_zero_rhs_and_limits(pkg, ora, ensemble):
     ps, sol = ensemble
     p, S = ps[2], sol[2]
