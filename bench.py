@@ -118,18 +118,25 @@ def bench_batch(P, torch, dev, log, members=64, nrhs=4):
     1e-10, advanced together by the batched kernels (one launch per kernel
     per iteration for the whole ensemble)."""
     from gen import orca
+    from paper_1210_1878_amd import autotune
     t0 = time.perf_counter()
     ens = orca.ensemble_problems(count=members, nrhs=nrhs)
-    solvers = []
-    for p in ens:
-        A = P.Stencil5.from_problem(p)
-        solvers.append(P.Solver(A, P.ainv_setup(A, 0.1), "mixed", device=dev))
+    As = [P.Stencil5.from_problem(p) for p in ens]
+    Fs = [P.ainv_setup(A, 0.1) for A in As]
     Bs = [torch.from_numpy(p.B).to(dev) for p in ens]
     cells = sum(p.n for p in ens)
     log(f"ensemble: {members} grids, {cells} cells, setup {time.perf_counter() - t0:.1f}s")
+    # slice width and chunk of the ensemble picked by timing whole batched solves
+    t0 = time.perf_counter()
+    tuned = autotune.tune_batch(
+        lambda w: [(P.Solver(A, F, "mixed", device=dev, slice_width=w), B) for A, F, B in zip(As, Fs, Bs)],
+        widths=(8, 16, 32), chunks=(8, 16, 32), tol=TOL)
+    log(f"ensemble autotune ({time.perf_counter() - t0:.1f}s): slice width {tuned['slice_width']}, "
+        f"chunk {tuned['chunk']}; " + ", ".join(f"w{w}/c{c}: {ms:.0f} ms" for w, c, ms in tuned["table"]))
+    solvers = [P.Solver(A, F, "mixed", device=dev, slice_width=tuned["slice_width"]) for A, F in zip(As, Fs)]
 
     def run_batch():
-        Bt = P.Batch(max_slots=members, device=dev)
+        Bt = P.Batch(max_slots=members, device=dev, chunk=tuned["chunk"])
         for S, B in zip(solvers, Bs):
             Bt.add(S, B, tol=TOL, inner_tol=1e-5, max_outer=30)
         return Bt.solve()
@@ -158,7 +165,9 @@ def bench_batch(P, torch, dev, log, members=64, nrhs=4):
             "solves_per_s": round(members * nrhs / dt, 1), "all_converged": ok,
             "worst_true_relres": worst, "inner_iters_per_item_rhs": round(inner / members, 1),
             "sequential_ms": round(dts * 1e3, 2),
-            "speedup_vs_sequential": round(dts / dt, 2)}
+            "speedup_vs_sequential": round(dts / dt, 2),
+            "autotuned": {"slice_width": tuned["slice_width"], "chunk": tuned["chunk"],
+                          "table_ms": [[w, c, round(ms, 1)] for w, c, ms in tuned["table"]]}}
 
 
 SERVE_CLASS_CELLS = (2_000_000,)
@@ -166,7 +175,7 @@ SERVE_GUESS = (2.0, -1.0)      # x0 = 2 D^{t-1} - D^{t-2}
 
 
 def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=10.0,
-                class_cells=SERVE_CLASS_CELLS):
+                class_cells=SERVE_CLASS_CELLS, coupled=False):
     """Time-step solves on a catalogue of resident grids from 182x149 to
     4322x3059 (mixed precision to 1e-10, warm starts, continuous batching).
     Capacity first: a closed loop keeps every grid busy and gives each grid's
@@ -182,8 +191,11 @@ def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=
     srv = serve.Server(probs, drop_tol=0.05, device=dev, chunk=16, class_cells=class_cells)
     log(f"serving: {len(probs)} resident grids ({srv.resident_bytes / 2**30:.2f} GiB), "
         f"setup {time.perf_counter() - t0:.1f}s")
-    stepper = serve.CoupledTimeStepper(probs, srv.solvers, dev, seed=CONFIG_SERVE_SEED,
-                                       guess=SERVE_GUESS)
+    if coupled:
+        stepper = serve.CoupledTimeStepper(probs, srv.solvers, dev, seed=CONFIG_SERVE_SEED,
+                                           guess=SERVE_GUESS)
+    else:
+        stepper = serve.TimeStepper(probs, dev, seed=CONFIG_SERVE_SEED)
     # warm-up: one step per grid (graph capture, first touch)
     warm = [serve.Request(rid=-1 - g, grid=g, arrival=0.0) for g in range(len(probs))]
     srv.run(warm, make_rhs=stepper, on_done=stepper.done)
@@ -191,11 +203,12 @@ def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=
     cap = [sum(1 for r in done if r.grid == g) / el for g in range(len(probs))]
     log(f"capacity (closed loop, {el:.1f}s): {sum(cap):.1f} solves/s; per grid "
         + ", ".join(f"{a}x{b}: {c:.2f}" for (a, b), c in zip(shapes, cap)))
-    out = {"workload": "coupled time steps (right-hand side of eq. (8) from seeded, slowly "
-                       "varying face transports; first guess x0 = 2 D^{t-1} - D^{t-2}; "
-                       "eq. (1) height update) on 8 resident ORCA-shaped grids 182x149 .. "
-                       "4322x3059, mixed precision to 1e-10, continuous batching; per-grid "
-                       "Poisson arrivals at a load factor of each grid's closed-loop throughput",
+    steps = ("coupled time steps (right-hand side of eq. (8) from seeded, slowly varying face "
+             "transports; first guess x0 = 2 D^{t-1} - D^{t-2}; eq. (1) height update)" if coupled else
+             "warm-started time steps (b_t = b_{t-1} + 1% seeded noise on ocean cells, x0 = x_{t-1})")
+    out = {"workload": steps + " on 8 resident ORCA-shaped grids 182x149 .. 4322x3059, mixed "
+                       "precision to 1e-10, continuous batching; per-grid Poisson arrivals at a "
+                       "load factor of each grid's closed-loop throughput",
            "grids": [f"{a}x{b}" for a, b in shapes],
            "size_classes": "grids split at " + ", ".join(f"{c:,} cells" for c in sorted(class_cells))
                            + "; one batch per class, each on its own stream, running concurrently",
@@ -278,11 +291,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--chunk", type=int, default=32)
     ap.add_argument("--max-blocks", type=int, default=0,
-                    help="workgroups per kernel; 0 = the solver's default (FP64 1280, mixed 1792)")
+                    help="workgroups per kernel; 0 = the solver's default (FP64 1024, mixed 1536)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched ensemble")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--no-timestep", action="store_true", help="skip the coupled time steps")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner report")
     ap.add_argument("--kernels-only", action="store_true",
                     help="profiling driver: a 256 MiB device copy (counter calibration), then the "
                          "three FP64 and FP32 iteration kernels, --reps launches each")
@@ -401,6 +415,21 @@ def main():
     dtb = time.perf_counter() - t0
     log(f"banded factor of T (q=4, diagonal storage): {rb.iters} iterations, {dtb * 1e3:.2f} ms/solve")
 
+    # ---- autotuner on the benchmark grid (reported; the timed solves above use
+    # the defaults the committed profiles describe) -------------------------
+    tuned64 = None
+    if not args.no_tune:
+        from paper_1210_1878_amd import autotune
+        t0 = time.perf_counter()
+        tuned64 = autotune.tune_solver(A, G, b, "fp64", device=dev)
+        log(f"autotune fp64 ({time.perf_counter() - t0:.1f}s): slice width {tuned64['slice_width']}, "
+            f"blocks {tuned64['max_blocks']}, chunk {tuned64['chunk']}, "
+            f"{tuned64['iteration_ms'] * 1e3:.1f} us per iteration")
+        tuned64 = {"slice_width": tuned64["slice_width"], "max_blocks": tuned64["max_blocks"],
+                   "chunk": tuned64["chunk"], "iteration_us": round(tuned64["iteration_ms"] * 1e3, 2),
+                   "table_us": [[w, mb, round(ms * 1e3, 2)] for w, mb, ms in tuned64["table"]],
+                   "chunk_ms_per_solve": [[c, round(ms, 2)] for c, ms in tuned64["chunks"]]}
+
     # ---- the time step around the solve (eq. (1), eq. (8), first guess) ----
     tstep = None if args.no_timestep else bench_timestep(P, torch, S64, p, log)
 
@@ -430,6 +459,8 @@ def main():
 
     batched = None if args.no_batch else bench_batch(P, torch, dev, log)
     served = None if args.no_serve else bench_serve(P, torch, dev, log)
+    served_coupled = None if args.no_serve or args.no_timestep else bench_serve(
+        P, torch, dev, lambda m: log("coupled " + m), loads=(0.8,), coupled=True)
 
     cpu = None
     if not args.no_cpu:
@@ -447,7 +478,8 @@ def main():
                                "PCG to relres 1e-10 from x0=0",
                    "nx": NX, "ny": NY, "n": p.n, "nnz_off": G.nnz_off, "index_bytes": S64.index_bytes, "formats": {"fp64": S64.formats, "mixed": Smx.formats}, "tol": TOL,
                    "drop_tol": TAU, "iters_per_solve": fp64_iters, "chunk": args.chunk,
-                   "graph": not args.no_graph, "max_blocks": args.max_blocks or "default: fp64 1280, mixed 1792"},
+                   "graph": not args.no_graph, "max_blocks": args.max_blocks or "default: fp64 1024, mixed 1536",
+                   "slice_width": {"fp64": S64.slice_width or 32, "mixed": Smx.slice_width or 24}},
         "fp64": {"iters": fp64_iters, "ms_per_solve": round(dt * 1e3 / args.steps, 3),
                  "true_relres": fp64_true, "model_bytes_per_iter": b_iter,
                  "model_gbs_per_iter_kernels": round(b_iter / it_time / 1e9, 1),
@@ -464,9 +496,11 @@ def main():
                    "true_relres": rj.true_relres},
         "band_factor_q4": {"iters": rb.iters, "ms_per_solve": round(dtb * 1e3, 3),
                            "true_relres": rb.true_relres, "band_q": Sb.band_q},
+        "autotune_fp64": tuned64,
         "timestep": tstep,
         "batched": batched,
         "served": served,
+        "served_coupled_time_steps": served_coupled,
         "setup_s": round(setup_s, 3),
         "roofline": roof,
         "cpu_baseline": cpu,

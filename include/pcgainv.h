@@ -131,6 +131,18 @@ int pcga_solver_create(const pcga_a5_t *A, const pcga_ainv_t *F, int precision,
                        void *dev_workspace, size_t bytes, void *stream,
                        pcga_solver_t **out);
 int pcga_solver_destroy(pcga_solver_t *S);
+/* The same with the sliced-ELL target width (1..64; 0: the default, 32 for
+ * PCGA_FP64 and 24 for PCGA_MIXED): a slice
+ * starts with one lane per row and doubles its lanes per row (halving its
+ * rows) until its longest row needs at most slice_width entry steps (or one
+ * row has all 64 lanes).  Results are the same method; the summation order
+ * inside a row, and so the rounding, depends on the width.  An autotuner
+ * picks it by timing (paper_1210_1878_amd/autotune.py). */
+int pcga_workspace_bytes_ex(const pcga_a5_t *A, const pcga_ainv_t *F, int precision,
+                            int32_t slice_width, size_t *bytes);
+int pcga_solver_create_ex(const pcga_a5_t *A, const pcga_ainv_t *F, int precision,
+                          int32_t slice_width, void *dev_workspace, size_t bytes, void *stream,
+                          pcga_solver_t **out);
 
 /* Solver facts: n, nnz_off, precision, the modelled device bytes one PCG
  * iteration must move (each array once; FP64: 144 n + (8 + b) nnz_pad, mixed
@@ -149,10 +161,10 @@ int pcga_solver_info(const pcga_solver_t *S, int64_t *n, int64_t *nnz_off,
                      int32_t *precision, double *bytes_per_iter, int32_t *index_bytes,
                      int32_t *formats);
 
-/* Launch tuning (used by the autotuner): iterations per chunk (even,
+/* Launch tuning (set by the autotuner): iterations per chunk (even,
  * 2..512), whether chunks are replayed through a captured HIP graph (1) or
  * launched directly (0), and the maximum number of workgroups per kernel
- * (8..2048; 0 selects the default, 1280 for PCGA_FP64 and 1792 for
+ * (8..2048; 0 selects the default, 1024 for PCGA_FP64 and 1536 for
  * PCGA_MIXED; each workgroup streams one contiguous range of the grid).
  * Takes effect at the next solve.  Results of a solve are bitwise
  * reproducible for fixed settings. */

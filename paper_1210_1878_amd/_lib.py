@@ -52,6 +52,10 @@ _SIGS = {
     "pcga_solver_create": ([ctypes.POINTER(A5), _p, ctypes.c_int, _p, _sz, _p, _pp],
                            ctypes.c_int),
     "pcga_solver_destroy": ([_p], ctypes.c_int),
+    "pcga_workspace_bytes_ex": ([ctypes.POINTER(A5), _p, ctypes.c_int, _i32, ctypes.POINTER(_sz)],
+                                ctypes.c_int),
+    "pcga_solver_create_ex": ([ctypes.POINTER(A5), _p, ctypes.c_int, _i32, _p, _sz, _p, _pp],
+                              ctypes.c_int),
     "pcga_solver_info": ([_p, _pi64, _pi64, _pi32, _pdbl, _pi32, _pi32], ctypes.c_int),
     "pcga_solver_tune": ([_p, _i32, _i32, _i32], ctypes.c_int),
     "pcga_pcg_solve": ([_p, _p, _p, _dbl, _i32, _pi32, _p, _i32, _pi32, _pdbl], ctypes.c_int),

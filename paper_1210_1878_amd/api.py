@@ -147,16 +147,19 @@ class Solver:
     """Device solver for one grid: A, Z^T/Z (sliced ELL) and D^-1 resident in
     a torch-allocated workspace; FP64 or mixed precision."""
 
-    def __init__(self, A: Stencil5, F: AInv, precision: str = "fp64", device=None, stream=None):
+    def __init__(self, A: Stencil5, F: AInv, precision: str = "fp64", device=None, stream=None,
+                 slice_width: int = 0):
         import torch
         L = _lib.load()
         self.A = A
+        self.slice_width = int(slice_width)
         self.precision = {"fp64": FP64, "mixed": MIXED}[precision]
         self.device = torch.device("cuda" if device is None else device)
         a5 = A.c_struct()
         nbytes = ctypes.c_size_t()
-        check(L.pcga_workspace_bytes(ctypes.byref(a5), F.handle, self.precision,
-                                     ctypes.byref(nbytes)), "pcga_workspace_bytes")
+        check(L.pcga_workspace_bytes_ex(ctypes.byref(a5), F.handle, self.precision,
+                                        self.slice_width, ctypes.byref(nbytes)),
+              "pcga_workspace_bytes_ex")
         self.workspace_bytes = nbytes.value
         with torch.cuda.device(self.device):
             # a stream of its own (default priority): chunks are captured into
@@ -164,10 +167,11 @@ class Solver:
             self.stream = torch.cuda.Stream(self.device) if stream is None else stream
             self.ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
             h = ctypes.c_void_p()
-            check(L.pcga_solver_create(ctypes.byref(a5), F.handle, self.precision,
-                                       ctypes.c_void_p(self.ws.data_ptr()), self.workspace_bytes,
-                                       ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
-                  "pcga_solver_create")
+            check(L.pcga_solver_create_ex(ctypes.byref(a5), F.handle, self.precision,
+                                          self.slice_width, ctypes.c_void_p(self.ws.data_ptr()),
+                                          self.workspace_bytes,
+                                          ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+                  "pcga_solver_create_ex")
         self._h = h
         n = ctypes.c_int64()
         nnz = ctypes.c_int64()

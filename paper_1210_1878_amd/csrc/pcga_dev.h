@@ -18,11 +18,10 @@ constexpr int kCPT = PCGA_CPT;     // stencil cells per thread per step
 constexpr int kStep = kBS * kCPT;  // stencil cells per workgroup step
 constexpr int kHistRing = 4096;    // residual-history ring (entries)
 constexpr int kMaxBlocks = 2048;   // workgroups per kernel = partial sums per reduction
-// Default workgroups per kernel (256 CUs): FP64, 5 per CU; the mixed form's
-// FP32 kernels hold fewer registers and are fastest at 7 per CU (measured at
-// 1442 x 1021 over 1280..2048).
-constexpr int kDefaultBlocks = 1280;
-constexpr int kDefaultBlocksMixed = 1792;
+// Default workgroups per kernel (256 CUs), as the autotuner picks them at
+// 1442 x 1021 with the default slice widths: FP64 4 per CU, mixed 6 per CU.
+constexpr int kDefaultBlocks = 1024;
+constexpr int kDefaultBlocksMixed = 1536;
 constexpr int kMaxBand = 8;          // widest band stored by diagonals
 // Memory-side cache (Infinity Cache) of one MI355X: 256 MiB.  The streams an
 // iteration reads are kept resident up to 95% of it (see cache_plan).

@@ -214,7 +214,12 @@ int check_a5(const pcga_a5_t *A) {
     return PCGA_OK;
 }
 
-constexpr int kTargetWidth = 16;
+// Default sliced-ELL target width (entry steps) by precision, as the autotuner
+// picks it at 1442 x 1021 (FP64: 97-98 us per iteration at 32 against 100 at
+// 16; mixed inner: 51.5 us at 24 against 52.3 at 16).
+constexpr int kTargetWidth = 32, kTargetWidthMixed = 24;
+constexpr int kMaxSliceWidth = 64;
+int default_width(int precision) { return precision == PCGA_MIXED ? kTargetWidthMixed : kTargetWidth; }
 
 // Per-slice work estimate, in units of about 10 ns of one wavefront's time:
 // a fixed part (headers, own-row operands, the pipeline's drain at the end of
@@ -429,14 +434,27 @@ static std::vector<double> band_diagonals(const AinvFactor &F, int q) {
 
 int pcga_workspace_bytes(const pcga_a5_t *A, const pcga_ainv_t *F, int precision,
                          size_t *bytes) {
+    return pcga_workspace_bytes_ex(A, F, precision, 0, bytes);
+}
+
+int pcga_solver_create(const pcga_a5_t *A, const pcga_ainv_t *F, int precision, void *ws,
+                       size_t bytes, void *stream, pcga_solver_t **out) {
+    return pcga_solver_create_ex(A, F, precision, 0, ws, bytes, stream, out);
+}
+
+int pcga_workspace_bytes_ex(const pcga_a5_t *A, const pcga_ainv_t *F, int precision,
+                            int32_t slice_width, size_t *bytes) {
     if (!bytes || !F) return fail(PCGA_EINVAL, "NULL argument");
+    if (slice_width == 0) slice_width = default_width(precision);
+    if (slice_width < 1 || slice_width > kMaxSliceWidth)
+        return fail(PCGA_EINVAL, "slice_width must be 0 or 1.." + std::to_string(kMaxSliceWidth));
     int st = check_a5(A);
     if (st) return st;
     if (precision != PCGA_FP64 && precision != PCGA_MIXED)
         return fail(PCGA_EINVAL, "precision must be PCGA_FP64 or PCGA_MIXED");
     if (F->F.n != (int64_t)A->nx * A->ny) return fail(PCGA_EINVAL, "F does not match A");
     HostLayouts H;
-    st = build_layouts(F->F, kTargetWidth, H);
+    st = build_layouts(F->F, slice_width, H);
     if (st) return st;
     pcga_solver S;
     S.precision = precision;
@@ -446,11 +464,15 @@ int pcga_workspace_bytes(const pcga_a5_t *A, const pcga_ainv_t *F, int precision
     return PCGA_OK;
 }
 
-int pcga_solver_create(const pcga_a5_t *A, const pcga_ainv_t *F, int precision, void *ws,
-                       size_t bytes, void *stream, pcga_solver_t **out) {
+int pcga_solver_create_ex(const pcga_a5_t *A, const pcga_ainv_t *F, int precision,
+                          int32_t slice_width, void *ws, size_t bytes, void *stream,
+                          pcga_solver_t **out) {
     if (!out) return fail(PCGA_EINVAL, "out is NULL");
     *out = nullptr;
     if (!F || !ws) return fail(PCGA_EINVAL, "NULL F or workspace");
+    if (slice_width == 0) slice_width = default_width(precision);
+    if (slice_width < 1 || slice_width > kMaxSliceWidth)
+        return fail(PCGA_EINVAL, "slice_width must be 0 or 1.." + std::to_string(kMaxSliceWidth));
     int st = check_a5(A);
     if (st) return st;
     if (precision != PCGA_FP64 && precision != PCGA_MIXED)
@@ -460,7 +482,7 @@ int pcga_solver_create(const pcga_a5_t *A, const pcga_ainv_t *F, int precision, 
     if (((uintptr_t)ws & 255u) != 0) return fail(PCGA_EINVAL, "workspace must be 256-byte aligned");
 
     HostLayouts H;
-    st = build_layouts(F->F, kTargetWidth, H);
+    st = build_layouts(F->F, slice_width, H);
     if (st) return st;
     pcga_solver *S = new (std::nothrow) pcga_solver;
     if (!S) return fail(PCGA_ENOMEM, "host allocation failed");

@@ -133,6 +133,18 @@ def test_workspace_bytes_query():
     assert sizes[_lib.MIXED] < sizes[_lib.FP64] * 1.1
     nb = ctypes.c_size_t()
     assert L.pcga_workspace_bytes(ctypes.byref(a5), G.handle, 7, ctypes.byref(nb)) == _lib.EINVAL
+    # the sliced-ELL target width: 0 (the default, 32 for FP64) or 1..64
+    nbd = ctypes.c_size_t()
+    assert L.pcga_workspace_bytes_ex(ctypes.byref(a5), G.handle, _lib.FP64, 32, ctypes.byref(nbd)) == 0
+    assert nbd.value == sizes[_lib.FP64]
+    assert L.pcga_workspace_bytes_ex(ctypes.byref(a5), G.handle, _lib.FP64, 0, ctypes.byref(nbd)) == 0
+    assert nbd.value == sizes[_lib.FP64]
+    for w in (1, 8, 64):
+        assert L.pcga_workspace_bytes_ex(ctypes.byref(a5), G.handle, _lib.FP64, w, ctypes.byref(nb)) == 0
+        assert nb.value >= 8 * 12 * n
+    for w in (-3, 65):
+        assert L.pcga_workspace_bytes_ex(ctypes.byref(a5), G.handle, _lib.FP64, w,
+                                         ctypes.byref(nb)) == _lib.EINVAL
 
 
 @pytest.mark.parametrize("q", [0, 1, 2, 4, 8])

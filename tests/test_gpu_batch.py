@@ -138,6 +138,26 @@ def test_batch_launch_grid_does_not_change_results(pkg, ensemble):
             Bt.set_grid(bad)
 
 
+def test_batch_autotuner(pkg, ora, ensemble):
+    from paper_1210_1878_amd import autotune
+    ps, sol = ensemble
+    say("ensemble autotune (widths 8/16, chunks 8/16)")
+    As = [pkg.Stencil5.from_problem(p) for p in ps]
+    Fs = [pkg.ainv_setup(A, 0.1) for A in As]
+    Bs = [torch.from_numpy(p.B).cuda() for p in ps]
+    r = autotune.tune_batch(lambda w: [(pkg.Solver(A, F, "mixed", slice_width=w), B)
+                                       for A, F, B in zip(As, Fs, Bs)],
+                            widths=(8, 16), chunks=(8, 16))
+    assert r["slice_width"] in (8, 16) and r["chunk"] in (8, 16) and len(r["table"]) == 4
+    # the tuned ensemble still meets the target
+    Bt = pkg.Batch(max_slots=len(ps), chunk=r["chunk"])
+    slots = {}
+    for i, (A, F, B) in enumerate(zip(As, Fs, Bs)):
+        slots[Bt.add(pkg.Solver(A, F, "mixed", slice_width=r["slice_width"]), B, tol=1e-10)] = i
+    for s, (X, q) in Bt.solve().items():
+        _check_item(ora, ps[slots[s]], X, q, 4)
+
+
 def test_batch_zero_rhs_and_limits(pkg, ora, ensemble):
     ps, sol = ensemble
     p, S = ps[2], sol[2]

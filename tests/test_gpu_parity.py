@@ -161,6 +161,39 @@ def test_pcg_iteration_matched(pkg, ora, name):
     assert np.allclose(g.hist, o.hist, rtol=1e-6, atol=1e-14)
 
 
+@pytest.mark.parametrize("width", [1, 8, 32, 64])
+def test_pcg_other_slice_widths(pkg, ora, width):
+    """Any sliced-ELL target width is the same method: iteration-matched
+    solution and natural stop as with the default."""
+    p, tau = case("orca182x149")
+    say("pcg with slice width", width)
+    A = pkg.Stencil5.from_problem(p)
+    S = pkg.Solver(A, pkg.ainv_setup(A, tau), "fp64", slice_width=width)
+    F = ora.ainv_setup(p, tau)
+    K = ora.pcg(p, F, tol=1e-10).iters
+    g = S.solve(torch.from_numpy(p.b).cuda(), tol=0.0, maxit=K)
+    o = ora.pcg(p, F, tol=0.0, maxit=K)
+    assert np.linalg.norm(g.x.cpu().numpy() - o.x) <= 1e-9 * np.linalg.norm(o.x)
+    g = S.solve(torch.from_numpy(p.b).cuda(), tol=1e-10)
+    assert g.status == 0 and abs(g.iters - K) <= 2
+
+
+def test_autotuner_small(pkg):
+    from paper_1210_1878_amd import autotune
+    p, tau = case("orca182x149")
+    A = pkg.Stencil5.from_problem(p)
+    G = pkg.ainv_setup(A, tau)
+    b = torch.from_numpy(p.b).cuda()
+    r = autotune.tune_solver(A, G, b, "fp64", widths=(8, 16), blocks=(64, 256), chunks=(16, 32), reps=5)
+    say("autotune", {k: r[k] for k in ("slice_width", "max_blocks", "chunk")})
+    assert r["slice_width"] in (8, 16) and r["max_blocks"] in (64, 256) and r["chunk"] in (16, 32)
+    assert len(r["table"]) == 4 and all(ms > 0 for _, _, ms in r["table"])
+    S = pkg.Solver(A, G, "fp64", slice_width=r["slice_width"])
+    S.tune(chunk=r["chunk"], max_blocks=r["max_blocks"])
+    g = S.solve(b, tol=1e-10)
+    assert g.status == 0 and g.hist[-1] <= 1e-10
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_pcg_natural_stop(pkg, ora, name):
     p, tau = case(name)
