@@ -503,6 +503,15 @@ def main():
         "served_coupled_time_steps": served_coupled,
         "setup_s": round(setup_s, 3),
         "roofline": roof,
+        # the paper's figures (Sec. 6), quoted with their hardware as context;
+        # flops per iteration: the five-point product (9 n), the two sparse
+        # products (2 flops per nonzero of Z in each, plus 3 n for the unit
+        # diagonals and D^-1), three dot products and three axpys (12 n)
+        "paper_context": {"gpu_gflops": 87.0, "gpu": "NVIDIA Tesla S2050 (Fermi), FP32, CUBLAS/CUSPARSE CSR",
+                          "cpu_gflops": 1.43, "cpu": "Intel Xeon E5620, serial ANSI C, FP32",
+                          "workload": "ORCA-025 1442x1021, NEMO mesh",
+                          "this_fp64_gflops": round((24.0 * p.n + 4.0 * G.nnz_off) * it_s / 1e9, 1),
+                          "flops_per_iter": 24 * p.n + 4 * G.nnz_off},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
