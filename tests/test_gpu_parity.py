@@ -452,3 +452,33 @@ def test_pcg_paper_band_preconditioner(pkg, ora, q):
     ka = ora.pcg(p, ora.ainv_setup(p, 0.1), tol=1e-10).iters
     say(f"  iterations: jacobi {kj}, band q={q} {K}, ainv {ka}")
     assert K <= kj and ka < K
+
+
+def test_largest_catalogue_grid(pkg, ora):
+    """4322x3059 (13.2 M cells, the largest grid of the serving catalogue):
+    the preconditioner apply against the oracle over the whole grid, and the
+    FP64 solve's true residual recomputed with the oracle's product."""
+    p = orca.orca_problem(4322, 3059, orca.CONFIG_SEED_BASE + 47)
+    say("largest grid", p.n, "cells: setups")
+    A = pkg.Stencil5.from_problem(p)
+    G = pkg.ainv_setup(A, 0.05)
+    F = ora.ainv_setup(p, 0.05)
+    assert G.nnz_off == F.nnz_off
+    S = pkg.Solver(A, G, "fp64")
+    say("  solver index bytes", S.index_bytes, "formats", S.formats)
+    x = np.random.default_rng(31).standard_normal(p.n)
+    t, s = S.apply_prec(dev(x))
+    t_ref = ora.zt_apply(F, x)
+    s_ref = ora.z_apply(F, t_ref)
+    Fa = ora.AInv(F.n, F.colptr, F.rowidx, np.abs(F.val), F.D)
+    t_mag = ora.zt_apply(Fa, np.abs(x))
+    s_mag = ora.z_apply(Fa, t_mag)
+    width = int(np.diff(F.colptr).max()) + 2
+    assert np.all(np.abs(t.cpu().numpy() - t_ref) <= width * 4 * EPS * t_mag)
+    assert np.all(np.abs(s.cpu().numpy() - s_ref) <= 2 * width * 4 * EPS * s_mag)
+    say("  FP64 solve")
+    g = S.solve(dev(p.b), tol=1e-10)
+    xg = g.x.cpu().numpy()
+    true = np.linalg.norm(p.b - ora.spmv(p, xg)) / np.linalg.norm(p.b)
+    say("  iterations", g.iters, "true relres", true)
+    assert g.status == 0 and g.hist[-1] <= 1e-10 and true <= 1.05e-10
