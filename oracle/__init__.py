@@ -53,6 +53,10 @@ def lib():
                                      ctypes.POINTER(_p), ctypes.POINTER(_i64),
                                      ctypes.POINTER(_i64)]
         L.ora_ainv_setup.restype = _int
+        L.ora_ainv_setup_fill.argtypes = [_i64, _i64, _int, _p, _p, _p, _dbl, _i64,
+                                          ctypes.POINTER(_p), ctypes.POINTER(_i64),
+                                          ctypes.POINTER(_i64)]
+        L.ora_ainv_setup_fill.restype = _int
         L.ora_ainv_export.argtypes = [_p, _p, _p, _p, _p]
         L.ora_ainv_export.restype = None
         L.ora_ainv_free.argtypes = [_p]
@@ -127,15 +131,25 @@ def spmv(p, x):
     return y
 
 
-def ainv_setup(p, tau) -> AInv:
-    """AINV by A-orthogonalisation with drop tolerance tau (tau=inf: Jacobi)."""
+def ainv_setup(p, tau, fill=None) -> AInv:
+    """AINV by A-orthogonalisation with drop tolerance tau (tau=inf: Jacobi).
+
+    fill: at most this many off-diagonal entries per column of Z, the ones of
+    largest magnitude (the fixed-fill Bridson class of Sec. 5); None: no cap."""
     L = lib()
     h = ctypes.c_void_p()
     nnz = ctypes.c_int64()
     brow = ctypes.c_int64()
     diag, ae, an = _f64(p.diag), _f64(p.ae), _f64(p.an)
-    st = L.ora_ainv_setup(p.nx, p.ny, int(p.periodic), _ptr(diag), _ptr(ae), _ptr(an),
-                          float(tau), ctypes.byref(h), ctypes.byref(nnz), ctypes.byref(brow))
+    if fill is None:
+        st = L.ora_ainv_setup(p.nx, p.ny, int(p.periodic), _ptr(diag), _ptr(ae), _ptr(an),
+                              float(tau), ctypes.byref(h), ctypes.byref(nnz), ctypes.byref(brow))
+    else:
+        if int(fill) < 0:
+            raise ValueError("fill must be >= 0")
+        st = L.ora_ainv_setup_fill(p.nx, p.ny, int(p.periodic), _ptr(diag), _ptr(ae),
+                                   _ptr(an), float(tau), int(fill), ctypes.byref(h),
+                                   ctypes.byref(nnz), ctypes.byref(brow))
     if st != OK:
         raise OracleError(st, f"(breakdown row {brow.value})")
     n = p.nx * p.ny

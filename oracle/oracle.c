@@ -15,6 +15,9 @@
  *                   A-orthogonalisation with a drop tolerance (the AINV of
  *                   the paper's ref. [book4-14]; the threshold variant is the
  *                   "drop tolerance" Bridson class of Sec. 5).
+ *   ora_ainv_setup_fill  the same with at most `fill` off-diagonal entries
+ *                   kept in each column of Z (the fixed-fill Bridson class
+ *                   of Sec. 5).
  *   ora_prec_apply  s = Z D^-1 Z^T r (Algorithm 1, preconditioning step).
  *   ora_pcg         Algorithm 1 (FSAI/AINV-PCG), FP64.
  *   ora_pcg_mixed   FP64 iterative refinement around an FP32 inner PCG.
@@ -37,6 +40,8 @@
  *   - Drop rule: after each column update, every off-diagonal entry that was
  *     touched and has |z| < tau, or is exactly zero, is removed.  The unit
  *     diagonal is never dropped; an entry equal to tau is kept.
+ *   - Fixed fill: the count is applied to a finished column, before its pivot
+ *     p_i is formed, so p_i and every later update use the capped column.
  */
 #include <math.h>
 #include <stdint.h>
@@ -183,10 +188,43 @@ void ora_ainv_free(void *h) {
     free(F);
 }
 
-/* Returns ORA_OK and a handle, or ORA_EBREAKDOWN (p_i <= 0) / ORA_EINVAL. */
-int ora_ainv_setup(int64_t nx, int64_t ny, int periodic, const double *diag,
-                   const double *ae, const double *an, double tau, void **out,
-                   int64_t *nnz_off, int64_t *breakdown_row) {
+/* Fixed fill (the second Bridson class of Sec. 5, a set number of nonzeros
+ * in each row of the lower factor Z^T, i.e. each column of Z): keep the
+ * `fill` off-diagonal entries of z_i of largest magnitude.  Equal magnitudes
+ * are ranked by row, the larger row (nearer the diagonal) first.  The kept
+ * entries stay in increasing row order.  Plain selection by repeated scans:
+ * the columns are short. */
+static int keep_largest(ora_col *z, int64_t fill) {
+    if (z->len <= fill) return ORA_OK;
+    char *keep = (char *)calloc((size_t)z->len, 1);
+    if (!keep) return ORA_ENOMEM;
+    for (int64_t k = 0; k < fill; k++) {
+        int64_t best = -1;
+        for (int64_t a = 0; a < z->len; a++) {
+            if (keep[a]) continue;
+            if (best < 0 || fabs(z->v[a]) > fabs(z->v[best]) ||
+                (fabs(z->v[a]) == fabs(z->v[best]) && z->r[a] > z->r[best]))
+                best = a;
+        }
+        keep[best] = 1;
+    }
+    int64_t w = 0;
+    for (int64_t a = 0; a < z->len; a++) {
+        if (!keep[a]) continue;
+        z->r[w] = z->r[a];
+        z->v[w] = z->v[a];
+        w++;
+    }
+    z->len = w;
+    free(keep);
+    return ORA_OK;
+}
+
+/* Returns ORA_OK and a handle, or ORA_EBREAKDOWN (p_i <= 0) / ORA_EINVAL /
+ * ORA_ENOMEM.  fill < 0: no cap on the entries per column. */
+int ora_ainv_setup_fill(int64_t nx, int64_t ny, int periodic, const double *diag,
+                        const double *ae, const double *an, double tau, int64_t fill,
+                        void **out, int64_t *nnz_off, int64_t *breakdown_row) {
     *out = NULL;
     if (breakdown_row) *breakdown_row = -1;
     int st = check_a5(nx, ny, periodic, diag, ae, an);
@@ -213,6 +251,11 @@ int ora_ainv_setup(int64_t nx, int64_t ny, int periodic, const double *diag,
         double vals[5];
         int m = a_row(nx, ny, periodic, diag, ae, an, i, cols, vals);
         ora_col *zi = &F->z[i];
+        /* every update of z_i has been applied (only steps < i touch it) */
+        if (fill >= 0) {
+            st = keep_largest(zi, fill);
+            if (st) goto done;
+        }
 
         /* p_i = a_i^T z_i */
         double p = 0.0;
@@ -330,6 +373,13 @@ done:
     if (st) { ora_ainv_free(F); return st; }
     *out = F;
     return ORA_OK;
+}
+
+int ora_ainv_setup(int64_t nx, int64_t ny, int periodic, const double *diag,
+                   const double *ae, const double *an, double tau, void **out,
+                   int64_t *nnz_off, int64_t *breakdown_row) {
+    return ora_ainv_setup_fill(nx, ny, periodic, diag, ae, an, tau, -1, out, nnz_off,
+                               breakdown_row);
 }
 
 /* Export Z (strictly upper part) in CSC: colptr[n+1], rowidx/val[nnz_off],
