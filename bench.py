@@ -6,7 +6,8 @@ tolerance 0.05) of the synthetic 1442x1021 problem from x0 = 0 to relative
 residual 1e-10, inputs resident in HBM.  `value` = iterations per second over
 the K timed steps.  The same JSON line carries the mixed-precision solve (FP32
 inner PCG + FP64 refinement) on the same GPU, the diagonal (Jacobi)
-preconditioner baseline, the paper's banded factor of T (q = 4), the roofline of the dominant kernel (HIP-event
+preconditioner baseline, the paper's banded factor of T (q = 4), the fixed-fill
+AINV (the second Bridson class of Sec. 5) at a few counts per column, the roofline of the dominant kernel (HIP-event
 timing on the solver stream), and the FP64 oracle timed on the host.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -23,6 +24,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 NX, NY, TAU, TOL = 1442, 1021, 0.05, 1e-10
+# fixed-fill AINV settings reported beside the threshold factor: (drop_tol, count)
+FIXED_FILL = ((0.01, 4), (0.01, 6), (0.01, 8), (0.005, 10))
 PEAK_HBM_GBS = 8000.0
 METRIC = "PCG iter/s + HBM GB/s @1442x1021 FP64 vs mixed; served solves/s, p99 lat"
 
@@ -415,6 +418,26 @@ def main():
     dtb = time.perf_counter() - t0
     log(f"banded factor of T (q=4, diagonal storage): {rb.iters} iterations, {dtb * 1e3:.2f} ms/solve")
 
+    # ---- the second Bridson class of Sec. 5: a fixed count per column of Z ---
+    fixed_fill = []
+    for tau_f, fill in FIXED_FILL:
+        Gf = P.ainv_setup(A, tau_f, fill=fill)
+        Sf = P.Solver(A, Gf, "fp64", device=dev)
+        Sf.tune(chunk=args.chunk, use_graph=not args.no_graph, max_blocks=args.max_blocks)
+        Sf.solve(b, tol=TOL)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rf = Sf.solve(b, tol=TOL)
+        torch.cuda.synchronize()
+        dtf = time.perf_counter() - t0
+        fixed_fill.append({"drop_tol": tau_f, "fill": fill, "nnz_off": Gf.nnz_off,
+                           "iters": rf.iters, "ms_per_solve": round(dtf * 1e3, 3),
+                           "true_relres": rf.true_relres})
+        log(f"fixed fill (drop_tol {tau_f}, {fill} per column): nnz_off {Gf.nnz_off} "
+            f"({Gf.nnz_off / p.n:.2f}/cell), {rf.iters} iterations, {dtf * 1e3:.2f} ms/solve")
+        Sf.close()
+        del Gf
+
     # ---- autotuner on the benchmark grid (reported; the timed solves above use
     # the defaults the committed profiles describe) -------------------------
     tuned64 = None
@@ -496,6 +519,7 @@ def main():
                    "true_relres": rj.true_relres},
         "band_factor_q4": {"iters": rb.iters, "ms_per_solve": round(dtb * 1e3, 3),
                            "true_relres": rb.true_relres, "band_q": Sb.band_q},
+        "fixed_fill": fixed_fill,
         "autotune_fp64": tuned64,
         "timestep": tstep,
         "batched": batched,

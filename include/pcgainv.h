@@ -90,6 +90,21 @@ const char *pcga_last_error(void);
  */
 int pcga_ainv_setup(const pcga_a5_t *A, double drop_tol, pcga_ainv_t **out);
 
+/* pcga_ainv_setup_fill: the fixed-fill form, the second Bridson class of
+ * Sec. 5 (a set number of nonzeros in each row of the lower factor Z^T, i.e.
+ * each column of Z).  The same A-orthogonalisation as pcga_ainv_setup, with
+ * drop_tol applied after every update as there (0 disables it); in addition,
+ * when column z_j has received all its updates it keeps only its `max_fill`
+ * off-diagonal entries of largest magnitude (equal magnitudes: the larger
+ * row, nearer the diagonal, first), and p_j is formed from the capped
+ * column.  max_fill = 0 gives Z = I, D = diag(A); a cap above the longest
+ * column of the threshold factor gives that factor bitwise.  Every row of Z^T
+ * then has at most max_fill off-diagonal entries.  Deterministic.
+ * Errors: EINVAL (as pcga_ainv_setup, or max_fill < 0), EBREAKDOWN, ENOMEM.
+ * On error *out is NULL (when out is not). */
+int pcga_ainv_setup_fill(const pcga_a5_t *A, double drop_tol, int32_t max_fill,
+                         pcga_ainv_t **out);
+
 /* pcga_fsai_band_setup: the paper's own preconditioner (Sec. 3, six-step
  * scheme; Propositions 2-3): the factored approximate inverse of T, the part
  * of A with |col - row| <= 1 in natural ordering (east-west couplings inside

@@ -42,6 +42,7 @@ _SIGS = {
     "pcga_strerror": ([ctypes.c_int], ctypes.c_char_p),
     "pcga_last_error": ([], ctypes.c_char_p),
     "pcga_ainv_setup": ([ctypes.POINTER(A5), _dbl, _pp], ctypes.c_int),
+    "pcga_ainv_setup_fill": ([ctypes.POINTER(A5), _dbl, _i32, _pp], ctypes.c_int),
     "pcga_fsai_band_setup": ([ctypes.POINTER(A5), _i32, _pp], ctypes.c_int),
     "pcga_ainv_info": ([_p, _pi64, _pi64], ctypes.c_int),
     "pcga_ainv_export": ([_p, _p, _p, _p, _p], ctypes.c_int),

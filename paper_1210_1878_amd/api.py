@@ -102,13 +102,21 @@ class AInv:
             self._h = None
 
 
-def ainv_setup(A: Stencil5, drop_tol: float) -> AInv:
-    """Approximate inverse factor by A-orthogonalisation with a drop tolerance."""
+def ainv_setup(A: Stencil5, drop_tol: float, fill=None) -> AInv:
+    """Approximate inverse factor by A-orthogonalisation with a drop tolerance.
+
+    fill: keep at most this many off-diagonal entries in each column of Z, the
+    largest in magnitude (the fixed-fill Bridson class of Sec. 5); None: no
+    cap."""
     L = _lib.load()
     h = ctypes.c_void_p()
     a5 = A.c_struct()
-    check(L.pcga_ainv_setup(ctypes.byref(a5), float(drop_tol), ctypes.byref(h)),
-          "pcga_ainv_setup")
+    if fill is None:
+        check(L.pcga_ainv_setup(ctypes.byref(a5), float(drop_tol), ctypes.byref(h)),
+              "pcga_ainv_setup")
+    else:
+        check(L.pcga_ainv_setup_fill(ctypes.byref(a5), float(drop_tol), int(fill),
+                                     ctypes.byref(h)), "pcga_ainv_setup_fill")
     return AInv(h)
 
 

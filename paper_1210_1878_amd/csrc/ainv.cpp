@@ -15,6 +15,10 @@
 //   - a new entry takes the value 0.0 - m*v.
 // This file must be compiled without floating-point contraction.
 //
+// With a fill cap the finished column is capped before its pivot; steps only
+// read final columns, so this equals capping each column when it becomes the
+// pivot of the right-looking statement.
+//
 // Candidate steps for column j are kept in a min-heap: a step i can touch
 // z_j only if row i of A has a column where z_j is nonzero, i.e. i is a grid
 // neighbour (or the cell itself) of some entry of z_j.
@@ -80,7 +84,26 @@ static int stencil_of(const A5View &A, int64_t r, int64_t *out) {
     return m;
 }
 
-int ainv_build(const A5View &A, double tau, AinvFactor &F, int64_t *bad_row) {
+// Fixed fill (the second Bridson class of Sec. 5: a set number of nonzeros
+// per row of the lower factor Z^T, i.e. per column of Z): a finished column
+// keeps its `fill` off-diagonal entries of largest magnitude, the larger row
+// first among equal magnitudes, and its pivot is formed from what is kept.
+static void cap_column(int64_t j, int64_t fill, const std::vector<int64_t> &pattern,
+                       const std::vector<double> &w, std::vector<int64_t> &live,
+                       std::vector<int64_t> &off) {
+    off.clear();
+    for (int64_t r : pattern)
+        if (r != j && live[r] == j) off.push_back(r);
+    if ((int64_t)off.size() <= fill) return;
+    auto first = [&](int64_t a, int64_t b) {
+        const double fa = std::fabs(w[a]), fb = std::fabs(w[b]);
+        return fa != fb ? fa > fb : a > b;
+    };
+    std::nth_element(off.begin(), off.begin() + fill, off.end(), first);
+    for (size_t t = (size_t)fill; t < off.size(); t++) live[off[t]] = -1;
+}
+
+int ainv_build(const A5View &A, double tau, int64_t fill, AinvFactor &F, int64_t *bad_row) {
     if (bad_row) *bad_row = -1;
     int st = A.validate();
     if (st) return st;
@@ -99,6 +122,7 @@ int ainv_build(const A5View &A, double tau, AinvFactor &F, int64_t *bad_row) {
         std::vector<int64_t> queued(n, -1);   // queued[i] == j: step i already queued
         std::vector<int64_t> pattern;         // rows ever inserted into z_j
         std::priority_queue<int64_t, std::vector<int64_t>, std::greater<int64_t>> steps;
+        std::vector<int64_t> off;             // scratch of cap_column
 
         int64_t cols[5];
         double vals[5];
@@ -152,6 +176,7 @@ int ainv_build(const A5View &A, double tau, AinvFactor &F, int64_t *bad_row) {
                     }
                 }
             }
+            if (fill >= 0) cap_column(j, fill, pattern, w, live, off);
             // p_j = a_j^T z_j
             const int m = A.row(j, cols, vals);
             double p = 0.0;

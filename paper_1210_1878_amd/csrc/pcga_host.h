@@ -30,7 +30,8 @@ struct AinvFactor {
     int64_t nnz_off() const { return colptr.empty() ? 0 : colptr.back(); }
 };
 
-int ainv_build(const A5View &A, double tau, AinvFactor &F, int64_t *bad_row);
+// fill < 0: no cap on the off-diagonal entries per column
+int ainv_build(const A5View &A, double tau, int64_t fill, AinvFactor &F, int64_t *bad_row);
 int fsai_band_build(const A5View &A, int64_t q, AinvFactor &F, int64_t *bad_row);
 
 // Sliced ELL with a per-slice number of lanes per row ("SELL-L").

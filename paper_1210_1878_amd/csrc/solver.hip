@@ -315,7 +315,8 @@ const char *pcga_strerror(int s) {
 
 const char *pcga_last_error(void) { return last_error().c_str(); }
 
-int pcga_ainv_setup(const pcga_a5_t *A, double drop_tol, pcga_ainv_t **out) {
+static int ainv_setup_impl(const pcga_a5_t *A, double drop_tol, int64_t fill,
+                           pcga_ainv_t **out) {
     if (!out) return fail(PCGA_EINVAL, "out is NULL");
     *out = nullptr;
     int st = check_a5(A);
@@ -324,7 +325,7 @@ int pcga_ainv_setup(const pcga_a5_t *A, double drop_tol, pcga_ainv_t **out) {
     pcga_ainv *h = new (std::nothrow) pcga_ainv;
     if (!h) return fail(PCGA_ENOMEM, "host allocation failed");
     int64_t bad = -1;
-    st = ainv_build(view_of(A), drop_tol, h->F, &bad);
+    st = ainv_build(view_of(A), drop_tol, fill, h->F, &bad);
     if (st) {
         delete h;
         if (st == PCGA_EBREAKDOWN)
@@ -333,6 +334,17 @@ int pcga_ainv_setup(const pcga_a5_t *A, double drop_tol, pcga_ainv_t **out) {
     }
     *out = h;
     return PCGA_OK;
+}
+
+int pcga_ainv_setup(const pcga_a5_t *A, double drop_tol, pcga_ainv_t **out) {
+    return ainv_setup_impl(A, drop_tol, -1, out);
+}
+
+int pcga_ainv_setup_fill(const pcga_a5_t *A, double drop_tol, int32_t max_fill,
+                         pcga_ainv_t **out) {
+    if (out) *out = nullptr;
+    if (max_fill < 0) return fail(PCGA_EINVAL, "max_fill must be >= 0");
+    return ainv_setup_impl(A, drop_tol, max_fill, out);
 }
 
 int pcga_fsai_band_setup(const pcga_a5_t *A, int32_t q, pcga_ainv_t **out) {

@@ -161,3 +161,37 @@ def test_fsai_band_bitwise_equal_to_oracle(ora, q):
         assert np.array_equal(D.view(np.uint64), F.D.view(np.uint64))
     with pytest.raises(_lib.PcgaError):
         fsai_band_setup(Stencil5.from_problem(orca.box_problem(5, 4)), -1)
+
+
+def _fill_equal(ora, p, tau, fill):
+    F = ora.ainv_setup(p, tau, fill=fill)
+    G = ainv_setup(Stencil5.from_problem(p), tau, fill=fill)
+    colptr, rowidx, val, D = G.export()
+    assert np.array_equal(colptr, F.colptr)
+    assert np.array_equal(rowidx.astype(np.int64), F.rowidx)
+    assert np.array_equal(val.view(np.uint64), F.val.view(np.uint64))
+    assert np.array_equal(D.view(np.uint64), F.D.view(np.uint64))
+
+
+@pytest.mark.parametrize("tau,fill", [(0.0, 0), (0.0, 1), (0.0, 3), (0.0, 8), (0.01, 4),
+                                      (0.05, 6), (0.1, 100)])
+def test_fixed_fill_bitwise_equal_to_oracle(ora, tau, fill):
+    """The fixed-fill AINV (second Bridson class of Sec. 5): the library's
+    left-looking setup equals the oracle's right-looking one to the bit."""
+    for p in (orca.orca_problem(37, 23, 5), orca.box_problem(20, 9, seed=2),
+              const_periodic(9, 5)):
+        _fill_equal(ora, p, tau, fill)
+
+
+def test_fixed_fill_bitwise_equal_to_oracle_orca2(ora):
+    _fill_equal(ora, orca.orca_problem(182, 149, orca.CONFIG_SEED_BASE + 1), 0.01, 6)
+
+
+def test_fixed_fill_errors():
+    A = Stencil5.from_problem(laplace1d(8))
+    with pytest.raises(_lib.PcgaError) as e:
+        ainv_setup(A, 0.0, fill=-1)
+    assert e.value.status == _lib.EINVAL
+    with pytest.raises(_lib.PcgaError) as e:
+        ainv_setup(A, -1.0, fill=2)
+    assert e.value.status == _lib.EINVAL

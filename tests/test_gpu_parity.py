@@ -482,3 +482,71 @@ def test_largest_catalogue_grid(pkg, ora):
     true = np.linalg.norm(p.b - ora.spmv(p, xg)) / np.linalg.norm(p.b)
     say("  iterations", g.iters, "true relres", true)
     assert g.status == 0 and g.hist[-1] <= 1e-10 and true <= 1.05e-10
+
+
+@pytest.mark.parametrize("tau,fill", [(0.01, 4), (0.01, 8), (0.0, 3)])
+def test_pcg_fixed_fill(pkg, ora, tau, fill):
+    """The fixed-fill AINV (second Bridson class of Sec. 5) through the same
+    sliced-ELL path: every row of Z^T holds at most `fill` off-diagonal
+    entries; device and oracle iterates match; the natural stop agrees; the
+    mixed form reaches the FP64 bar."""
+    p, _ = case("orca182x149")
+    say("fixed fill: drop_tol", tau, "fill", fill)
+    A = pkg.Stencil5.from_problem(p)
+    G = pkg.ainv_setup(A, tau, fill=fill)
+    F = ora.ainv_setup(p, tau, fill=fill)
+    assert G.nnz_off == F.nnz_off
+    assert int(np.diff(F.colptr).max()) <= fill
+    K = ora.pcg(p, F, tol=1e-10).iters
+    for prec in ("fp64", "mixed"):
+        S = pkg.Solver(A, G, prec)
+        if prec == "fp64":
+            g = S.solve(dev(p.b), tol=0.0, maxit=K)
+            o = ora.pcg(p, F, tol=0.0, maxit=K)
+            assert np.linalg.norm(g.x.cpu().numpy() - o.x) <= 1e-9 * np.linalg.norm(o.x)
+            nat = S.solve(dev(p.b), tol=1e-10)
+            say(f"  natural stop: device {nat.iters}, oracle {K}")
+            assert nat.status == 0 and abs(nat.iters - K) <= 2
+            assert nat.true_relres <= 1e-10
+        else:
+            m = S.solve_mixed(dev(p.b), tol=1e-10)
+            say(f"  mixed: outer {m.outer}, inner {m.inner_total}, true {m.true_relres:.2e}")
+            assert m.status == 0 and m.true_relres <= 1e-10
+        S.close()
+
+
+def test_full_size_fixed_fill(pkg, ora, orca025):
+    """Fixed fill at 1442x1021 (drop_tol 0.01, 8 per column): the
+    preconditioner apply against the oracle over the whole grid, 12 iterations
+    matched, then the natural stop with the true residual recomputed by the
+    oracle's product.  This iteration amplifies rounding quickly: the oracle's
+    own iterate after 40 steps moves by about 1e-6 (relative) when b is
+    perturbed by 1e-15, so iterates are compared where rounding has not yet
+    grown (as for the threshold factor)."""
+    p, _, A, _ = orca025
+    say("full size: fixed fill 8, drop_tol 0.01")
+    G = pkg.ainv_setup(A, 0.01, fill=8)
+    F = ora.ainv_setup(p, 0.01, fill=8)
+    assert G.nnz_off == F.nnz_off
+    S = pkg.Solver(A, G, "fp64")
+    x = np.random.default_rng(23).standard_normal(p.n)
+    t, s = S.apply_prec(dev(x))
+    t_ref = ora.zt_apply(F, x)
+    s_ref = ora.z_apply(F, t_ref)
+    Fa = ora.AInv(F.n, F.colptr, F.rowidx, np.abs(F.val), F.D)
+    t_mag = ora.zt_apply(Fa, np.abs(x))
+    s_mag = ora.z_apply(Fa, t_mag)
+    width = int(np.diff(F.colptr).max()) + 2
+    assert np.all(np.abs(t.cpu().numpy() - t_ref) <= width * 4 * EPS * t_mag)
+    assert np.all(np.abs(s.cpu().numpy() - s_ref) <= 2 * width * 4 * EPS * s_mag)
+    g = S.solve(dev(p.b), tol=0.0, maxit=12)
+    o = ora.pcg(p, F, tol=0.0, maxit=12)
+    assert g.iters == o.iters == 12
+    assert np.linalg.norm(g.x.cpu().numpy() - o.x) <= 1e-9 * np.linalg.norm(o.x)
+    assert np.allclose(g.hist, o.hist, rtol=1e-9)
+    full = S.solve(dev(p.b), tol=1e-10)
+    say("  iterations", full.iters, "true relres", full.true_relres)
+    assert full.status == 0
+    xf = full.x.cpu().numpy()
+    assert np.linalg.norm(p.b - ora.spmv(p, xf)) / np.linalg.norm(p.b) <= 1.05e-10
+    S.close()
