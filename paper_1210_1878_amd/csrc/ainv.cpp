@@ -94,6 +94,10 @@ static void cap_column(int64_t j, int64_t fill, const std::vector<int64_t> &patt
     off.clear();
     for (int64_t r : pattern)
         if (r != j && live[r] == j) off.push_back(r);
+    // an entry removed by the drop tolerance and inserted again by a later
+    // step (possible when couplings of both signs cancel) is listed twice
+    std::sort(off.begin(), off.end());
+    off.erase(std::unique(off.begin(), off.end()), off.end());
     if ((int64_t)off.size() <= fill) return;
     auto first = [&](int64_t a, int64_t b) {
         const double fa = std::fabs(w[a]), fb = std::fabs(w[b]);

@@ -54,3 +54,26 @@ def cholesky_ainv(M):
     dl = np.diag(L)
     Z = Linv.T * dl[None, :]
     return Z, dl ** 2
+
+
+def mixed_sign_dominant(nx, ny, periodic, seed):
+    """Five-point operator with couplings of both signs, U(-1, 1) seeded, and
+    a strictly dominant diagonal (1.05 x the row's absolute coupling sum plus
+    1e-3): symmetric positive definite but not an M-matrix."""
+    rng = np.random.default_rng(seed)
+    n = nx * ny
+    ae = rng.uniform(-1.0, 1.0, n)
+    an = rng.uniform(-1.0, 1.0, n)
+    if not periodic:
+        ae[nx - 1::nx] = 0.0
+    an[(ny - 1) * nx:] = 0.0
+    A = np.abs(ae).reshape(ny, nx)
+    west = np.roll(A, 1, axis=1)
+    if not periodic:
+        west[:, 0] = 0.0
+    N = np.abs(an).reshape(ny, nx)
+    south = np.zeros_like(N)
+    south[1:] = N[:-1]
+    diag = (A + west + N + south).ravel() * 1.05 + 1e-3
+    return Problem(nx, ny, periodic, diag, ae, an, np.ones(n, dtype=bool), np.ones(n),
+                   name=f"mixed{nx}x{ny}")

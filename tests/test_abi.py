@@ -10,7 +10,7 @@ import pytest
 from gen import orca
 from paper_1210_1878_amd import _lib
 from paper_1210_1878_amd.api import AInv, Stencil5, ainv_setup
-from tests._cases import const_periodic, laplace1d
+from tests._cases import const_periodic, laplace1d, mixed_sign_dominant
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -185,6 +185,17 @@ def test_fixed_fill_bitwise_equal_to_oracle(ora, tau, fill):
 
 def test_fixed_fill_bitwise_equal_to_oracle_orca2(ora):
     _fill_equal(ora, orca.orca_problem(182, 149, orca.CONFIG_SEED_BASE + 1), 0.01, 6)
+
+
+@pytest.mark.parametrize("seed,nx,ny,periodic", [(1, 16, 11, True), (2, 25, 7, False),
+                                                 (5, 21, 16, True)])
+def test_fixed_fill_mixed_sign_operator(ora, seed, nx, ny, periodic):
+    """Couplings of both signs can cancel an entry below the drop tolerance
+    and a later step can insert it again: the cap must count it once."""
+    p = mixed_sign_dominant(nx, ny, periodic, seed)
+    for tau in (0.001, 0.01):
+        for fill in (3, 8):
+            _fill_equal(ora, p, tau, fill)
 
 
 def test_fixed_fill_errors():

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 from gen import orca
-from tests._cases import const_periodic, laplace1d
+from tests._cases import const_periodic, laplace1d, mixed_sign_dominant
 
 EPS = np.finfo(float).eps
 
@@ -138,7 +138,9 @@ def _brute_force(A, tau, fill):
 
 @pytest.mark.parametrize("tau,fill", [(0.0, 1), (0.0, 2), (0.0, 4), (0.02, 2), (0.02, 3)])
 @pytest.mark.parametrize("make", [lambda: orca.orca_problem(7, 6, 3),
-                                  lambda: const_periodic(6, 5)])
+                                  lambda: const_periodic(6, 5),
+                                  lambda: mixed_sign_dominant(7, 6, True, 3),
+                                  lambda: mixed_sign_dominant(8, 5, False, 4)])
 def test_fill_matches_dense_brute_force(ora, make, tau, fill):
     p = make()
     A = _dense_a(p)
