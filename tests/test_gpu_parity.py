@@ -550,3 +550,42 @@ def test_full_size_fixed_fill(pkg, ora, orca025):
     xf = full.x.cpu().numpy()
     assert np.linalg.norm(p.b - ora.spmv(p, xf)) / np.linalg.norm(p.b) <= 1.05e-10
     S.close()
+
+
+@pytest.mark.parametrize("fill", [None, 6])
+def test_pcg_mixed_sign_operator(pkg, ora, fill):
+    """A symmetric positive definite operator with couplings of both signs
+    (not an M-matrix: the factor holds entries of both signs): matched
+    iterates, the natural stop, and the preconditioner apply against the
+    oracle, for the threshold and the fixed-fill factor."""
+    from tests._cases import mixed_sign_dominant
+    p = mixed_sign_dominant(203, 157, True, 11)
+    rng = np.random.default_rng(12)
+    p.b = rng.standard_normal(p.n)
+    say("mixed-sign operator", p.nx, "x", p.ny, "fill", fill)
+    A = pkg.Stencil5.from_problem(p)
+    G = pkg.ainv_setup(A, 0.01, fill=fill)
+    F = ora.ainv_setup(p, 0.01, fill=fill)
+    assert G.nnz_off == F.nnz_off
+    assert (F.val < 0).any() and (F.val > 0).any()
+    S = pkg.Solver(A, G, "fp64")
+    x = rng.standard_normal(p.n)
+    t, s = S.apply_prec(dev(x))
+    t_ref = ora.zt_apply(F, x)
+    s_ref = ora.z_apply(F, t_ref)
+    Fa = ora.AInv(F.n, F.colptr, F.rowidx, np.abs(F.val), F.D)
+    t_mag = ora.zt_apply(Fa, np.abs(x))
+    s_mag = ora.z_apply(Fa, t_mag)
+    width = int(np.diff(F.colptr).max()) + 2
+    assert np.all(np.abs(t.cpu().numpy() - t_ref) <= width * 4 * EPS * t_mag)
+    assert np.all(np.abs(s.cpu().numpy() - s_ref) <= 2 * width * 4 * EPS * s_mag)
+    K = ora.pcg(p, F, tol=1e-10).iters
+    g = S.solve(dev(p.b), tol=0.0, maxit=min(K, 12))
+    o = ora.pcg(p, F, tol=0.0, maxit=min(K, 12))
+    assert np.linalg.norm(g.x.cpu().numpy() - o.x) <= 1e-9 * np.linalg.norm(o.x)
+    nat = S.solve(dev(p.b), tol=1e-10)
+    say(f"  natural stop: device {nat.iters}, oracle {K}")
+    assert nat.status == 0 and abs(nat.iters - K) <= 2
+    xf = nat.x.cpu().numpy()
+    assert np.linalg.norm(p.b - ora.spmv(p, xf)) / np.linalg.norm(p.b) <= 1.05e-10
+    S.close()
