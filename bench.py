@@ -113,7 +113,21 @@ def cpu_baseline(p, seconds=15.0):
     dt = time.perf_counter() - t0
     return {"value": r.iters / dt, "unit": "iter/s", "cores": 1, "kind": "oracle",
             "sample": f"{r.iters} FP64 PCG-AINV iterations of the oracle on the 1442x1021 "
-                      f"problem from x0=0 (setup {setup_s:.1f}s excluded), one thread"}
+                      f"problem from x0=0 (setup {setup_s:.1f}s excluded), one thread",
+            "setup_s": round(setup_s, 2), "host_cpu": host_cpu_model(),
+            "host_threads": os.cpu_count()}
+
+
+def host_cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def bench_batch(P, torch, dev, log, members=64, nrhs=4):
@@ -470,6 +484,10 @@ def main():
     log("fp32 kernels ms: " + ", ".join(f"{k}={ms32[i]:.4f} ({gbs32[k]:.0f} GB/s)" for i, k in enumerate(names))
         + f", iteration={ms32[3]:.4f}")
     b_iter = sum(kb.values())
+    # land cells are identity rows with no Z entries: the same per-iteration
+    # bytes counted over ocean cells only (Z entries are all ocean)
+    n_ocean = int(p.ocean.sum())
+    b_iter_ocean = sum(kernel_bytes(n_ocean, G.nnz_off, 8, S64.index_bytes).values())
     b_iter32 = sum(kb32.values())
     it_time = ms[3] * 1e-3
     kname = kernel_names(8, S64.formats)[names[dom]]
@@ -507,6 +525,9 @@ def main():
                  "true_relres": fp64_true, "model_bytes_per_iter": b_iter,
                  "model_gbs_per_iter_kernels": round(b_iter / it_time / 1e9, 1),
                  "model_gbs_whole_solve": round(b_iter * it_s / 1e9, 1),
+                 "ocean_cells": n_ocean,
+                 "model_bytes_per_iter_ocean_only": b_iter_ocean,
+                 "model_gbs_whole_solve_ocean_only": round(b_iter_ocean * it_s / 1e9, 1),
                  "kernel_ms": dict(zip(names, [round(v, 5) for v in ms[:3]])),
                  "iteration_ms": round(ms[3], 5)},
         "mixed": {"ms_per_solve": round(dtm * 1e3, 3), "outer": m.outer, "inner_iters": m.inner_total,
