@@ -115,7 +115,50 @@ def cpu_baseline(p, seconds=15.0):
             "sample": f"{r.iters} FP64 PCG-AINV iterations of the oracle on the 1442x1021 "
                       f"problem from x0=0 (setup {setup_s:.1f}s excluded), one thread",
             "setup_s": round(setup_s, 2), "host_cpu": host_cpu_model(),
-            "host_threads": os.cpu_count()}
+            "host_threads": os.cpu_count(),
+            "jacobi": cpu_jacobi(p, max(2.0, seconds / 5)),
+            "ensemble": cpu_ensemble(max(2.0, seconds / 3))}
+
+
+def cpu_jacobi(p, seconds):
+    """The oracle's Jacobi PCG (drop tolerance +inf: Z = I, D = diag(A)) in
+    the same harness: iterations per second on the same problem."""
+    import oracle
+    F = oracle.ainv_setup(p, float("inf"))
+    t0 = time.perf_counter()
+    oracle.pcg(p, F, tol=0.0, maxit=5)
+    m = max(10, int(seconds / ((time.perf_counter() - t0) / 5)))
+    t0 = time.perf_counter()
+    r = oracle.pcg(p, F, tol=0.0, maxit=m)
+    return {"value": round(r.iters / (time.perf_counter() - t0), 2), "unit": "iter/s",
+            "sample": f"{r.iters} iterations"}
+
+
+def cpu_ensemble(seconds, members=64, nrhs=4):
+    """The oracle on the batched workload: whole FP64 solves to 1e-10 of the
+    ensemble's grids and right-hand sides, in order, until about `seconds`
+    have passed (setups excluded).  Reported per core, and as the aggregate of
+    one independent solve per host thread (the ensemble's solves share
+    nothing)."""
+    import oracle
+    from gen import orca
+    ens = orca.ensemble_problems(count=members, nrhs=nrhs)
+    done, busy = 0, 0.0
+    for q in ens:
+        F = oracle.ainv_setup(q, 0.1)
+        for r in range(nrhs):
+            t0 = time.perf_counter()
+            oracle.pcg(q, F, b=q.B[r], tol=TOL)
+            busy += time.perf_counter() - t0
+            done += 1
+        if busy >= seconds:
+            break
+    per_core = done / busy
+    threads = os.cpu_count() or 1
+    return {"solves_per_s_per_core": round(per_core, 2),
+            "solves_per_s_all_threads": round(per_core * threads, 1),
+            "sample": f"{done} of the {members * nrhs} ensemble solves (FP64, 1e-10), one thread; "
+                      f"the aggregate assumes one independent solve per host thread"}
 
 
 def host_cpu_model():
