@@ -426,13 +426,17 @@ def main():
 
     # ---- timed region: K FP64 solves -------------------------------------
     iters = 0
+    per_solve = []          # each solve returns after its result is on the host
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        ts = time.perf_counter()
         r = S64.solve(b, tol=TOL)
+        per_solve.append((time.perf_counter() - ts, r.iters))
         iters += r.iters
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    med_s, med_it = sorted(per_solve)[len(per_solve) // 2]
     it_s = iters / dt
     log(f"fp64: {args.steps} solves, {iters} iterations, {dt * 1e3 / args.steps:.2f} ms/solve, "
         f"{it_s:.0f} it/s, true relres {r.true_relres:.2e}")
@@ -568,6 +572,8 @@ def main():
                  "true_relres": fp64_true, "model_bytes_per_iter": b_iter,
                  "model_gbs_per_iter_kernels": round(b_iter / it_time / 1e9, 1),
                  "model_gbs_whole_solve": round(b_iter * it_s / 1e9, 1),
+                 "ms_per_solve_median": round(med_s * 1e3, 3),
+                 "it_s_median_solve": round(med_it / med_s, 1),
                  "ocean_cells": n_ocean,
                  "model_bytes_per_iter_ocean_only": b_iter_ocean,
                  "model_gbs_whole_solve_ocean_only": round(b_iter_ocean * it_s / 1e9, 1),
