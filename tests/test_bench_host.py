@@ -77,3 +77,18 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     line = json.loads(r.stdout.strip().splitlines()[-1])
     assert line["n_gpus"] == 2 and "one GPU" in line["error"]
+
+
+def test_cpu_baseline_helpers_small():
+    """The CPU-baseline legs run the oracle on bounded samples: Jacobi PCG on
+    a small grid and whole ensemble solves; rates are positive and the
+    ensemble aggregate is the per-core rate times the host threads."""
+    from gen import orca
+    p = orca.orca_problem(37, 23, 5)
+    j = bench.cpu_jacobi(p, 0.05)
+    assert j["value"] > 0 and j["unit"] == "iter/s"
+    e = bench.cpu_ensemble(0.01, members=2, nrhs=1)
+    assert e["solves_per_s_per_core"] > 0
+    threads = os.cpu_count() or 1
+    assert abs(e["solves_per_s_all_threads"] - e["solves_per_s_per_core"] * threads) <= 0.1 * threads
+    assert bench.host_cpu_model() is None or isinstance(bench.host_cpu_model(), str)
