@@ -151,12 +151,31 @@ class SolveResult:
         return iter((self.x, self.iters, self.hist))
 
 
+WS_ALIGN = 16 << 20     # alignment of a solver's workspace base (bytes)
+
+
+def workspace_size(A: Stencil5, F: AInv, precision: str = "fp64", slice_width: int = 0) -> int:
+    """Device bytes a Solver of these settings allocates (workspace plus the
+    alignment slack)."""
+    L = _lib.load()
+    nbytes = ctypes.c_size_t()
+    check(L.pcga_workspace_bytes_ex(ctypes.byref(A.c_struct()), F.handle,
+                                    {"fp64": FP64, "mixed": MIXED}[precision], int(slice_width),
+                                    ctypes.byref(nbytes)), "pcga_workspace_bytes_ex")
+    return nbytes.value + WS_ALIGN
+
+
 class Solver:
     """Device solver for one grid: A, Z^T/Z (sliced ELL) and D^-1 resident in
     a torch-allocated workspace; FP64 or mixed precision."""
 
     def __init__(self, A: Stencil5, F: AInv, precision: str = "fp64", device=None, stream=None,
-                 slice_width: int = 0):
+                 slice_width: int = 0, buffer=None):
+        """buffer: optional uint8 device tensor to carve the workspace from
+        (at least workspace_size(...) bytes); solvers built one after another
+        on the same buffer sit at the same address, which lets timings of
+        different settings be compared.  No other work may be using the
+        buffer (an earlier solver on it must be closed and its work finished)."""
         import torch
         L = _lib.load()
         self.A = A
@@ -173,7 +192,26 @@ class Solver:
             # a stream of its own (default priority): chunks are captured into
             # HIP graphs, which the legacy default stream does not allow
             self.stream = torch.cuda.Stream(self.device) if stream is None else stream
-            self.ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+            # the workspace starts on a 16 MiB boundary: at 1442x1021 an FP64
+            # iteration took 96-98 us from such a base and 102-106 us from
+            # some others (the resident part of the workspace fills most of
+            # the 256 MiB memory-side cache, so where it starts matters)
+            if buffer is None:
+                self._ws_buf = torch.empty(self.workspace_bytes + WS_ALIGN, dtype=torch.uint8,
+                                           device=self.device)
+            else:
+                want = (self.device.index if self.device.index is not None
+                        else torch.cuda.current_device())
+                if (buffer.dtype != torch.uint8 or buffer.device.type != "cuda"
+                        or buffer.device.index != want or not buffer.is_contiguous()):
+                    raise ValueError("buffer must be a contiguous uint8 tensor on the solver's device")
+                self._ws_buf = buffer
+            lead = (-self._ws_buf.data_ptr()) % WS_ALIGN
+            if lead + self.workspace_bytes > self._ws_buf.numel():
+                raise ValueError(f"buffer holds {self._ws_buf.numel()} bytes; this solver needs "
+                                 f"{self.workspace_bytes} from a 16 MiB boundary")
+            self.ws = self._ws_buf[lead:lead + self.workspace_bytes]
+            self.footprint_bytes = self.workspace_bytes + WS_ALIGN
             h = ctypes.c_void_p()
             check(L.pcga_solver_create_ex(ctypes.byref(a5), F.handle, self.precision,
                                           self.slice_width, ctypes.c_void_p(self.ws.data_ptr()),

@@ -18,7 +18,7 @@ from __future__ import annotations
 
 import time
 
-from .api import Batch, Solver
+from .api import Batch, Solver, workspace_size
 
 WIDTHS = (8, 12, 16, 24, 32)
 CHUNKS = (16, 32, 64)
@@ -39,8 +39,13 @@ def tune_solver(A, F, b, precision="fp64", widths=WIDTHS, blocks=None, chunks=CH
     blocks = _blocks_for(precision) if blocks is None else blocks
     table = []
     best = None
+    # every candidate is carved from one buffer, at one address: an FP64
+    # iteration's time depends on where its workspace sits in memory, which
+    # would otherwise differ from candidate to candidate
+    buf = torch.empty(max(workspace_size(A, F, precision, w) for w in widths),
+                      dtype=torch.uint8, device=torch.device("cuda" if device is None else device))
     for w in widths:
-        S = Solver(A, F, precision, device=device, slice_width=w)
+        S = Solver(A, F, precision, device=device, slice_width=w, buffer=buf)
         for mb in blocks:
             S.tune(max_blocks=mb)
             S.profile_iteration(b, reps=2, mode=1)          # capture, first touch
@@ -51,8 +56,9 @@ def tune_solver(A, F, b, precision="fp64", widths=WIDTHS, blocks=None, chunks=CH
             if best is None or ms < best[2]:
                 best = (w, mb, ms)
         S.close()
+        torch.cuda.synchronize()     # nothing may still use buf when it is rebuilt
     w, mb, it_ms = best
-    S = Solver(A, F, precision, device=device, slice_width=w)
+    S = Solver(A, F, precision, device=device, slice_width=w, buffer=buf)
     solve = S.solve if precision == "fp64" else S.solve_mixed
     timings = []
     for c in chunks:

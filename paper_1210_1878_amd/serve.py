@@ -62,7 +62,7 @@ class Server:
             A = Stencil5.from_problem(p)
             S = Solver(A, ainv_setup(A, drop_tol), "mixed", device=self.device)
             self.solvers.append(S)
-            self.resident_bytes += S.workspace_bytes
+            self.resident_bytes += S.footprint_bytes
         self.item_bytes = [Batch.item_bytes(S, 1) for S in self.solvers]
         self.budget = hbm_budget            # bytes for in-flight request vectors (None: no limit)
         self.max_slots = max_slots

@@ -589,3 +589,28 @@ def test_pcg_mixed_sign_operator(pkg, ora, fill):
     xf = nat.x.cpu().numpy()
     assert np.linalg.norm(p.b - ora.spmv(p, xf)) / np.linalg.norm(p.b) <= 1.05e-10
     S.close()
+
+
+def test_solver_on_shared_buffer(pkg):
+    """Solvers carved one after another from one buffer (what the autotuner
+    does) give bitwise the results of a solver with its own workspace; a
+    buffer that is too small is refused."""
+    p, _ = case("orca182x149")
+    A = pkg.Stencil5.from_problem(p)
+    G = pkg.ainv_setup(A, 0.1)
+    b = dev(p.b)
+    ref = pkg.Solver(A, G, "fp64").solve(b, tol=1e-10)
+    buf = torch.empty(max(pkg.workspace_size(A, G, "fp64", w) for w in (8, 32)),
+                      dtype=torch.uint8, device="cuda")
+    for w in (8, 0):
+        S = pkg.Solver(A, G, "fp64", slice_width=w, buffer=buf)
+        assert S.ws.data_ptr() % (16 << 20) == 0
+        r = S.solve(b, tol=1e-10)
+        if w == 0:
+            assert r.iters == ref.iters
+            assert torch.equal(r.x, ref.x)
+        S.close()
+        torch.cuda.synchronize()
+    small = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError):
+        pkg.Solver(A, G, "fp64", buffer=small)
