@@ -27,6 +27,7 @@ NX, NY, TAU, TOL = 1442, 1021, 0.05, 1e-10
 # fixed-fill AINV settings reported beside the threshold factor: (drop_tol, count)
 FIXED_FILL = ((0.01, 4), (0.01, 6), (0.01, 8), (0.005, 10))
 SAMPLE_TOL = 1e-14      # stopping tolerance of the oracle's timed samples
+PLACEMENTS = 4          # workspace bases the FP64 solver's placement probe tries
 PEAK_HBM_GBS = 8000.0
 METRIC = "PCG iter/s + HBM GB/s @1442x1021 FP64 vs mixed; served solves/s, p99 lat"
 
@@ -387,7 +388,11 @@ def main():
     G = P.ainv_setup(A, TAU)
     setup_s = time.perf_counter() - t0
     log(f"ainv_setup {setup_s:.2f}s nnz_off={G.nnz_off} ({G.nnz_off / p.n:.2f}/cell)")
-    S64 = P.Solver(A, G, "fp64", device=dev)
+    # the FP64 workspace's placement in memory changes the iteration time by
+    # up to 9%: the solver times a few bases and keeps the fastest
+    S64 = P.Solver(A, G, "fp64", device=dev, probe_placements=PLACEMENTS)
+    log("fp64 placement probe (ms per iteration): "
+        + ", ".join(f"{t:.4f}" for t in (S64.placement_ms or [])))
     Smx = P.Solver(A, G, "mixed", device=dev)
     for S in (S64, Smx):
         S.tune(chunk=args.chunk, use_graph=not args.no_graph, max_blocks=args.max_blocks)
@@ -575,6 +580,7 @@ def main():
                  "true_relres": fp64_true, "model_bytes_per_iter": b_iter,
                  "model_gbs_per_iter_kernels": round(b_iter / it_time / 1e9, 1),
                  "model_gbs_whole_solve": round(b_iter * it_s / 1e9, 1),
+                 "placement_probe_ms_per_iter": [round(t, 5) for t in (S64.placement_ms or [])],
                  "ms_per_solve_median": round(med_s * 1e3, 3),
                  "it_s_median_solve": round(med_it / med_s, 1),
                  "ocean_cells": n_ocean,

@@ -152,6 +152,7 @@ class SolveResult:
 
 
 WS_ALIGN = 16 << 20     # alignment of a solver's workspace base (bytes)
+PROBE_STEP = 4 << 20    # distance between the bases a placement probe tries
 
 
 def workspace_size(A: Stencil5, F: AInv, precision: str = "fp64", slice_width: int = 0) -> int:
@@ -170,12 +171,17 @@ class Solver:
     a torch-allocated workspace; FP64 or mixed precision."""
 
     def __init__(self, A: Stencil5, F: AInv, precision: str = "fp64", device=None, stream=None,
-                 slice_width: int = 0, buffer=None):
+                 slice_width: int = 0, buffer=None, probe_placements: int = 1):
         """buffer: optional uint8 device tensor to carve the workspace from
         (at least workspace_size(...) bytes); solvers built one after another
         on the same buffer sit at the same address, which lets timings of
         different settings be compared.  No other work may be using the
-        buffer (an earlier solver on it must be closed and its work finished)."""
+        buffer (an earlier solver on it must be closed and its work finished).
+
+        probe_placements: with k > 1 (and no buffer), the workspace is
+        allocated with room for k bases PROBE_STEP apart; the solver is built
+        at each, one whole iteration is timed, and the fastest base is kept
+        (`placement_ms` lists them).  Setup then costs k + 1 layout uploads."""
         import torch
         L = _lib.load()
         self.A = A
@@ -196,9 +202,11 @@ class Solver:
             # iteration took 96-98 us from such a base and 102-106 us from
             # some others (the resident part of the workspace fills most of
             # the 256 MiB memory-side cache, so where it starts matters)
+            probes = max(1, int(probe_placements)) if buffer is None else 1
             if buffer is None:
-                self._ws_buf = torch.empty(self.workspace_bytes + WS_ALIGN, dtype=torch.uint8,
-                                           device=self.device)
+                self._ws_buf = torch.empty(self.workspace_bytes + WS_ALIGN
+                                           + (probes - 1) * PROBE_STEP,
+                                           dtype=torch.uint8, device=self.device)
             else:
                 want = (self.device.index if self.device.index is not None
                         else torch.cuda.current_device())
@@ -210,8 +218,12 @@ class Solver:
             if lead + self.workspace_bytes > self._ws_buf.numel():
                 raise ValueError(f"buffer holds {self._ws_buf.numel()} bytes; this solver needs "
                                  f"{self.workspace_bytes} from a 16 MiB boundary")
+            self.placement_ms = None
+            if probes > 1:
+                lead = self._probe(L, a5, F, [lead + k * PROBE_STEP for k in range(probes)])
             self.ws = self._ws_buf[lead:lead + self.workspace_bytes]
-            self.footprint_bytes = self.workspace_bytes + WS_ALIGN
+            self.footprint_bytes = (self._ws_buf.numel() if buffer is None
+                                    else self.workspace_bytes + WS_ALIGN)
             h = ctypes.c_void_p()
             check(L.pcga_solver_create_ex(ctypes.byref(a5), F.handle, self.precision,
                                           self.slice_width, ctypes.c_void_p(self.ws.data_ptr()),
@@ -341,6 +353,33 @@ class Solver:
             self._h, p1, p2, float(a), float(c), _dev_ptr(out, torch.float64, self.n)),
             "pcga_ts_guess"))
         return out
+
+    def _probe(self, L, a5, F, offsets):
+        """Build the solver at each offset of the buffer in turn, time one
+        whole iteration there, and return the fastest offset."""
+        import torch
+        self.n = self.A.nx * self.A.ny
+        probe_b = torch.ones(self.n, dtype=torch.float64, device=self.device)
+        times = []
+        for off in offsets:
+            h = ctypes.c_void_p()
+            check(L.pcga_solver_create_ex(ctypes.byref(a5), F.handle, self.precision,
+                                          self.slice_width,
+                                          ctypes.c_void_p(self._ws_buf.data_ptr() + off),
+                                          self.workspace_bytes,
+                                          ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+                  "pcga_solver_create_ex")
+            self._h = h
+            try:
+                self.profile_iteration(probe_b, reps=3, mode=1)
+                times.append(min(self.profile_iteration(probe_b, reps=20, mode=1)[3]
+                                 for _ in range(2)))
+            finally:
+                torch.cuda.synchronize()
+                L.pcga_solver_destroy(h)
+                self._h = None
+        self.placement_ms = times
+        return offsets[min(range(len(times)), key=times.__getitem__)]
 
     def profile_iteration(self, b, reps=50, mode=1):
         """Average ms of the three iteration kernels and of a whole iteration

@@ -614,3 +614,21 @@ def test_solver_on_shared_buffer(pkg):
     small = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
     with pytest.raises(ValueError):
         pkg.Solver(A, G, "fp64", buffer=small)
+
+
+def test_solver_placement_probe(pkg):
+    """A solver that probes three workspace bases keeps one of them and
+    solves bitwise like a solver placed without probing."""
+    p, _ = case("orca182x149")
+    A = pkg.Stencil5.from_problem(p)
+    G = pkg.ainv_setup(A, 0.1)
+    b = dev(p.b)
+    ref = pkg.Solver(A, G, "fp64").solve(b, tol=1e-10)
+    S = pkg.Solver(A, G, "fp64", probe_placements=3)
+    assert S.placement_ms is not None and len(S.placement_ms) == 3
+    assert all(t > 0 for t in S.placement_ms)
+    lead = (-S._ws_buf.data_ptr()) % (16 << 20)          # the aligned first base
+    assert S.ws.data_ptr() - S._ws_buf.data_ptr() - lead in (0, 4 << 20, 8 << 20)
+    r = S.solve(b, tol=1e-10)
+    assert r.iters == ref.iters and torch.equal(r.x, ref.x)
+    S.close()
