@@ -286,10 +286,11 @@ def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=
                                                seed=CONFIG_SERVE_SEED + 1 + i)
         res = srv.run(reqs, make_rhs=stepper, on_done=stepper.done)
         st = serve.latency_stats(res, srv.klass)
+        f99 = lambda v: "n/a" if v is None else f"{v:.0f}"
         log(f"load {L:.2f}: {st['requests']} requests, p50 {st['p50_ms']:.1f} ms, "
-            f"p99 {st['p99_ms']:.1f} ms, {st['solves_per_s']:.2f} solves/s, "
+            f"p99 {f99(st['p99_ms'])} ms, {st['solves_per_s']:.2f} solves/s, "
             f"worst true relres {st['worst_true_relres']:.2e}; per size class "
-            + ", ".join(f"{k}: {v['requests']} req p50 {v['p50_ms']:.0f} p99 {v['p99_ms']:.0f} ms"
+            + ", ".join(f"{k}: {v['requests']} req p50 {v['p50_ms']:.0f} p99 {f99(v['p99_ms'])} ms"
                         for k, v in st["per_class"].items()))
         out["loads"][str(L)] = st
     return out

@@ -133,6 +133,16 @@ int pcga_ainv_import(int64_t n, const int64_t *colptr, const int32_t *rowidx,
 
 int pcga_ainv_free(pcga_ainv_t *F);
 
+/* pcga_layout_info: host-only inspection of the sliced-ELL layouts a solver
+ * would build from F at target width slice_width (0: the FP64 default, else
+ * 1..64); no device is needed.  out[12] receives, for Z^T (out[0..5]) and Z
+ * (out[6..11]): slices, slices stored with an offset table, the widest such
+ * slice in entry steps (at most 64: a table sits in one wavefront register),
+ * the widest slice, stored entries (with padding), and index bytes (2 or 4).
+ * Errors: EINVAL (NULL, bad width, or a layout that breaks its invariants),
+ * ENOMEM. */
+int pcga_layout_info(const pcga_ainv_t *F, int32_t slice_width, int64_t *out);
+
 /* ---- device solver ------------------------------------------------------
  * pcga_workspace_bytes: device bytes needed for (A, F, precision).
  * pcga_solver_create: validate, lay A and (Z, D) out in the workspace

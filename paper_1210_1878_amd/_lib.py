@@ -48,6 +48,7 @@ _SIGS = {
     "pcga_ainv_export": ([_p, _p, _p, _p, _p], ctypes.c_int),
     "pcga_ainv_import": ([_i64, _p, _p, _p, _p, _pp], ctypes.c_int),
     "pcga_ainv_free": ([_p], ctypes.c_int),
+    "pcga_layout_info": ([_p, _i32, _p], ctypes.c_int),
     "pcga_workspace_bytes": ([ctypes.POINTER(A5), _p, ctypes.c_int, ctypes.POINTER(_sz)],
                              ctypes.c_int),
     "pcga_solver_create": ([ctypes.POINTER(A5), _p, ctypes.c_int, _p, _sz, _p, _pp],

@@ -79,6 +79,18 @@ class AInv:
                                  val.ctypes.data, D.ctypes.data), "pcga_ainv_export")
         return colptr, rowidx[: self.nnz_off], val[: self.nnz_off], D
 
+    def layout_info(self, slice_width: int = 0) -> dict:
+        """Shape of the sliced-ELL layouts a solver would build at this target
+        width (host only): per matrix ("zt", "z") the slice count, table
+        slices, widest table slice, widest slice, stored entries and index
+        bytes."""
+        L = _lib.load()
+        out = np.zeros(12, dtype=np.int64)
+        check(L.pcga_layout_info(self._h, int(slice_width), out.ctypes.data), "pcga_layout_info")
+        keys = ("slices", "table_slices", "table_width_max", "width_max", "entries", "index_bytes")
+        return {m: {k: int(out[6 * i + j]) for j, k in enumerate(keys)}
+                for i, m in enumerate(("zt", "z"))}
+
     @classmethod
     def from_csc(cls, n, colptr, rowidx, val, D) -> "AInv":
         L = _lib.load()

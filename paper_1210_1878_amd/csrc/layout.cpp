@@ -60,7 +60,10 @@ void sell_build(int64_t m, const int64_t *rowptr, const int32_t *col, const doub
                 for (int64_t a = rowptr[r]; a < rowptr[r + 1]; a++) uni.push_back(col[a] - r);
             std::sort(uni.begin(), uni.end());
             uni.erase(std::unique(uni.begin(), uni.end()), uni.end());
-            if ((int64_t)uni.size() <= maxlen + std::max<int64_t>(2, maxlen / 4)) {
+            // the kernels hold a slice's table in one register of the
+            // wavefront (lane c holds table[c]), so a table has at most 64 steps
+            if ((int64_t)uni.size() <= kTableMax &&
+                (int64_t)uni.size() <= maxlen + std::max<int64_t>(2, maxlen / 4)) {
                 uniform = true;
                 width = (int64_t)uni.size();
             }
@@ -102,6 +105,24 @@ void sell_build(int64_t m, const int64_t *rowptr, const int32_t *col, const doub
         L.off.push_back(base + width * 64);
         R += nr;
     }
+}
+
+bool sell_check(const SellLayout &L) {
+    const int64_t ns = L.nslices();
+    if ((int64_t)L.meta.size() != ns || (int64_t)L.toff.size() != ns ||
+        (int64_t)L.off.size() != ns + 1)
+        return false;
+    for (int64_t s = 0; s < ns; s++) {
+        const int lg = L.meta[s] & 255;
+        const int64_t width = L.meta[s] >> 8;
+        if (lg < 0 || lg > 6 || width < 0) return false;
+        if (L.off[s + 1] - L.off[s] != width * 64) return false;
+        if (L.toff[s] >= 0) {
+            if (lg != 0 || width > kTableMax) return false;
+            if ((int64_t)L.toff[s] + width > (int64_t)L.tab.size()) return false;
+        }
+    }
+    return true;
 }
 
 bool sell_narrow(SellLayout &L, bool lower) {

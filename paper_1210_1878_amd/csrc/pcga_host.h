@@ -62,9 +62,18 @@ struct SellLayout {
     int64_t entries() const { return off.empty() ? 0 : off.back(); }
 };
 
+// Most entry steps of a table slice: the kernels keep a slice's offset table
+// in one wavefront register, lane c holding table[c].
+constexpr int64_t kTableMax = 64;
+
 // rows given as CSR (rowptr[m+1], col, val with columns ascending per row).
 void sell_build(int64_t m, const int64_t *rowptr, const int32_t *col, const double *val,
                 int target_width, SellLayout &L);
+
+// Structural invariants the kernels rely on: per-slice entry counts match
+// the widths, and every table slice is one lane per row with at most
+// kTableMax steps and a table inside `tab`.
+bool sell_check(const SellLayout &L);
 
 // Switch L to the narrow form when it fits (lower: every column <= its row,
 // else every column >= its row).  Returns whether it did.

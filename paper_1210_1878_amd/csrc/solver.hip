@@ -112,6 +112,8 @@ int build_layouts(const AinvFactor &F, int target_width, HostLayouts &H) {
     } catch (const std::bad_alloc &) {
         return fail(PCGA_ENOMEM, "host allocation failed while building sliced-ELL layouts");
     }
+    if (!sell_check(H.zt) || !sell_check(H.z))
+        return fail(PCGA_EINVAL, "internal: sliced-ELL layout violates its invariants");
     return PCGA_OK;
 }
 
@@ -420,6 +422,36 @@ int pcga_ainv_import(int64_t n, const int64_t *colptr, const int32_t *rowidx,
 
 int pcga_ainv_free(pcga_ainv_t *F) {
     delete F;
+    return PCGA_OK;
+}
+
+int pcga_layout_info(const pcga_ainv_t *F, int32_t slice_width, int64_t *out) {
+    if (!F || !out) return fail(PCGA_EINVAL, "NULL argument");
+    if (slice_width == 0) slice_width = kTargetWidth;
+    if (slice_width < 1 || slice_width > kMaxSliceWidth)
+        return fail(PCGA_EINVAL, "slice_width must be 0 or 1.." + std::to_string(kMaxSliceWidth));
+    HostLayouts H;
+    const int st = build_layouts(F->F, slice_width, H);
+    if (st) return st;
+    const SellLayout *Ls[2] = {&H.zt, &H.z};
+    for (int m = 0; m < 2; m++) {
+        const SellLayout &L = *Ls[m];
+        int64_t ntab = 0, wtab = 0, wmax = 0;
+        for (int64_t s = 0; s < L.nslices(); s++) {
+            const int64_t w = L.meta[s] >> 8;
+            wmax = std::max(wmax, w);
+            if (L.toff[s] >= 0) {
+                ntab++;
+                wtab = std::max(wtab, w);
+            }
+        }
+        out[6 * m + 0] = L.nslices();
+        out[6 * m + 1] = ntab;
+        out[6 * m + 2] = wtab;
+        out[6 * m + 3] = wmax;
+        out[6 * m + 4] = L.entries();
+        out[6 * m + 5] = L.narrow ? 2 : 4;
+    }
     return PCGA_OK;
 }
 

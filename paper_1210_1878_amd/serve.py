@@ -26,6 +26,9 @@ import numpy as np
 from .api import Batch, Solver, Stencil5, ainv_setup
 
 
+REJECTED = -5   # the request's vectors alone exceed the memory budget (PCGA_ENOMEM)
+
+
 @dataclasses.dataclass
 class Request:
     rid: int
@@ -81,6 +84,17 @@ class Server:
     def fits(self, grid):
         return self.budget is None or self.in_flight_bytes + self.item_bytes[grid] <= self.budget
 
+    def can_ever_fit(self, grid):
+        """Whether a request of this grid fits the budget with nothing else in
+        flight; one that cannot is rejected at arrival instead of waiting
+        forever."""
+        return self.budget is None or self.item_bytes[grid] <= self.budget
+
+    def _reject(self, req, now):
+        req.admitted = now
+        req.finished = now
+        req.status = REJECTED
+
     def admit(self, req, now):
         k = self.klass[req.grid]
         slot = self.batches[k].add(self.solvers[req.grid], req.b.unsqueeze(0),
@@ -126,7 +140,9 @@ class Server:
         """Serve `requests` (sorted by arrival).  make_rhs(req) fills req.b and
         req.x0 when the request is admitted (it may use the grid's previous
         solution); on_done(req) is called when a solution is back.
-        Returns the finished requests."""
+        Returns the finished requests; a request whose grid's vectors alone
+        exceed the memory budget is returned at once with status REJECTED
+        and no solution (on_done is not called for it)."""
         t0 = clock()
         pending = collections.deque(requests)
         queue = []
@@ -136,7 +152,12 @@ class Server:
         while pending or queue or slots:
             now = clock() - t0
             while pending and pending[0].arrival <= now:
-                queue.append(pending.popleft())
+                req = pending.popleft()
+                if self.can_ever_fit(req.grid):
+                    queue.append(req)
+                else:
+                    self._reject(req, clock() - t0)
+                    done.append(req)
             # admission: FIFO among requests whose grid is idle and that fit;
             # a class batch takes new items only between its launches
             rest = []
@@ -184,6 +205,9 @@ class Server:
         done = []
         rid = [0]
         self._flying = set()
+        too_big = [g for g in range(len(self.solvers)) if not self.can_ever_fit(g)]
+        if too_big:
+            raise ValueError(f"grids {too_big}: one request exceeds the memory budget")
         waiting = list(range(len(self.solvers)))   # grids whose next step is due
 
         def submit(g):
@@ -334,22 +358,46 @@ class CoupledTimeStepper:
         self.eta[g] = [e[1], self.solvers[g].ts_eta(e[0], x, self.dt)]
 
 
-def latency_stats(done, klass=None):
+P99_MIN_SAMPLES = 100   # fewer samples than this: no p99 is quoted (None)
+
+
+def _pct(lat_s, q):
+    return float(np.percentile(lat_s, q) * 1e3)
+
+
+def latency_stats(done, klass=None, per_grid=False):
     """Latency percentiles (arrival to solution) and throughput; with
-    klass[grid] also per size class."""
+    klass[grid] also per size class, with per_grid also per grid.  Every
+    group reports its sample count; its p99 is None below P99_MIN_SAMPLES
+    samples.  Rejected requests are counted, not timed."""
+    rejected = sum(1 for r in done if r.status == REJECTED)
+    done = [r for r in done if r.status != REJECTED]
+    if not done:
+        return {"requests": 0, "rejected": rejected}
     lat = np.array([r.latency for r in done])
     span = max(r.finished for r in done) - min(r.arrival for r in done)
-    out = {"requests": len(done), "p50_ms": float(np.percentile(lat, 50) * 1e3),
-           "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+    out = {"requests": len(done), "rejected": rejected, "p50_ms": _pct(lat, 50),
+           "p99_ms": _pct(lat, 99) if len(lat) >= P99_MIN_SAMPLES else None,
+           "mean_ms": float(lat.mean() * 1e3),
            "solves_per_s": len(done) / span if span > 0 else float("nan"),
            "worst_true_relres": float(max(r.true_relres for r in done)),
            "all_ok": all(r.status == 0 for r in done)}
+    def group(sel):
+        lk = np.array([r.latency for r in done if sel(r)])
+        if not len(lk):
+            return None
+        return {"requests": int(len(lk)), "p50_ms": _pct(lk, 50),
+                "p99_ms": _pct(lk, 99) if len(lk) >= P99_MIN_SAMPLES else None,
+                "max_ms": float(lk.max() * 1e3)}
+
     if klass is not None:
         per = {}
         for k in sorted(set(klass)):
-            lk = np.array([r.latency for r in done if klass[r.grid] == k])
-            if len(lk):
-                per[str(k)] = {"requests": int(len(lk)), "p50_ms": float(np.percentile(lk, 50) * 1e3),
-                               "p99_ms": float(np.percentile(lk, 99) * 1e3)}
+            g = group(lambda r: klass[r.grid] == k)
+            if g:
+                per[str(k)] = g
         out["per_class"] = per
+    if per_grid:
+        out["per_grid"] = {str(gi): group(lambda r: r.grid == gi)
+                           for gi in sorted({r.grid for r in done})}
     return out

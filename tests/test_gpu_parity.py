@@ -178,6 +178,42 @@ def test_pcg_other_slice_widths(pkg, ora, width):
     assert g.status == 0 and abs(g.iters - K) <= 2
 
 
+@pytest.mark.parametrize("width", [48, 64])
+def test_wide_slices_tau001(pkg, ora, width):
+    """Target widths up to 64 on the 182x149 factor at drop tolerance 0.01,
+    whose one-lane-per-row slices have offset unions wider than one wavefront
+    register: such slices must use per-lane indices.  The apply element by
+    element and the iteration-matched solve against the oracle."""
+    p = orca.orca_problem(182, 149, orca.CONFIG_SEED_BASE + 1)
+    A = pkg.Stencil5.from_problem(p)
+    G = pkg.ainv_setup(A, 0.01)
+    F = ora.ainv_setup(p, 0.01)
+    info = G.layout_info(width)
+    say("wide slices, tau 0.01, width", width, info)
+    assert info["zt"]["table_width_max"] <= 64 and info["z"]["table_width_max"] <= 64
+    r = np.random.default_rng(15).standard_normal(p.n)
+    Fa = ora.AInv(F.n, F.colptr, F.rowidx, np.abs(F.val), F.D)
+    t_ref = ora.zt_apply(F, r)
+    s_ref = ora.z_apply(F, t_ref)
+    t_mag = ora.zt_apply(Fa, np.abs(r))
+    s_mag = ora.z_apply(Fa, t_mag)
+    wmax = int(np.diff(F.colptr).max()) + 2
+    for prec in ("fp64", "mixed"):
+        S = pkg.Solver(A, G, prec, slice_width=width)
+        t, s = S.apply_prec(dev(r))
+        u = 4 * EPS if prec == "fp64" else 4 * np.finfo(np.float32).eps
+        assert np.all(np.abs(t.cpu().numpy() - t_ref) <= wmax * u * t_mag + 1e-300)
+        assert np.all(np.abs(s.cpu().numpy() - s_ref) <= 2 * wmax * u * s_mag + 1e-300)
+        if prec == "fp64":
+            K = ora.pcg(p, F, tol=1e-10).iters
+            g = S.solve(dev(p.b), tol=0.0, maxit=K)
+            o = ora.pcg(p, F, tol=0.0, maxit=K)
+            assert np.linalg.norm(g.x.cpu().numpy() - o.x) <= 1e-9 * np.linalg.norm(o.x)
+            nat = S.solve(dev(p.b), tol=1e-10)
+            assert nat.status == 0 and abs(nat.iters - K) <= 2
+        S.close()
+
+
 def test_autotuner_small(pkg):
     from paper_1210_1878_amd import autotune
     p, tau = case("orca182x149")
