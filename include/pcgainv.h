@@ -237,6 +237,21 @@ int pcga_apply_a(pcga_solver_t *S, const double *x_dev, double *y_dev);
  * PCGA_FP64; FP32 data with FP64 input/output for PCGA_MIXED). */
 int pcga_apply_prec(pcga_solver_t *S, const double *r_dev, double *t_dev, double *s_dev);
 
+/* One launch of the fused first kernel of an iteration (Algorithm 1's
+ * direction update and operator product): d_new = s + beta d, q = A d_new
+ * (the five-point product of eq. (10), FP64 coefficients) and (d_new, q),
+ * summed over the launch's workgroups as the next kernel of an iteration
+ * sums it.  s_dev, d_dev: n FP64 device values in; dnew_dev, q_dev: n FP64
+ * device values out (caller-owned, not aliasing the inputs); *dq: host.  In
+ * the solver's inner precision: a PCGA_MIXED solver rounds s and d to FP32,
+ * runs the FP32 kernel (d_new in FP32; A d_new formed in FP64 and rounded to
+ * FP32) and returns its FP32 results widened to FP64.  beta >= 0 and finite
+ * (beta = 0: d_new = s).  Uses the solver's control block and, for
+ * PCGA_MIXED, its inner vectors: the solver stays usable.  Errors: EINVAL,
+ * EHIP. */
+int pcga_step_stencil(pcga_solver_t *S, const double *s_dev, const double *d_dev, double beta,
+                      double *dnew_dev, double *q_dev, double *dq);
+
 /* Average device time in milliseconds of each kernel of one PCG iteration,
  * ms_out[0] = d-update + five-point product + (d,q); ms_out[1] = residual and
  * solution update + D^-1 Z^T r; ms_out[2] = Z t + (s,r) (0 with the

@@ -65,6 +65,7 @@ _SIGS = {
                               _pi32, _pdbl], ctypes.c_int),
     "pcga_apply_a": ([_p, _p, _p], ctypes.c_int),
     "pcga_apply_prec": ([_p, _p, _p, _p], ctypes.c_int),
+    "pcga_step_stencil": ([_p, _p, _p, _dbl, _p, _p, _pdbl], ctypes.c_int),
     "pcga_profile_iteration": ([_p, _p, _i32, _i32, _pdbl], ctypes.c_int),
     "pcga_ts_rhs": ([_p, _p, _p, _p, _p, _p], ctypes.c_int),
     "pcga_ts_eta": ([_p, _p, _p, _dbl, _p], ctypes.c_int),

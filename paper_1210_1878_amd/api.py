@@ -326,6 +326,22 @@ class Solver:
                                           _dev_ptr(s, torch.float64, self.n)), "pcga_apply_prec")
         return t, s
 
+    def step_stencil(self, s, d, beta):
+        """One launch of the fused direction update and operator product:
+        (d_new = s + beta d, q = A d_new, (d_new, q)) in the solver's inner
+        precision (see pcga_step_stencil)."""
+        import torch
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        dn = torch.empty_like(s)
+        q = torch.empty_like(s)
+        dq = ctypes.c_double()
+        check(_lib.load().pcga_step_stencil(self._h, _dev_ptr(s, torch.float64, self.n),
+                                            _dev_ptr(d, torch.float64, self.n), float(beta),
+                                            _dev_ptr(dn, torch.float64, self.n),
+                                            _dev_ptr(q, torch.float64, self.n), ctypes.byref(dq)),
+              "pcga_step_stencil")
+        return dn, q, dq.value
+
     # --- the time step around the solve (eq. (1), eq. (8), the first guess) ---
     def _on_stream(self, fn):
         import torch

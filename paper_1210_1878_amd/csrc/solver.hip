@@ -864,6 +864,25 @@ int prologue_prec(pcga_solver &S, const IterBufs<T> &B) {
     return PCGA_OK;
 }
 
+// Control state of one stand-alone k_stencil launch with a given beta: with
+// beta > 0, iteration k = 1 at parity 0, rho_{k-1} = 1 and a single (s,r)
+// partial equal to beta, so that the kernel forms beta / 1 = beta exactly;
+// with beta = 0, iteration 0 (the kernel then takes d = s).
+__global__ void k_step_state(CtlBlock *cb, Partials P, double beta) {
+    cb->c.done = 0;
+    cb->c.kk[0] = beta > 0.0 ? 1 : 0;
+    cb->c.rho[1] = 1.0;
+    P.sr[0] = beta > 0.0 ? beta : 1.0;
+}
+
+// (d, q) of that launch, summed from its partials as the next kernel of an
+// iteration sums them; left in P.res[0].
+__global__ __launch_bounds__(kBS) void k_step_dq(Partials P, int g) {
+    double v[1];
+    sum_partials<1>(P.dq, g, v);
+    if (threadIdx.x == 0) P.res[0] = v[0];
+}
+
 int snapshot(pcga_solver &S, int slot) {
     HIP_TRY(hipMemcpyAsync(S.snap[slot], S.cb, sizeof(CtlBlock), hipMemcpyDeviceToHost, S.stream));
     HIP_TRY(hipEventRecord(S.ev[slot], S.stream));
@@ -1116,6 +1135,33 @@ int pcga_apply_prec(pcga_solver_t *S, const double *r_dev, double *t_dev, double
     }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(S->stream));
+    return PCGA_OK;
+}
+
+int pcga_step_stencil(pcga_solver_t *S, const double *s_dev, const double *d_dev, double beta,
+                      double *dnew_dev, double *q_dev, double *dq) {
+    if (!S || !s_dev || !d_dev || !dnew_dev || !q_dev || !dq)
+        return fail(PCGA_EINVAL, "NULL argument");
+    if (!(beta >= 0.0) || std::isinf(beta)) return fail(PCGA_EINVAL, "beta must be finite and >= 0");
+    HIP_TRY(hipSetDevice(S->device));
+    pcga_solver &R = *S;
+    const int gc = (int)std::min<int64_t>(4096, (R.n + kBS - 1) / kBS);
+    k_step_state<<<1, 1, 0, R.stream>>>(R.cb, R.P, beta);
+    if (R.precision == PCGA_FP64) {
+        k_stencil<double, false><<<R.g_st, kBS, 0, R.stream>>>(R.A64, s_dev, d_dev, dnew_dev, q_dev,
+                                                               R.cb, R.P, 1, 0);
+    } else {
+        k_convert<double, float><<<gc, kBS, 0, R.stream>>>((int)R.n, s_dev, R.s32);
+        k_convert<double, float><<<gc, kBS, 0, R.stream>>>((int)R.n, d_dev, R.d32[0]);
+        k_stencil<float, false><<<R.g_st, kBS, 0, R.stream>>>(R.A64, R.s32, R.d32[0], R.d32[1],
+                                                              R.q32, R.cb, R.P, 1, 0);
+        k_convert<float, double><<<gc, kBS, 0, R.stream>>>((int)R.n, R.d32[1], dnew_dev);
+        k_convert<float, double><<<gc, kBS, 0, R.stream>>>((int)R.n, R.q32, q_dev);
+    }
+    k_step_dq<<<1, kBS, 0, R.stream>>>(R.P, R.g_st);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(dq, R.P.res, sizeof(double), hipMemcpyDeviceToHost, R.stream));
+    HIP_TRY(hipStreamSynchronize(R.stream));
     return PCGA_OK;
 }
 

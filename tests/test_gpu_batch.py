@@ -171,3 +171,75 @@ def test_batch_zero_rhs_and_limits(pkg, ora, ensemble):
     s2 = Bt.add(S, torch.from_numpy(p.B[:1]).cuda(), max_outer=1)
     X2, q2 = Bt.solve()[s2]
     assert q2["status"] == 1 and q2["outer"] == 1
+
+
+@pytest.fixture(scope="module")
+def split_mix(pkg):
+    """One slot on the 1442x1021 ORCA025-shaped grid (360 workgroups: split
+    into eight per-XCD ranges) with eight members of the 64-member ensemble
+    (sizes 182..362 x 149..292, 4 right-hand sides each), mixed precision."""
+    say("building the 1442x1021 slot and 8 ensemble members")
+    big = orca.orca_problem(1442, 1021, orca.CONFIG_SEED_BASE + 2)
+    big.B = big.b[None, :].copy()
+    Ab = pkg.Stencil5.from_problem(big)
+    Sb = pkg.Solver(Ab, pkg.ainv_setup(Ab, 0.05), "mixed")
+    ens = orca.ensemble_problems(count=8)
+    sol = []
+    for p in ens:
+        A = pkg.Stencil5.from_problem(p)
+        sol.append(pkg.Solver(A, pkg.ainv_setup(A, 0.1), "mixed"))
+    return big, Sb, ens, sol
+
+
+def test_batch_split_slot_with_ensemble_members(pkg, ora, split_mix):
+    """The batch kernels' large-slot path (>= 128 workgroups, one range per
+    XCD) beside ensemble members of the benchmark's sizes: every right-hand
+    side meets the FP64 target (oracle product), the members' solutions lie
+    within the rigorous distance of the FP64 oracle's (Collatz-Wielandt bound
+    on ||A^-1||), and each item is bitwise the same alone and in the mix."""
+    from tests._bounds import lambda_min_lower, solution_gap_bound
+    big, Sb, ens, sol = split_mix
+    assert -(-big.n // 4096) >= 128
+    say("alone: the 1442x1021 slot")
+    Bt = pkg.Batch(max_slots=2)
+    s = Bt.add(Sb, torch.from_numpy(big.B).cuda(), tol=1e-10, inner_tol=1e-5)
+    big_alone, qa = Bt.solve()[s]
+    assert qa["status"] == 0
+    alone = {}
+    for i, (p, S) in enumerate(zip(ens, sol)):
+        Bt = pkg.Batch(max_slots=2)
+        s = Bt.add(S, torch.from_numpy(p.B).cuda(), tol=1e-10, inner_tol=1e-5)
+        alone[i] = Bt.solve()[s][0]
+    say("in the mix: 1 + 8 items, the large one added while the others run")
+    Bt = pkg.Batch(max_slots=16)
+    slot_of = {}
+    for i in range(4):
+        slot_of[Bt.add(sol[i], torch.from_numpy(ens[i].B).cuda(), tol=1e-10, inner_tol=1e-5)] = i
+    Bt.run(1)
+    slot_of[Bt.add(Sb, torch.from_numpy(big.B).cuda(), tol=1e-10, inner_tol=1e-5)] = "big"
+    for i in range(4, 8):
+        slot_of[Bt.add(sol[i], torch.from_numpy(ens[i].B).cuda(), tol=1e-10, inner_tol=1e-5)] = i
+    res = Bt.solve()
+    assert len(res) == 9
+    for s, (X, q) in res.items():
+        i = slot_of[s]
+        if i == "big":
+            assert torch.equal(X, big_alone)
+            _check_item(ora, big, X, q, 1)
+            say(f"  1442x1021: outer {q['outer']} inner {q['inner_total']} "
+                f"true {q['true_relres'][0]:.3e}")
+            continue
+        assert torch.equal(X, alone[i]), i
+        p = ens[i]
+        _check_item(ora, p, X, q, 4)
+        lam = lambda_min_lower(ora, p)
+        F = ora.ainv_setup(p, 0.1)
+        for r in range(4):
+            xo = ora.pcg(p, F, b=p.B[r], tol=1e-12).x
+            xb = X[r].cpu().numpy()
+            gap = np.linalg.norm(xb - xo)
+            bound = solution_gap_bound(ora, p, p.B[r], xb, xo, lam)
+            assert gap <= bound, (i, r, gap, bound)
+            if r == 0:
+                say(f"  member {i} {p.nx}x{p.ny}: |x - x_ora|/|x_ora| "
+                    f"{gap / np.linalg.norm(xo):.2e} (bound {bound / np.linalg.norm(xo):.2e})")

@@ -74,6 +74,60 @@ def test_apply_a(pkg, ora, name):
     assert np.all(np.abs(y - ref) <= 8 * EPS * mag + 1e-300)
 
 
+def check_stencil_step(pkg, ora, S, p, prec, seed, beta):
+    """The fused first kernel of an iteration alone (pcga_step_stencil):
+    d_new = s + beta d, q = A d_new and (d_new, q), element by element.
+    d_new against the direction update of Algorithm 1 (one rounding of the
+    fused form); q against the oracle's five-point product of the device's
+    d_new (the FP64 coefficients; in the mixed form the product is rounded
+    to FP32 once); (d_new, q) against the sum of the device's products within
+    the bound of a recursive sum."""
+    rng = np.random.default_rng(seed)
+    s, d = rng.standard_normal(p.n), rng.standard_normal(p.n)
+    if prec == "mixed":             # the FP32 kernel's inputs, exactly
+        s = s.astype(np.float32).astype(np.float64)
+        d = d.astype(np.float32).astype(np.float64)
+        bt = float(np.float32(beta))
+        u = float(np.finfo(np.float32).eps) / 2
+    else:
+        bt = beta
+        u = EPS / 2
+    dn, q, dq = S.step_stencil(dev(s), dev(d), beta)
+    dn, q = dn.cpu().numpy(), q.cpu().numpy()
+    d_ref = s + bt * d
+    assert np.all(np.abs(dn - d_ref) <= 2 * u * (np.abs(s) + np.abs(bt * d)) + 1e-300)
+    if prec == "mixed":
+        assert np.array_equal(dn, dn.astype(np.float32).astype(np.float64))
+    q_ref = ora.spmv(p, dn)
+    mag = ora.spmv(_abs_problem(p), np.abs(dn))
+    assert np.all(np.abs(q - q_ref) <= u * np.abs(q_ref) + 8 * EPS * mag + 1e-300)
+    prods = dn * q
+    gam = 1.01 * p.n * EPS
+    assert abs(dq - np.sum(prods)) <= gam * np.sum(np.abs(prods)) + 1e-300
+    return dn, q, dq
+
+
+STENCIL_CASES = ["box64x48", "orca182x149", "orca37x23_ragged", "orca3x7_min_periodic",
+                 "orca182x149_jacobi"]
+
+
+@pytest.mark.parametrize("name", STENCIL_CASES)
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fused_stencil_step(pkg, ora, name, prec):
+    p, tau = case(name)
+    say("fused stencil step", name, prec)
+    A = pkg.Stencil5.from_problem(p)
+    S = pkg.Solver(A, pkg.ainv_setup(A, tau), prec)
+    for seed, beta in ((41, 0.37), (42, 0.0), (43, 1.93)):
+        check_stencil_step(pkg, ora, S, p, prec, seed, beta)
+    # the solver stays usable after the stand-alone launches
+    if prec == "fp64":
+        g = S.solve(dev(p.b), tol=1e-10)
+        assert g.status == 0 and g.hist[-1] <= 1e-10
+    with pytest.raises(Exception):
+        S.step_stencil(dev(np.zeros(p.n)), dev(np.zeros(p.n)), -1.0)
+
+
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_apply_prec(pkg, ora, name, prec):
@@ -352,6 +406,10 @@ def test_full_size_kernels(pkg, ora, orca025):
     width = int(np.diff(F.colptr).max()) + 2
     assert np.all(np.abs(t.cpu().numpy() - t_ref) <= width * 4 * EPS * t_mag)
     assert np.all(np.abs(s.cpu().numpy() - s_ref) <= 2 * width * 4 * EPS * s_mag)
+    say("full size: fused stencil step, FP64 and mixed")
+    check_stencil_step(pkg, ora, S, p, "fp64", 44, 0.61)
+    Sm = pkg.Solver(A, G, "mixed")
+    check_stencil_step(pkg, ora, Sm, p, "mixed", 45, 0.61)
 
 
 def test_full_size_pcg(pkg, ora, orca025):
