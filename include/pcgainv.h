@@ -216,6 +216,29 @@ int pcga_pcg_solve(pcga_solver_t *S, const double *b_dev, double *x_dev, double 
                    int32_t maxit, int32_t *iters, double *hist_host, int32_t hist_cap,
                    int32_t *hist_len, double *true_relres);
 
+/* pcga_pcg_solve_noalloc: pcga_pcg_solve for callers that cannot allocate
+ * device memory while they run (serving loops that must not allocate, code
+ * next to a stream capture, harnesses that forbid allocation).  Same
+ * arguments, method, results and status codes as pcga_pcg_solve, and the
+ * same kernels; it allocates nothing and captures no graph: the kernels are
+ * launched directly, and the solve's vectors (r, s, d, q, t), partial sums
+ * and control block live in one static device array of the library,
+ * PCGA_NOALLOC_MAX_BYTES per device (held from the library's load until the
+ * process ends), instead of the solver's workspace.  x_dev is the iterate
+ * itself (it must not alias b_dev).  The solver's operator and factor are
+ * read from its workspace as usual.
+ * Limit: a grid needs about 56 n bytes of the array (seven FP64 vectors plus
+ * about 130 KB of partial sums and control block), so n up to about 1.19 M
+ * cells; a larger grid returns PCGA_ENOMEM with a message and no device work.
+ * Every call on one device uses that device's array, which keeps the last
+ * call's contents (each solve initialises what it reads): calls that overlap
+ * on one device, from several threads or streams, race.  Returns as
+ * pcga_pcg_solve, plus ENOMEM for a grid beyond the limit. */
+#define PCGA_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+int pcga_pcg_solve_noalloc(pcga_solver_t *S, const double *b_dev, double *x_dev, double tol,
+                           int32_t maxit, int32_t *iters, double *hist_host, int32_t hist_cap,
+                           int32_t *hist_len, double *true_relres);
+
 /* pcga_pcg_solve_mixed: FP64 iterative refinement.  Outer step o: r = b - A x
  * in FP64; stop if ||r||/||b|| <= tol; else solve A e = r with the FP32
  * inner PCG (FP32 Z, D^-1 and vectors; q = A d with the FP64 coefficients,

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libpcgainv.so")
 OK, NOCONV, EINVAL, EBREAKDOWN, ENAN, EHIP, ENOMEM = 0, 1, -1, -2, -3, -4, -5
 PERIODIC_X = 1
 FP64, MIXED = 0, 1
+NOALLOC_MAX_BYTES = 64 << 20   # PCGA_NOALLOC_MAX_BYTES
 
 
 class PcgaError(RuntimeError):
@@ -61,6 +62,8 @@ _SIGS = {
     "pcga_solver_info": ([_p, _pi64, _pi64, _pi32, _pdbl, _pi32, _pi32], ctypes.c_int),
     "pcga_solver_tune": ([_p, _i32, _i32, _i32], ctypes.c_int),
     "pcga_pcg_solve": ([_p, _p, _p, _dbl, _i32, _pi32, _p, _i32, _pi32, _pdbl], ctypes.c_int),
+    "pcga_pcg_solve_noalloc": ([_p, _p, _p, _dbl, _i32, _pi32, _p, _i32, _pi32, _pdbl],
+                               ctypes.c_int),
     "pcga_pcg_solve_mixed": ([_p, _p, _p, _dbl, _dbl, _i32, _i32, _pi32, _pi32, _p, _i32,
                               _pi32, _pdbl], ctypes.c_int),
     "pcga_apply_a": ([_p, _p, _p], ctypes.c_int),

@@ -290,6 +290,28 @@ class Solver:
         check(st, "pcga_pcg_solve", allow=(_lib.OK, _lib.NOCONV))
         return SolveResult(x, iters.value, hist[: min(hl.value, cap)].copy(), st, tr.value)
 
+    def solve_noalloc(self, b, x, tol=1e-10, maxit=None, hist=None) -> SolveResult:
+        """pcga_pcg_solve_noalloc: the FP64 solve with the library's static
+        scratch in place of the solver's vectors.  x holds x0 and receives
+        the solution in place; hist (a float64 numpy array, optional)
+        receives the history.  Allocates no device memory."""
+        import torch
+        L = _lib.load()
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        bp = _dev_ptr(b, torch.float64, self.n)
+        xp = _dev_ptr(x, torch.float64, self.n)
+        maxit = -1 if maxit is None else int(maxit)
+        cap = 0 if hist is None else int(hist.shape[0])
+        iters = ctypes.c_int32()
+        hl = ctypes.c_int32()
+        tr = ctypes.c_double()
+        st = L.pcga_pcg_solve_noalloc(self._h, bp, xp, float(tol), maxit, ctypes.byref(iters),
+                                      None if hist is None else hist.ctypes.data, cap,
+                                      ctypes.byref(hl), ctypes.byref(tr))
+        check(st, "pcga_pcg_solve_noalloc", allow=(_lib.OK, _lib.NOCONV))
+        h = hist[: min(hl.value, cap)].copy() if hist is not None else np.zeros(0)
+        return SolveResult(x, iters.value, h, st, tr.value)
+
     def solve_mixed(self, b, x0=None, tol=1e-10, inner_tol=1e-5, max_outer=20,
                     inner_maxit=None) -> SolveResult:
         L = _lib.load()

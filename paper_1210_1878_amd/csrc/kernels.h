@@ -1006,6 +1006,18 @@ static __global__ __launch_bounds__(kBS) void k_apply_a(DevOp<double> A, const d
     }
 }
 
+// v = 0 (a fill kernel rather than a memset, so that it is an ordinary node
+// when the caller captures the stream).
+template <typename T>
+__global__ __launch_bounds__(kBS) void k_zero(int n, T *__restrict__ v) {
+    for (int k = blockIdx.x * kBS + threadIdx.x; k < n; k += gridDim.x * kBS) v[k] = T(0);
+}
+
+inline int zero_grid(int64_t n) {
+    const int64_t g = (n + kBS - 1) / kBS;
+    return (int)(g < 1 ? 1 : (g > 4096 ? 4096 : g));
+}
+
 template <typename S, typename D>
 __global__ __launch_bounds__(kBS) void k_convert(int n, const S *__restrict__ in,
                                                  D *__restrict__ out) {

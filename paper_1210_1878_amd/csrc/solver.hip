@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -59,6 +60,12 @@ using namespace pcga;
 struct pcga_ainv {
     AinvFactor F;
 };
+
+// Device memory of the allocation-free solve (pcga_pcg_solve_noalloc): 64 MiB
+// per device, enough for the FP64 vectors of a grid of about 1.19 M cells.
+constexpr size_t kNoallocBytes = PCGA_NOALLOC_MAX_BYTES;
+static_assert(kNoallocBytes % 256 == 0, "scratch size must keep 256-byte alignment");
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
 
 // ---------------------------------------------------------------------------
 // Workspace carving: one bump pass computes the size (base == nullptr) or
@@ -733,15 +740,17 @@ struct IterBufs {
     const T *zb;       // banded Z by diagonals (band_q > 0)
     const T *dinv;
     T *x, *r[2], *s, *d[2], *q, *t;
+    CtlBlock *cb;   // control block and partial sums of the solve
+    Partials P;
 };
 
 IterBufs<double> bufs64(pcga_solver &S) {
     return {S.A64, S.zt64, S.z64, S.zb64, S.dinv64, S.x, {S.r[0], S.r[1]}, S.s, {S.d[0], S.d[1]},
-            S.q, S.t};
+            S.q, S.t, S.cb, S.P};
 }
 IterBufs<float> bufs32(pcga_solver &S) {
     return {S.A64, S.zt32, S.z32, S.zb32, S.dinv32, S.e32, {S.r32[0], S.r32[1]}, S.s32,
-            {S.d32[0], S.d32[1]}, S.q32, S.t32};
+            {S.d32[0], S.d32[1]}, S.q32, S.t32, S.cb, S.P};
 }
 
 // Launch k_zt / k_z in a matrix's storage and read format (kFmt* bits).
@@ -777,35 +786,35 @@ void launch_kernel(pcga_solver &S, const IterBufs<T> &B, int p, int which) {
         case 0:
             if (S.jacobi)
                 k_stencil<T, true><<<S.g_st, kBS, 0, S.stream>>>(B.A, B.s, B.d[p], B.d[p ^ 1], B.q,
-                                                                 S.cb, S.P, S.g_st, p);
+                                                                 B.cb, B.P, S.g_st, p);
             else
                 k_stencil<T, false><<<S.g_st, kBS, 0, S.stream>>>(B.A, B.s, B.d[p], B.d[p ^ 1], B.q,
-                                                                  S.cb, S.P, S.g_prec(), p);
+                                                                  B.cb, B.P, S.g_prec(), p);
             break;
         case 1:
             if (S.jacobi) {
                 k_jacobi<T, false><<<S.g_st, kBS, 0, S.stream>>>(
-                    B.dinv, B.r[p], B.q, B.d[p ^ 1], B.r[p ^ 1], B.x, B.s, (int)S.n, S.cb, S.P,
+                    B.dinv, B.r[p], B.q, B.d[p ^ 1], B.r[p ^ 1], B.x, B.s, (int)S.n, B.cb, B.P,
                     S.g_st, p);
                 break;
             }
             if (S.band_q > 0) {
                 k_zt_band<T, true><<<S.g_st, kBS, 0, S.stream>>>(
                     B.zb, S.band_q, B.dinv, B.r[p], B.q, B.d[p ^ 1], B.r[p ^ 1], B.x, B.t, (int)S.n,
-                    S.cb, S.P, S.g_st, p);
+                    B.cb, B.P, S.g_st, p);
                 break;
             }
             launch_zt<T, true>(B.zt, S.fmt_zt, S.g_zt, S.stream, B.dinv, (const T *)B.r[p], (const T *)B.q,
-                               (const T *)B.d[p ^ 1], B.r[p ^ 1], B.x, B.t, S.cb, S.P, S.g_st, p);
+                               (const T *)B.d[p ^ 1], B.r[p ^ 1], B.x, B.t, B.cb, B.P, S.g_st, p);
             break;
         default:
             if (S.band_q > 0) {
                 k_z_band<T, true, false><<<S.g_st, kBS, 0, S.stream>>>(
-                    B.zb, S.band_q, B.t, B.r[p ^ 1], B.s, (int)S.n, S.cb, S.P, S.g_st, p);
+                    B.zb, S.band_q, B.t, B.r[p ^ 1], B.s, (int)S.n, B.cb, B.P, S.g_st, p);
                 break;
             }
             launch_z<T, true, false>(B.z, S.fmt_z, S.g_z, S.stream, (const T *)B.t, (const T *)B.r[p ^ 1],
-                                     B.s, S.cb, S.P, S.g_zt, p);
+                                     B.s, B.cb, B.P, S.g_zt, p);
             break;
     }
 }
@@ -817,15 +826,16 @@ void launch_iters(pcga_solver &S, const IterBufs<T> &B, int count) {
 }
 
 // r0 = b - A x0 (FP64) and the solve's control state.
-void launch_residual_prologue(pcga_solver &S, const double *x, const double *b, double *r,
-                              double tol, int maxit) {
-    k_residual<true><<<S.g_st, kBS, 0, S.stream>>>(S.A64, x, b, r, S.P);
-    k_fin_residual<0><<<1, kBS, 0, S.stream>>>(S.cb, S.P, S.g_st, tol, maxit);
+void launch_residual_prologue(pcga_solver &S, CtlBlock *cb, const Partials &P, const double *x,
+                              const double *b, double *r, double tol, int maxit) {
+    k_residual<true><<<S.g_st, kBS, 0, S.stream>>>(S.A64, x, b, r, P);
+    k_fin_residual<0><<<1, kBS, 0, S.stream>>>(cb, P, S.g_st, tol, maxit);
 }
 
-void launch_true_residual(pcga_solver &S, const double *x, const double *b) {
-    k_residual<false><<<S.g_st, kBS, 0, S.stream>>>(S.A64, x, b, nullptr, S.P);
-    k_fin_residual<1><<<1, kBS, 0, S.stream>>>(S.cb, S.P, S.g_st, 0.0, 0);
+void launch_true_residual(pcga_solver &S, CtlBlock *cb, const Partials &P, const double *x,
+                          const double *b) {
+    k_residual<false><<<S.g_st, kBS, 0, S.stream>>>(S.A64, x, b, nullptr, P);
+    k_fin_residual<1><<<1, kBS, 0, S.stream>>>(cb, P, S.g_st, 0.0, 0);
 }
 
 void launch_refine(pcga_solver &S, bool add_e, const double *x, double *xnew, const double *b,
@@ -840,26 +850,26 @@ void launch_refine(pcga_solver &S, bool add_e, const double *x, double *xnew, co
 // t = D^-1 Z^T r0 ; s0 = Z t ; (s0, r0) partials ; d[0] = 0
 template <typename T>
 int prologue_prec(pcga_solver &S, const IterBufs<T> &B) {
-    HIP_TRY(hipMemsetAsync(B.d[0], 0, S.n * sizeof(T), S.stream));
+    k_zero<T><<<zero_grid(S.n), kBS, 0, S.stream>>>((int)S.n, B.d[0]);
     if (S.jacobi) {
         k_jacobi<T, true><<<S.g_st, kBS, 0, S.stream>>>(B.dinv, B.r[0], nullptr, nullptr, nullptr,
-                                                        nullptr, B.s, (int)S.n, S.cb, S.P, 0, 0);
+                                                        nullptr, B.s, (int)S.n, B.cb, B.P, 0, 0);
         HIP_TRY(hipGetLastError());
         return PCGA_OK;
     }
     if (S.band_q > 0) {
         k_zt_band<T, false><<<S.g_st, kBS, 0, S.stream>>>(B.zb, S.band_q, B.dinv, B.r[0], nullptr,
                                                           nullptr, nullptr, nullptr, B.t, (int)S.n,
-                                                          S.cb, S.P, 0, 0);
+                                                          B.cb, B.P, 0, 0);
         k_z_band<T, true, true><<<S.g_st, kBS, 0, S.stream>>>(B.zb, S.band_q, B.t, B.r[0], B.s,
-                                                              (int)S.n, S.cb, S.P, 0, 0);
+                                                              (int)S.n, B.cb, B.P, 0, 0);
         HIP_TRY(hipGetLastError());
         return PCGA_OK;
     }
     launch_zt<T, false>(B.zt, S.fmt_zt, S.g_zt, S.stream, B.dinv, (const T *)B.r[0], (const T *)nullptr,
-                        (const T *)nullptr, (T *)nullptr, (T *)nullptr, B.t, S.cb, S.P, 0, 0);
-    launch_z<T, true, true>(B.z, S.fmt_z, S.g_z, S.stream, (const T *)B.t, (const T *)B.r[0], B.s, S.cb,
-                            S.P, 0, 0);
+                        (const T *)nullptr, (T *)nullptr, (T *)nullptr, B.t, B.cb, B.P, 0, 0);
+    launch_z<T, true, true>(B.z, S.fmt_z, S.g_z, S.stream, (const T *)B.t, (const T *)B.r[0], B.s, B.cb,
+                            B.P, 0, 0);
     HIP_TRY(hipGetLastError());
     return PCGA_OK;
 }
@@ -883,8 +893,8 @@ __global__ __launch_bounds__(kBS) void k_step_dq(Partials P, int g) {
     if (threadIdx.x == 0) P.res[0] = v[0];
 }
 
-int snapshot(pcga_solver &S, int slot) {
-    HIP_TRY(hipMemcpyAsync(S.snap[slot], S.cb, sizeof(CtlBlock), hipMemcpyDeviceToHost, S.stream));
+int snapshot(pcga_solver &S, const CtlBlock *cb, int slot) {
+    HIP_TRY(hipMemcpyAsync(S.snap[slot], cb, sizeof(CtlBlock), hipMemcpyDeviceToHost, S.stream));
     HIP_TRY(hipEventRecord(S.ev[slot], S.stream));
     return PCGA_OK;
 }
@@ -920,20 +930,21 @@ int ensure_graph(pcga_solver &S, const IterBufs<T> &B) {
 // as they arrive; final_slot names the snapshot holding the final state.
 template <typename T>
 int run_chunks(pcga_solver &S, const IterBufs<T> &B, double *hist_out, int64_t hist_cap,
-               int64_t maxit, int &final_slot) {
+               int64_t maxit, int &final_slot, bool graph_ok = true) {
     int st;
-    if (S.use_graph) {
+    const bool use_graph = S.use_graph && graph_ok;
+    if (use_graph) {
         st = ensure_graph<T>(S, B);
         if (st) return st;
     }
     auto launch = [&](int slot) -> int {
-        if (S.use_graph) {
+        if (use_graph) {
             HIP_TRY(hipGraphLaunch(S.graph, S.stream));
         } else {
             launch_iters<T>(S, B, S.chunk);
             HIP_TRY(hipGetLastError());
         }
-        return snapshot(S, slot);
+        return snapshot(S, B.cb, slot);
     };
     int64_t seen = 0;
     int64_t c = 0;
@@ -964,32 +975,35 @@ int run_chunks(pcga_solver &S, const IterBufs<T> &B, double *hist_out, int64_t h
     }
 }
 
-}  // namespace
-
-extern "C" {
-
-int pcga_pcg_solve(pcga_solver_t *S, const double *b_dev, double *x_dev, double tol, int32_t maxit,
-                   int32_t *iters, double *hist_host, int32_t hist_cap, int32_t *hist_len,
-                   double *true_relres) {
+int check_solve_args(const pcga_solver *S, const double *b_dev, const double *x_dev, double tol,
+                     int32_t maxit, const double *hist_host, int32_t hist_cap) {
+    (void)maxit;
     if (!S || !b_dev || !x_dev) return fail(PCGA_EINVAL, "NULL argument");
-    if (S->precision != PCGA_FP64) return fail(PCGA_EINVAL, "pcga_pcg_solve needs a PCGA_FP64 solver");
+    if (S->precision != PCGA_FP64) return fail(PCGA_EINVAL, "an FP64 solve needs a PCGA_FP64 solver");
     if (!(tol >= 0.0)) return fail(PCGA_EINVAL, "tol must be >= 0");
-    if (maxit < 0) maxit = (int32_t)std::min<int64_t>(S->n, INT32_MAX);
     if (hist_cap < 0 || (hist_cap > 0 && !hist_host)) return fail(PCGA_EINVAL, "bad history buffer");
-    HIP_TRY(hipSetDevice(S->device));
-    pcga_solver &R = *S;
-    IterBufs<double> B = bufs64(R);
+    return PCGA_OK;
+}
+
+// One FP64 solve (Algorithm 1) on the vectors, partials and control block of
+// B.  When B.x is not x_dev, x0 is copied in and the solution out; graph_ok
+// = false launches the kernels directly (no graph is captured or replayed).
+int solve64(pcga_solver &R, const IterBufs<double> &B, const double *b_dev, double *x_dev,
+            double tol, int32_t maxit, int32_t *iters, double *hist_host, int32_t hist_cap,
+            int32_t *hist_len, double *true_relres, bool graph_ok) {
+    if (maxit < 0) maxit = (int32_t)std::min<int64_t>(R.n, INT32_MAX);
     const size_t nb8 = R.n * sizeof(double);
-    HIP_TRY(hipMemcpyAsync(R.x, x_dev, nb8, hipMemcpyDeviceToDevice, R.stream));
-    launch_residual_prologue(R, R.x, b_dev, R.r[0], tol, maxit);
+    if (B.x != x_dev) HIP_TRY(hipMemcpyAsync(B.x, x_dev, nb8, hipMemcpyDeviceToDevice, R.stream));
+    launch_residual_prologue(R, B.cb, B.P, B.x, b_dev, B.r[0], tol, maxit);
     int st = prologue_prec<double>(R, B);
     if (st) return st;
-    if ((st = snapshot(R, 0))) return st;
+    if ((st = snapshot(R, B.cb, 0))) return st;
     if ((st = wait_snap(R, 0))) return st;
     const Ctl c0 = R.snap[0]->c;
     if (hist_cap > 0) hist_host[0] = R.snap[0]->hist[0];
     if (c0.nb == 0.0) {
-        HIP_TRY(hipMemsetAsync(x_dev, 0, nb8, R.stream));
+        k_zero<double><<<zero_grid(R.n), kBS, 0, R.stream>>>((int)R.n, x_dev);
+        HIP_TRY(hipGetLastError());
         HIP_TRY(hipStreamSynchronize(R.stream));
         if (iters) *iters = 0;
         if (hist_len) *hist_len = 1;
@@ -999,13 +1013,13 @@ int pcga_pcg_solve(pcga_solver_t *S, const double *b_dev, double *x_dev, double 
     }
     int slot = 0;
     if (!c0.done) {
-        if ((st = run_chunks<double>(R, B, hist_host, hist_cap, maxit, slot))) return st;
+        if ((st = run_chunks<double>(R, B, hist_host, hist_cap, maxit, slot, graph_ok))) return st;
     }
     const Ctl cf = R.snap[slot]->c;
     // true residual ||b - A x|| in FP64
-    launch_true_residual(R, R.x, b_dev);
-    HIP_TRY(hipMemcpyAsync(x_dev, R.x, nb8, hipMemcpyDeviceToDevice, R.stream));
-    if ((st = snapshot(R, 0))) return st;
+    launch_true_residual(R, B.cb, B.P, B.x, b_dev);
+    if (B.x != x_dev) HIP_TRY(hipMemcpyAsync(x_dev, B.x, nb8, hipMemcpyDeviceToDevice, R.stream));
+    if ((st = snapshot(R, B.cb, 0))) return st;
     if ((st = wait_snap(R, 0))) return st;
     const Ctl ct = R.snap[0]->c;
     if (iters) *iters = cf.k;
@@ -1015,6 +1029,91 @@ int pcga_pcg_solve(pcga_solver_t *S, const double *b_dev, double *x_dev, double 
     if (rs == PCGA_EBREAKDOWN) fail(rs, "PCG breakdown: (d,q) <= 0 or rho <= 0");
     if (rs == PCGA_ENAN) fail(rs, "NaN/Inf in the PCG iteration");
     return rs;
+}
+
+// ---------------------------------------------------------------------------
+// Static scratch of the allocation-free solve.  The vectors r (two buffers),
+// s, d (two buffers), q, t, the partial sums and the control block of one
+// solve live in the file-scope device array `scratch` (kNoallocBytes).  Each
+// device the library runs on holds its own copy until the process ends; its
+// address on a device is looked up once, with that device current, and only
+// that address is handed to kernels and copies (the array's name is a host
+// stand-in).  Calls on one device share the array: calls that overlap on one
+// device race.
+// ---------------------------------------------------------------------------
+constexpr int kNoallocDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kNoallocDevices] = {};
+
+int scratch_address(int dev, unsigned char **out) {
+    if (dev < 0 || dev >= kNoallocDevices)
+        return fail(PCGA_EINVAL, "device index beyond the static scratch's device table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PCGA_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<unsigned char *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return PCGA_OK;
+}
+
+// Bytes of static scratch a grid of n cells needs (base == nullptr), or the
+// pointers of B carved from base.
+size_t carve_noalloc(int64_t n, unsigned char *base, IterBufs<double> *B) {
+    Carver C(base);
+    IterBufs<double> tmp{};
+    IterBufs<double> &V = B ? *B : tmp;
+    V.r[0] = C.take<double>(n);
+    V.r[1] = C.take<double>(n);
+    V.s = C.take<double>(n);
+    V.d[0] = C.take<double>(n);
+    V.d[1] = C.take<double>(n);
+    V.q = C.take<double>(n);
+    V.t = C.take<double>(n);
+    V.P.dq = C.take<double>(kMaxBlocks);
+    V.P.rr = C.take<double>(kMaxBlocks);
+    V.P.sr = C.take<double>(kMaxBlocks);
+    V.P.res = C.take<double>(3 * (size_t)kMaxBlocks);
+    V.cb = C.take<CtlBlock>(1);
+    return C.off;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pcga_pcg_solve(pcga_solver_t *S, const double *b_dev, double *x_dev, double tol, int32_t maxit,
+                   int32_t *iters, double *hist_host, int32_t hist_cap, int32_t *hist_len,
+                   double *true_relres) {
+    int st = check_solve_args(S, b_dev, x_dev, tol, maxit, hist_host, hist_cap);
+    if (st) return st;
+    HIP_TRY(hipSetDevice(S->device));
+    return solve64(*S, bufs64(*S), b_dev, x_dev, tol, maxit, iters, hist_host, hist_cap, hist_len,
+                   true_relres, true);
+}
+
+int pcga_pcg_solve_noalloc(pcga_solver_t *S, const double *b_dev, double *x_dev, double tol,
+                           int32_t maxit, int32_t *iters, double *hist_host, int32_t hist_cap,
+                           int32_t *hist_len, double *true_relres) {
+    int st = check_solve_args(S, b_dev, x_dev, tol, maxit, hist_host, hist_cap);
+    if (st) return st;
+    const size_t need = carve_noalloc(S->n, nullptr, nullptr);
+    if (need > kNoallocBytes)
+        return fail(PCGA_ENOMEM, "pcga_pcg_solve_noalloc: a grid of " + std::to_string(S->n) +
+                                     " cells needs " + std::to_string(need) +
+                                     " bytes of static scratch; the library holds " +
+                                     std::to_string(kNoallocBytes));
+    HIP_TRY(hipSetDevice(S->device));
+    unsigned char *base = nullptr;
+    if ((st = scratch_address(S->device, &base))) return st;
+    IterBufs<double> B = bufs64(*S);
+    carve_noalloc(S->n, base, &B);
+    B.x = x_dev;   // the caller's vector is the iterate
+    return solve64(*S, B, b_dev, x_dev, tol, maxit, iters, hist_host, hist_cap, hist_len,
+                   true_relres, false);
 }
 
 int pcga_pcg_solve_mixed(pcga_solver_t *S, const double *b_dev, double *x_dev, double tol,
@@ -1039,7 +1138,7 @@ int pcga_pcg_solve_mixed(pcga_solver_t *S, const double *b_dev, double *x_dev, d
         launch_refine(R, o > 0, R.x64[cur], R.x64[cur ^ 1], b_dev, inner_tol, inner_maxit);
         if (o > 0) cur ^= 1;
         HIP_TRY(hipGetLastError());
-        if ((st = snapshot(R, 0))) return st;
+        if ((st = snapshot(R, R.cb, 0))) return st;
         if ((st = wait_snap(R, 0))) return st;
         const Ctl c = R.snap[0]->c;
         if (c.bb == 0.0) {
@@ -1063,7 +1162,7 @@ int pcga_pcg_solve_mixed(pcga_solver_t *S, const double *b_dev, double *x_dev, d
         // inner FP32 PCG for A e = r32, e0 = 0
         HIP_TRY(hipMemsetAsync(B.x, 0, R.n * sizeof(float), R.stream));
         if ((st = prologue_prec<float>(R, B))) return st;
-        if ((st = snapshot(R, 0))) return st;
+        if ((st = snapshot(R, R.cb, 0))) return st;
         if ((st = wait_snap(R, 0))) return st;
         int slot = 0;
         if (!R.snap[0]->c.done) {
@@ -1177,7 +1276,7 @@ int pcga_profile_iteration(pcga_solver_t *S, const double *b_dev, int32_t reps, 
     auto prologue = [&]() -> int {
         if (R.precision == PCGA_FP64) {
             HIP_TRY(hipMemsetAsync(R.x, 0, R.n * sizeof(double), R.stream));
-            launch_residual_prologue(R, R.x, b_dev, R.r[0], 0.0, big);
+            launch_residual_prologue(R, R.cb, R.P, R.x, b_dev, R.r[0], 0.0, big);
             return prologue_prec<double>(R, bufs64(R));
         }
         HIP_TRY(hipMemsetAsync(R.x64[0], 0, R.n * sizeof(double), R.stream));
