@@ -199,6 +199,15 @@ int pcga_solver_info(const pcga_solver_t *S, int64_t *n, int64_t *nnz_off,
  * Takes effect at the next solve.  Results of a solve are bitwise
  * reproducible for fixed settings. */
 int pcga_solver_tune(pcga_solver_t *S, int32_t chunk, int32_t use_graph, int32_t max_blocks);
+/* Workgroups per launch of each kernel of an iteration, for kernels whose
+ * register use allows a different occupancy than the others: g_stencil for
+ * the five-point kernels (also the residual passes), g_zt for the Z^T sweep,
+ * g_z for the Z sweep; each 1..2048, or 0 for the max_blocks of
+ * pcga_solver_tune.  Each count is capped by the work there is (a workgroup
+ * per 256 cells, or per four slices).  Results depend on the counts only
+ * through the order in which per-workgroup partial sums are added.  Errors:
+ * EINVAL, EHIP. */
+int pcga_solver_set_grids(pcga_solver_t *S, int32_t g_stencil, int32_t g_zt, int32_t g_z);
 
 /* ---- solves --------------------------------------------------------------
  * pcga_pcg_solve: Algorithm 1 with s = Z D^-1 Z^T r and the direction update

@@ -23,13 +23,38 @@ _LIB = os.environ.get("PCGA_ORACLE_LIB", os.path.join(_HERE, "liboracle.so"))
 OK, NOCONV, EINVAL, EBREAKDOWN, ENOMEM = 0, 1, -1, -2, -3
 
 
+# Evaluation-order builds of the same source (see oracle.c): the method is the
+# same, only the order of the inner products' additions or the fusing of
+# multiply-adds differs.  Used to measure rounding sensitivity.
+VARIANTS = {
+    "reverse": ["-ffp-contract=off", "-DORA_DOT_ORDER=1"],
+    "blocked": ["-ffp-contract=off", "-DORA_DOT_ORDER=2"],
+    "fused": ["-ffp-contract=fast", "-mfma"],
+    "fused_blocked": ["-ffp-contract=fast", "-mfma", "-DORA_DOT_ORDER=2"],
+}
+
+
+def _variant_path(name):
+    return os.path.join(_HERE, f"liboracle_{name}.so")
+
+
+def _compile(out, flags):
+    tmp = out + ".tmp"
+    subprocess.run(["gcc", "-O2"] + flags + ["-fno-fast-math", "-fPIC", "-shared", "-std=c99",
+                                             "-o", tmp, _SRC, "-lm"], check=True)
+    os.replace(tmp, out)
+
+
 def build(force: bool = True) -> str:
-    """Compile liboracle.so from oracle.c with gcc (unfused FP64)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                        "-shared", "-std=c99", "-o", tmp, _SRC, "-lm"], check=True)
-        os.replace(tmp, _LIB)
+    """Compile liboracle.so from oracle.c with gcc (unfused FP64), and the
+    evaluation-order builds liboracle_<variant>.so."""
+    def stale(path):
+        return force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC)
+    if stale(_LIB):
+        _compile(_LIB, ["-ffp-contract=off"])
+    for name, flags in VARIANTS.items():
+        if stale(_variant_path(name)):
+            _compile(_variant_path(name), flags)
     return _LIB
 
 
@@ -41,49 +66,66 @@ _dbl = ctypes.c_double
 _int = ctypes.c_int
 
 
-def lib():
+_variant_libs = {}
+
+
+def lib(variant=None):
+    """The default build, or the evaluation-order build `variant`."""
     global _lib
+    if variant is not None:
+        if variant not in VARIANTS:
+            raise ValueError(f"unknown oracle build {variant!r}")
+        if variant not in _variant_libs:
+            path = _variant_path(variant)
+            if not os.path.exists(path):
+                build(force=False)
+            _variant_libs[variant] = _declare(ctypes.CDLL(path))
+        return _variant_libs[variant]
     if _lib is None:
         if not os.path.exists(_LIB):
             build(force=False)
-        L = ctypes.CDLL(_LIB)
-        L.ora_spmv.argtypes = [_i64, _i64, _int, _p, _p, _p, _p, _p]
-        L.ora_spmv.restype = None
-        L.ora_ainv_setup.argtypes = [_i64, _i64, _int, _p, _p, _p, _dbl,
-                                     ctypes.POINTER(_p), ctypes.POINTER(_i64),
-                                     ctypes.POINTER(_i64)]
-        L.ora_ainv_setup.restype = _int
-        L.ora_ainv_setup_fill.argtypes = [_i64, _i64, _int, _p, _p, _p, _dbl, _i64,
-                                          ctypes.POINTER(_p), ctypes.POINTER(_i64),
-                                          ctypes.POINTER(_i64)]
-        L.ora_ainv_setup_fill.restype = _int
-        L.ora_ainv_export.argtypes = [_p, _p, _p, _p, _p]
-        L.ora_ainv_export.restype = None
-        L.ora_ainv_free.argtypes = [_p]
-        L.ora_ainv_free.restype = None
-        L.ora_zt_apply.argtypes = [_i64, _p, _p, _p, _p, _p, _p]
-        L.ora_zt_apply.restype = None
-        L.ora_z_apply.argtypes = [_i64, _p, _p, _p, _p, _p]
-        L.ora_z_apply.restype = None
-        L.ora_prec_apply.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _p]
-        L.ora_prec_apply.restype = None
-        L.ora_pcg.argtypes = [_i64, _i64, _int, _p, _p, _p, _p, _p, _p, _p, _p, _p,
-                              _dbl, _i64, ctypes.POINTER(_i64), _p, _p, _p]
-        L.ora_pcg.restype = _int
-        L.ora_pcg_mixed.argtypes = [_i64, _i64, _int, _p, _p, _p, _p, _p, _p, _p, _p,
-                                    _p, _dbl, _dbl, _i64, _i64, ctypes.POINTER(_i64),
-                                    ctypes.POINTER(_i64), _p]
-        L.ora_pcg_mixed.restype = _int
-        L.ora_fsai_band.argtypes = [_i64, _i64, _int, _p, _p, _p, _i64, _p, _p]
-        L.ora_fsai_band.restype = _int
-        L.ora_ts_rhs.argtypes = [_i64, _i64, _int, _p, _p, _p, _p, _p]
-        L.ora_ts_rhs.restype = None
-        L.ora_ts_eta.argtypes = [_i64, _p, _p, _dbl, _p]
-        L.ora_ts_eta.restype = None
-        L.ora_ts_guess.argtypes = [_i64, _p, _p, _dbl, _dbl, _p]
-        L.ora_ts_guess.restype = None
-        _lib = L
+        _lib = _declare(ctypes.CDLL(_LIB))
     return _lib
+
+
+def _declare(L):
+    """Argument and result types of the entry points."""
+    L.ora_spmv.argtypes = [_i64, _i64, _int, _p, _p, _p, _p, _p]
+    L.ora_spmv.restype = None
+    L.ora_ainv_setup.argtypes = [_i64, _i64, _int, _p, _p, _p, _dbl,
+                                 ctypes.POINTER(_p), ctypes.POINTER(_i64),
+                                 ctypes.POINTER(_i64)]
+    L.ora_ainv_setup.restype = _int
+    L.ora_ainv_setup_fill.argtypes = [_i64, _i64, _int, _p, _p, _p, _dbl, _i64,
+                                      ctypes.POINTER(_p), ctypes.POINTER(_i64),
+                                      ctypes.POINTER(_i64)]
+    L.ora_ainv_setup_fill.restype = _int
+    L.ora_ainv_export.argtypes = [_p, _p, _p, _p, _p]
+    L.ora_ainv_export.restype = None
+    L.ora_ainv_free.argtypes = [_p]
+    L.ora_ainv_free.restype = None
+    L.ora_zt_apply.argtypes = [_i64, _p, _p, _p, _p, _p, _p]
+    L.ora_zt_apply.restype = None
+    L.ora_z_apply.argtypes = [_i64, _p, _p, _p, _p, _p]
+    L.ora_z_apply.restype = None
+    L.ora_prec_apply.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _p]
+    L.ora_prec_apply.restype = None
+    L.ora_pcg.argtypes = [_i64, _i64, _int, _p, _p, _p, _p, _p, _p, _p, _p, _p,
+                          _dbl, _i64, ctypes.POINTER(_i64), _p, _p, _p]
+    L.ora_pcg.restype = _int
+    L.ora_pcg_mixed.argtypes = [_i64, _i64, _int, _p, _p, _p, _p, _p, _p, _p, _p,
+                                _p, _dbl, _dbl, _i64, _i64, ctypes.POINTER(_i64),
+                                ctypes.POINTER(_i64), _p]
+    L.ora_pcg_mixed.restype = _int
+    L.ora_fsai_band.argtypes = [_i64, _i64, _int, _p, _p, _p, _i64, _p, _p]
+    L.ora_fsai_band.restype = _int
+    L.ora_ts_rhs.argtypes = [_i64, _i64, _int, _p, _p, _p, _p, _p]
+    L.ora_ts_rhs.restype = None
+    L.ora_ts_eta.argtypes = [_i64, _p, _p, _dbl, _p]
+    L.ora_ts_eta.restype = None
+    L.ora_ts_guess.argtypes = [_i64, _p, _p, _dbl, _dbl, _p]
+    L.ora_ts_guess.restype = None
+    return L
 
 
 def _ptr(a):
@@ -196,8 +238,10 @@ class PCGResult:
         self.betas = betas
 
 
-def pcg(p, F: AInv, b=None, x0=None, tol=1e-10, maxit=None, scalars=False) -> PCGResult:
-    """Algorithm 1 in FP64.  Returns x, iteration count and residual history."""
+def pcg(p, F: AInv, b=None, x0=None, tol=1e-10, maxit=None, scalars=False,
+        variant=None) -> PCGResult:
+    """Algorithm 1 in FP64.  Returns x, iteration count and residual history.
+    variant: run an evaluation-order build (VARIANTS) instead of the default."""
     n = p.nx * p.ny
     b = _f64(p.b if b is None else b)
     x = np.zeros(n) if x0 is None else _f64(x0).copy()
@@ -206,7 +250,7 @@ def pcg(p, F: AInv, b=None, x0=None, tol=1e-10, maxit=None, scalars=False) -> PC
     it = ctypes.c_int64()
     al = np.zeros(max(maxit, 1)) if scalars else None
     be = np.zeros(max(maxit, 1)) if scalars else None
-    st = lib().ora_pcg(p.nx, p.ny, int(p.periodic), _ptr(_f64(p.diag)), _ptr(_f64(p.ae)),
+    st = lib(variant).ora_pcg(p.nx, p.ny, int(p.periodic), _ptr(_f64(p.diag)), _ptr(_f64(p.ae)),
                        _ptr(_f64(p.an)), _ptr(F.colptr), _ptr(F.rowidx), _ptr(F.val),
                        _ptr(F.D), _ptr(b), _ptr(x), float(tol), maxit, ctypes.byref(it),
                        _ptr(hist), _ptr(al) if scalars else None,
@@ -217,6 +261,16 @@ def pcg(p, F: AInv, b=None, x0=None, tol=1e-10, maxit=None, scalars=False) -> PC
     return PCGResult(x, k, hist[: k + 1].copy(), st,
                      al[:k].copy() if scalars else None,
                      be[: max(k - 1, 0)].copy() if scalars else None)
+
+
+def stop_window(p, F: AInv, b=None, x0=None, tol=1e-10):
+    """Stopping iterations of Algorithm 1 under the default build and every
+    evaluation-order build: {build: iterations}, with None for the default.
+    Their spread is what rounding order alone does to the stopping test."""
+    out = {None: pcg(p, F, b=b, x0=x0, tol=tol).iters}
+    for v in VARIANTS:
+        out[v] = pcg(p, F, b=b, x0=x0, tol=tol, variant=v).iters
+    return out
 
 
 class MixedResult:

@@ -42,6 +42,16 @@
  *     diagonal is never dropped; an entry equal to tau is kept.
  *   - Fixed fill: the count is applied to a finished column, before its pivot
  *     p_i is formed, so p_i and every later update use the capped column.
+ *
+ * Evaluation-order builds.  Algorithm 1 fixes what each inner product is,
+ * not the order in which its terms are added.  The default build adds them
+ * in index order.  Built with -DORA_DOT_ORDER=1 it adds them in reverse
+ * order, with -DORA_DOT_ORDER=2 in 1024 contiguous blocks whose sums are then
+ * added in order (the shape of a reduction over workgroups); built with
+ * contraction on (-ffp-contract=fast) multiply-adds are fused.  These builds
+ * compute the same method and differ only in rounding; the tests use them to
+ * measure how far rounding order alone moves the iterates and the stopping
+ * iteration of a given problem.
  */
 #include <math.h>
 #include <stdint.h>
@@ -440,9 +450,27 @@ void ora_prec_apply(int64_t n, const int64_t *colptr, const int64_t *rowidx,
     ora_z_apply(n, colptr, rowidx, val, tmp, s);
 }
 
+#ifndef ORA_DOT_ORDER
+#define ORA_DOT_ORDER 0
+#endif
+
 static double dot(int64_t n, const double *a, const double *b) {
     double s = 0.0;
+#if ORA_DOT_ORDER == 1
+    for (int64_t k = n - 1; k >= 0; k--) { double p = a[k] * b[k]; s = s + p; }
+#elif ORA_DOT_ORDER == 2
+    const int64_t nblk = 1024;
+    for (int64_t g = 0; g < nblk; g++) {
+        double part = 0.0;
+        for (int64_t k = g * n / nblk; k < (g + 1) * n / nblk; k++) {
+            double p = a[k] * b[k];
+            part = part + p;
+        }
+        s = s + part;
+    }
+#else
     for (int64_t k = 0; k < n; k++) { double p = a[k] * b[k]; s = s + p; }
+#endif
     return s;
 }
 

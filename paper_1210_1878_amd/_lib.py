@@ -61,6 +61,7 @@ _SIGS = {
                               ctypes.c_int),
     "pcga_solver_info": ([_p, _pi64, _pi64, _pi32, _pdbl, _pi32, _pi32], ctypes.c_int),
     "pcga_solver_tune": ([_p, _i32, _i32, _i32], ctypes.c_int),
+    "pcga_solver_set_grids": ([_p, _i32, _i32, _i32], ctypes.c_int),
     "pcga_pcg_solve": ([_p, _p, _p, _dbl, _i32, _pi32, _p, _i32, _pi32, _pdbl], ctypes.c_int),
     "pcga_pcg_solve_noalloc": ([_p, _p, _p, _dbl, _i32, _pi32, _p, _i32, _pi32, _pdbl],
                                ctypes.c_int),

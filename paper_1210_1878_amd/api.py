@@ -266,6 +266,12 @@ class Solver:
         check(_lib.load().pcga_solver_tune(self._h, int(chunk), int(bool(use_graph)),
                                            int(max_blocks)), "pcga_solver_tune")
 
+    def set_grids(self, g_stencil=0, g_zt=0, g_z=0):
+        """Workgroups per launch of the five-point, Z^T and Z kernels (0: the
+        tune() cap)."""
+        check(_lib.load().pcga_solver_set_grids(self._h, int(g_stencil), int(g_zt), int(g_z)),
+              "pcga_solver_set_grids")
+
     def _xb(self, b, x0):
         import torch
         # order the solver's stream after the caller's work on b / x0

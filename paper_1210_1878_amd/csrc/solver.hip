@@ -726,6 +726,21 @@ int pcga_solver_tune(pcga_solver_t *S, int32_t chunk, int32_t use_graph, int32_t
     return upload_bounds(*S);
 }
 
+int pcga_solver_set_grids(pcga_solver_t *S, int32_t g_stencil, int32_t g_zt, int32_t g_z) {
+    if (!S) return fail(PCGA_EINVAL, "S is NULL");
+    const int32_t g[3] = {g_stencil, g_zt, g_z};
+    for (int i = 0; i < 3; i++)
+        if (g[i] < 0 || g[i] > kMaxBlocks)
+            return fail(PCGA_EINVAL, "workgroup counts must be 0..." + std::to_string(kMaxBlocks));
+    if (S->graph) {
+        (void)hipGraphExecDestroy(S->graph);
+        S->graph = nullptr;
+    }
+    for (int i = 0; i < 3; i++) S->g_cap[i] = g[i];
+    S->grids();
+    return upload_bounds(*S);
+}
+
 }  // extern "C"
 
 // ===========================================================================

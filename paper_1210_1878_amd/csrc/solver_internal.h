@@ -65,13 +65,19 @@ struct pcga_solver {
     int32_t *bnd_zt_b = nullptr, *bnd_z_b = nullptr;   // device: ranges for a batch slot
     double bytes_per_iter = 0.0;
 
+    // per-kernel workgroup caps (five-point kernels, Z^T sweep, Z sweep); 0:
+    // max_blocks
+    int g_cap[3] = {0, 0, 0};
     void grids() {
-        const int gm = std::max(1, std::min(max_blocks, pcga::kMaxBlocks));
+        auto cap = [&](int i) {
+            const int c = g_cap[i] > 0 ? g_cap[i] : max_blocks;
+            return std::max(1, std::min(c, pcga::kMaxBlocks));
+        };
         const int nsteps = (int)((n + pcga::kStep - 1) / pcga::kStep);
-        g_st = std::max(1, std::min(nsteps, gm));
+        g_st = std::max(1, std::min(nsteps, cap(0)));
         const int nsz = precision == PCGA_FP64 ? zt64.nslices : zt32.nslices;
         const int nsr = precision == PCGA_FP64 ? z64.nslices : z32.nslices;
-        g_zt = std::max(1, std::min((nsz + pcga::kWavesPerBlock - 1) / pcga::kWavesPerBlock, gm));
-        g_z = std::max(1, std::min((nsr + pcga::kWavesPerBlock - 1) / pcga::kWavesPerBlock, gm));
+        g_zt = std::max(1, std::min((nsz + pcga::kWavesPerBlock - 1) / pcga::kWavesPerBlock, cap(1)));
+        g_z = std::max(1, std::min((nsr + pcga::kWavesPerBlock - 1) / pcga::kWavesPerBlock, cap(2)));
     }
 };

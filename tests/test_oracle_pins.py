@@ -408,3 +408,37 @@ def test_mixed_refinement_reaches_fp64_residual(ora):
     assert all(h[i + 1] < 1e-3 * h[i] for i in range(len(h) - 1))
     xs = np.linalg.solve(A, p.b)
     assert np.linalg.norm(m.x - xs) <= np.linalg.cond(A) * 1e-10 * np.linalg.norm(xs)
+
+
+def test_evaluation_order_builds_compute_the_same_method(ora):
+    """The oracle's evaluation-order builds (reversed or blocked inner-product
+    sums, fused multiply-adds) differ from the default build by rounding only:
+    on the 182x149 grid their iterates after 15 iterations agree with the
+    default build's to 1e-12 (relative), all stop at the same 1e-10 target,
+    and each iterate is still the A-norm minimiser over the Krylov space on
+    the 64x48 box (the default build's pin, repeated per build)."""
+    p = orca.orca_problem(182, 149, orca.CONFIG_SEED_BASE + 1)
+    F = ora.ainv_setup(p, 0.1)
+    ref = ora.pcg(p, F, tol=0.0, maxit=15).x
+    window = ora.stop_window(p, F, tol=1e-10)
+    assert set(window) == {None} | set(ora.VARIANTS)
+    for v in ora.VARIANTS:
+        x = ora.pcg(p, F, tol=0.0, maxit=15, variant=v).x
+        assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
+        r = ora.pcg(p, F, tol=1e-10, variant=v)
+        assert r.status == 0 and r.hist[-1] <= 1e-10
+        assert abs(r.iters - window[None]) <= 5
+    pb = orca.box_problem()
+    Fb = ora.ainv_setup(pb, 0.1)
+    M = pb.dense()
+    xs = np.linalg.solve(M, pb.b)
+    for v in [None] + list(ora.VARIANTS):
+        # x_3 minimises the A-norm error over x0 + K_3(P A, P r0), x0 = 0
+        Pm = Fb.dense_z() @ np.diag(1.0 / Fb.D) @ Fb.dense_z().T
+        K = [Pm @ pb.b]
+        for _ in range(2):
+            K.append(Pm @ (M @ K[-1]))
+        V = np.array(K).T
+        c = np.linalg.solve(V.T @ M @ V, V.T @ pb.b)
+        x3 = ora.pcg(pb, Fb, tol=0.0, maxit=3, variant=v).x
+        assert np.linalg.norm(x3 - V @ c) <= 1e-10 * np.linalg.norm(xs)
