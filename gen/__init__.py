@@ -2,8 +2,9 @@
 
 This package only builds *inputs*: the coefficients of the 5-point elliptic
 operator (eq. (8) coefficients placed as in the five-point system eq. (10)),
-land masks, bathymetry and right-hand sides.  It holds none of the solver's
-arithmetic (no PCG, no approximate inverse).
+land masks, bathymetry and right-hand sides, and general sparse SPD matrices
+of unstructured point clouds in CSR (`unstructured`).  It holds none of the
+solver's arithmetic (no PCG, no approximate inverse).
 """
 from .orca import (  # noqa: F401
     Problem,
@@ -13,3 +14,4 @@ from .orca import (  # noqa: F401
     rhs_normal,
     CONFIG_SEED_BASE,
 )
+from .unstructured import CsrProblem, csr_from_grid, unstructured_problem  # noqa: F401,E402

@@ -113,6 +113,14 @@ def _declare(L):
     L.ora_pcg.argtypes = [_i64, _i64, _int, _p, _p, _p, _p, _p, _p, _p, _p, _p,
                           _dbl, _i64, ctypes.POINTER(_i64), _p, _p, _p]
     L.ora_pcg.restype = _int
+    L.ora_csr_spmv.argtypes = [_i64, _p, _p, _p, _p, _p]
+    L.ora_csr_spmv.restype = None
+    L.ora_ainv_setup_csr.argtypes = [_i64, _p, _p, _p, _dbl, _i64, ctypes.POINTER(_p),
+                                     ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
+    L.ora_ainv_setup_csr.restype = _int
+    L.ora_pcg_csr.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _p, _p, _p, _dbl, _i64,
+                              ctypes.POINTER(_i64), _p, _p, _p]
+    L.ora_pcg_csr.restype = _int
     L.ora_pcg_mixed.argtypes = [_i64, _i64, _int, _p, _p, _p, _p, _p, _p, _p, _p,
                                 _p, _dbl, _dbl, _i64, _i64, ctypes.POINTER(_i64),
                                 ctypes.POINTER(_i64), _p]
@@ -164,10 +172,22 @@ class AInv:
         return Z
 
 
+def _is_csr(p):
+    return hasattr(p, "rowptr")
+
+
+def _i64a(a):
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
 def spmv(p, x):
-    """y = A x, rows summed in increasing column order."""
+    """y = A x, rows summed in increasing column order (five-point or CSR)."""
     x = _f64(x)
     y = np.empty_like(x)
+    if _is_csr(p):
+        lib().ora_csr_spmv(p.n, _ptr(_i64a(p.rowptr)), _ptr(_i64a(p.col)), _ptr(_f64(p.val)),
+                           _ptr(x), _ptr(y))
+        return y
     lib().ora_spmv(p.nx, p.ny, int(p.periodic), _ptr(_f64(p.diag)), _ptr(_f64(p.ae)),
                    _ptr(_f64(p.an)), _ptr(x), _ptr(y))
     return y
@@ -182,6 +202,14 @@ def ainv_setup(p, tau, fill=None) -> AInv:
     h = ctypes.c_void_p()
     nnz = ctypes.c_int64()
     brow = ctypes.c_int64()
+    if _is_csr(p):
+        rp, cl, vl = _i64a(p.rowptr), _i64a(p.col), _f64(p.val)
+        st = L.ora_ainv_setup_csr(p.n, _ptr(rp), _ptr(cl), _ptr(vl), float(tau),
+                                  -1 if fill is None else int(fill), ctypes.byref(h),
+                                  ctypes.byref(nnz), ctypes.byref(brow))
+        if st != OK:
+            raise OracleError(st, f"(breakdown row {brow.value})")
+        return _export(L, h, p.n, nnz.value)
     diag, ae, an = _f64(p.diag), _f64(p.ae), _f64(p.an)
     if fill is None:
         st = L.ora_ainv_setup(p.nx, p.ny, int(p.periodic), _ptr(diag), _ptr(ae), _ptr(an),
@@ -194,14 +222,17 @@ def ainv_setup(p, tau, fill=None) -> AInv:
                                    ctypes.byref(nnz), ctypes.byref(brow))
     if st != OK:
         raise OracleError(st, f"(breakdown row {brow.value})")
-    n = p.nx * p.ny
+    return _export(L, h, p.nx * p.ny, nnz.value)
+
+
+def _export(L, h, n, nnz):
     colptr = np.empty(n + 1, dtype=np.int64)
-    rowidx = np.empty(max(nnz.value, 1), dtype=np.int64)
-    val = np.empty(max(nnz.value, 1), dtype=np.float64)
+    rowidx = np.empty(max(nnz, 1), dtype=np.int64)
+    val = np.empty(max(nnz, 1), dtype=np.float64)
     D = np.empty(n, dtype=np.float64)
     L.ora_ainv_export(h, _ptr(colptr), _ptr(rowidx), _ptr(val), _ptr(D))
     L.ora_ainv_free(h)
-    return AInv(n, colptr, rowidx[: nnz.value], val[: nnz.value], D)
+    return AInv(n, colptr, rowidx[:nnz], val[:nnz], D)
 
 
 def zt_apply(F: AInv, r):
@@ -242,7 +273,7 @@ def pcg(p, F: AInv, b=None, x0=None, tol=1e-10, maxit=None, scalars=False,
         variant=None) -> PCGResult:
     """Algorithm 1 in FP64.  Returns x, iteration count and residual history.
     variant: run an evaluation-order build (VARIANTS) instead of the default."""
-    n = p.nx * p.ny
+    n = p.n
     b = _f64(p.b if b is None else b)
     x = np.zeros(n) if x0 is None else _f64(x0).copy()
     maxit = n if maxit is None else int(maxit)
@@ -250,11 +281,15 @@ def pcg(p, F: AInv, b=None, x0=None, tol=1e-10, maxit=None, scalars=False,
     it = ctypes.c_int64()
     al = np.zeros(max(maxit, 1)) if scalars else None
     be = np.zeros(max(maxit, 1)) if scalars else None
-    st = lib(variant).ora_pcg(p.nx, p.ny, int(p.periodic), _ptr(_f64(p.diag)), _ptr(_f64(p.ae)),
-                       _ptr(_f64(p.an)), _ptr(F.colptr), _ptr(F.rowidx), _ptr(F.val),
-                       _ptr(F.D), _ptr(b), _ptr(x), float(tol), maxit, ctypes.byref(it),
-                       _ptr(hist), _ptr(al) if scalars else None,
-                       _ptr(be) if scalars else None)
+    tail = (_ptr(F.colptr), _ptr(F.rowidx), _ptr(F.val), _ptr(F.D), _ptr(b), _ptr(x),
+            float(tol), maxit, ctypes.byref(it), _ptr(hist), _ptr(al) if scalars else None,
+            _ptr(be) if scalars else None)
+    if _is_csr(p):
+        rp, cl, vl = _i64a(p.rowptr), _i64a(p.col), _f64(p.val)
+        st = lib(variant).ora_pcg_csr(p.n, _ptr(rp), _ptr(cl), _ptr(vl), *tail)
+    else:
+        st = lib(variant).ora_pcg(p.nx, p.ny, int(p.periodic), _ptr(_f64(p.diag)),
+                                  _ptr(_f64(p.ae)), _ptr(_f64(p.an)), *tail)
     if st < 0:
         raise OracleError(st)
     k = it.value

@@ -11,6 +11,9 @@
  *
  * Contents
  *   ora_spmv        y = A x for the 5-point operator of eq. (10).
+ *   ora_csr_*       the same setup, product and Algorithm 1 for a general
+ *                   sparse SPD matrix in CSR (a matrix that does not come
+ *                   from the grid, as in the comparison of Sec. 5).
  *   ora_ainv_*      approximate inverse A^-1 ~ Z D^-1 Z^T by
  *                   A-orthogonalisation with a drop tolerance (the AINV of
  *                   the paper's ref. [book4-14]; the threshold variant is the
@@ -136,6 +139,115 @@ static int check_a5(int64_t nx, int64_t ny, int periodic, const double *diag,
 }
 
 /* ------------------------------------------------------------------------ */
+/* A general sparse SPD operator in CSR (Sec. 5 compares the preconditioners */
+/* also on a matrix that does not come from the grid): rowptr[n+1],           */
+/* col/val[rowptr[n]], columns strictly ascending within each row, the        */
+/* diagonal present and positive, A symmetric entry by entry.                 */
+/* ------------------------------------------------------------------------ */
+static int check_csr(int64_t n, const int64_t *rowptr, const int64_t *col,
+                     const double *val) {
+    if (n < 1 || !rowptr || rowptr[0] != 0) return ORA_EINVAL;
+    for (int64_t k = 0; k < n; k++) {
+        int have_diag = 0;
+        if (rowptr[k + 1] < rowptr[k]) return ORA_EINVAL;
+        for (int64_t a = rowptr[k]; a < rowptr[k + 1]; a++) {
+            if (col[a] < 0 || col[a] >= n) return ORA_EINVAL;
+            if (a > rowptr[k] && col[a] <= col[a - 1]) return ORA_EINVAL;
+            if (!isfinite(val[a])) return ORA_EINVAL;
+            if (col[a] == k) {
+                if (!(val[a] > 0.0)) return ORA_EINVAL;
+                have_diag = 1;
+            }
+            /* the mirror entry (col[a], k) with the same value */
+            int64_t lo = rowptr[col[a]], hi = rowptr[col[a] + 1];
+            while (lo < hi) {
+                int64_t mid = (lo + hi) / 2;
+                if (col[mid] < k) lo = mid + 1; else hi = mid;
+            }
+            if (lo == rowptr[col[a] + 1] || col[lo] != k || val[lo] != val[a]) return ORA_EINVAL;
+        }
+        if (!have_diag) return ORA_EINVAL;
+    }
+    return ORA_OK;
+}
+
+/* The operator of a solve: the five-point A5 storage or a CSR matrix. */
+typedef struct {
+    int64_t n;
+    int csr;
+    int64_t nx, ny;
+    int periodic;
+    const double *diag, *ae, *an;
+    const int64_t *rowptr, *col;
+    const double *val;
+    int64_t maxrow;   /* longest row */
+} ora_op;
+
+static ora_op op_a5(int64_t nx, int64_t ny, int periodic, const double *diag,
+                    const double *ae, const double *an) {
+    ora_op A;
+    memset(&A, 0, sizeof(A));
+    A.n = nx * ny;
+    A.nx = nx;
+    A.ny = ny;
+    A.periodic = periodic;
+    A.diag = diag;
+    A.ae = ae;
+    A.an = an;
+    A.maxrow = 5;
+    return A;
+}
+
+static ora_op op_csr(int64_t n, const int64_t *rowptr, const int64_t *col,
+                     const double *val) {
+    ora_op A;
+    memset(&A, 0, sizeof(A));
+    A.n = n;
+    A.csr = 1;
+    A.rowptr = rowptr;
+    A.col = col;
+    A.val = val;
+    A.maxrow = 1;
+    for (int64_t k = 0; k < n; k++)
+        if (rowptr[k + 1] - rowptr[k] > A.maxrow) A.maxrow = rowptr[k + 1] - rowptr[k];
+    return A;
+}
+
+/* Row k as (column, value) pairs sorted by column (capacity A->maxrow). */
+static int op_row(const ora_op *A, int64_t k, int64_t *cols, double *vals) {
+    if (!A->csr) return a_row(A->nx, A->ny, A->periodic, A->diag, A->ae, A->an, k, cols, vals);
+    int m = 0;
+    for (int64_t a = A->rowptr[k]; a < A->rowptr[k + 1]; a++) {
+        cols[m] = A->col[a];
+        vals[m] = A->val[a];
+        m++;
+    }
+    return m;
+}
+
+/* y = A x, each row summed in increasing column order. */
+static void op_apply(const ora_op *A, const double *x, double *y) {
+    if (!A->csr) {
+        ora_spmv(A->nx, A->ny, A->periodic, A->diag, A->ae, A->an, x, y);
+        return;
+    }
+    for (int64_t k = 0; k < A->n; k++) {
+        double s = 0.0;
+        for (int64_t a = A->rowptr[k]; a < A->rowptr[k + 1]; a++) {
+            double p = A->val[a] * x[A->col[a]];
+            s = s + p;
+        }
+        y[k] = s;
+    }
+}
+
+void ora_csr_spmv(int64_t n, const int64_t *rowptr, const int64_t *col, const double *val,
+                  const double *x, double *y) {
+    ora_op A = op_csr(n, rowptr, col, val);
+    op_apply(&A, x, y);
+}
+
+/* ------------------------------------------------------------------------ */
 /* AINV by A-orthogonalisation with a drop tolerance.                        */
 /*                                                                          */
 /* Z is unit upper triangular; column z_j holds its off-diagonal entries     */
@@ -230,22 +342,14 @@ static int keep_largest(ora_col *z, int64_t fill) {
     return ORA_OK;
 }
 
-/* Returns ORA_OK and a handle, or ORA_EBREAKDOWN (p_i <= 0) / ORA_EINVAL /
- * ORA_ENOMEM.  fill < 0: no cap on the entries per column. */
-int ora_ainv_setup_fill(int64_t nx, int64_t ny, int periodic, const double *diag,
-                        const double *ae, const double *an, double tau, int64_t fill,
-                        void **out, int64_t *nnz_off, int64_t *breakdown_row) {
-    *out = NULL;
-    if (breakdown_row) *breakdown_row = -1;
-    int st = check_a5(nx, ny, periodic, diag, ae, an);
-    if (st) return st;
-    if (!(tau >= 0.0)) return ORA_EINVAL;
-    int64_t n = nx * ny;
+/* The method on any operator: Z, D of A ~ (Z D^-1 Z^T)^-1, see above. */
+static int ainv_core(const ora_op *A, double tau, int64_t fill, void **out,
+                     int64_t *nnz_off, int64_t *breakdown_row) {
+    int st = ORA_OK;
+    int64_t n = A->n;
+    int64_t *cols = (int64_t *)malloc((size_t)A->maxrow * sizeof(int64_t));
+    double *vals = (double *)malloc((size_t)A->maxrow * sizeof(double));
     ora_ainv *F = (ora_ainv *)calloc(1, sizeof(ora_ainv));
-    if (!F) return ORA_ENOMEM;
-    F->n = n;
-    F->z = (ora_col *)calloc((size_t)n, sizeof(ora_col));
-    F->D = (double *)malloc((size_t)n * sizeof(double));
     ora_list *rows = (ora_list *)calloc((size_t)n, sizeof(ora_list));
     int64_t *seen = (int64_t *)malloc((size_t)n * sizeof(int64_t));
     int64_t *cand = NULL;
@@ -253,13 +357,15 @@ int ora_ainv_setup_fill(int64_t nx, int64_t ny, int periodic, const double *diag
     int64_t *mr = NULL;
     double *mv = NULL;
     int64_t mcap = 0;
-    if (!F->z || !F->D || !rows || !seen) { st = ORA_ENOMEM; goto done; }
+    if (!F || !cols || !vals || !rows || !seen) { st = ORA_ENOMEM; goto done; }
+    F->n = n;
+    F->z = (ora_col *)calloc((size_t)n, sizeof(ora_col));
+    F->D = (double *)malloc((size_t)n * sizeof(double));
+    if (!F->z || !F->D) { st = ORA_ENOMEM; goto done; }
     for (int64_t j = 0; j < n; j++) seen[j] = -1;
 
     for (int64_t i = 0; i < n; i++) {
-        int64_t cols[5];
-        double vals[5];
-        int m = a_row(nx, ny, periodic, diag, ae, an, i, cols, vals);
+        int m = op_row(A, i, cols, vals);
         ora_col *zi = &F->z[i];
         /* every update of z_i has been applied (only steps < i touch it) */
         if (fill >= 0) {
@@ -380,9 +486,25 @@ done:
     free(cand);
     free(mr);
     free(mv);
+    free(cols);
+    free(vals);
     if (st) { ora_ainv_free(F); return st; }
     *out = F;
     return ORA_OK;
+}
+
+/* Returns ORA_OK and a handle, or ORA_EBREAKDOWN (p_i <= 0) / ORA_EINVAL /
+ * ORA_ENOMEM.  fill < 0: no cap on the entries per column. */
+int ora_ainv_setup_fill(int64_t nx, int64_t ny, int periodic, const double *diag,
+                        const double *ae, const double *an, double tau, int64_t fill,
+                        void **out, int64_t *nnz_off, int64_t *breakdown_row) {
+    *out = NULL;
+    if (breakdown_row) *breakdown_row = -1;
+    int st = check_a5(nx, ny, periodic, diag, ae, an);
+    if (st) return st;
+    if (!(tau >= 0.0)) return ORA_EINVAL;
+    ora_op A = op_a5(nx, ny, periodic, diag, ae, an);
+    return ainv_core(&A, tau, fill, out, nnz_off, breakdown_row);
 }
 
 int ora_ainv_setup(int64_t nx, int64_t ny, int periodic, const double *diag,
@@ -390,6 +512,19 @@ int ora_ainv_setup(int64_t nx, int64_t ny, int periodic, const double *diag,
                    int64_t *nnz_off, int64_t *breakdown_row) {
     return ora_ainv_setup_fill(nx, ny, periodic, diag, ae, an, tau, -1, out, nnz_off,
                                breakdown_row);
+}
+
+/* The same A-orthogonalisation on a CSR matrix (see check_csr). */
+int ora_ainv_setup_csr(int64_t n, const int64_t *rowptr, const int64_t *col,
+                       const double *val, double tau, int64_t fill, void **out,
+                       int64_t *nnz_off, int64_t *breakdown_row) {
+    *out = NULL;
+    if (breakdown_row) *breakdown_row = -1;
+    int st = check_csr(n, rowptr, col, val);
+    if (st) return st;
+    if (!(tau >= 0.0)) return ORA_EINVAL;
+    ora_op A = op_csr(n, rowptr, col, val);
+    return ainv_core(&A, tau, fill, out, nnz_off, breakdown_row);
 }
 
 /* Export Z (strictly upper part) in CSC: colptr[n+1], rowidx/val[nnz_off],
@@ -480,12 +615,11 @@ static double dot(int64_t n, const double *a, const double *b) {
 /*  alphas/betas (optional, capacity maxit): the CG scalars per iteration.    */
 /*  Returns ORA_OK (converged), ORA_NOCONV, ORA_EBREAKDOWN, ORA_ENOMEM.       */
 /* ------------------------------------------------------------------------ */
-int ora_pcg(int64_t nx, int64_t ny, int periodic, const double *diag,
-            const double *ae, const double *an, const int64_t *colptr,
-            const int64_t *rowidx, const double *val, const double *D,
-            const double *b, double *x, double tol, int64_t maxit,
-            int64_t *iters, double *hist, double *alphas, double *betas) {
-    int64_t n = nx * ny;
+static int pcg_core(const ora_op *A, const int64_t *colptr,
+                    const int64_t *rowidx, const double *val, const double *D,
+                    const double *b, double *x, double tol, int64_t maxit,
+                    int64_t *iters, double *hist, double *alphas, double *betas) {
+    int64_t n = A->n;
     double *r = (double *)malloc((size_t)n * sizeof(double));
     double *s = (double *)malloc((size_t)n * sizeof(double));
     double *d = (double *)malloc((size_t)n * sizeof(double));
@@ -501,7 +635,7 @@ int ora_pcg(int64_t nx, int64_t ny, int periodic, const double *diag,
         hist[0] = 0.0;
         goto out;
     }
-    ora_spmv(nx, ny, periodic, diag, ae, an, x, q);
+    op_apply(A, x, q);
     for (int64_t k = 0; k < n; k++) r[k] = b[k] - q[k];
     ora_prec_apply(n, colptr, rowidx, val, D, r, s, tmp);
     for (int64_t k = 0; k < n; k++) d[k] = s[k];
@@ -509,7 +643,7 @@ int ora_pcg(int64_t nx, int64_t ny, int periodic, const double *diag,
     int64_t it = 0;
     hist[0] = sqrt(dot(n, r, r)) / nb;
     while (hist[it] > tol && it < maxit) {
-        ora_spmv(nx, ny, periodic, diag, ae, an, d, q);
+        op_apply(A, d, q);
         double dq = dot(n, d, q);
         if (!(dq > 0.0) || !(rho > 0.0)) { st = ORA_EBREAKDOWN; break; }
         double alpha = rho / dq;
@@ -532,6 +666,24 @@ int ora_pcg(int64_t nx, int64_t ny, int periodic, const double *diag,
 out:
     free(r); free(s); free(d); free(q); free(tmp);
     return st;
+}
+
+int ora_pcg(int64_t nx, int64_t ny, int periodic, const double *diag,
+            const double *ae, const double *an, const int64_t *colptr,
+            const int64_t *rowidx, const double *val, const double *D,
+            const double *b, double *x, double tol, int64_t maxit,
+            int64_t *iters, double *hist, double *alphas, double *betas) {
+    ora_op A = op_a5(nx, ny, periodic, diag, ae, an);
+    return pcg_core(&A, colptr, rowidx, val, D, b, x, tol, maxit, iters, hist, alphas, betas);
+}
+
+/* Algorithm 1 on a CSR matrix (see check_csr; not re-checked here). */
+int ora_pcg_csr(int64_t n, const int64_t *rowptr, const int64_t *col, const double *aval,
+                const int64_t *colptr, const int64_t *rowidx, const double *val,
+                const double *D, const double *b, double *x, double tol, int64_t maxit,
+                int64_t *iters, double *hist, double *alphas, double *betas) {
+    ora_op A = op_csr(n, rowptr, col, aval);
+    return pcg_core(&A, colptr, rowidx, val, D, b, x, tol, maxit, iters, hist, alphas, betas);
 }
 
 /* ------------------------------------------------------------------------ */
