@@ -69,6 +69,20 @@ typedef struct pcga_a5 {
     const double *diag, *ae, *an;  /* host, n = nx*ny each, caller-owned */
 } pcga_a5_t;
 
+/* A general sparse SPD operator in CSR, for matrices that do not come from
+ * the grid (the comparison of Sec. 5 also uses one): n rows; rowptr[n+1]
+ * (rowptr[0] = 0, non-decreasing); col[rowptr[n]] with the columns of each
+ * row strictly ascending; val[rowptr[n]].  The diagonal must be present and
+ * positive, every value finite, and A symmetric entry by entry (A[i,j] ==
+ * A[j,i] bitwise); the calls check this and return PCGA_EINVAL otherwise.
+ * Host arrays, caller-owned.  n <= 2^31 - 1. */
+typedef struct pcga_csr {
+    int64_t n;
+    const int64_t *rowptr;
+    const int32_t *col;
+    const double *val;
+} pcga_csr_t;
+
 typedef struct pcga_ainv pcga_ainv_t;       /* opaque host (Z, D) */
 typedef struct pcga_solver pcga_solver_t;   /* opaque device solver */
 
@@ -117,6 +131,15 @@ int pcga_fsai_band_setup(const pcga_a5_t *A, int32_t q, pcga_ainv_t **out);
 
 /* Sizes of a setup result: n and the number of stored off-diagonal entries
  * of Z (the unit diagonal is implicit). */
+/* pcga_ainv_setup_csr: the same A-orthogonalisation on a CSR operator (the
+ * rows of A in their stored, ascending column order): Z, D with
+ * Z D^-1 Z^T ~ A^-1.  max_fill >= 0 keeps at most that many off-diagonal
+ * entries per column of Z (the fixed-fill class of Sec. 5), < 0 no cap.
+ * Errors: EINVAL (A fails the CSR checks, drop_tol < 0), EBREAKDOWN,
+ * ENOMEM. */
+int pcga_ainv_setup_csr(const pcga_csr_t *A, double drop_tol, int32_t max_fill,
+                        pcga_ainv_t **out);
+
 int pcga_ainv_info(const pcga_ainv_t *F, int64_t *n, int64_t *nnz_off);
 
 /* Export Z (strict upper part) in CSC with rows ascending in each column:
@@ -161,6 +184,23 @@ int pcga_solver_create(const pcga_a5_t *A, const pcga_ainv_t *F, int precision,
                        void *dev_workspace, size_t bytes, void *stream,
                        pcga_solver_t **out);
 int pcga_solver_destroy(pcga_solver_t *S);
+
+/* A solver for a CSR operator (see pcga_csr_t): A is laid out in the same
+ * sliced ELL as Z (its diagonal among the entries, 32-bit columns or
+ * per-slice offset tables), and each iteration's first kernel forms
+ * d = s + beta d at every row it gathers while it computes q = A d.
+ * precision must be PCGA_FP64; slice_width as in pcga_solver_create_ex (0:
+ * default).  The solve calls (pcga_pcg_solve, pcga_pcg_solve_noalloc),
+ * pcga_apply_a, pcga_apply_prec, pcga_profile_iteration, pcga_solver_info,
+ * pcga_solver_tune, pcga_solver_set_grids (g_stencil then sets the operator
+ * kernel's workgroups), pcga_ts_eta and pcga_ts_guess work on it;
+ * pcga_step_stencil, pcga_ts_rhs and batches need the five-point operator
+ * and return PCGA_EINVAL.  Errors as pcga_solver_create. */
+int pcga_workspace_bytes_csr(const pcga_csr_t *A, const pcga_ainv_t *F, int precision,
+                             int32_t slice_width, size_t *bytes);
+int pcga_solver_create_csr(const pcga_csr_t *A, const pcga_ainv_t *F, int precision,
+                           int32_t slice_width, void *ws, size_t bytes, void *stream,
+                           pcga_solver_t **out);
 /* The same with the sliced-ELL target width (1..64; 0: the default, 32 for
  * PCGA_FP64 and 24 for PCGA_MIXED): a slice
  * starts with one lane per row and doubles its lanes per row (halving its

@@ -29,6 +29,11 @@ class A5(ctypes.Structure):
                 ("diag", ctypes.c_void_p), ("ae", ctypes.c_void_p), ("an", ctypes.c_void_p)]
 
 
+class Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("val", ctypes.c_void_p)]
+
+
 _p = ctypes.c_void_p
 _pp = ctypes.POINTER(ctypes.c_void_p)
 _i32 = ctypes.c_int32
@@ -45,6 +50,11 @@ _SIGS = {
     "pcga_ainv_setup": ([ctypes.POINTER(A5), _dbl, _pp], ctypes.c_int),
     "pcga_ainv_setup_fill": ([ctypes.POINTER(A5), _dbl, _i32, _pp], ctypes.c_int),
     "pcga_fsai_band_setup": ([ctypes.POINTER(A5), _i32, _pp], ctypes.c_int),
+    "pcga_ainv_setup_csr": ([ctypes.POINTER(Csr), _dbl, _i32, _pp], ctypes.c_int),
+    "pcga_workspace_bytes_csr": ([ctypes.POINTER(Csr), _p, ctypes.c_int, _i32,
+                                  ctypes.POINTER(_sz)], ctypes.c_int),
+    "pcga_solver_create_csr": ([ctypes.POINTER(Csr), _p, ctypes.c_int, _i32, _p, _sz, _p, _pp],
+                               ctypes.c_int),
     "pcga_ainv_info": ([_p, _pi64, _pi64], ctypes.c_int),
     "pcga_ainv_export": ([_p, _p, _p, _p, _p], ctypes.c_int),
     "pcga_ainv_import": ([_i64, _p, _p, _p, _p, _pp], ctypes.c_int),

@@ -51,6 +51,31 @@ class Stencil5:
                        self.diag.ctypes.data, self.ae.ctypes.data, self.an.ctypes.data)
 
 
+@dataclasses.dataclass
+class CsrMatrix:
+    """General sparse SPD operator in CSR (see pcga_csr_t in include/pcgainv.h):
+    rowptr int64[n+1], col int32[nnz] ascending per row, val float64[nnz]."""
+    n: int
+    rowptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray
+
+    def __post_init__(self):
+        self.rowptr = np.ascontiguousarray(self.rowptr, dtype=np.int64)
+        self.col = np.ascontiguousarray(self.col, dtype=np.int32)
+        self.val = np.ascontiguousarray(self.val, dtype=np.float64)
+        if self.rowptr.shape != (self.n + 1,) or self.col.shape != self.val.shape:
+            raise ValueError("CSR arrays do not match n")
+
+    @classmethod
+    def from_problem(cls, p) -> "CsrMatrix":
+        return cls(int(p.n), p.rowptr, p.col, p.val)
+
+    def c_struct(self) -> _lib.Csr:
+        return _lib.Csr(self.n, self.rowptr.ctypes.data, self.col.ctypes.data,
+                        self.val.ctypes.data)
+
+
 class AInv:
     """Handle to (Z, D) computed on the host."""
 
@@ -122,6 +147,12 @@ def ainv_setup(A: Stencil5, drop_tol: float, fill=None) -> AInv:
     cap."""
     L = _lib.load()
     h = ctypes.c_void_p()
+    if isinstance(A, CsrMatrix):
+        cs = A.c_struct()
+        check(L.pcga_ainv_setup_csr(ctypes.byref(cs), float(drop_tol),
+                                    -1 if fill is None else int(fill), ctypes.byref(h)),
+              "pcga_ainv_setup_csr")
+        return AInv(h)
     a5 = A.c_struct()
     if fill is None:
         check(L.pcga_ainv_setup(ctypes.byref(a5), float(drop_tol), ctypes.byref(h)),
@@ -170,12 +201,38 @@ PROBE_STEP = 4 << 20    # distance between the bases a placement probe tries
 def workspace_size(A: Stencil5, F: AInv, precision: str = "fp64", slice_width: int = 0) -> int:
     """Device bytes a Solver of these settings allocates (workspace plus the
     alignment slack)."""
+    return _workspace_bytes(A, F, {"fp64": FP64, "mixed": MIXED}[precision],
+                            int(slice_width)) + WS_ALIGN
+
+
+def _workspace_bytes(A, F, precision, slice_width):
     L = _lib.load()
     nbytes = ctypes.c_size_t()
-    check(L.pcga_workspace_bytes_ex(ctypes.byref(A.c_struct()), F.handle,
-                                    {"fp64": FP64, "mixed": MIXED}[precision], int(slice_width),
-                                    ctypes.byref(nbytes)), "pcga_workspace_bytes_ex")
-    return nbytes.value + WS_ALIGN
+    cs = A.c_struct()
+    if isinstance(A, CsrMatrix):
+        check(L.pcga_workspace_bytes_csr(ctypes.byref(cs), F.handle, precision, slice_width,
+                                         ctypes.byref(nbytes)), "pcga_workspace_bytes_csr")
+    else:
+        check(L.pcga_workspace_bytes_ex(ctypes.byref(cs), F.handle, precision, slice_width,
+                                        ctypes.byref(nbytes)), "pcga_workspace_bytes_ex")
+    return nbytes.value
+
+
+def _create(A, F, precision, slice_width, ws_ptr, ws_bytes, stream_ptr):
+    L = _lib.load()
+    h = ctypes.c_void_p()
+    cs = A.c_struct()
+    if isinstance(A, CsrMatrix):
+        check(L.pcga_solver_create_csr(ctypes.byref(cs), F.handle, precision, slice_width,
+                                       ctypes.c_void_p(ws_ptr), ws_bytes,
+                                       ctypes.c_void_p(stream_ptr), ctypes.byref(h)),
+              "pcga_solver_create_csr")
+    else:
+        check(L.pcga_solver_create_ex(ctypes.byref(cs), F.handle, precision, slice_width,
+                                      ctypes.c_void_p(ws_ptr), ws_bytes,
+                                      ctypes.c_void_p(stream_ptr), ctypes.byref(h)),
+              "pcga_solver_create_ex")
+    return h
 
 
 class Solver:
@@ -200,12 +257,7 @@ class Solver:
         self.slice_width = int(slice_width)
         self.precision = {"fp64": FP64, "mixed": MIXED}[precision]
         self.device = torch.device("cuda" if device is None else device)
-        a5 = A.c_struct()
-        nbytes = ctypes.c_size_t()
-        check(L.pcga_workspace_bytes_ex(ctypes.byref(a5), F.handle, self.precision,
-                                        self.slice_width, ctypes.byref(nbytes)),
-              "pcga_workspace_bytes_ex")
-        self.workspace_bytes = nbytes.value
+        self.workspace_bytes = _workspace_bytes(A, F, self.precision, self.slice_width)
         with torch.cuda.device(self.device):
             # a stream of its own (default priority): chunks are captured into
             # HIP graphs, which the legacy default stream does not allow
@@ -232,16 +284,12 @@ class Solver:
                                  f"{self.workspace_bytes} from a 16 MiB boundary")
             self.placement_ms = None
             if probes > 1:
-                lead = self._probe(L, a5, F, [lead + k * PROBE_STEP for k in range(probes)])
+                lead = self._probe(L, F, [lead + k * PROBE_STEP for k in range(probes)])
             self.ws = self._ws_buf[lead:lead + self.workspace_bytes]
             self.footprint_bytes = (self._ws_buf.numel() if buffer is None
                                     else self.workspace_bytes + WS_ALIGN)
-            h = ctypes.c_void_p()
-            check(L.pcga_solver_create_ex(ctypes.byref(a5), F.handle, self.precision,
-                                          self.slice_width, ctypes.c_void_p(self.ws.data_ptr()),
-                                          self.workspace_bytes,
-                                          ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
-                  "pcga_solver_create_ex")
+            h = _create(A, F, self.precision, self.slice_width, self.ws.data_ptr(),
+                        self.workspace_bytes, self.stream.cuda_stream)
         self._h = h
         n = ctypes.c_int64()
         nnz = ctypes.c_int64()
@@ -410,21 +458,17 @@ class Solver:
             "pcga_ts_guess"))
         return out
 
-    def _probe(self, L, a5, F, offsets):
+    def _probe(self, L, F, offsets):
         """Build the solver at each offset of the buffer in turn, time one
         whole iteration there, and return the fastest offset."""
         import torch
-        self.n = self.A.nx * self.A.ny
+        self.n = self.A.n
         probe_b = torch.ones(self.n, dtype=torch.float64, device=self.device)
         times = []
         for off in offsets:
-            h = ctypes.c_void_p()
-            check(L.pcga_solver_create_ex(ctypes.byref(a5), F.handle, self.precision,
-                                          self.slice_width,
-                                          ctypes.c_void_p(self._ws_buf.data_ptr() + off),
-                                          self.workspace_bytes,
-                                          ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
-                  "pcga_solver_create_ex")
+            h = _create(self.A, F, self.precision, self.slice_width,
+                        self._ws_buf.data_ptr() + off, self.workspace_bytes,
+                        self.stream.cuda_stream)
             self._h = h
             try:
                 self.profile_iteration(probe_b, reps=3, mode=1)

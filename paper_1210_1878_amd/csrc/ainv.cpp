@@ -21,7 +21,8 @@
 //
 // Candidate steps for column j are kept in a min-heap: a step i can touch
 // z_j only if row i of A has a column where z_j is nonzero, i.e. i is a grid
-// neighbour (or the cell itself) of some entry of z_j.
+// neighbour (or the cell itself) of some entry of z_j; for a general sparse
+// A, a row that shares a column with an entry of z_j.
 
 #include <algorithm>
 #include <cmath>
@@ -73,15 +74,56 @@ int A5View::validate() const {
 
 // Rows of A whose stencil contains column r (A is symmetric, so these are the
 // columns of row r): r itself and its grid neighbours.
-static int stencil_of(const A5View &A, int64_t r, int64_t *out) {
-    const int64_t nx = A.nx, i = r % nx, j = r / nx;
+int A5View::nbrs(int64_t r, int64_t *out) const {
+    const int64_t i = r % nx, j = r / nx;
     int m = 0;
     out[m++] = r;
-    if (i > 0) out[m++] = r - 1; else if (A.periodic) out[m++] = r + nx - 1;
-    if (i < nx - 1) out[m++] = r + 1; else if (A.periodic) out[m++] = r - nx + 1;
+    if (i > 0) out[m++] = r - 1; else if (periodic) out[m++] = r + nx - 1;
+    if (i < nx - 1) out[m++] = r + 1; else if (periodic) out[m++] = r - nx + 1;
     if (j > 0) out[m++] = r - nx;
-    if (j < A.ny - 1) out[m++] = r + nx;
+    if (j < ny - 1) out[m++] = r + nx;
     return m;
+}
+
+int CsrView::row(int64_t k, int64_t *cols, double *vals) const {
+    int m = 0;
+    for (int64_t a = rowptr[k]; a < rowptr[k + 1]; a++, m++) {
+        cols[m] = col[a];
+        vals[m] = val[a];
+    }
+    return m;
+}
+
+int CsrView::nbrs(int64_t r, int64_t *out) const {
+    int m = 0;
+    for (int64_t a = rowptr[r]; a < rowptr[r + 1]; a++) out[m++] = col[a];
+    return m;
+}
+
+int CsrView::validate() {
+    if (nrows < 1 || nrows > (int64_t)INT32_MAX || !rowptr || !col || !val) return PCGA_EINVAL;
+    if (rowptr[0] != 0) return PCGA_EINVAL;
+    longest = 1;
+    for (int64_t k = 0; k < nrows; k++) {
+        if (rowptr[k + 1] < rowptr[k]) return PCGA_EINVAL;
+        longest = std::max<int64_t>(longest, rowptr[k + 1] - rowptr[k]);
+        bool diag = false;
+        for (int64_t a = rowptr[k]; a < rowptr[k + 1]; a++) {
+            const int64_t c = col[a];
+            if (c < 0 || c >= nrows || !std::isfinite(val[a])) return PCGA_EINVAL;
+            if (a > rowptr[k] && c <= col[a - 1]) return PCGA_EINVAL;
+            if (c == k) {
+                if (!(val[a] > 0.0)) return PCGA_EINVAL;
+                diag = true;
+            }
+            // the mirror entry (c, k) with the same value
+            const int32_t *b0 = col + rowptr[c], *b1 = col + rowptr[c + 1];
+            const int32_t *f = std::lower_bound(b0, b1, (int32_t)k);
+            if (f == b1 || *f != k || val[f - col] != val[a]) return PCGA_EINVAL;
+        }
+        if (!diag) return PCGA_EINVAL;
+    }
+    return PCGA_OK;
 }
 
 // Fixed fill (the second Bridson class of Sec. 5: a set number of nonzeros
@@ -107,12 +149,13 @@ static void cap_column(int64_t j, int64_t fill, const std::vector<int64_t> &patt
     for (size_t t = (size_t)fill; t < off.size(); t++) live[off[t]] = -1;
 }
 
-int ainv_build(const A5View &A, double tau, int64_t fill, AinvFactor &F, int64_t *bad_row) {
+// The method on any operator view (rows of A and, by symmetry, the rows that
+// share a column); the view has been validated.
+template <class Op>
+static int ainv_build_impl(const Op &A, double tau, int64_t fill, AinvFactor &F, int64_t *bad_row) {
     if (bad_row) *bad_row = -1;
-    int st = A.validate();
-    if (st) return st;
     if (!(tau >= 0.0)) return PCGA_EINVAL;
-    const int64_t n = (int64_t)A.nx * A.ny;
+    const int64_t n = A.n();
     try {
         F.n = n;
         F.colptr.assign(1, 0);
@@ -128,9 +171,10 @@ int ainv_build(const A5View &A, double tau, int64_t fill, AinvFactor &F, int64_t
         std::priority_queue<int64_t, std::vector<int64_t>, std::greater<int64_t>> steps;
         std::vector<int64_t> off;             // scratch of cap_column
 
-        int64_t cols[5];
-        double vals[5];
-        int64_t nb[5];
+        std::vector<int64_t> colsv(A.maxrow()), nbv(A.maxrow());
+        std::vector<double> valsv(A.maxrow());
+        int64_t *cols = colsv.data(), *nb = nbv.data();
+        double *vals = valsv.data();
 
         for (int64_t j = 0; j < n; j++) {
             pattern.clear();
@@ -138,7 +182,7 @@ int ainv_build(const A5View &A, double tau, int64_t fill, AinvFactor &F, int64_t
             live[j] = j;
             pattern.push_back(j);
             {
-                int m = stencil_of(A, j, nb);
+                int m = A.nbrs(j, nb);
                 for (int t = 0; t < m; t++)
                     if (nb[t] < j && queued[nb[t]] != j) { queued[nb[t]] = j; steps.push(nb[t]); }
             }
@@ -172,7 +216,7 @@ int ainv_build(const A5View &A, double tau, int64_t fill, AinvFactor &F, int64_t
                     if (!had) {
                         live[r] = j;
                         pattern.push_back(r);
-                        int mm = stencil_of(A, r, nb);
+                        int mm = A.nbrs(r, nb);
                         for (int t = 0; t < mm; t++) {
                             const int64_t s = nb[t];
                             if (s > i && s < j && queued[s] != j) { queued[s] = j; steps.push(s); }
@@ -210,6 +254,21 @@ int ainv_build(const A5View &A, double tau, int64_t fill, AinvFactor &F, int64_t
         return PCGA_ENOMEM;
     }
     return PCGA_OK;
+}
+
+int ainv_build(const A5View &A, double tau, int64_t fill, AinvFactor &F, int64_t *bad_row) {
+    if (bad_row) *bad_row = -1;
+    const int st = A.validate();
+    if (st) return st;
+    return ainv_build_impl(A, tau, fill, F, bad_row);
+}
+
+int ainv_build(const CsrView &A, double tau, int64_t fill, AinvFactor &F, int64_t *bad_row) {
+    if (bad_row) *bad_row = -1;
+    CsrView V = A;
+    const int st = V.validate();
+    if (st) return st;
+    return ainv_build_impl(V, tau, fill, F, bad_row);
 }
 
 // The paper's banded factor of T (Sec. 3, six-step pattern scheme).  T keeps

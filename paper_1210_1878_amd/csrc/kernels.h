@@ -350,6 +350,11 @@ __device__ __forceinline__ bool sell_stream(const DevSell<T> &M, int first, int 
 #pragma unroll
         for (int u = 0; u < U; u++) acc = fma(c0 + u < m.width ? zv[u] : T(0), g.fin(gv[u]), acc);
     };
+    // a chunk known to lie inside the slice (no step to mask)
+    auto accumulate_full = [&](const T (&zv)[U], const GR (&gv)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; u++) acc = fma(zv[u], g.fin(gv[u]), acc);
+    };
     // next slice's header, table and own-row operands (prefetched)
     SliceMeta mn{0, 0, 0, -1, 0};
     int tabn = 0;
@@ -367,6 +372,19 @@ __device__ __forceinline__ bool sell_stream(const DevSell<T> &M, int first, int 
     if (!pre()) return false;
     for (int i0 = 0; i0 < nsw;) {
         for (int i = 0; i < cnt; i++) {
+            // Issue priority by progress: a wave that has done less of its
+            // slices gets priority (3 in its first quarter, 0 in its last).
+            // Without it the oldest waves of a CU win issue arbitration and
+            // finish first, and the kernel ends on a tail of the youngest
+            // ones (per-wave timestamps at 1442x1021: ends spread over
+            // 23-39 us; with it 32-38 us, about 2% off an iteration).
+            {
+                const int lvl = 3 - (4 * (i0 + i)) / nsw;
+                if (lvl >= 3) __builtin_amdgcn_s_setprio(3);
+                else if (lvl == 2) __builtin_amdgcn_s_setprio(2);
+                else if (lvl == 1) __builtin_amdgcn_s_setprio(1);
+                else __builtin_amdgcn_s_setprio(0);
+            }
             const SliceMeta m = mn;
             const int tabv = tabn;
             const Own own = ownn;
@@ -377,27 +395,34 @@ __device__ __forceinline__ bool sell_stream(const DevSell<T> &M, int first, int 
                 GR ga[U], gb[U];
                 load_vals(m, 0, za);
                 gather_tab(m, tabv, rowc, 0, ga);
-                // the last chunk is summed on its own exit path, so that a chunk
-                // summed inside the loop has the next chunk's loads issued on
-                // every path that reaches it
+                // Chunks alternate between the buffers a and b; every chunk is
+                // summed with the next chunk's loads already issued.  The loop
+                // has a fixed trip count and no exit in its body, so that its
+                // head is reached with the same loads in flight (chunk a) on
+                // every path, and the waits before each sum are exact.
+                // (the scheduling barriers keep each chunk's loads ahead of the
+                // previous chunk's sum)
+                const int nch = (m.width + U - 1) / U;
                 int c0 = 0;
-                for (;;) {
-                    if (c0 + U >= m.width) {
-                        accumulate(m, c0, za, ga);
-                        break;
-                    }
+                for (int k = 2; k < nch; k += 2) {
                     load_vals(m, c0 + U, zb);
                     gather_tab(m, tabv, rowc, c0 + U, gb);
+                    __builtin_amdgcn_sched_barrier(0);
+                    accumulate_full(za, ga);
+                    load_vals(m, c0 + 2 * U, za);
+                    gather_tab(m, tabv, rowc, c0 + 2 * U, ga);
+                    __builtin_amdgcn_sched_barrier(0);
+                    accumulate_full(zb, gb);
+                    c0 += 2 * U;
+                }
+                if (c0 + U < m.width) {
+                    load_vals(m, c0 + U, zb);
+                    gather_tab(m, tabv, rowc, c0 + U, gb);
+                    __builtin_amdgcn_sched_barrier(0);
+                    accumulate_full(za, ga);
+                    accumulate(m, c0 + U, zb, gb);
+                } else {
                     accumulate(m, c0, za, ga);
-                    c0 += U;
-                    if (c0 + U >= m.width) {
-                        accumulate(m, c0, zb, gb);
-                        break;
-                    }
-                    load_vals(m, c0 + U, za);
-                    gather_tab(m, tabv, rowc, c0 + U, ga);
-                    accumulate(m, c0, zb, gb);
-                    c0 += U;
                 }
             } else {
                 for (int c0 = 0; c0 < m.width; c0 += U) {
@@ -693,6 +718,130 @@ __global__ __launch_bounds__(kBS) void k_z(DevSell<T> Z, const T *__restrict__ t
     if (DOT) {
         double pv[1] = {sr};
         put_partials<1>(pv, P.sr, L);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// General sparse A (a CSR matrix from outside the grid, as in the comparison
+// of Sec. 5), stored in the sliced-ELL layout with its diagonal among the
+// entries (32-bit columns, or per-slice offset tables).
+//
+// k_spmv_sell: the five-point kernel's step on such an operator:
+// rho_k = sum of (s,r) partials, beta = rho_k / rho_{k-1};
+// d_new = s + beta d_old on the wave's rows and, recomputed, at every gathered
+// column; q = A d_new; (d_new, q) partials.
+// ---------------------------------------------------------------------------
+template <int FMT>
+__global__ __launch_bounds__(kBS) void k_spmv_sell(DevSell<double> A, const double *__restrict__ s,
+                                                   const double *__restrict__ dold,
+                                                   double *__restrict__ dnew, double *__restrict__ q,
+                                                   CtlBlock *cb, Partials P, int g_sr, int par) {
+    Ctl *c = &cb->c;
+    if (c->done) return;
+    const PartialsLoad<1> pl = load_partials<1>(P.sr, g_sr);
+    const int G = gridDim.x, L = logical_block(blockIdx.x, G);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
+    const int v = L * kWavesPerBlock + w;
+    const int s0 = A.bounds[v], s1 = A.bounds[v + 1];
+    double bt = 0.0, dq = 0.0;
+    // gathered d_new = s + beta d_old: loaded raw, combined when summed
+    struct GS {
+        double s, d;
+    };
+    struct {
+        const double *ss, *dd;
+        const double *pb;
+        __device__ GS operator()(int kk) const { return GS{ss[kk], dd[kk]}; }
+        __device__ double fin(const GS &g) const { return fma(*pb, g.d, g.s); }
+    } g{s, dold, &bt};
+    struct OwnA {
+        double sk, dk;
+    };
+    auto ownf = [&](const SliceMeta &m) {
+        const int row = m.row0 + (lane >> m.lg);
+        const int rw = row < A.nrows ? row : A.nrows - 1;
+        return OwnA{s[rw], dold[rw]};
+    };
+    auto epi = [&](const SliceMeta &m, double acc, const OwnA &o) {
+        for (int sh = (1 << m.lg) >> 1; sh > 0; sh >>= 1) acc += __shfl_xor(acc, sh, kWave);
+        const int row = m.row0 + (lane >> m.lg);
+        if ((lane & ((1 << m.lg) - 1)) == 0 && row < A.nrows) {
+            const double dn = fma(bt, o.dk, o.sk);
+            dnew[row] = dn;
+            q[row] = acc;
+            dq += dn * acc;
+        }
+    };
+    auto pre = [&]() {
+        double rs[1];
+        reduce_partials<1>(pl, g_sr, rs);
+        const double rho = rs[0];
+        if (!finite_pos(rho)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                c->status = is_bad(rho) ? kStNan : kStBreak;
+                c->done = 1;
+            }
+            return false;
+        }
+        const int k = c->kk[par];
+        bt = (k == 0) ? 0.0 : rho / c->rho[par ^ 1];
+        if (blockIdx.x == 0 && threadIdx.x == 0) c->rho[par] = rho;
+        return true;
+    };
+    if (!sell_stream<double, PipeUnroll<double, false>::U, FMT, false>(A, s0, s1 - s0, lane, g, ownf,
+                                                                        epi, pre))
+        return;
+    double pv[1] = {dq};
+    put_partials<1>(pv, P.dq, L);
+}
+
+// r = b - A x over a sliced-ELL operator (WRITE: store r), with ||b||^2 and
+// ||r||^2 partials in P.res, as k_residual for the five-point operator.
+// APPLY: y = A x into r instead (b not read, no partials).
+template <bool WRITE, bool APPLY>
+__global__ __launch_bounds__(kBS) void k_residual_sell(DevSell<double> A,
+                                                       const double *__restrict__ x,
+                                                       const double *__restrict__ b,
+                                                       double *__restrict__ r, Partials P) {
+    const int G = gridDim.x, L = logical_block(blockIdx.x, G);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int v = L * kWavesPerBlock + w;
+    const int s0 = A.bounds[v], s1 = A.bounds[v + 1];
+    double bb = 0.0, rr = 0.0;
+    struct {
+        const double *xx;
+        __device__ double operator()(int kk) const { return xx[kk]; }
+        __device__ double fin(double t) const { return t; }
+    } g{x};
+    struct OwnR {
+        double bk;
+    };
+    auto ownf = [&](const SliceMeta &m) {
+        const int row = m.row0 + (lane >> m.lg);
+        const int rw = row < A.nrows ? row : A.nrows - 1;
+        return OwnR{APPLY ? 0.0 : b[rw]};
+    };
+    auto epi = [&](const SliceMeta &m, double acc, const OwnR &o) {
+        for (int sh = (1 << m.lg) >> 1; sh > 0; sh >>= 1) acc += __shfl_xor(acc, sh, kWave);
+        const int row = m.row0 + (lane >> m.lg);
+        if ((lane & ((1 << m.lg) - 1)) == 0 && row < A.nrows) {
+            if (APPLY) {
+                r[row] = acc;
+            } else {
+                const double rk = o.bk - acc;
+                if (WRITE) r[row] = rk;
+                bb += o.bk * o.bk;
+                rr += rk * rk;
+            }
+        }
+    };
+    sell_stream<double, PipeUnroll<double, false>::U, 0, false>(A, s0, s1 - s0, lane, g, ownf, epi,
+                                                                 []() { return true; });
+    if (!APPLY) {
+        double pv[2] = {bb, rr};
+        put_partials<2>(pv, P.res, L);
     }
 }
 

@@ -16,8 +16,28 @@ struct A5View {
     const double *diag = nullptr, *ae = nullptr, *an = nullptr;
 
     int64_t n() const { return nx * ny; }
+    int64_t maxrow() const { return 5; }
     int row(int64_t k, int64_t *cols, double *vals) const;
+    // rows of A with an entry in column r (by symmetry, the columns of row r)
+    int nbrs(int64_t r, int64_t *out) const;
     int validate() const;
+};
+
+// Read-only view of a general sparse SPD operator in CSR (see pcgainv.h):
+// rows with strictly ascending columns, the diagonal present and positive,
+// symmetric entry by entry.
+struct CsrView {
+    int64_t nrows = 0;
+    const int64_t *rowptr = nullptr;
+    const int32_t *col = nullptr;
+    const double *val = nullptr;
+    int64_t longest = 1;   // set by validate()
+
+    int64_t n() const { return nrows; }
+    int64_t maxrow() const { return longest; }
+    int row(int64_t k, int64_t *cols, double *vals) const;
+    int nbrs(int64_t r, int64_t *out) const;
+    int validate();
 };
 
 // Unit upper triangular Z (strict upper part in CSC, rows ascending) and D.
@@ -32,6 +52,7 @@ struct AinvFactor {
 
 // fill < 0: no cap on the off-diagonal entries per column
 int ainv_build(const A5View &A, double tau, int64_t fill, AinvFactor &F, int64_t *bad_row);
+int ainv_build(const CsrView &A, double tau, int64_t fill, AinvFactor &F, int64_t *bad_row);
 int fsai_band_build(const A5View &A, int64_t q, AinvFactor &F, int64_t *bad_row);
 
 // Sliced ELL with a per-slice number of lanes per row ("SELL-L").

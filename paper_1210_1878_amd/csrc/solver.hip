@@ -88,6 +88,7 @@ struct Carver {
 
 struct HostLayouts {
     SellLayout zt, z;
+    SellLayout a;   // a general sparse A (CSR input); empty for the five-point operator
 };
 
 int build_layouts(const AinvFactor &F, int target_width, HostLayouts &H) {
@@ -134,9 +135,11 @@ size_t carve(pcga_solver &S, void *base, const HostLayouts &H) {
     Carver C(base);
     const int64_t n = S.n;
     const bool f64 = S.precision == PCGA_FP64;
-    S.A64.diag = C.take<double>(n);
-    S.A64.ae = C.take<double>(n);
-    S.A64.an = C.take<double>(n);
+    if (!S.csr) {
+        S.A64.diag = C.take<double>(n);
+        S.A64.ae = C.take<double>(n);
+        S.A64.an = C.take<double>(n);
+    }
     auto sell = [&](const SellLayout &L, auto &dst, auto tag) {
         using T = decltype(tag);
         dst.row0 = C.take<int32_t>(L.nslices());
@@ -155,6 +158,10 @@ size_t carve(pcga_solver &S, void *base, const HostLayouts &H) {
         dst.nslices = (int32_t)L.nslices();
         dst.nrows = (int32_t)L.nrows_total;
     };
+    if (S.csr) {
+        sell(H.a, S.a64, double());
+        S.bnd_a = C.take<int32_t>(kWavesPerBlock * kMaxBlocks + 1);
+    }
     if (S.band_q > 0) {
         if (f64)
             S.zb64 = C.take<double>((size_t)S.band_q * n);
@@ -278,7 +285,8 @@ void cache_plan(pcga_solver &S, const HostLayouts &H) {
     const double ib = H.zt.narrow ? 2.0 : 4.0;
     const double ezt = (double)H.zt.entries(), ez = (double)H.z.entries();
     const double streams[4] = {w * ezt, w * ez, ib * ezt, ib * ez};   // kept in this order
-    double used = (9.0 * w + 24.0) * (double)S.n;
+    const double op_bytes = S.csr ? 12.0 * (double)H.a.entries() : 24.0 * (double)S.n;
+    double used = 9.0 * w * (double)S.n + op_bytes;
     int kept = 0;
     while (kept < 4 && used + streams[kept] <= kResidentBudget) used += streams[kept++];
     // streams not kept: Z idx (kept < 4), Z^T idx (< 3), Z val (< 2), Z^T val (< 1)
@@ -297,6 +305,11 @@ int upload_bounds(pcga_solver &S) {
     if (e == hipSuccess) e = hipMemcpyAsync(S.bnd_z, b.data(), b.size() * 4, hipMemcpyHostToDevice, S.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(S.bnd_zt_b, bzb.data(), bzb.size() * 4, hipMemcpyHostToDevice, S.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(S.bnd_z_b, bb.data(), bb.size() * 4, hipMemcpyHostToDevice, S.stream);
+    std::vector<int32_t> ba;
+    if (S.csr) {
+        ba = balanced_bounds(S.cost_a, S.g_a * kWavesPerBlock);
+        if (e == hipSuccess) e = hipMemcpyAsync(S.bnd_a, ba.data(), ba.size() * 4, hipMemcpyHostToDevice, S.stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(S.stream);
     if (e != hipSuccess) return fail(PCGA_EHIP, std::string("bounds upload: ") + hipGetErrorString(e));
     return PCGA_OK;
@@ -307,6 +320,275 @@ int upload_bounds(pcga_solver &S) {
 // ===========================================================================
 // C ABI
 // ===========================================================================
+// Width q of Z's band (largest j - i over stored entries Z[i, j]) when it is
+// at most kMaxBand, else 0 (also 0 for Z = I).
+static int band_width(const AinvFactor &F) {
+    int64_t q = 0;
+    for (int64_t j = 0; j < F.n; j++)
+        for (int64_t a = F.colptr[j]; a < F.colptr[j + 1]; a++) {
+            q = std::max<int64_t>(q, j - F.rowidx[a]);
+            if (q > kMaxBand) return 0;
+        }
+    return (int)q;
+}
+
+// Z by diagonals: zb[(m-1) n + j] = Z[j-m, j], m = 1..q (0 where not stored).
+static std::vector<double> band_diagonals(const AinvFactor &F, int q) {
+    std::vector<double> zb((size_t)q * F.n, 0.0);
+    for (int64_t j = 0; j < F.n; j++)
+        for (int64_t a = F.colptr[j]; a < F.colptr[j + 1]; a++)
+            zb[(size_t)(j - F.rowidx[a] - 1) * F.n + j] = F.val[a];
+    return zb;
+}
+
+namespace {
+
+// The operator a solver is built for: the five-point A5 arrays, or a general
+// sparse SPD matrix in CSR.
+struct OpDesc {
+    const pcga_a5_t *a5 = nullptr;
+    CsrView csr;
+    bool is_csr() const { return csr.rowptr != nullptr; }
+    int64_t n() const { return is_csr() ? csr.nrows : (int64_t)a5->nx * a5->ny; }
+    int set_csr(const pcga_csr_t *A) {
+        if (!A) return fail(PCGA_EINVAL, "A is NULL");
+        csr.nrows = A->n;
+        csr.rowptr = A->rowptr;
+        csr.col = A->col;
+        csr.val = A->val;
+        if (csr.validate() != PCGA_OK) {
+            csr.rowptr = nullptr;
+            return fail(PCGA_EINVAL,
+                        "CSR A: needs n >= 1, rowptr[0] = 0 and monotone, columns strictly "
+                        "ascending in each row, a positive diagonal, finite values and "
+                        "A[i,j] == A[j,i]");
+        }
+        return PCGA_OK;
+    }
+    int check() const { return is_csr() ? PCGA_OK : check_a5(a5); }
+};
+
+// Host layouts and the size-determining fields of S for (operator, F).
+int prepare(const OpDesc &D, const pcga_ainv_t *F, int precision, int slice_width,
+            HostLayouts &H, pcga_solver &S) {
+    if (!F) return fail(PCGA_EINVAL, "NULL argument");
+    if (slice_width == 0) slice_width = default_width(precision);
+    if (slice_width < 1 || slice_width > kMaxSliceWidth)
+        return fail(PCGA_EINVAL, "slice_width must be 0 or 1.." + std::to_string(kMaxSliceWidth));
+    int st = D.check();
+    if (st) return st;
+    if (precision != PCGA_FP64 && precision != PCGA_MIXED)
+        return fail(PCGA_EINVAL, "precision must be PCGA_FP64 or PCGA_MIXED");
+    if (D.is_csr() && precision != PCGA_FP64)
+        return fail(PCGA_EINVAL, "a CSR operator is solved in PCGA_FP64");
+    if (F->F.n != D.n()) return fail(PCGA_EINVAL, "F does not match A");
+    st = build_layouts(F->F, slice_width, H);
+    if (st) return st;
+    if (D.is_csr()) {
+        try {
+            sell_build(D.csr.nrows, D.csr.rowptr, D.csr.col, D.csr.val, slice_width, H.a);
+        } catch (const std::bad_alloc &) {
+            return fail(PCGA_ENOMEM, "host allocation failed while building the layout of A");
+        }
+        if (!sell_check(H.a)) return fail(PCGA_EINVAL, "internal: layout of A violates its invariants");
+    }
+    S.precision = precision;
+    S.n = F->F.n;
+    S.csr = D.is_csr();
+    S.band_q = band_width(F->F);
+    return PCGA_OK;
+}
+
+int workspace_bytes_impl(const OpDesc &D, const pcga_ainv_t *F, int precision, int32_t slice_width,
+                         size_t *bytes) {
+    if (!bytes) return fail(PCGA_EINVAL, "NULL argument");
+    HostLayouts H;
+    pcga_solver S;
+    int st = prepare(D, F, precision, slice_width, H, S);
+    if (st) return st;
+    *bytes = carve(S, nullptr, H);
+    return PCGA_OK;
+}
+
+int create_impl(const OpDesc &D, const pcga_ainv_t *F, int precision, int32_t slice_width,
+                void *ws, size_t bytes, void *stream, pcga_solver_t **out) {
+    if (!out) return fail(PCGA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!F || !ws) return fail(PCGA_EINVAL, "NULL F or workspace");
+    if (((uintptr_t)ws & 255u) != 0) return fail(PCGA_EINVAL, "workspace must be 256-byte aligned");
+    HostLayouts H;
+    pcga_solver *S = new (std::nothrow) pcga_solver;
+    if (!S) return fail(PCGA_ENOMEM, "host allocation failed");
+    int st = prepare(D, F, precision, slice_width, H, *S);
+    if (st) {
+        delete S;
+        return st;
+    }
+    const int64_t n = S->n;
+    S->max_blocks = precision == PCGA_MIXED ? kDefaultBlocksMixed : kDefaultBlocks;
+    S->nnz_off = F->F.nnz_off();
+    // the two-launch diagonal path fuses the five-point product; a CSR
+    // operator runs the general three-launch iteration also for Z = I
+    S->jacobi = S->nnz_off == 0 && !S->csr;
+    if (S->csr) {
+        S->nnz_a = D.csr.rowptr[D.csr.nrows];
+    } else {
+        S->nx = D.a5->nx;
+        S->ny = D.a5->ny;
+        S->periodic = (D.a5->flags & PCGA_PERIODIC_X) ? 1 : 0;
+    }
+    S->stream = (hipStream_t)stream;
+    const size_t need = carve(*S, nullptr, H);
+    if (bytes < need) {
+        delete S;
+        return fail(PCGA_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+    }
+    S->ws = ws;
+    S->ws_bytes = bytes;
+    carve(*S, ws, H);
+    if (!S->csr) {
+        S->A64.nx = D.a5->nx;
+        S->A64.ny = D.a5->ny;
+        S->A64.periodic = S->periodic;
+        S->A64.n = (int32_t)n;
+        S->A64.inv_nx = 1.0 / (double)D.a5->nx;
+    }
+    S->sell_entries = H.zt.entries() + H.z.entries();
+
+    auto fail_free = [&](int code) {
+        if (S->snap[0]) (void)hipHostFree(S->snap[0]);
+        if (S->snap[1]) (void)hipHostFree(S->snap[1]);
+        if (S->ev[0]) (void)hipEventDestroy(S->ev[0]);
+        if (S->ev[1]) (void)hipEventDestroy(S->ev[1]);
+        delete S;
+        return code;
+    };
+#define CR(expr)                                                                               \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail_free(fail(PCGA_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_))); \
+    } while (0)
+
+    CR(hipGetDevice(&S->device));
+    CR(hipHostMalloc((void **)&S->snap[0], sizeof(CtlBlock), hipHostMallocDefault));
+    CR(hipHostMalloc((void **)&S->snap[1], sizeof(CtlBlock), hipHostMallocDefault));
+    CR(hipEventCreateWithFlags(&S->ev[0], hipEventDisableTiming));
+    CR(hipEventCreateWithFlags(&S->ev[1], hipEventDisableTiming));
+
+    hipStream_t sm = S->stream;
+    const size_t nb8 = n * sizeof(double);
+    // operator (FP64 always; FP32 copy for the mixed inner solve)
+    if (!S->csr) {
+        CR(hipMemcpyAsync((void *)S->A64.diag, D.a5->diag, nb8, hipMemcpyHostToDevice, sm));
+        CR(hipMemcpyAsync((void *)S->A64.ae, D.a5->ae, nb8, hipMemcpyHostToDevice, sm));
+        CR(hipMemcpyAsync((void *)S->A64.an, D.a5->an, nb8, hipMemcpyHostToDevice, sm));
+    }
+    std::vector<double> dinv(n);
+    for (int64_t k = 0; k < n; k++) dinv[k] = 1.0 / F->F.D[k];
+    auto up_sell = [&](const SellLayout &L, auto &dst) -> hipError_t {
+        using T = std::remove_const_t<std::remove_pointer_t<decltype(dst.val)>>;
+        hipError_t e;
+        e = hipMemcpyAsync((void *)dst.row0, L.row0.data(), L.row0.size() * 4, hipMemcpyHostToDevice, sm);
+        if (e) return e;
+        e = hipMemcpyAsync((void *)dst.meta, L.meta.data(), L.meta.size() * 4, hipMemcpyHostToDevice, sm);
+        if (e) return e;
+        e = hipMemcpyAsync((void *)dst.off, L.off.data(), L.off.size() * 8, hipMemcpyHostToDevice, sm);
+        if (e) return e;
+        if (!L.toff.empty()) {
+            e = hipMemcpyAsync((void *)dst.toff, L.toff.data(), L.toff.size() * 4,
+                               hipMemcpyHostToDevice, sm);
+            if (e) return e;
+        }
+        if (!L.tab.empty()) {
+            e = hipMemcpyAsync((void *)dst.tab, L.tab.data(), L.tab.size() * 4,
+                               hipMemcpyHostToDevice, sm);
+            if (e) return e;
+        }
+        if (L.entries() == 0) return hipSuccess;
+        if (L.narrow)
+            e = hipMemcpyAsync((void *)dst.dist, L.dist.data(), L.dist.size() * 2, hipMemcpyHostToDevice, sm);
+        else
+            e = hipMemcpyAsync((void *)dst.idx, L.idx.data(), L.idx.size() * 4, hipMemcpyHostToDevice, sm);
+        if (e) return e;
+        if constexpr (std::is_same_v<T, double>) {
+            return hipMemcpyAsync((void *)dst.val, L.val.data(), L.val.size() * 8,
+                                  hipMemcpyHostToDevice, sm);
+        } else {
+            std::vector<float> v32(L.val.begin(), L.val.end());
+            e = hipMemcpyAsync((void *)dst.val, v32.data(), v32.size() * 4, hipMemcpyHostToDevice, sm);
+            if (e) return e;
+            return hipStreamSynchronize(sm);   // v32 is a temporary
+        }
+    };
+    if (S->band_q > 0) {
+        const std::vector<double> zb = band_diagonals(F->F, S->band_q);
+        if (precision == PCGA_FP64) {
+            CR(hipMemcpyAsync(S->zb64, zb.data(), zb.size() * 8, hipMemcpyHostToDevice, sm));
+        } else {
+            const std::vector<float> zf(zb.begin(), zb.end());
+            CR(hipMemcpyAsync(S->zb32, zf.data(), zf.size() * 4, hipMemcpyHostToDevice, sm));
+        }
+        CR(hipStreamSynchronize(sm));   // zb / zf are temporaries
+    }
+    if (S->csr) CR(up_sell(H.a, S->a64));
+    if (precision == PCGA_FP64) {
+        CR(hipMemcpyAsync(S->dinv64, dinv.data(), nb8, hipMemcpyHostToDevice, sm));
+        CR(up_sell(H.zt, S->zt64));
+        CR(up_sell(H.z, S->z64));
+    } else {
+        std::vector<float> f(n);
+        for (int64_t k = 0; k < n; k++) f[k] = (float)dinv[k];
+        CR(hipMemcpyAsync(S->dinv32, f.data(), n * 4, hipMemcpyHostToDevice, sm));
+        CR(hipStreamSynchronize(sm));
+        CR(up_sell(H.zt, S->zt32));
+        CR(up_sell(H.z, S->z32));
+    }
+    CR(hipMemsetAsync(S->cb, 0, sizeof(CtlBlock), sm));
+    CR(hipStreamSynchronize(sm));
+#undef CR
+    S->cost_zt = slice_costs(H.zt);
+    S->cost_z = slice_costs(H.z);
+    if (S->csr) {
+        S->cost_a = slice_costs(H.a);
+        S->a64.bounds = S->bnd_a;
+    }
+    S->zt64.bounds = S->zt32.bounds = S->bnd_zt;
+    S->z64.bounds = S->z32.bounds = S->bnd_z;
+    S->zt64.bounds_b = S->zt32.bounds_b = S->bnd_zt_b;
+    S->z64.bounds_b = S->z32.bounds_b = S->bnd_z_b;
+    S->grids();
+    st = upload_bounds(*S);
+    if (st) {
+        pcga_solver_destroy(S);
+        return st;
+    }
+    // modelled compulsory bytes per iteration (see kernels.h):
+    //   stencil: s, d_old read; d_new, q written       4 n words + FP64 diag, ae, an
+    //   zt: r, q, d, x, dinv read; r', x, t written; Z^T entries     8 n words + E_zt
+    //   z:  t, r' read; s written; Z entries                         3 n words + E_z
+    //   (an entry: its value and a 4-byte column or 2-byte distance)
+    const double E = (double)S->sell_entries;
+    S->index_bytes = H.zt.narrow ? 2 : 4;
+    cache_plan(*S, H);
+    //   (the stencil reads the FP64 coefficients diag, ae, an also for the
+    //   FP32 inner iteration: 24 n bytes)
+    //   (a CSR operator: s, d_old read, d_new, q written and A's entries, a
+    //   value and a 4-byte column each, instead of the five-point kernel's
+    //   7 n words)
+    if (S->csr)
+        S->bytes_per_iter = 8.0 * 15.0 * n + 12.0 * (double)S->nnz_a + (8.0 + S->index_bytes) * E;
+    else if (precision == PCGA_FP64)
+        S->bytes_per_iter = 8.0 * 18.0 * n + (8.0 + S->index_bytes) * E;
+    else
+        S->bytes_per_iter = 4.0 * 15.0 * n + 24.0 * n + (4.0 + S->index_bytes) * E;
+    *out = S;
+    return PCGA_OK;
+}
+
+
+}  // namespace
+
 extern "C" {
 
 const char *pcga_strerror(int s) {
@@ -462,27 +744,6 @@ int pcga_layout_info(const pcga_ainv_t *F, int32_t slice_width, int64_t *out) {
     return PCGA_OK;
 }
 
-// Width q of Z's band (largest j - i over stored entries Z[i, j]) when it is
-// at most kMaxBand, else 0 (also 0 for Z = I).
-static int band_width(const AinvFactor &F) {
-    int64_t q = 0;
-    for (int64_t j = 0; j < F.n; j++)
-        for (int64_t a = F.colptr[j]; a < F.colptr[j + 1]; a++) {
-            q = std::max<int64_t>(q, j - F.rowidx[a]);
-            if (q > kMaxBand) return 0;
-        }
-    return (int)q;
-}
-
-// Z by diagonals: zb[(m-1) n + j] = Z[j-m, j], m = 1..q (0 where not stored).
-static std::vector<double> band_diagonals(const AinvFactor &F, int q) {
-    std::vector<double> zb((size_t)q * F.n, 0.0);
-    for (int64_t j = 0; j < F.n; j++)
-        for (int64_t a = F.colptr[j]; a < F.colptr[j + 1]; a++)
-            zb[(size_t)(j - F.rowidx[a] - 1) * F.n + j] = F.val[a];
-    return zb;
-}
-
 int pcga_workspace_bytes(const pcga_a5_t *A, const pcga_ainv_t *F, int precision,
                          size_t *bytes) {
     return pcga_workspace_bytes_ex(A, F, precision, 0, bytes);
@@ -495,190 +756,57 @@ int pcga_solver_create(const pcga_a5_t *A, const pcga_ainv_t *F, int precision, 
 
 int pcga_workspace_bytes_ex(const pcga_a5_t *A, const pcga_ainv_t *F, int precision,
                             int32_t slice_width, size_t *bytes) {
-    if (!bytes || !F) return fail(PCGA_EINVAL, "NULL argument");
-    if (slice_width == 0) slice_width = default_width(precision);
-    if (slice_width < 1 || slice_width > kMaxSliceWidth)
-        return fail(PCGA_EINVAL, "slice_width must be 0 or 1.." + std::to_string(kMaxSliceWidth));
-    int st = check_a5(A);
+    OpDesc D;
+    D.a5 = A;
+    return workspace_bytes_impl(D, F, precision, slice_width, bytes);
+}
+
+int pcga_workspace_bytes_csr(const pcga_csr_t *A, const pcga_ainv_t *F, int precision,
+                             int32_t slice_width, size_t *bytes) {
+    OpDesc D;
+    int st = D.set_csr(A);
     if (st) return st;
-    if (precision != PCGA_FP64 && precision != PCGA_MIXED)
-        return fail(PCGA_EINVAL, "precision must be PCGA_FP64 or PCGA_MIXED");
-    if (F->F.n != (int64_t)A->nx * A->ny) return fail(PCGA_EINVAL, "F does not match A");
-    HostLayouts H;
-    st = build_layouts(F->F, slice_width, H);
-    if (st) return st;
-    pcga_solver S;
-    S.precision = precision;
-    S.n = F->F.n;
-    S.band_q = band_width(F->F);
-    *bytes = carve(S, nullptr, H);
-    return PCGA_OK;
+    return workspace_bytes_impl(D, F, precision, slice_width, bytes);
 }
 
 int pcga_solver_create_ex(const pcga_a5_t *A, const pcga_ainv_t *F, int precision,
                           int32_t slice_width, void *ws, size_t bytes, void *stream,
                           pcga_solver_t **out) {
+    OpDesc D;
+    D.a5 = A;
+    return create_impl(D, F, precision, slice_width, ws, bytes, stream, out);
+}
+
+int pcga_ainv_setup_csr(const pcga_csr_t *A, double drop_tol, int32_t max_fill,
+                        pcga_ainv_t **out) {
     if (!out) return fail(PCGA_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!F || !ws) return fail(PCGA_EINVAL, "NULL F or workspace");
-    if (slice_width == 0) slice_width = default_width(precision);
-    if (slice_width < 1 || slice_width > kMaxSliceWidth)
-        return fail(PCGA_EINVAL, "slice_width must be 0 or 1.." + std::to_string(kMaxSliceWidth));
-    int st = check_a5(A);
+    OpDesc D;
+    int st = D.set_csr(A);
     if (st) return st;
-    if (precision != PCGA_FP64 && precision != PCGA_MIXED)
-        return fail(PCGA_EINVAL, "precision must be PCGA_FP64 or PCGA_MIXED");
-    const int64_t n = (int64_t)A->nx * A->ny;
-    if (F->F.n != n) return fail(PCGA_EINVAL, "F does not match A");
-    if (((uintptr_t)ws & 255u) != 0) return fail(PCGA_EINVAL, "workspace must be 256-byte aligned");
-
-    HostLayouts H;
-    st = build_layouts(F->F, slice_width, H);
-    if (st) return st;
-    pcga_solver *S = new (std::nothrow) pcga_solver;
-    if (!S) return fail(PCGA_ENOMEM, "host allocation failed");
-    S->precision = precision;
-    S->max_blocks = precision == PCGA_MIXED ? kDefaultBlocksMixed : kDefaultBlocks;
-    S->n = n;
-    S->nnz_off = F->F.nnz_off();
-    S->jacobi = S->nnz_off == 0;
-    S->band_q = band_width(F->F);
-    S->nx = A->nx;
-    S->ny = A->ny;
-    S->periodic = (A->flags & PCGA_PERIODIC_X) ? 1 : 0;
-    S->stream = (hipStream_t)stream;
-    const size_t need = carve(*S, nullptr, H);
-    if (bytes < need) {
-        delete S;
-        return fail(PCGA_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
-    }
-    S->ws = ws;
-    S->ws_bytes = bytes;
-    carve(*S, ws, H);
-    S->A64.nx = A->nx;
-    S->A64.ny = A->ny;
-    S->A64.periodic = S->periodic;
-    S->A64.n = (int32_t)n;
-    S->A64.inv_nx = 1.0 / (double)A->nx;
-    S->sell_entries = H.zt.entries() + H.z.entries();
-
-    auto fail_free = [&](int code) {
-        if (S->snap[0]) (void)hipHostFree(S->snap[0]);
-        if (S->snap[1]) (void)hipHostFree(S->snap[1]);
-        if (S->ev[0]) (void)hipEventDestroy(S->ev[0]);
-        if (S->ev[1]) (void)hipEventDestroy(S->ev[1]);
-        delete S;
-        return code;
-    };
-#define CR(expr)                                                                               \
-    do {                                                                                       \
-        hipError_t e_ = (expr);                                                                \
-        if (e_ != hipSuccess)                                                                  \
-            return fail_free(fail(PCGA_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_))); \
-    } while (0)
-
-    CR(hipGetDevice(&S->device));
-    CR(hipHostMalloc((void **)&S->snap[0], sizeof(CtlBlock), hipHostMallocDefault));
-    CR(hipHostMalloc((void **)&S->snap[1], sizeof(CtlBlock), hipHostMallocDefault));
-    CR(hipEventCreateWithFlags(&S->ev[0], hipEventDisableTiming));
-    CR(hipEventCreateWithFlags(&S->ev[1], hipEventDisableTiming));
-
-    hipStream_t sm = S->stream;
-    const size_t nb8 = n * sizeof(double);
-    // operator (FP64 always; FP32 copy for the mixed inner solve)
-    CR(hipMemcpyAsync((void *)S->A64.diag, A->diag, nb8, hipMemcpyHostToDevice, sm));
-    CR(hipMemcpyAsync((void *)S->A64.ae, A->ae, nb8, hipMemcpyHostToDevice, sm));
-    CR(hipMemcpyAsync((void *)S->A64.an, A->an, nb8, hipMemcpyHostToDevice, sm));
-    std::vector<double> dinv(n);
-    for (int64_t k = 0; k < n; k++) dinv[k] = 1.0 / F->F.D[k];
-    auto up_sell = [&](const SellLayout &L, auto &dst) -> hipError_t {
-        using T = std::remove_const_t<std::remove_pointer_t<decltype(dst.val)>>;
-        hipError_t e;
-        e = hipMemcpyAsync((void *)dst.row0, L.row0.data(), L.row0.size() * 4, hipMemcpyHostToDevice, sm);
-        if (e) return e;
-        e = hipMemcpyAsync((void *)dst.meta, L.meta.data(), L.meta.size() * 4, hipMemcpyHostToDevice, sm);
-        if (e) return e;
-        e = hipMemcpyAsync((void *)dst.off, L.off.data(), L.off.size() * 8, hipMemcpyHostToDevice, sm);
-        if (e) return e;
-        if (!L.toff.empty()) {
-            e = hipMemcpyAsync((void *)dst.toff, L.toff.data(), L.toff.size() * 4,
-                               hipMemcpyHostToDevice, sm);
-            if (e) return e;
-        }
-        if (!L.tab.empty()) {
-            e = hipMemcpyAsync((void *)dst.tab, L.tab.data(), L.tab.size() * 4,
-                               hipMemcpyHostToDevice, sm);
-            if (e) return e;
-        }
-        if (L.entries() == 0) return hipSuccess;
-        if (L.narrow)
-            e = hipMemcpyAsync((void *)dst.dist, L.dist.data(), L.dist.size() * 2, hipMemcpyHostToDevice, sm);
-        else
-            e = hipMemcpyAsync((void *)dst.idx, L.idx.data(), L.idx.size() * 4, hipMemcpyHostToDevice, sm);
-        if (e) return e;
-        if constexpr (std::is_same_v<T, double>) {
-            return hipMemcpyAsync((void *)dst.val, L.val.data(), L.val.size() * 8,
-                                  hipMemcpyHostToDevice, sm);
-        } else {
-            std::vector<float> v32(L.val.begin(), L.val.end());
-            e = hipMemcpyAsync((void *)dst.val, v32.data(), v32.size() * 4, hipMemcpyHostToDevice, sm);
-            if (e) return e;
-            return hipStreamSynchronize(sm);   // v32 is a temporary
-        }
-    };
-    if (S->band_q > 0) {
-        const std::vector<double> zb = band_diagonals(F->F, S->band_q);
-        if (precision == PCGA_FP64) {
-            CR(hipMemcpyAsync(S->zb64, zb.data(), zb.size() * 8, hipMemcpyHostToDevice, sm));
-        } else {
-            const std::vector<float> zf(zb.begin(), zb.end());
-            CR(hipMemcpyAsync(S->zb32, zf.data(), zf.size() * 4, hipMemcpyHostToDevice, sm));
-        }
-        CR(hipStreamSynchronize(sm));   // zb / zf are temporaries
-    }
-    if (precision == PCGA_FP64) {
-        CR(hipMemcpyAsync(S->dinv64, dinv.data(), nb8, hipMemcpyHostToDevice, sm));
-        CR(up_sell(H.zt, S->zt64));
-        CR(up_sell(H.z, S->z64));
-    } else {
-        std::vector<float> f(n);
-        for (int64_t k = 0; k < n; k++) f[k] = (float)dinv[k];
-        CR(hipMemcpyAsync(S->dinv32, f.data(), n * 4, hipMemcpyHostToDevice, sm));
-        CR(hipStreamSynchronize(sm));
-        CR(up_sell(H.zt, S->zt32));
-        CR(up_sell(H.z, S->z32));
-    }
-    CR(hipMemsetAsync(S->cb, 0, sizeof(CtlBlock), sm));
-    CR(hipStreamSynchronize(sm));
-#undef CR
-    S->cost_zt = slice_costs(H.zt);
-    S->cost_z = slice_costs(H.z);
-    S->zt64.bounds = S->zt32.bounds = S->bnd_zt;
-    S->z64.bounds = S->z32.bounds = S->bnd_z;
-    S->zt64.bounds_b = S->zt32.bounds_b = S->bnd_zt_b;
-    S->z64.bounds_b = S->z32.bounds_b = S->bnd_z_b;
-    S->grids();
-    st = upload_bounds(*S);
+    if (!(drop_tol >= 0.0)) return fail(PCGA_EINVAL, "drop_tol must be >= 0 (inf allowed)");
+    pcga_ainv *h = new (std::nothrow) pcga_ainv;
+    if (!h) return fail(PCGA_ENOMEM, "host allocation failed");
+    int64_t bad = -1;
+    st = ainv_build(D.csr, drop_tol, max_fill < 0 ? -1 : (int64_t)max_fill, h->F, &bad);
     if (st) {
-        pcga_solver_destroy(S);
-        return st;
+        delete h;
+        if (st == PCGA_EBREAKDOWN)
+            return fail(st, "AINV breakdown: pivot p_i <= 0 at row " + std::to_string(bad));
+        return fail(st, "AINV setup failed");
     }
-    // modelled compulsory bytes per iteration (see kernels.h):
-    //   stencil: s, d_old read; d_new, q written       4 n words + FP64 diag, ae, an
-    //   zt: r, q, d, x, dinv read; r', x, t written; Z^T entries     8 n words + E_zt
-    //   z:  t, r' read; s written; Z entries                         3 n words + E_z
-    //   (an entry: its value and a 4-byte column or 2-byte distance)
-    const double E = (double)S->sell_entries;
-    S->index_bytes = H.zt.narrow ? 2 : 4;
-    cache_plan(*S, H);
-    //   (the stencil reads the FP64 coefficients diag, ae, an also for the
-    //   FP32 inner iteration: 24 n bytes)
-    if (precision == PCGA_FP64)
-        S->bytes_per_iter = 8.0 * 18.0 * n + (8.0 + S->index_bytes) * E;
-    else
-        S->bytes_per_iter = 4.0 * 15.0 * n + 24.0 * n + (4.0 + S->index_bytes) * E;
-    *out = S;
+    *out = h;
     return PCGA_OK;
+}
+
+int pcga_solver_create_csr(const pcga_csr_t *A, const pcga_ainv_t *F, int precision,
+                           int32_t slice_width, void *ws, size_t bytes, void *stream,
+                           pcga_solver_t **out) {
+    if (out) *out = nullptr;
+    OpDesc D;
+    int st = D.set_csr(A);
+    if (st) return st;
+    return create_impl(D, F, precision, slice_width, ws, bytes, stream, out);
 }
 
 int pcga_solver_destroy(pcga_solver_t *S) {
@@ -799,7 +927,11 @@ template <typename T>
 void launch_kernel(pcga_solver &S, const IterBufs<T> &B, int p, int which) {
     switch (which) {
         case 0:
-            if (S.jacobi)
+            if (S.csr)
+                k_spmv_sell<0><<<S.g_a, kBS, 0, S.stream>>>(S.a64, (const double *)B.s,
+                                                            (const double *)B.d[p], (double *)B.d[p ^ 1],
+                                                            (double *)B.q, B.cb, B.P, S.g_prec(), p);
+            else if (S.jacobi)
                 k_stencil<T, true><<<S.g_st, kBS, 0, S.stream>>>(B.A, B.s, B.d[p], B.d[p ^ 1], B.q,
                                                                  B.cb, B.P, S.g_st, p);
             else
@@ -816,11 +948,11 @@ void launch_kernel(pcga_solver &S, const IterBufs<T> &B, int p, int which) {
             if (S.band_q > 0) {
                 k_zt_band<T, true><<<S.g_st, kBS, 0, S.stream>>>(
                     B.zb, S.band_q, B.dinv, B.r[p], B.q, B.d[p ^ 1], B.r[p ^ 1], B.x, B.t, (int)S.n,
-                    B.cb, B.P, S.g_st, p);
+                    B.cb, B.P, S.g_op(), p);
                 break;
             }
             launch_zt<T, true>(B.zt, S.fmt_zt, S.g_zt, S.stream, B.dinv, (const T *)B.r[p], (const T *)B.q,
-                               (const T *)B.d[p ^ 1], B.r[p ^ 1], B.x, B.t, B.cb, B.P, S.g_st, p);
+                               (const T *)B.d[p ^ 1], B.r[p ^ 1], B.x, B.t, B.cb, B.P, S.g_op(), p);
             break;
         default:
             if (S.band_q > 0) {
@@ -843,14 +975,20 @@ void launch_iters(pcga_solver &S, const IterBufs<T> &B, int count) {
 // r0 = b - A x0 (FP64) and the solve's control state.
 void launch_residual_prologue(pcga_solver &S, CtlBlock *cb, const Partials &P, const double *x,
                               const double *b, double *r, double tol, int maxit) {
-    k_residual<true><<<S.g_st, kBS, 0, S.stream>>>(S.A64, x, b, r, P);
-    k_fin_residual<0><<<1, kBS, 0, S.stream>>>(cb, P, S.g_st, tol, maxit);
+    if (S.csr)
+        k_residual_sell<true, false><<<S.g_a, kBS, 0, S.stream>>>(S.a64, x, b, r, P);
+    else
+        k_residual<true><<<S.g_st, kBS, 0, S.stream>>>(S.A64, x, b, r, P);
+    k_fin_residual<0><<<1, kBS, 0, S.stream>>>(cb, P, S.g_op(), tol, maxit);
 }
 
 void launch_true_residual(pcga_solver &S, CtlBlock *cb, const Partials &P, const double *x,
                           const double *b) {
-    k_residual<false><<<S.g_st, kBS, 0, S.stream>>>(S.A64, x, b, nullptr, P);
-    k_fin_residual<1><<<1, kBS, 0, S.stream>>>(cb, P, S.g_st, 0.0, 0);
+    if (S.csr)
+        k_residual_sell<false, false><<<S.g_a, kBS, 0, S.stream>>>(S.a64, x, b, nullptr, P);
+    else
+        k_residual<false><<<S.g_st, kBS, 0, S.stream>>>(S.A64, x, b, nullptr, P);
+    k_fin_residual<1><<<1, kBS, 0, S.stream>>>(cb, P, S.g_op(), 0.0, 0);
 }
 
 void launch_refine(pcga_solver &S, bool add_e, const double *x, double *xnew, const double *b,
@@ -1205,7 +1343,10 @@ int pcga_apply_a(pcga_solver_t *S, const double *x_dev, double *y_dev) {
     if (!S || !x_dev || !y_dev) return fail(PCGA_EINVAL, "NULL argument");
     HIP_TRY(hipSetDevice(S->device));
     const int g = (int)std::min<int64_t>(4096, (S->n + kBS - 1) / kBS);
-    k_apply_a<<<g, kBS, 0, S->stream>>>(S->A64, x_dev, y_dev);
+    if (S->csr)
+        k_residual_sell<false, true><<<S->g_a, kBS, 0, S->stream>>>(S->a64, x_dev, nullptr, y_dev, S->P);
+    else
+        k_apply_a<<<g, kBS, 0, S->stream>>>(S->A64, x_dev, y_dev);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(S->stream));
     return PCGA_OK;
@@ -1257,6 +1398,7 @@ int pcga_step_stencil(pcga_solver_t *S, const double *s_dev, const double *d_dev
     if (!S || !s_dev || !d_dev || !dnew_dev || !q_dev || !dq)
         return fail(PCGA_EINVAL, "NULL argument");
     if (!(beta >= 0.0) || std::isinf(beta)) return fail(PCGA_EINVAL, "beta must be finite and >= 0");
+    if (S->csr) return fail(PCGA_EINVAL, "pcga_step_stencil needs a five-point solver");
     HIP_TRY(hipSetDevice(S->device));
     pcga_solver &R = *S;
     const int gc = (int)std::min<int64_t>(4096, (R.n + kBS - 1) / kBS);

@@ -21,6 +21,14 @@ struct pcga_solver {
     size_t ws_bytes = 0;
 
     pcga::DevOp<double> A64{};
+    // General sparse A (pcga_solver_create_csr): stored in sliced ELL, applied
+    // by k_spmv_sell / k_residual_sell with g_a workgroups; A64 is unused
+    bool csr = false;
+    int64_t nnz_a = 0;
+    pcga::DevSell<double> a64{};
+    int32_t *bnd_a = nullptr;
+    std::vector<int32_t> cost_a;
+    int g_a = 1;
     pcga::DevSell<double> zt64{}, z64{};
     pcga::DevSell<float> zt32{}, z32{};
     double *dinv64 = nullptr;
@@ -79,5 +87,10 @@ struct pcga_solver {
         const int nsr = precision == PCGA_FP64 ? z64.nslices : z32.nslices;
         g_zt = std::max(1, std::min((nsz + pcga::kWavesPerBlock - 1) / pcga::kWavesPerBlock, cap(1)));
         g_z = std::max(1, std::min((nsr + pcga::kWavesPerBlock - 1) / pcga::kWavesPerBlock, cap(2)));
+        g_a = std::max(1, std::min((a64.nslices + pcga::kWavesPerBlock - 1) / pcga::kWavesPerBlock,
+                                   cap(0)));
     }
+    // workgroups of the operator kernels (their partial sums are read by the
+    // next kernel): the five-point kernels, or the sliced-ELL sweep of a CSR A
+    int g_op() const { return csr ? g_a : g_st; }
 };

@@ -97,6 +97,7 @@ extern "C" {
 int pcga_ts_rhs(pcga_solver_t *S, const double *e2u, const double *mu, const double *e1v,
                 const double *mv, double *b) {
     if (!S || !e2u || !mu || !e1v || !mv || !b) return fail(PCGA_EINVAL, "NULL argument");
+    if (S->csr) return fail(PCGA_EINVAL, "pcga_ts_rhs needs a five-point (grid) solver");
     if (hipSetDevice(S->device) != hipSuccess) return fail(PCGA_EHIP, "hipSetDevice failed");
     k_ts_rhs<<<ts_grid(S->n), kTsBlock, 0, S->stream>>>(S->nx, S->ny, S->periodic, e2u, mu, e1v,
                                                          mv, b);
