@@ -62,6 +62,10 @@ extern "C" {
 #define PCGA_MIXED 1        /* FP32 inner PCG (Z, D^-1, vectors; the FP64     */
                             /* operator applied to FP32 vectors), FP64        */
                             /* scalars, residual, solution and refinement     */
+#define PCGA_MIXED_A32 2    /* as PCGA_MIXED with the inner operator in FP32  */
+                            /* too (coefficients rounded, q = A d summed in   */
+                            /* FP32): every inner datum FP32; FP64 kept for   */
+                            /* the residual, the solution and alpha/beta      */
 
 typedef struct pcga_a5 {
     int32_t nx, ny;

@@ -125,6 +125,10 @@ def _declare(L):
                                 _p, _dbl, _dbl, _i64, _i64, ctypes.POINTER(_i64),
                                 ctypes.POINTER(_i64), _p]
     L.ora_pcg_mixed.restype = _int
+    L.ora_pcg_mixed_ex.argtypes = L.ora_pcg_mixed.argtypes + [_int]
+    L.ora_pcg_mixed_ex.restype = _int
+    L.ora_spmv32.argtypes = [_i64, _i64, _int, _p, _p, _p, _p, _p, _int]
+    L.ora_spmv32.restype = None
     L.ora_fsai_band.argtypes = [_i64, _i64, _int, _p, _p, _p, _i64, _p, _p]
     L.ora_fsai_band.restype = _int
     L.ora_ts_rhs.argtypes = [_i64, _i64, _int, _p, _p, _p, _p, _p]
@@ -317,9 +321,20 @@ class MixedResult:
         self.status = status
 
 
+def spmv32(p, x, a32=False):
+    """q = A d of the mixed form's inner solve on float32 x: FP64 coefficients
+    summed in FP64 and rounded (a32 False), or coefficients and sums in FP32."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.empty_like(x)
+    lib().ora_spmv32(p.nx, p.ny, int(p.periodic), _ptr(_f64(p.diag)), _ptr(_f64(p.ae)),
+                     _ptr(_f64(p.an)), _ptr(x), _ptr(y), int(bool(a32)))
+    return y
+
+
 def pcg_mixed(p, F: AInv, b=None, x0=None, tol=1e-10, inner_tol=1e-5, max_outer=30,
-              inner_maxit=None) -> MixedResult:
-    """FP64 refinement around an FP32 inner PCG (FP64 scalars)."""
+              inner_maxit=None, a32=False) -> MixedResult:
+    """FP64 refinement around an FP32 inner PCG (FP64 scalars).  a32: the
+    inner operator in FP32 as well (coefficients rounded, sums in FP32)."""
     n = p.nx * p.ny
     b = _f64(p.b if b is None else b)
     x = np.zeros(n) if x0 is None else _f64(x0).copy()
@@ -327,11 +342,11 @@ def pcg_mixed(p, F: AInv, b=None, x0=None, tol=1e-10, inner_tol=1e-5, max_outer=
     hist = np.zeros(max_outer + 1)
     o = ctypes.c_int64()
     tot = ctypes.c_int64()
-    st = lib().ora_pcg_mixed(p.nx, p.ny, int(p.periodic), _ptr(_f64(p.diag)),
+    st = lib().ora_pcg_mixed_ex(p.nx, p.ny, int(p.periodic), _ptr(_f64(p.diag)),
                              _ptr(_f64(p.ae)), _ptr(_f64(p.an)), _ptr(F.colptr),
                              _ptr(F.rowidx), _ptr(F.val), _ptr(F.D), _ptr(b), _ptr(x),
                              float(tol), float(inner_tol), int(max_outer), inner_maxit,
-                             ctypes.byref(o), ctypes.byref(tot), _ptr(hist))
+                             ctypes.byref(o), ctypes.byref(tot), _ptr(hist), int(bool(a32)))
     if st < 0:
         raise OracleError(st)
     return MixedResult(x, o.value, tot.value, hist[: o.value + 1].copy(), st)

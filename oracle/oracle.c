@@ -695,15 +695,28 @@ int ora_pcg_csr(int64_t n, const int64_t *rowptr, const int64_t *col, const doub
 /*          sums the FP64 coefficients times the FP32 d in FP64 and rounds   */
 /*          q to float (rounded coefficients would cap each outer step's     */
 /*          reduction on fine grids).                                         */
+/*   a32 != 0: the operator too in FP32 for the inner solve (its            */
+/*          coefficients rounded to float, q = A d summed in float): every   */
+/*          inner datum in FP32, FP64 kept for the residual, the solution    */
+/*          and the CG scalars.                                              */
 /* outer_hist[o] = ||b - A x_o||/||b|| (capacity max_outer+1).               */
 /* ------------------------------------------------------------------------ */
 static void spmv32(int64_t nx, int64_t ny, int periodic, const double *diag,
-                   const double *ae, const double *an, const float *x, float *y) {
+                   const double *ae, const double *an, const float *x, float *y, int a32) {
     int64_t n = nx * ny;
     int64_t cols[5];
     double vals[5];
     for (int64_t k = 0; k < n; k++) {
         int m = a_row(nx, ny, periodic, diag, ae, an, k, cols, vals);
+        if (a32) {
+            float s = 0.0f;
+            for (int t = 0; t < m; t++) {
+                float p = (float)vals[t] * x[cols[t]];
+                s = s + p;
+            }
+            y[k] = s;
+            continue;
+        }
         double s = 0.0;
         for (int t = 0; t < m; t++) {
             double p = vals[t] * (double)x[cols[t]];
@@ -741,12 +754,12 @@ static void prec32(int64_t n, const int64_t *colptr, const int64_t *rowidx,
     }
 }
 
-int ora_pcg_mixed(int64_t nx, int64_t ny, int periodic, const double *diag,
-                  const double *ae, const double *an, const int64_t *colptr,
-                  const int64_t *rowidx, const double *val, const double *D,
-                  const double *b, double *x, double tol, double inner_tol,
-                  int64_t max_outer, int64_t inner_maxit, int64_t *outer,
-                  int64_t *inner_total, double *outer_hist) {
+int ora_pcg_mixed_ex(int64_t nx, int64_t ny, int periodic, const double *diag,
+                     const double *ae, const double *an, const int64_t *colptr,
+                     const int64_t *rowidx, const double *val, const double *D,
+                     const double *b, double *x, double tol, double inner_tol,
+                     int64_t max_outer, int64_t inner_maxit, int64_t *outer,
+                     int64_t *inner_total, double *outer_hist, int a32) {
     int64_t n = nx * ny;
     int64_t nnz = colptr[n];
     double *r64 = (double *)malloc((size_t)n * sizeof(double));
@@ -792,7 +805,7 @@ int ora_pcg_mixed(int64_t nx, int64_t ny, int periodic, const double *diag,
         double rel = 1.0;
         int64_t it = 0;
         while (rel > inner_tol && it < inner_maxit) {
-            spmv32(nx, ny, periodic, diag, ae, an, d, q);
+            spmv32(nx, ny, periodic, diag, ae, an, d, q, a32);
             double dq = dot32(n, d, q);
             if (!(dq > 0.0) || !(rho > 0.0)) { st = ORA_EBREAKDOWN; goto out; }
             double alpha = rho / dq;
@@ -819,6 +832,22 @@ out:
     free(r64); free(y64); free(val32); free(D32); free(e); free(r); free(s);
     free(d); free(q); free(t);
     return st;
+}
+
+int ora_pcg_mixed(int64_t nx, int64_t ny, int periodic, const double *diag,
+                  const double *ae, const double *an, const int64_t *colptr,
+                  const int64_t *rowidx, const double *val, const double *D,
+                  const double *b, double *x, double tol, double inner_tol,
+                  int64_t max_outer, int64_t inner_maxit, int64_t *outer,
+                  int64_t *inner_total, double *outer_hist) {
+    return ora_pcg_mixed_ex(nx, ny, periodic, diag, ae, an, colptr, rowidx, val, D, b, x, tol,
+                            inner_tol, max_outer, inner_maxit, outer, inner_total, outer_hist, 0);
+}
+
+/* y = A x in the inner precision of the mixed solve (a32 as above), for pins. */
+void ora_spmv32(int64_t nx, int64_t ny, int periodic, const double *diag, const double *ae,
+                const double *an, const float *x, float *y, int a32) {
+    spmv32(nx, ny, periodic, diag, ae, an, x, y, a32);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libpcgainv.so")
 
 OK, NOCONV, EINVAL, EBREAKDOWN, ENAN, EHIP, ENOMEM = 0, 1, -1, -2, -3, -4, -5
 PERIODIC_X = 1
-FP64, MIXED = 0, 1
+FP64, MIXED, MIXED_A32 = 0, 1, 2
 NOALLOC_MAX_BYTES = 64 << 20   # PCGA_NOALLOC_MAX_BYTES
 
 

@@ -17,7 +17,9 @@ import dataclasses
 import numpy as np
 
 from . import _lib
-from ._lib import FP64, MIXED, PERIODIC_X, check
+from ._lib import FP64, MIXED, MIXED_A32, PERIODIC_X, check
+
+_PRECISIONS = {"fp64": FP64, "mixed": MIXED, "mixed_a32": MIXED_A32}
 
 
 @dataclasses.dataclass
@@ -201,7 +203,7 @@ PROBE_STEP = 4 << 20    # distance between the bases a placement probe tries
 def workspace_size(A: Stencil5, F: AInv, precision: str = "fp64", slice_width: int = 0) -> int:
     """Device bytes a Solver of these settings allocates (workspace plus the
     alignment slack)."""
-    return _workspace_bytes(A, F, {"fp64": FP64, "mixed": MIXED}[precision],
+    return _workspace_bytes(A, F, _PRECISIONS[precision],
                             int(slice_width)) + WS_ALIGN
 
 
@@ -255,7 +257,7 @@ class Solver:
         L = _lib.load()
         self.A = A
         self.slice_width = int(slice_width)
-        self.precision = {"fp64": FP64, "mixed": MIXED}[precision]
+        self.precision = _PRECISIONS[precision]
         self.device = torch.device("cuda" if device is None else device)
         self.workspace_bytes = _workspace_bytes(A, F, self.precision, self.slice_width)
         with torch.cuda.device(self.device):

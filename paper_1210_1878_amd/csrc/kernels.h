@@ -497,8 +497,10 @@ __device__ __forceinline__ bool stop_test(CtlBlock *cb, double rr, int k) {
 // ---------------------------------------------------------------------------
 // STOP (diagonal preconditioner path, two launches per iteration): the stop
 // test on ||r_k|| from the previous k_jacobi's partials runs here first.
-template <typename T, bool STOP>
-__global__ __launch_bounds__(kBS) void k_stencil(DevOp<double> A, const T *__restrict__ s,
+// C: type of the coefficients and of the product's arithmetic (double also
+// for FP32 vectors; float for the mixed form with an FP32 operator).
+template <typename T, bool STOP, typename C = double>
+__global__ __launch_bounds__(kBS) void k_stencil(DevOp<C> A, const T *__restrict__ s,
                                                  const T *__restrict__ dold,
                                                  T *__restrict__ dnew, T *__restrict__ q,
                                                  CtlBlock *cb, Partials P, int g_sr, int par) {
@@ -510,7 +512,7 @@ __global__ __launch_bounds__(kBS) void k_stencil(DevOp<double> A, const T *__res
     // before any arithmetic (branch-free neighbour indices, clamped cells).
     struct Step {
         T sv[kCPT][5], dv[kCPT][5];
-        Nbr<double> m[kCPT];
+        Nbr<C> m[kCPT];
         int kc[kCPT];
     };
     int c0, c1;
@@ -561,10 +563,9 @@ __global__ __launch_bounds__(kBS) void k_stencil(DevOp<double> A, const T *__res
                 T v[5];
 #pragma unroll
                 for (int e = 0; e < 5; e++) v[e] = fma(bt, st.dv[u][e], st.sv[u][e]);
-                // the operator is applied in FP64 (exact coefficients) also to
-                // FP32 vectors; q is rounded to T
-                const T y = (T)apply_row(st.m[u], (double)v[0], (double)v[1], (double)v[2],
-                                         (double)v[3], (double)v[4]);
+                // the operator is applied in C (FP64, exact coefficients, also
+                // to FP32 vectors; or all FP32); q is rounded to T
+                const T y = (T)apply_row(st.m[u], (C)v[0], (C)v[1], (C)v[2], (C)v[3], (C)v[4]);
                 dnew[st.kc[u]] = v[2];
                 q[st.kc[u]] = y;
                 acc += (double)v[2] * (double)y;

@@ -18,6 +18,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.h"
@@ -140,6 +141,11 @@ size_t carve(pcga_solver &S, void *base, const HostLayouts &H) {
         S.A64.ae = C.take<double>(n);
         S.A64.an = C.take<double>(n);
     }
+    if (S.precision == PCGA_MIXED_A32) {
+        S.A32.diag = C.take<float>(n);
+        S.A32.ae = C.take<float>(n);
+        S.A32.an = C.take<float>(n);
+    }
     auto sell = [&](const SellLayout &L, auto &dst, auto tag) {
         using T = decltype(tag);
         dst.row0 = C.take<int32_t>(L.nslices());
@@ -235,7 +241,7 @@ int check_a5(const pcga_a5_t *A) {
 // 16; mixed inner: 51.5 us at 24 against 52.3 at 16).
 constexpr int kTargetWidth = 32, kTargetWidthMixed = 24;
 constexpr int kMaxSliceWidth = 64;
-int default_width(int precision) { return precision == PCGA_MIXED ? kTargetWidthMixed : kTargetWidth; }
+int default_width(int precision) { return precision != PCGA_FP64 ? kTargetWidthMixed : kTargetWidth; }
 
 // Per-slice work estimate, in units of about 10 ns of one wavefront's time:
 // a fixed part (headers, own-row operands, the pipeline's drain at the end of
@@ -377,8 +383,8 @@ int prepare(const OpDesc &D, const pcga_ainv_t *F, int precision, int slice_widt
         return fail(PCGA_EINVAL, "slice_width must be 0 or 1.." + std::to_string(kMaxSliceWidth));
     int st = D.check();
     if (st) return st;
-    if (precision != PCGA_FP64 && precision != PCGA_MIXED)
-        return fail(PCGA_EINVAL, "precision must be PCGA_FP64 or PCGA_MIXED");
+    if (precision != PCGA_FP64 && precision != PCGA_MIXED && precision != PCGA_MIXED_A32)
+        return fail(PCGA_EINVAL, "precision must be PCGA_FP64, PCGA_MIXED or PCGA_MIXED_A32");
     if (D.is_csr() && precision != PCGA_FP64)
         return fail(PCGA_EINVAL, "a CSR operator is solved in PCGA_FP64");
     if (F->F.n != D.n()) return fail(PCGA_EINVAL, "F does not match A");
@@ -425,7 +431,7 @@ int create_impl(const OpDesc &D, const pcga_ainv_t *F, int precision, int32_t sl
         return st;
     }
     const int64_t n = S->n;
-    S->max_blocks = precision == PCGA_MIXED ? kDefaultBlocksMixed : kDefaultBlocks;
+    S->max_blocks = precision != PCGA_FP64 ? kDefaultBlocksMixed : kDefaultBlocks;
     S->nnz_off = F->F.nnz_off();
     // the two-launch diagonal path fuses the five-point product; a CSR
     // operator runs the general three-launch iteration also for Z = I
@@ -452,6 +458,11 @@ int create_impl(const OpDesc &D, const pcga_ainv_t *F, int precision, int32_t sl
         S->A64.periodic = S->periodic;
         S->A64.n = (int32_t)n;
         S->A64.inv_nx = 1.0 / (double)D.a5->nx;
+        S->A32.nx = S->A64.nx;
+        S->A32.ny = S->A64.ny;
+        S->A32.periodic = S->A64.periodic;
+        S->A32.n = S->A64.n;
+        S->A32.inv_nx = S->A64.inv_nx;
     }
     S->sell_entries = H.zt.entries() + H.z.entries();
 
@@ -483,6 +494,15 @@ int create_impl(const OpDesc &D, const pcga_ainv_t *F, int precision, int32_t sl
         CR(hipMemcpyAsync((void *)S->A64.diag, D.a5->diag, nb8, hipMemcpyHostToDevice, sm));
         CR(hipMemcpyAsync((void *)S->A64.ae, D.a5->ae, nb8, hipMemcpyHostToDevice, sm));
         CR(hipMemcpyAsync((void *)S->A64.an, D.a5->an, nb8, hipMemcpyHostToDevice, sm));
+    }
+    if (precision == PCGA_MIXED_A32) {
+        const double *src[3] = {D.a5->diag, D.a5->ae, D.a5->an};
+        const float *dst[3] = {S->A32.diag, S->A32.ae, S->A32.an};
+        for (int a = 0; a < 3; a++) {
+            std::vector<float> f(src[a], src[a] + n);
+            CR(hipMemcpyAsync((void *)dst[a], f.data(), n * 4, hipMemcpyHostToDevice, sm));
+            CR(hipStreamSynchronize(sm));   // f is a temporary
+        }
     }
     std::vector<double> dinv(n);
     for (int64_t k = 0; k < n; k++) dinv[k] = 1.0 / F->F.D[k];
@@ -580,6 +600,8 @@ int create_impl(const OpDesc &D, const pcga_ainv_t *F, int precision, int32_t sl
         S->bytes_per_iter = 8.0 * 15.0 * n + 12.0 * (double)S->nnz_a + (8.0 + S->index_bytes) * E;
     else if (precision == PCGA_FP64)
         S->bytes_per_iter = 8.0 * 18.0 * n + (8.0 + S->index_bytes) * E;
+    else if (precision == PCGA_MIXED_A32)
+        S->bytes_per_iter = 4.0 * 15.0 * n + 12.0 * n + (4.0 + S->index_bytes) * E;
     else
         S->bytes_per_iter = 4.0 * 15.0 * n + 24.0 * n + (4.0 + S->index_bytes) * E;
     *out = S;
@@ -840,7 +862,7 @@ int pcga_solver_tune(pcga_solver_t *S, int32_t chunk, int32_t use_graph, int32_t
     if (!S) return fail(PCGA_EINVAL, "S is NULL");
     if (chunk < 2 || chunk > 512 || (chunk & 1))
         return fail(PCGA_EINVAL, "chunk must be even, 2..512");
-    if (max_blocks == 0) max_blocks = S->precision == PCGA_MIXED ? kDefaultBlocksMixed : kDefaultBlocks;
+    if (max_blocks == 0) max_blocks = S->precision != PCGA_FP64 ? kDefaultBlocksMixed : kDefaultBlocks;
     if (max_blocks < 8 || max_blocks > kMaxBlocks)
         return fail(PCGA_EINVAL, "max_blocks must be 0 or 8.." + std::to_string(kMaxBlocks));
     if (S->graph && (chunk != S->graph_chunk || max_blocks != S->max_blocks)) {
@@ -922,6 +944,12 @@ void launch_z(const DevSell<T> &M, int fmt, int grid, hipStream_t st, Args... ar
 }
 #undef PCGA_FMT_CASES
 
+// The FP32 inner iteration of a PCGA_MIXED_A32 solver applies the FP32 operator.
+template <typename T>
+bool a32_inner(const pcga_solver &S) {
+    return std::is_same_v<T, float> && S.precision == PCGA_MIXED_A32;
+}
+
 // One kernel of iteration parity p: 0 stencil, 1 axpy + Z^T, 2 Z + dot.
 template <typename T>
 void launch_kernel(pcga_solver &S, const IterBufs<T> &B, int p, int which) {
@@ -931,7 +959,16 @@ void launch_kernel(pcga_solver &S, const IterBufs<T> &B, int p, int which) {
                 k_spmv_sell<0><<<S.g_a, kBS, 0, S.stream>>>(S.a64, (const double *)B.s,
                                                             (const double *)B.d[p], (double *)B.d[p ^ 1],
                                                             (double *)B.q, B.cb, B.P, S.g_prec(), p);
-            else if (S.jacobi)
+            else if (a32_inner<T>(S)) {
+                if constexpr (std::is_same_v<T, float>) {
+                    if (S.jacobi)
+                        k_stencil<T, true, float><<<S.g_st, kBS, 0, S.stream>>>(
+                            S.A32, B.s, B.d[p], B.d[p ^ 1], B.q, B.cb, B.P, S.g_st, p);
+                    else
+                        k_stencil<T, false, float><<<S.g_st, kBS, 0, S.stream>>>(
+                            S.A32, B.s, B.d[p], B.d[p ^ 1], B.q, B.cb, B.P, S.g_prec(), p);
+                }
+            } else if (S.jacobi)
                 k_stencil<T, true><<<S.g_st, kBS, 0, S.stream>>>(B.A, B.s, B.d[p], B.d[p ^ 1], B.q,
                                                                  B.cb, B.P, S.g_st, p);
             else
@@ -1274,8 +1311,8 @@ int pcga_pcg_solve_mixed(pcga_solver_t *S, const double *b_dev, double *x_dev, d
                          int32_t *inner_total, double *hist_host, int32_t hist_cap,
                          int32_t *hist_len, double *true_relres) {
     if (!S || !b_dev || !x_dev) return fail(PCGA_EINVAL, "NULL argument");
-    if (S->precision != PCGA_MIXED)
-        return fail(PCGA_EINVAL, "pcga_pcg_solve_mixed needs a PCGA_MIXED solver");
+    if (S->precision != PCGA_MIXED && S->precision != PCGA_MIXED_A32)
+        return fail(PCGA_EINVAL, "pcga_pcg_solve_mixed needs a PCGA_MIXED or PCGA_MIXED_A32 solver");
     if (!(tol >= 0.0) || !(inner_tol > 0.0) || max_outer < 0)
         return fail(PCGA_EINVAL, "bad tolerances or max_outer");
     if (inner_maxit < 0) inner_maxit = (int32_t)std::min<int64_t>(S->n, INT32_MAX);
@@ -1409,8 +1446,12 @@ int pcga_step_stencil(pcga_solver_t *S, const double *s_dev, const double *d_dev
     } else {
         k_convert<double, float><<<gc, kBS, 0, R.stream>>>((int)R.n, s_dev, R.s32);
         k_convert<double, float><<<gc, kBS, 0, R.stream>>>((int)R.n, d_dev, R.d32[0]);
-        k_stencil<float, false><<<R.g_st, kBS, 0, R.stream>>>(R.A64, R.s32, R.d32[0], R.d32[1],
-                                                              R.q32, R.cb, R.P, 1, 0);
+        if (R.precision == PCGA_MIXED_A32)
+            k_stencil<float, false, float><<<R.g_st, kBS, 0, R.stream>>>(
+                R.A32, R.s32, R.d32[0], R.d32[1], R.q32, R.cb, R.P, 1, 0);
+        else
+            k_stencil<float, false><<<R.g_st, kBS, 0, R.stream>>>(R.A64, R.s32, R.d32[0], R.d32[1],
+                                                                  R.q32, R.cb, R.P, 1, 0);
         k_convert<float, double><<<gc, kBS, 0, R.stream>>>((int)R.n, R.d32[1], dnew_dev);
         k_convert<float, double><<<gc, kBS, 0, R.stream>>>((int)R.n, R.q32, q_dev);
     }

@@ -21,6 +21,7 @@ struct pcga_solver {
     size_t ws_bytes = 0;
 
     pcga::DevOp<double> A64{};
+    pcga::DevOp<float> A32{};   // PCGA_MIXED_A32: the operator rounded to FP32 (inner solve)
     // General sparse A (pcga_solver_create_csr): stored in sliced ELL, applied
     // by k_spmv_sell / k_residual_sell with g_a workgroups; A64 is unused
     bool csr = false;

@@ -84,7 +84,7 @@ def check_stencil_step(pkg, ora, S, p, prec, seed, beta):
     the bound of a recursive sum."""
     rng = np.random.default_rng(seed)
     s, d = rng.standard_normal(p.n), rng.standard_normal(p.n)
-    if prec == "mixed":             # the FP32 kernel's inputs, exactly
+    if prec != "fp64":              # the FP32 kernel's inputs, exactly
         s = s.astype(np.float32).astype(np.float64)
         d = d.astype(np.float32).astype(np.float64)
         bt = float(np.float32(beta))
@@ -96,11 +96,17 @@ def check_stencil_step(pkg, ora, S, p, prec, seed, beta):
     dn, q = dn.cpu().numpy(), q.cpu().numpy()
     d_ref = s + bt * d
     assert np.all(np.abs(dn - d_ref) <= 2 * u * (np.abs(s) + np.abs(bt * d)) + 1e-300)
-    if prec == "mixed":
+    if prec != "fp64":
         assert np.array_equal(dn, dn.astype(np.float32).astype(np.float64))
-    q_ref = ora.spmv(p, dn)
     mag = ora.spmv(_abs_problem(p), np.abs(dn))
-    assert np.all(np.abs(q - q_ref) <= u * np.abs(q_ref) + 8 * EPS * mag + 1e-300)
+    if prec == "mixed_a32":
+        # FP32 coefficients, FP32 sums: the oracle's FP32 product of the
+        # device's d_new, within the bound of a 5-term FP32 sum
+        q_ref = ora.spmv32(p, dn, a32=True).astype(np.float64)
+        assert np.all(np.abs(q - q_ref) <= 12 * u * mag + 1e-300)
+    else:
+        q_ref = ora.spmv(p, dn)
+        assert np.all(np.abs(q - q_ref) <= u * np.abs(q_ref) + 8 * EPS * mag + 1e-300)
     prods = dn * q
     gam = 1.01 * p.n * EPS
     assert abs(dq - np.sum(prods)) <= gam * np.sum(np.abs(prods)) + 1e-300
@@ -112,7 +118,7 @@ STENCIL_CASES = ["box64x48", "orca182x149", "orca37x23_ragged", "orca3x7_min_per
 
 
 @pytest.mark.parametrize("name", STENCIL_CASES)
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_a32"])
 def test_fused_stencil_step(pkg, ora, name, prec):
     p, tau = case(name)
     say("fused stencil step", name, prec)
@@ -300,11 +306,12 @@ def test_pcg_natural_stop(pkg, ora, name):
 
 
 @pytest.mark.parametrize("name", ["box64x48", "orca182x149", "orca37x23_ragged"])
-def test_mixed_reaches_fp64_residual(pkg, ora, name):
+@pytest.mark.parametrize("form", ["mixed", "mixed_a32"])
+def test_mixed_reaches_fp64_residual(pkg, ora, name, form):
     p, tau = case(name)
-    say("mixed", name)
+    say(form, name)
     A = pkg.Stencil5.from_problem(p)
-    S = pkg.Solver(A, pkg.ainv_setup(A, tau), "mixed")
+    S = pkg.Solver(A, pkg.ainv_setup(A, tau), form)
     m = S.solve_mixed(dev(p.b), tol=1e-10, inner_tol=1e-5, max_outer=20)
     assert m.status == 0
     x = m.x.cpu().numpy()
@@ -315,7 +322,8 @@ def test_mixed_reaches_fp64_residual(pkg, ora, name):
     xo = ora.pcg(p, ora.ainv_setup(p, tau), tol=1e-12).x
     err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
     say("  mixed outer", m.outer, "inner", m.inner_total, "rel err vs FP64 oracle", err)
-    om = ora.pcg_mixed(p, ora.ainv_setup(p, tau), tol=1e-10, inner_tol=1e-5)
+    om = ora.pcg_mixed(p, ora.ainv_setup(p, tau), tol=1e-10, inner_tol=1e-5,
+                       a32=(form == "mixed_a32"))
     assert abs(m.outer - om.outer) <= 1
 
 
@@ -502,14 +510,17 @@ def test_full_size_jacobi_two_launch_path(pkg, ora, orca025):
     assert np.linalg.norm(p.b - ora.spmv(p, x)) / np.linalg.norm(p.b) <= 1e-8
 
 
-def test_full_size_mixed(pkg, ora, orca025, orca025_stops):
-    """FP32 inner PCG with FP64 refinement at 1442x1021: the true FP64
-    residual at the 1e-10 target, and the error against the FP64 oracle's
-    solution stated (two solutions at relative residual 1e-10 of this
-    ill-conditioned system need not be closer than about 1e-9)."""
+@pytest.mark.parametrize("form", ["mixed", "mixed_a32"])
+def test_full_size_mixed(pkg, ora, orca025, orca025_stops, form):
+    """FP32 inner PCG with FP64 refinement at 1442x1021, with the FP64
+    operator applied to the FP32 inner vectors (mixed) or the operator in FP32
+    too (mixed_a32): the true FP64 residual at the 1e-10 target, and the error
+    against the FP64 oracle's solution stated (two solutions at relative
+    residual 1e-10 of this ill-conditioned system need not be closer than
+    about 1e-9)."""
     p, F, A, G = orca025
-    say("full size: mixed precision")
-    S = pkg.Solver(A, G, "mixed")
+    say("full size:", form)
+    S = pkg.Solver(A, G, form)
     m = S.solve_mixed(dev(p.b), tol=1e-10, inner_tol=1e-5, max_outer=20)
     assert m.status == 0
     x = m.x.cpu().numpy()

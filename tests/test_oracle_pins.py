@@ -442,3 +442,27 @@ def test_evaluation_order_builds_compute_the_same_method(ora):
         c = np.linalg.solve(V.T @ M @ V, V.T @ pb.b)
         x3 = ora.pcg(pb, Fb, tol=0.0, maxit=3, variant=v).x
         assert np.linalg.norm(x3 - V @ c) <= 1e-10 * np.linalg.norm(xs)
+
+
+def test_mixed_inner_operator_forms(ora):
+    """The mixed form's inner product q = A d on FP32 vectors: with FP64
+    coefficients it is the FP64 five-point product rounded to FP32 once; with
+    the operator in FP32 it is the same sum done in FP32 arithmetic on rounded
+    coefficients (checked against numpy float32 operations in the same
+    order).  Both mixed forms reach the FP64 target."""
+    p = orca.orca_problem(37, 23, 5)
+    d = np.random.default_rng(4).standard_normal(p.n).astype(np.float32)
+    q64 = ora.spmv32(p, d, a32=False)
+    assert np.array_equal(q64, ora.spmv(p, d.astype(np.float64)).astype(np.float32))
+    q32 = ora.spmv32(p, d, a32=True)
+    M = p.dense()
+    for k in range(p.n):
+        acc = np.float32(0.0)
+        for c in np.nonzero(M[k])[0]:       # row k in increasing column order
+            acc = np.float32(acc + np.float32(np.float32(M[k, c]) * d[c]))
+        assert q32[k] == acc
+    F = ora.ainv_setup(p, 0.05)
+    for a32 in (False, True):
+        m = ora.pcg_mixed(p, F, tol=1e-10, a32=a32)
+        x = m.x
+        assert np.linalg.norm(p.b - ora.spmv(p, x)) / np.linalg.norm(p.b) <= 1e-10
