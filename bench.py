@@ -7,8 +7,10 @@ residual 1e-10, inputs resident in HBM.  `value` = iterations per second over
 the K timed steps.  The same JSON line carries the mixed-precision solve (FP32
 inner PCG + FP64 refinement) on the same GPU, the diagonal (Jacobi)
 preconditioner baseline, the paper's banded factor of T (q = 4), the fixed-fill
-AINV (the second Bridson class of Sec. 5) at a few counts per column, the roofline of the dominant kernel (HIP-event
-timing on the solver stream), and the FP64 oracle timed on the host.
+AINV (the second Bridson class of Sec. 5), a general sparse (CSR) operator, the
+roofline of the dominant kernel (HIP-event timing on the solver stream) and of
+the whole iteration, the batched and served workloads with their modelled
+bandwidth, and the FP64 oracle timed on the host.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -25,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 NX, NY, TAU, TOL = 1442, 1021, 0.05, 1e-10
 # fixed-fill AINV settings reported beside the threshold factor: (drop_tol, count)
-FIXED_FILL = ((0.01, 4), (0.01, 6), (0.01, 8), (0.005, 10))
+FIXED_FILL = ((0.01, 8),)
 SAMPLE_TOL = 1e-14      # stopping tolerance of the oracle's timed samples
 PLACEMENTS = 4          # workspace bases the FP64 solver's placement probe tries
 PEAK_HBM_GBS = 8000.0
@@ -56,7 +58,26 @@ def kernel_bytes(n, nnz_off, word, index_bytes=4):
     }
 
 
+def survey_bytes(n, nnz_off):
+    """Compulsory bytes of one FP64 iteration by method step (FP64 values,
+    int32 column per nonzero of Z, each array counted once per step):
+    direction update + five-point product + (d,q) 56 n; alpha, the two axpys
+    and ||r||^2 48 n; t = D^-1 Z^T r 24 n + 12 nnz; s = Z t and (s,r)
+    24 n + 12 nnz.  The Z^T kernel fuses the second and third steps."""
+    return {"stencil": 56 * n, "axpy_zt": 48 * n + 24 * n + 12 * nnz_off,
+            "z_dot": 24 * n + 12 * nnz_off, "iteration": 152 * n + 24 * nnz_off}
+
+
+def batch_step_bytes(n, nnz_stored, nrhs, index_bytes):
+    """Compulsory bytes of one inner step of a batch slot (FP32 vectors
+    interleaved over nrhs right-hand sides, FP64 operator, FP32 Z values):
+    stencil 16 R n + 24 n; Z^T kernel 28 R n + 4 n + (4 + b) E; Z kernel
+    12 R n + (4 + b) E."""
+    return 56 * nrhs * n + 28 * n + 2 * (4 + index_bytes) * nnz_stored
+
+
 COUNTER_FILE = os.path.join(ROOT, "profiles", "pcg_iteration_kernels_1442x1021_hbm_traffic.json")
+TRACE_FILE = os.path.join(ROOT, "profiles", "pcg_iteration_kernels_1442x1021_trace.json")
 KERNEL_SOURCES = ["paper_1210_1878_amd/csrc/kernels.h", "paper_1210_1878_amd/csrc/pcga_dev.h",
                   "paper_1210_1878_amd/csrc/solver.hip", "paper_1210_1878_amd/csrc/timestep.hip"]
 # Time-step passes around the solve: algorithmic bytes per cell (each array once)
@@ -97,6 +118,21 @@ def measured_traffic(kernel):
     if k is None:
         return None, "kernel not in the counter summary"
     return k["hbm_bytes_per_launch"], rec.get("profile", "")
+
+
+def traced_us(kernel):
+    """Average duration in us of `kernel` in the committed rocprofv3 kernel
+    trace of `bench.py --kernels-only`, or None when the kernel sources
+    changed since the trace was taken."""
+    try:
+        with open(TRACE_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["avg_us"]
 
 
 def cpu_baseline(p, seconds=15.0):
@@ -199,10 +235,12 @@ def bench_batch(P, torch, dev, log, members=64, nrhs=4):
         f"chunk {tuned['chunk']}; " + ", ".join(f"w{w}/c{c}: {ms:.0f} ms" for w, c, ms in tuned["table"]))
     solvers = [P.Solver(A, F, "mixed", device=dev, slice_width=tuned["slice_width"]) for A, F in zip(As, Fs)]
 
+    slot_of = {}
+
     def run_batch():
         Bt = P.Batch(max_slots=members, device=dev, chunk=tuned["chunk"])
-        for S, B in zip(solvers, Bs):
-            Bt.add(S, B, tol=TOL, inner_tol=1e-5, max_outer=30)
+        for i, (S, B) in enumerate(zip(solvers, Bs)):
+            slot_of[Bt.add(S, B, tol=TOL, inner_tol=1e-5, max_outer=30)] = i
         return Bt.solve()
 
     run_batch()                                  # warm-up (graph capture)
@@ -214,6 +252,11 @@ def bench_batch(P, torch, dev, log, members=64, nrhs=4):
     worst = max(max(q["true_relres"]) for (_, q) in res.values())
     ok = all(q["status"] == 0 for (_, q) in res.values())
     inner = sum(q["inner_total"] for (_, q) in res.values())
+    # modelled bytes of all slot steps (inner steps; the few refinement steps
+    # are left out, so the figure is a lower bound)
+    moved = sum(q["inner_total"] * batch_step_bytes(solvers[slot_of[s]].n, solvers[slot_of[s]].nnz_off,
+                                                    nrhs, solvers[slot_of[s]].index_bytes)
+                for s, (_, q) in res.items())
     # the same solves one at a time through the single-grid mixed solver
     t0 = time.perf_counter()
     for S, B in zip(solvers, Bs):
@@ -230,16 +273,99 @@ def bench_batch(P, torch, dev, log, members=64, nrhs=4):
             "worst_true_relres": worst, "inner_iters_per_item_rhs": round(inner / members, 1),
             "sequential_ms": round(dts * 1e3, 2),
             "speedup_vs_sequential": round(dts / dt, 2),
+            "model_bytes": moved,
+            "roofline": {"bound": "hbm", "achieved": round(moved / dt / 1e9, 1), "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": round(moved / dt / 1e9 / PEAK_HBM_GBS, 4),
+                         "model": "per slot inner step 56 R n + 28 n + 2 (4 + b) nnz_off bytes "
+                                  "(R = 4 right-hand sides), summed over the slots' inner steps"},
             "autotuned": {"slice_width": tuned["slice_width"], "chunk": tuned["chunk"],
                           "table_ms": [[w, c, round(ms, 1)] for w, c, ms in tuned["table"]]}}
 
 
+CSR_POINTS = 1_500_000
+
+
+def bench_csr(P, torch, dev, log):
+    """A general sparse SPD matrix that is not a grid (seeded unstructured
+    point cloud, about 1.5 M rows, reverse Cuthill-McKee order), FP64
+    PCG-AINV to 1e-10 through the CSR path."""
+    from gen.unstructured import unstructured_problem
+    t0 = time.perf_counter()
+    q = unstructured_problem(CSR_POINTS, 1878 + 7)
+    A = P.CsrMatrix.from_problem(q)
+    G = P.ainv_setup(A, TAU)
+    S = P.Solver(A, G, "fp64", device=dev)
+    bq = torch.from_numpy(q.b).to(dev)
+    log(f"csr: {q.n} rows, {q.nnz} entries, nnz_off(Z) {G.nnz_off}, setup {time.perf_counter() - t0:.1f}s")
+    S.solve(bq, tol=TOL)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = S.solve(bq, tol=TOL)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = S.profile_iteration(bq, reps=50, mode=1)
+    bpi = S.bytes_per_iter
+    S.close()
+    log(f"csr: {r.iters} iterations, {el * 1e3:.1f} ms, {r.iters / el:.0f} it/s, iteration "
+        f"{ms[3] * 1e3:.1f} us ({bpi / (ms[3] * 1e-3) / 1e9:.0f} GB/s modelled), true relres "
+        f"{r.true_relres:.2e}")
+    return {"workload": f"unstructured point-cloud SPD matrix (k-nearest-neighbour couplings, "
+                        f"RCM order), {q.n} rows, {q.nnz} entries, AINV drop tol {TAU}, FP64 to {TOL}",
+            "n": q.n, "nnz": q.nnz, "nnz_off_z": G.nnz_off, "iters": r.iters,
+            "ms_per_solve": round(el * 1e3, 2), "it_s": round(r.iters / el, 1),
+            "true_relres": r.true_relres, "iteration_us": round(ms[3] * 1e3, 2),
+            "kernel_us": [round(x * 1e3, 2) for x in ms[:3]],
+            "model_bytes_per_iter": bpi,
+            "model_gbs": round(bpi / (ms[3] * 1e-3) / 1e9, 1)}
+
+
 SERVE_CLASS_CELLS = (2_000_000,)
+SERVE_SOLO_CELLS = 1_000_000   # grids served by a lane of their own (single-grid mixed solve)
+SERVE_BUDGET_FRAC = 0.6        # memory budget: this share of all grids' request vectors
 SERVE_GUESS = (2.0, -1.0)      # x0 = 2 D^{t-1} - D^{t-2}
 
 
-def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=10.0,
-                class_cells=SERVE_CLASS_CELLS, coupled=False):
+def served_bytes(done, solvers):
+    """Modelled bytes of the served requests' inner steps (one right-hand
+    side; see batch_step_bytes)."""
+    return sum(r.inner * batch_step_bytes(solvers[r.grid].n, solvers[r.grid].nnz_off, 1,
+                                          solvers[r.grid].index_bytes)
+               for r in done if r.status == 0)
+
+
+def fp64_sequential(P, torch, dev, probs, seconds, log):
+    """The same kind of requests served without batching and in FP64: every
+    grid's next warm-started time step (1% noise on the right-hand side, x0 =
+    the previous solution) solved in turn by a single-grid FP64 solver, until
+    `seconds` have passed (at least one round).  Solves per second."""
+    from paper_1210_1878_amd import serve
+    solvers = [P.Solver(P.Stencil5.from_problem(p), P.ainv_setup(P.Stencil5.from_problem(p), 0.05),
+                        "fp64", device=dev) for p in probs]
+    stepper = serve.TimeStepper(probs, dev, seed=CONFIG_SERVE_SEED + 9)
+    done, rid = 0, 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while True:
+        for g, S in enumerate(solvers):
+            req = serve.Request(rid=rid, grid=g, arrival=0.0)
+            rid += 1
+            stepper(req)
+            res = S.solve(req.b, req.x0, tol=TOL)
+            req.x = res.x
+            stepper.done(req)
+            done += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    for S in solvers:
+        S.close()
+    log(f"fp64, one solve at a time: {done} solves in {el:.1f}s ({done / el:.2f} solves/s)")
+    return {"solves": done, "seconds": round(el, 2), "solves_per_s": round(done / el, 2)}
+
+
+def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=15.0,
+                class_cells=SERVE_CLASS_CELLS, coupled=False, compare_fp64=False):
     """Time-step solves on a catalogue of resident grids from 182x149 to
     4322x3059 (mixed precision to 1e-10, warm starts, continuous batching).
     Capacity first: a closed loop keeps every grid busy and gives each grid's
@@ -252,9 +378,11 @@ def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=
               (1442, 1021), (4322, 3059)]
     t0 = time.perf_counter()
     probs = [orca.orca_problem(nx, ny, orca.CONFIG_SEED_BASE + 40 + i) for i, (nx, ny) in enumerate(shapes)]
-    srv = serve.Server(probs, drop_tol=0.05, device=dev, chunk=16, class_cells=class_cells)
+    srv = serve.Server(probs, drop_tol=0.05, device=dev, chunk=16, class_cells=class_cells,
+                       solo_cells=SERVE_SOLO_CELLS)
+    srv.budget = int(SERVE_BUDGET_FRAC * sum(srv.item_bytes))
     log(f"serving: {len(probs)} resident grids ({srv.resident_bytes / 2**30:.2f} GiB), "
-        f"setup {time.perf_counter() - t0:.1f}s")
+        f"request-memory budget {srv.budget / 2**20:.0f} MiB, setup {time.perf_counter() - t0:.1f}s")
     if coupled:
         stepper = serve.CoupledTimeStepper(probs, srv.solvers, dev, seed=CONFIG_SERVE_SEED,
                                            guess=SERVE_GUESS)
@@ -263,8 +391,11 @@ def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=
     # warm-up: one step per grid (graph capture, first touch)
     warm = [serve.Request(rid=-1 - g, grid=g, arrival=0.0) for g in range(len(probs))]
     srv.run(warm, make_rhs=stepper, on_done=stepper.done)
+    srv.budget = None        # the closed loop keeps every grid busy
     done, el = srv.saturate(saturate_s, make_rhs=stepper, on_done=stepper.done)
+    srv.budget = int(SERVE_BUDGET_FRAC * sum(srv.item_bytes))
     cap = [sum(1 for r in done if r.grid == g) / el for g in range(len(probs))]
+    cap_bytes = served_bytes(done, srv.solvers)
     log(f"capacity (closed loop, {el:.1f}s): {sum(cap):.1f} solves/s; per grid "
         + ", ".join(f"{a}x{b}: {c:.2f}" for (a, b), c in zip(shapes, cap)))
     steps = ("coupled time steps (right-hand side of eq. (8) from seeded, slowly varying face "
@@ -275,17 +406,29 @@ def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=
                        "load factor of each grid's closed-loop throughput",
            "grids": [f"{a}x{b}" for a, b in shapes],
            "size_classes": "grids split at " + ", ".join(f"{c:,} cells" for c in sorted(class_cells))
-                           + "; one batch per class, each on its own stream, running concurrently",
+                           + "; one batch per class, each on its own stream, running concurrently; "
+                           f"grids of at least {SERVE_SOLO_CELLS:,} cells are served by a lane of "
+                           "their own (single-grid mixed solve on a host thread)",
            "grid_class": srv.klass,
+           "solo_grids": [f"{a}x{b}" for (a, b), so in zip(shapes, srv.solo) if so],
+           "hbm_budget_bytes": srv.budget,
            "capacity_solves_per_s": round(sum(cap), 2),
            "capacity_per_grid": [round(c, 3) for c in cap],
            "capacity_worst_true_relres": float(max(r.true_relres for r in done)),
+           "capacity_roofline": {"bound": "hbm", "achieved": round(cap_bytes / el / 1e9, 1),
+                                 "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                 "frac": round(cap_bytes / el / 1e9 / PEAK_HBM_GBS, 4),
+                                 "model": "inner steps of the served solves x (56 n + 28 n + 2 (4 + b) "
+                                          "nnz_off) bytes, over the closed-loop time"},
            "loads": {}}
     for i, L in enumerate(loads):
         reqs = serve.poisson_arrivals_per_grid([L * c for c in cap], horizon_s,
                                                seed=CONFIG_SERVE_SEED + 1 + i)
         res = srv.run(reqs, make_rhs=stepper, on_done=stepper.done)
-        st = serve.latency_stats(res, srv.klass)
+        st = serve.latency_stats(res, srv.klass, per_grid=True)
+        st["held_for_memory"] = srv.held_for_memory
+        span = max(r.finished for r in res) - min(r.arrival for r in res)
+        st["model_gbs"] = round(served_bytes(res, srv.solvers) / span / 1e9, 1)
         f99 = lambda v: "n/a" if v is None else f"{v:.0f}"
         log(f"load {L:.2f}: {st['requests']} requests, p50 {st['p50_ms']:.1f} ms, "
             f"p99 {f99(st['p99_ms'])} ms, {st['solves_per_s']:.2f} solves/s, "
@@ -293,6 +436,11 @@ def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=
             + ", ".join(f"{k}: {v['requests']} req p50 {v['p50_ms']:.0f} p99 {f99(v['p99_ms'])} ms"
                         for k, v in st["per_class"].items()))
         out["loads"][str(L)] = st
+    if compare_fp64:
+        out["fp64_one_at_a_time"] = fp64_sequential(P, torch, dev, probs, saturate_s, log)
+        out["fp64_one_at_a_time"]["served_capacity_ratio"] = round(
+            sum(cap) / out["fp64_one_at_a_time"]["solves_per_s"], 2)
+    srv.close()
     return out
 
 
@@ -362,6 +510,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--no-timestep", action="store_true", help="skip the coupled time steps")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner report")
+    ap.add_argument("--no-csr", action="store_true", help="skip the general sparse operator")
     ap.add_argument("--kernels-only", action="store_true",
                     help="profiling driver: a 256 MiB device copy (counter calibration), then the "
                          "three FP64 and FP32 iteration kernels, --reps launches each")
@@ -385,6 +534,20 @@ def main():
     p = orca.orca_problem(NX, NY, orca.CONFIG_SEED_BASE + 2)
     log(f"generated {NX}x{NY} in {time.perf_counter() - t0:.1f}s")
     A = P.Stencil5.from_problem(p)
+    # the FP64 oracle's solution, for the mixed forms' error: computed on a
+    # host thread while the device work goes on (the oracle releases the
+    # interpreter while it runs)
+    oracle_x = {}
+    if not args.no_cpu and not args.kernels_only:
+        import threading
+
+        def _oracle_solution():
+            import oracle
+            F = oracle.ainv_setup(p, TAU)
+            r = oracle.pcg(p, F, tol=TOL)
+            oracle_x["x"], oracle_x["iters"] = r.x, r.iters
+        ora_thread = threading.Thread(target=_oracle_solution, daemon=True)
+        ora_thread.start()
     t0 = time.perf_counter()
     G = P.ainv_setup(A, TAU)
     setup_s = time.perf_counter() - t0
@@ -463,6 +626,25 @@ def main():
     err_mx = float((m.x - x64).norm() / x64.norm())
     log(f"mixed: {dtm * 1e3:.2f} ms/solve, outer {m.outer}, inner {m.inner_total}, "
         f"true relres {m.true_relres:.2e}, |x_mixed - x_fp64|/|x_fp64| {err_mx:.2e}")
+    x_mixed = m.x.cpu().numpy()
+    # the spec reading of the mixed form: the inner operator in FP32 too
+    Sa32 = P.Solver(A, G, "mixed_a32", device=dev)
+    Sa32.tune(chunk=args.chunk, use_graph=not args.no_graph, max_blocks=args.max_blocks)
+    Sa32.solve_mixed(b, tol=TOL)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ma = Sa32.solve_mixed(b, tol=TOL, inner_tol=1e-5, max_outer=30)
+    torch.cuda.synchronize()
+    dta = (time.perf_counter() - t0) / args.steps
+    ms_a32 = Sa32.profile_iteration(b, reps=100, mode=1)
+    x_a32 = ma.x.cpu().numpy()
+    log(f"mixed, FP32 operator: {dta * 1e3:.2f} ms/solve, outer {ma.outer}, inner {ma.inner_total}, "
+        f"true relres {ma.true_relres:.2e}, inner iteration {ms_a32[3] * 1e3:.1f} us")
+    Sa32.close()
+
+    # ---- a general sparse (CSR) SPD matrix: unstructured, not a grid -------
+    csr = None if args.no_csr else bench_csr(P, torch, dev, log)
 
     # ---- Jacobi (NEMO diagonal preconditioner) baseline on the GPU ---------
     Gj = P.ainv_setup(A, float("inf"))
@@ -531,6 +713,7 @@ def main():
     ms32 = Smx.profile_iteration(b, reps=100, mode=1)
     kb = kernel_bytes(p.n, G.nnz_off, 8, S64.index_bytes)
     kb32 = kernel_bytes(p.n, G.nnz_off, 4, Smx.index_bytes)
+    sb = survey_bytes(p.n, G.nnz_off)
     names = list(kb)
     gbs = {k: kb[k] / (ms[i] * 1e-3) / 1e9 for i, k in enumerate(names)}
     gbs32 = {k: kb32[k] / (ms32[i] * 1e-3) / 1e9 for i, k in enumerate(names)}
@@ -548,19 +731,43 @@ def main():
     it_time = ms[3] * 1e-3
     kname = kernel_names(8, S64.formats)[names[dom]]
     traffic, tnote = measured_traffic(kname)
+    rp_us = traced_us(kname)
+    dom_bytes = sb[names[dom]]
     roof = {"bound": "hbm", "kernel": kname,
-            "achieved": round(gbs[names[dom]], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(gbs[names[dom]] / PEAK_HBM_GBS, 4), "traffic": traffic,
-            "traffic_source": tnote,
-            "bytes_per_launch": kb[names[dom]], "ms_per_launch": ms[dom]}
+            "achieved": round(dom_bytes / (ms[dom] * 1e-3) / 1e9, 1), "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": round(dom_bytes / (ms[dom] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+            "traffic": traffic,
+            "traffic_note": "rocprofv3 FETCH_SIZE and WRITE_SIZE per launch, each scaled by its "
+                            "reading on a plain device copy: bytes the L2 fetched from and wrote "
+                            "to memory, including reads served by the 256 MiB memory-side cache, "
+                            "so an upper bound of the HBM traffic (" + tnote + ")",
+            "bytes_per_launch": dom_bytes,
+            "bytes_model": "method steps alpha + axpys + ||r||^2 (48 n) and D^-1 Z^T r "
+                           "(24 n + 12 nnz_off), FP64 values and int32 indices",
+            "ms_per_launch": ms[dom],
+            "rocprof_us_per_launch": rp_us,
+            "frac_rocprof": None if rp_us is None else round(dom_bytes / (rp_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
+            "kernel_own_bytes_per_launch": kb[names[dom]],
+            "frac_kernel_own_bytes": round(gbs[names[dom]] / PEAK_HBM_GBS, 4),
+            "per_iteration": {"bytes": sb["iteration"], "us": round(ms[3] * 1e3, 2),
+                              "frac": round(sb["iteration"] / it_time / 1e9 / PEAK_HBM_GBS, 4),
+                              "frac_whole_solve": round(sb["iteration"] * it_s / 1e9 / PEAK_HBM_GBS, 4),
+                              "model": "152 n + 24 nnz_off bytes per FP64 iteration"}}
 
     batched = None if args.no_batch else bench_batch(P, torch, dev, log)
-    served = None if args.no_serve else bench_serve(P, torch, dev, log)
+    served = None if args.no_serve else bench_serve(P, torch, dev, log, compare_fp64=True)
     served_coupled = None if args.no_serve or args.no_timestep else bench_serve(
         P, torch, dev, lambda m: log("coupled " + m), loads=(0.8,), coupled=True)
 
     cpu = None
+    err_ora = err_a32_ora = None
     if not args.no_cpu:
+        ora_thread.join()
+        xo = oracle_x["x"]
+        err_ora = float(np.linalg.norm(x_mixed - xo) / np.linalg.norm(xo))
+        err_a32_ora = float(np.linalg.norm(x_a32 - xo) / np.linalg.norm(xo))
+        log(f"mixed vs the FP64 oracle's solution ({oracle_x['iters']} iterations): "
+            f"{err_ora:.2e}; with the FP32 operator {err_a32_ora:.2e}")
         log(f"cpu baseline (oracle, ~{args.cpu_seconds:.0f}s)")
         cpu = cpu_baseline(p, args.cpu_seconds)
         log(f"cpu: {cpu['value']:.2f} it/s")
@@ -591,10 +798,17 @@ def main():
                  "iteration_ms": round(ms[3], 5)},
         "mixed": {"ms_per_solve": round(dtm * 1e3, 3), "outer": m.outer, "inner_iters": m.inner_total,
                   "inner_it_s": round(m.inner_total / dtm, 1), "true_relres": m.true_relres,
-                  "rel_err_vs_fp64": err_mx, "speedup_vs_fp64": round(dt / args.steps / dtm, 3),
+                  "rel_err_vs_fp64": err_mx, "rel_err_vs_oracle": err_ora,
+                  "speedup_vs_fp64": round(dt / args.steps / dtm, 3),
                   "model_bytes_per_inner_iter": b_iter32,
                   "kernel_ms": dict(zip(names, [round(v, 5) for v in ms32[:3]])),
                   "iteration_ms": round(ms32[3], 5)},
+        "mixed_fp32_operator": {"ms_per_solve": round(dta * 1e3, 3), "outer": ma.outer,
+                                "inner_iters": ma.inner_total, "true_relres": ma.true_relres,
+                                "rel_err_vs_oracle": err_a32_ora,
+                                "speedup_vs_fp64": round(dt / args.steps / dta, 3),
+                                "iteration_ms": round(ms_a32[3], 5)},
+        "csr_unstructured": csr,
         "jacobi": {"iters": rj.iters, "ms_per_solve": round(dtj * 1e3, 3),
                    "true_relres": rj.true_relres},
         "band_factor_q4": {"iters": rb.iters, "ms_per_solve": round(dtb * 1e3, 3),

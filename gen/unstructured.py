@@ -15,8 +15,9 @@ Construction (all seeded):
   - ordering: reverse Cuthill-McKee of the graph (a usual numbering of
     unstructured meshes);
   - "laplacian": A_ij = -w_ij, A_ii = sum_j w_ij + sigma_i with sigma_i > 0
-    only on points near the square's boundary (a Dirichlet-like condition):
-    an irreducibly diagonally dominant M-matrix, hence SPD;
+    only on points near the square's boundary (a Dirichlet-like condition)
+    and on one point of every connected component that has none: each block
+    is an irreducibly diagonally dominant M-matrix, hence SPD;
   - "mixed": the same magnitudes with seeded signs on the couplings and
     A_ii = sum_j |w_ij| + sigma_i: SPD by diagonal dominance, not an
     M-matrix.
@@ -107,8 +108,14 @@ def unstructured_problem(npts: int, seed: int, k: int = 6, kind: str = "laplacia
     np.add.at(deg, j, w)
     edge = np.minimum.reduce([pts[:, 0], pts[:, 1], 1.0 - pts[:, 0], 1.0 - pts[:, 1]])
     sigma = np.where(edge < 2.0 / np.sqrt(n), 1.0, 0.0)
-    if not sigma.any():
-        sigma[0] = 1.0
+    # every connected component of the graph needs one shifted point, or its
+    # block of A is singular (a kNN graph of clustered points can fall apart)
+    from scipy.sparse.csgraph import connected_components
+    ncomp, comp = connected_components(G.tocsr(), directed=False)
+    has = np.zeros(ncomp, dtype=bool)
+    has[comp[sigma > 0]] = True
+    for cidx in np.nonzero(~has)[0]:
+        sigma[np.argmax(comp == cidx)] = 1.0
     diag = deg + sigma
     r = np.concatenate([i, j, np.arange(n)])
     c = np.concatenate([j, i, np.arange(n)])

@@ -11,14 +11,20 @@ sequential) and their vectors fit the device-memory budget.  Grids are split
 into size classes, each with its own batch on its own HIP stream: a batch
 advances all of its admitted requests together (one launch per kernel per
 step), and the classes run concurrently, so that steps of a very large grid
-do not hold back the many steps a small grid's solve needs.  Latency is
-measured from arrival to the moment the solution is back in the request's
-output tensor.
+do not hold back the many steps a small grid's solve needs.  Grids of at
+least `solo_cells` cells are not batched: each has a lane of its own, a host
+thread that runs the grid's steps through the single-grid mixed solve on the
+grid's stream (its kernels stream the large grid's arrays better than the
+batched kernels do), concurrently with the batches.  Latency is measured
+from arrival to the moment the solution is back in the request's output
+tensor.
 """
 from __future__ import annotations
 
 import collections
 import dataclasses
+import queue as _queue
+import threading
 import time
 
 import numpy as np
@@ -49,12 +55,50 @@ class Request:
         return self.finished - self.arrival
 
 
+class _SoloLane:
+    """One grid served outside the batches: a host thread that solves the
+    grid's admitted steps one at a time with the single-grid mixed solve
+    (the library releases the interpreter while it runs) and posts each
+    finished request to the server's completion queue."""
+
+    def __init__(self, solver, server, done_q):
+        self.S = solver
+        self.srv = server
+        self.done_q = done_q
+        self.inbox = _queue.Queue()
+        self.thread = threading.Thread(target=self._loop, daemon=True)
+        self.thread.start()
+
+    def submit(self, req):
+        self.inbox.put(req)
+
+    def _loop(self):
+        while True:
+            req = self.inbox.get()
+            if req is None:
+                return
+            srv = self.srv
+            try:
+                res = self.S.solve_mixed(req.b, x0=req.x0, tol=srv.tol, inner_tol=srv.inner_tol,
+                                         max_outer=srv.max_outer)
+                q = {"status": res.status, "true_relres": [res.true_relres], "outer": res.outer,
+                     "inner_total": res.inner_total}
+                self.done_q.put((req, res.x.unsqueeze(0), q))
+            except Exception as e:     # reported as a failed request, the lane goes on
+                self.done_q.put((req, None, {"status": -4, "true_relres": [float("nan")],
+                                             "outer": 0, "inner_total": 0, "error": repr(e)}))
+
+    def close(self):
+        self.inbox.put(None)
+        self.thread.join(timeout=60)
+
+
 class Server:
     """Holds resident grids and serves time-step solves by continuous batching."""
 
     def __init__(self, problems, drop_tol=0.05, device=None, hbm_budget=None, max_slots=64,
                  tol=1e-10, inner_tol=1e-5, max_outer=30, chunk=16, class_cells=(2_000_000,),
-                 class_grid=None):
+                 class_grid=None, solo_cells=None):
         import torch
         self.torch = torch
         self.device = torch.device("cuda" if device is None else device)
@@ -69,10 +113,14 @@ class Server:
         self.item_bytes = [Batch.item_bytes(S, 1) for S in self.solvers]
         self.budget = hbm_budget            # bytes for in-flight request vectors (None: no limit)
         self.max_slots = max_slots
-        # size class of each grid: index of the first bound above its cell count
+        # size class of each grid: index of the first bound above its cell count;
+        # grids of at least solo_cells cells form the last class, one lane each
         bounds = sorted(class_cells)
         self.klass = [sum(1 for c in bounds if p.nx * p.ny >= c) for p in problems]
-        used = sorted(set(self.klass))
+        self.solo = [solo_cells is not None and p.nx * p.ny >= solo_cells for p in problems]
+        solo_class = len(bounds) + 1
+        self.klass = [solo_class if so else k for k, so in zip(self.klass, self.solo)]
+        used = sorted({k for k, so in zip(self.klass, self.solo) if not so})
         # class_grid: workgroups per launch of each class's batch (None: 2048),
         # so that a large grid's kernels can leave CUs to the other classes
         grids = class_grid or {}
@@ -80,6 +128,15 @@ class Server:
                                  grid=grids.get(k)) for k in used}
         self.in_flight_bytes = 0
         self.busy = [False] * len(self.solvers)
+        self._solo_done = _queue.Queue()
+        self.lanes = {g: _SoloLane(S, self, self._solo_done)
+                      for g, (S, so) in enumerate(zip(self.solvers, self.solo)) if so}
+        self._solo_flying = 0
+
+    def close(self):
+        for lane in self.lanes.values():
+            lane.close()
+        self.lanes = {}
 
     def fits(self, grid):
         return self.budget is None or self.in_flight_bytes + self.item_bytes[grid] <= self.budget
@@ -97,6 +154,13 @@ class Server:
 
     def admit(self, req, now):
         k = self.klass[req.grid]
+        if self.solo[req.grid]:
+            self.in_flight_bytes += self.item_bytes[req.grid]
+            self.busy[req.grid] = True
+            req.admitted = now
+            self._solo_flying += 1
+            self.lanes[req.grid].submit(req)
+            return ("solo", req.rid)
         slot = self.batches[k].add(self.solvers[req.grid], req.b.unsqueeze(0),
                                    X0=req.x0.unsqueeze(0), tol=self.tol,
                                    inner_tol=self.inner_tol, max_outer=self.max_outer, tag=req.rid)
@@ -113,6 +177,16 @@ class Server:
                 B.launch(poll_chunks)
                 self._flying.add(k)
         while True:
+            out = []
+            while True:
+                try:
+                    req, X, q = self._solo_done.get_nowait()
+                except _queue.Empty:
+                    break
+                self._solo_flying -= 1
+                out.append((("solo", req.rid), X, q))
+            if out:
+                return out
             for k in list(self._flying):
                 ready, _ = self.batches[k].wait(block=False)
                 if not ready:
@@ -132,7 +206,7 @@ class Server:
         req.status = q["status"]
         req.true_relres = q["true_relres"][0]
         req.outer, req.inner = q["outer"], q["inner_total"]
-        req.x = X[0]
+        req.x = X[0] if X is not None else None
         self.busy[req.grid] = False
         self.in_flight_bytes -= self.item_bytes[req.grid]
 
@@ -149,6 +223,7 @@ class Server:
         slots = {}
         done = []
         self._flying = set()
+        held = set()            # requests that waited for memory at least once
         while pending or queue or slots:
             now = clock() - t0
             while pending and pending[0].arrival <= now:
@@ -163,12 +238,15 @@ class Server:
             rest = []
             for req in queue:
                 k = self.klass[req.grid]
-                if (not self.busy[req.grid] and k not in self._flying
-                        and sum(1 for key in slots if key[0] == k) < self.batch_capacity()
-                        and self.fits(req.grid)):
+                free = (self.solo[req.grid] or
+                        (k not in self._flying
+                         and sum(1 for key in slots if key[0] == k) < self.batch_capacity()))
+                if not self.busy[req.grid] and free and self.fits(req.grid):
                     make_rhs(req)
                     slots[self.admit(req, clock() - t0)] = req
                 else:
+                    if not self.busy[req.grid] and free:
+                        held.add(req.rid)
                     rest.append(req)
             queue = rest
             if not slots:
@@ -184,6 +262,7 @@ class Server:
                 if on_done:
                     on_done(req)
         self._drain()
+        self.held_for_memory = len(held)
         return done
 
     def _drain(self):
@@ -218,7 +297,7 @@ class Server:
             slots[self.admit(req, clock() - t0)] = req
 
         while slots or waiting:
-            for g in [g for g in waiting if self.klass[g] not in self._flying]:
+            for g in [g for g in waiting if self.solo[g] or self.klass[g] not in self._flying]:
                 waiting.remove(g)
                 submit(g)
             if not slots:

@@ -138,3 +138,43 @@ def test_coupled_time_steps(setup, ora):
         got = stepper.eta[g][1].cpu().numpy()
         assert np.array_equal(got, eta[1])
         say("  grid", g, "steps", len(rs), "inner iterations", [r.inner for r in rs])
+
+
+def test_solo_lane_for_large_grids(setup, ora):
+    """Grids at or above solo_cells are served by a lane of their own (the
+    single-grid mixed solve on a host thread) while the others share a batch:
+    every result meets the FP64 target, equals the same solve run alone bit
+    for bit, steps of one grid stay sequential, and the lane's work overlaps
+    the batch's."""
+    P, serve, probs = setup
+    big = orca.orca_problem(182, 149, 200)
+    grids = probs + [big]
+    say("solo lane: 182x149 beside 3 batched grids")
+    srv = serve.Server(grids, drop_tol=0.1, device="cuda", chunk=8, solo_cells=20_000)
+    try:
+        assert srv.solo == [False, False, False, True]
+        reqs = serve.poisson_arrivals(rate=300.0, count=16, n_grids=len(grids), seed=13)
+        stepper = serve.TimeStepper(grids, torch.device("cuda"), seed=6)
+        done = srv.run(reqs, make_rhs=stepper, on_done=stepper.done)
+        assert len(done) == 16 and srv.in_flight_bytes == 0 and not any(srv.busy)
+        solo = [r for r in done if r.grid == 3]
+        assert solo
+        for r in done:
+            p = grids[r.grid]
+            b, x = r.b.cpu().numpy(), r.x.cpu().numpy()
+            assert r.status == 0
+            assert np.linalg.norm(b - ora.spmv(p, x)) / np.linalg.norm(b) <= 1e-10
+            if r.grid == 3:
+                alone = srv.solvers[3].solve_mixed(r.b, x0=r.x0, tol=1e-10, inner_tol=1e-5,
+                                                   max_outer=30)
+                assert torch.equal(alone.x, r.x)
+        rs = sorted(solo, key=lambda r: r.admitted)
+        assert all(a.finished <= b.admitted for a, b in zip(rs, rs[1:]))
+        others = [r for r in done if r.grid != 3]
+        overlap = sum(any(o.admitted < s.finished and o.finished > s.admitted for o in others)
+                      for s in solo)
+        say("  solo steps", len(solo), "overlapping batched steps", overlap,
+            "per class", serve.latency_stats(done, srv.klass)["per_class"])
+        assert overlap > 0
+    finally:
+        srv.close()
