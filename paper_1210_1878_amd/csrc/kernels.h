@@ -47,10 +47,6 @@ namespace pcga {
 
 enum : int { kStOk = 0, kStNoconv = 1, kStBreak = -2, kStNan = -3 };
 
-__device__ __forceinline__ int logical_block(int b, int G) {
-    const int q = G >> 3, rem = G & 7, x = b & 7, i = b >> 3;
-    return x * q + (x < rem ? x : rem) + i;
-}
 
 __device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v < INFINITY; }
 __device__ __forceinline__ bool is_bad(double v) { return !(v == v) || v == INFINITY || v == -INFINITY; }
@@ -167,10 +163,6 @@ __device__ __forceinline__ void put_partials(double (&v)[NV], double *part, int 
     }
 }
 
-__device__ __forceinline__ void range_of(int L, int G, int total, int &a, int &b) {
-    a = (int)(((int64_t)L * total) / G);
-    b = (int)(((int64_t)(L + 1) * total) / G);
-}
 
 // Neighbour indices and couplings of cell k, branch-free: an absent
 // neighbour points at k itself with a zero coupling.
@@ -259,10 +251,11 @@ __device__ __forceinline__ SliceMeta header_of(const SliceHeaders &h, int i) {
 //   bit 0: 16-bit distances instead of 32-bit columns;
 //   bit 1: indices read with non-temporal loads;
 //   bit 2: values read with non-temporal loads.
+//   bit 3 (Z^T kernel only): the solution x read and written non-temporally.
 // Non-temporal reads keep a stream out of the caches, so that the data the
 // host chose to keep resident in the 256 MB memory-side cache (the vectors,
 // then as much of Z as fits) is not evicted by a stream that cannot fit.
-constexpr int kFmtNarrow = 1, kFmtNtIdx = 2, kFmtNtVal = 4;
+constexpr int kFmtNarrow = 1, kFmtNtIdx = 2, kFmtNtVal = 4, kFmtNtX = 8;
 
 template <bool NT, typename P>
 __device__ __forceinline__ P stream_load(const P *p) {
@@ -621,7 +614,7 @@ __global__ __launch_bounds__(kBS) void k_zt(DevSell<T> Zt, const T *__restrict__
         o.rj = rcur[rw];
         o.qj = FUSED ? q[rw] : T(0);
         o.dj = FUSED ? dcur[rw] : T(0);
-        o.xj = FUSED ? x[rw] : T(0);
+        o.xj = FUSED ? stream_load<(FMT & kFmtNtX) != 0>(x + rw) : T(0);
         o.ij = dinv[rw];
         return o;
     };
@@ -632,7 +625,10 @@ __global__ __launch_bounds__(kBS) void k_zt(DevSell<T> Zt, const T *__restrict__
             const T rj = FUSED ? fma(-at, o.qj, o.rj) : o.rj;
             if (FUSED) {
                 rnext[row] = rj;
-                x[row] = fma(at, o.dj, o.xj);
+                if (FMT & kFmtNtX)
+                    __builtin_nontemporal_store(fma(at, o.dj, o.xj), x + row);
+                else
+                    x[row] = fma(at, o.dj, o.xj);
                 rr += (double)rj * (double)rj;
             }
             t[row] = (acc + rj) * o.ij;

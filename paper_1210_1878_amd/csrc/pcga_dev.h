@@ -27,6 +27,8 @@ constexpr int kMaxBand = 8;          // widest band stored by diagonals
 // iteration reads are kept resident up to 95% of it (see cache_plan).
 constexpr double kMallBytes = 268435456.0;
 constexpr double kResidentBudget = 0.95 * kMallBytes;
+// Above this share of the cache the resident set sheds the solution vector.
+constexpr double kSpillFraction = 0.90;
 constexpr int kSlotCells = 4096;   // cells per workgroup of a batch slot (target)
 
 // Workgroups of a batch slot: a function of the grid alone, so that a slot's
@@ -34,6 +36,21 @@ constexpr int kSlotCells = 4096;   // cells per workgroup of a batch slot (targe
 inline int slot_blocks(int64_t n) {
     const int64_t g = (n + kSlotCells - 1) / kSlotCells;
     return (int)(g < 1 ? 1 : (g > kMaxBlocks ? kMaxBlocks : g));
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; logical_block maps
+// the hardware index so that the logical blocks of one XCD are consecutive
+// (then contiguous cell or slice ranges of one XCD share its L2: grid
+// neighbours and gathered rows are read from the same L2).
+__device__ __forceinline__ int logical_block(int b, int G) {
+    const int q = G >> 3, rem = G & 7, x = b & 7, i = b >> 3;
+    return x * q + (x < rem ? x : rem) + i;
+}
+
+// Range [a, b) of `total` items of logical block L out of G.
+__device__ __forceinline__ void range_of(int L, int G, int total, int &a, int &b) {
+    a = (int)(((int64_t)L * total) / G);
+    b = (int)(((int64_t)(L + 1) * total) / G);
 }
 
 // Five-point operator in A5 form, device copy.  inv_nx = 1/nx (row index by

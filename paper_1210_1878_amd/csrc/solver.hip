@@ -295,9 +295,19 @@ void cache_plan(pcga_solver &S, const HostLayouts &H) {
     double used = 9.0 * w * (double)S.n + op_bytes;
     int kept = 0;
     while (kept < 4 && used + streams[kept] <= kResidentBudget) used += streams[kept++];
+    // A resident set this close to the cache's size made the iteration time
+    // depend on where the workspace lies (at 1442 x 1021, 244 MB, 91% full:
+    // 96-106 us over twelve bases); the solution x, read and written once per
+    // iteration and never gathered, is then streamed instead (87% full:
+    // 98.0-98.9 us).
+    bool nt_x = false;
+    if (S.precision == PCGA_FP64 && used > kSpillFraction * kMallBytes) {
+        used -= w * (double)S.n;
+        nt_x = true;
+    }
     // streams not kept: Z idx (kept < 4), Z^T idx (< 3), Z val (< 2), Z^T val (< 1)
     const int nar = H.zt.narrow ? kFmtNarrow : 0;
-    S.fmt_zt = nar | (kept < 3 ? kFmtNtIdx : 0) | (kept < 1 ? kFmtNtVal : 0);
+    S.fmt_zt = nar | (kept < 3 ? kFmtNtIdx : 0) | (kept < 1 ? kFmtNtVal : 0) | (nt_x ? kFmtNtX : 0);
     S.fmt_z = nar | (kept < 4 ? kFmtNtIdx : 0) | (kept < 2 ? kFmtNtVal : 0);
 }
 
@@ -932,7 +942,15 @@ IterBufs<float> bufs32(pcga_solver &S) {
 template <typename T, bool FUSED, typename... Args>
 void launch_zt(const DevSell<T> &M, int fmt, int grid, hipStream_t st, Args... args) {
 #define PCGA_K(F) k_zt<T, FUSED, F>
-    PCGA_FMT_CASES(PCGA_K, M, args...)
+    if (FUSED && (fmt & kFmtNtX)) {
+        fmt &= ~kFmtNtX;
+#define PCGA_KX(F) k_zt<T, FUSED, F | kFmtNtX>
+        PCGA_FMT_CASES(PCGA_KX, M, args...)
+#undef PCGA_KX
+    } else {
+        fmt &= ~kFmtNtX;
+        PCGA_FMT_CASES(PCGA_K, M, args...)
+    }
 #undef PCGA_K
 }
 

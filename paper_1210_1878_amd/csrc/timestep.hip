@@ -40,10 +40,14 @@ static __global__ __launch_bounds__(kTsBlock) void k_ts_rhs(int nx, int ny, int 
                                                     const double *__restrict__ mv,
                                                     double *__restrict__ b) {
 #pragma clang fp contract(off)
-    const int64_t n = (int64_t)nx * ny;
-    for (int64_t k = blockIdx.x * (int64_t)kTsBlock + threadIdx.x; k < n;
-         k += (int64_t)gridDim.x * kTsBlock) {
-        const int j = (int)(k / nx), i = (int)(k - (int64_t)j * nx);
+    // contiguous cell ranges, consecutive on each XCD: the west and south
+    // face values a cell reads were, mostly, fetched by a workgroup of the
+    // same XCD (its L2)
+    const int n = nx * ny;
+    int c0, c1;
+    range_of(logical_block(blockIdx.x, gridDim.x), gridDim.x, n, c0, c1);
+    for (int k = c0 + threadIdx.x; k < c1; k += kTsBlock) {
+        const int j = k / nx, i = k - j * nx;
         double fe = 0.0, fw = 0.0, fn = 0.0, fs = 0.0;
         if (i < nx - 1 || periodic) fe = e2u[k] * mu[k];
         if (i > 0)
