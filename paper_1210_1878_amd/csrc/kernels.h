@@ -488,10 +488,29 @@ __device__ __forceinline__ bool stop_test(CtlBlock *cb, double rr, int k) {
 // k_stencil: rho_k, beta; d_new = s + beta d_old; q = A d_new; (d_new,q) partials
 // par = k & 1 (fixed per position in a captured chunk; chunks are even).
 // ---------------------------------------------------------------------------
+// The grid is cut into tiles of kTileRows rows by kBS columns, one column per
+// thread and one tile per workgroup (a workgroup takes a contiguous range of
+// tiles when there are more tiles than workgroups).  Each thread reads s and
+// d_old of its column once, over the tile's rows and one halo row either
+// side, and keeps d_new of those rows in registers: they are its south and
+// north neighbours.  Rows of d_new and of the east couplings go through LDS
+// to the west and east neighbours; a few threads load the two halo columns
+// (periodic wrap included).  That is about 8 vector loads per cell where
+// gathering the five neighbours' s and d_old takes 15.  An absent neighbour
+// takes the cell's own d_new with a zero coupling, and the terms of
+// q = A d_new are added in increasing column order (apply_row).
 // STOP (diagonal preconditioner path, two launches per iteration): the stop
 // test on ||r_k|| from the previous k_jacobi's partials runs here first.
 // C: type of the coefficients and of the product's arithmetic (double also
 // for FP32 vectors; float for the mixed form with an FP32 operator).
+// Column held at a tile's LDS position for grid column i in [-1, nx]: the
+// periodic wrap, else clamped (a clamped column's value is never used).
+__device__ __forceinline__ int tile_col(int i, int nx, bool periodic) {
+    if (i < 0) return periodic ? nx - 1 : 0;
+    if (i >= nx) return (periodic && i == nx) ? 0 : nx - 1;
+    return i;
+}
+
 template <typename T, bool STOP, typename C = double>
 __global__ __launch_bounds__(kBS) void k_stencil(DevOp<C> A, const T *__restrict__ s,
                                                  const T *__restrict__ dold,
@@ -500,35 +519,58 @@ __global__ __launch_bounds__(kBS) void k_stencil(DevOp<C> A, const T *__restrict
     Ctl *c = &cb->c;
     if (c->done) return;
     const PartialsLoad<1> pr = load_partials<1>(P.rr, STOP ? g_sr : 0);
+    constexpr int TR = kTileRows, TH = kTileRows + 2, TW = kBS + 2;
+    __shared__ T vt[TH][TW];          // d_new of the tile, halo included
+    __shared__ C at[TR][kBS + 1];     // east couplings, column 0: the west halo
+    const int nx = A.nx, ny = A.ny;
+    const bool per = A.periodic != 0;
+    const int ntc = (nx + kBS - 1) / kBS;
+    const int ntiles = ntc * ((ny + TR - 1) / TR);
     const int G = gridDim.x, L = logical_block(blockIdx.x, G);
-    // Operands of kCPT cells per thread per step: every load of a step is issued
-    // before any arithmetic (branch-free neighbour indices, clamped cells).
-    struct Step {
-        T sv[kCPT][5], dv[kCPT][5];
-        Nbr<C> m[kCPT];
-        int kc[kCPT];
+    int t0, t1;
+    range_of(L, G, ntiles, t0, t1);
+    const int tx = threadIdx.x;
+    // halo thread h < 2 TH: row h >> 1, west (even h) or east (odd h) column
+    const bool halo = tx < 2 * TH;
+    struct Tile {
+        T sv[TH], dv[TH], hs, hd;
+        C an[TR + 1], ae[TR], dg[TR], hae;
     };
-    int c0, c1;
-    range_of(L, G, A.n, c0, c1);
-    auto load_step = [&](int base, Step &st) {
+    auto load_tile = [&](int tile, Tile &w) {
+        const int tr = tile / ntc, i0 = (tile - tr * ntc) * kBS, j0 = tr * TR;
+        const int i = tile_col(i0 + tx, nx, per);
 #pragma unroll
-        for (int u = 0; u < kCPT; u++) {
-            st.kc[u] = base + u * kBS;
-            const int kk = st.kc[u] < c1 ? st.kc[u] : (c1 > 0 ? c1 - 1 : 0);
-            st.m[u] = neighbours(A, kk);
-            const int idx[5] = {st.m[u].kS, st.m[u].kW, kk, st.m[u].kE, st.m[u].kN};
+        for (int r = 0; r < TH; r++) {
+            const int j = min(max(j0 - 1 + r, 0), ny - 1);
+            w.sv[r] = s[j * nx + i];
+            w.dv[r] = dold[j * nx + i];
+        }
 #pragma unroll
-            for (int e = 0; e < 5; e++) {
-                st.sv[u][e] = s[idx[e]];
-                st.dv[u][e] = dold[idx[e]];
-            }
+        for (int r = 0; r < TR + 1; r++) {
+            const int j = min(max(j0 - 1 + r, 0), ny - 1);
+            w.an[r] = A.an[j * nx + i];
+        }
+#pragma unroll
+        for (int r = 0; r < TR; r++) {
+            const int k = min(j0 + r, ny - 1) * nx + i;
+            w.ae[r] = A.ae[k];
+            w.dg[r] = A.diag[k];
+        }
+        if (halo) {
+            const int hr = tx >> 1;
+            const int j = min(max(j0 - 1 + hr, 0), ny - 1);
+            const int hi = tile_col((tx & 1) ? i0 + kBS : i0 - 1, nx, per);
+            w.hs = s[j * nx + hi];
+            w.hd = dold[j * nx + hi];
+            // threads of the tile's rows also bring the west column's coupling
+            const int jr = min(j0 + min(hr, TR - 1), ny - 1);
+            w.hae = A.ae[jr * nx + tile_col(i0 - 1, nx, per)];
         }
     };
     const PartialsLoad<1> pl = load_partials<1>(P.sr, g_sr);
-    int base = c0 + threadIdx.x;
-    Step st;
-    load_step(base, st);   // in flight during the reduction (clamped, also for an empty range)
-    __builtin_amdgcn_sched_barrier(0);   // keep every load above the partials' first use
+    Tile w;
+    if (t0 < t1) load_tile(t0, w);   // in flight during the reduction
+    __builtin_amdgcn_sched_barrier(0);
     const int k = c->kk[par];
     if (STOP && k > 0) {
         double rr[1];
@@ -549,23 +591,52 @@ __global__ __launch_bounds__(kBS) void k_stencil(DevOp<C> A, const T *__restrict
     if (blockIdx.x == 0 && threadIdx.x == 0) c->rho[par] = rho;
     const T bt = (T)beta;
     double acc = 0.0;
-    while (base < c1 + (int)threadIdx.x) {
+    for (int tile = t0; tile < t1; tile++) {
+        if (tile > t0) {
+            __syncthreads();   // the previous tile's LDS reads are done
+            load_tile(tile, w);
+        }
+        const int tr = tile / ntc, i0 = (tile - tr * ntc) * kBS, j0 = tr * TR;
+        T v[TH];
 #pragma unroll
-        for (int u = 0; u < kCPT; u++) {
-            if (st.kc[u] < c1) {
-                T v[5];
+        for (int r = 0; r < TH; r++) {
+            v[r] = fma(bt, w.dv[r], w.sv[r]);
+            vt[r][tx + 1] = v[r];
+        }
 #pragma unroll
-                for (int e = 0; e < 5; e++) v[e] = fma(bt, st.dv[u][e], st.sv[u][e]);
-                // the operator is applied in C (FP64, exact coefficients, also
-                // to FP32 vectors; or all FP32); q is rounded to T
-                const T y = (T)apply_row(st.m[u], (C)v[0], (C)v[1], (C)v[2], (C)v[3], (C)v[4]);
-                dnew[st.kc[u]] = v[2];
-                q[st.kc[u]] = y;
-                acc += (double)v[2] * (double)y;
+        for (int r = 0; r < TR; r++) at[r][tx + 1] = w.ae[r];
+        if (halo) {
+            vt[tx >> 1][(tx & 1) ? TW - 1 : 0] = fma(bt, w.hd, w.hs);
+            if ((tx & 1) == 0 && (tx >> 1) < TR) at[tx >> 1][0] = w.hae;
+        }
+        __syncthreads();
+        const int i = i0 + tx;
+        if (i < nx) {
+            const bool hasW = i > 0 || per;
+            const bool hasE = i < nx - 1 || per;
+#pragma unroll
+            for (int r = 0; r < TR; r++) {
+                const int j = j0 + r;
+                if (j < ny) {
+                    const T vC = v[r + 1];
+                    const T vS = j > 0 ? v[r] : vC;
+                    const T vN = j < ny - 1 ? v[r + 2] : vC;
+                    const T vW = hasW ? vt[r + 1][tx] : vC;
+                    const T vE = hasE ? vt[r + 1][tx + 2] : vC;
+                    Nbr<C> m;
+                    m.cS = j > 0 ? w.an[r] : C(0);
+                    m.cW = hasW ? at[r][tx] : C(0);
+                    m.cC = w.dg[r];
+                    m.cE = w.ae[r];
+                    m.cN = w.an[r + 1];
+                    const T y = (T)apply_row(m, (C)vS, (C)vW, (C)vC, (C)vE, (C)vN);
+                    const int kc = j * nx + i;
+                    dnew[kc] = vC;
+                    q[kc] = y;
+                    acc += (double)vC * (double)y;
+                }
             }
         }
-        base += kStep;
-        if (base < c1 + (int)threadIdx.x) load_step(base, st);
     }
     double pv[1] = {acc};
     put_partials<1>(pv, P.dq, L);

@@ -14,10 +14,18 @@ constexpr int kWavesPerBlock = kBS / kWave;
 #ifndef PCGA_CPT
 #define PCGA_CPT 1
 #endif
-constexpr int kCPT = PCGA_CPT;     // stencil cells per thread per step
-constexpr int kStep = kBS * kCPT;  // stencil cells per workgroup step
+constexpr int kCPT = PCGA_CPT;     // cells per thread per step (elementwise kernels)
+constexpr int kStep = kBS * kCPT;  // cells per workgroup step
 constexpr int kHistRing = 4096;    // residual-history ring (entries)
 constexpr int kMaxBlocks = 2048;   // workgroups per kernel = partial sums per reduction
+// k_stencil: grid rows per tile (tiles are kTileRows x kBS cells)
+#ifndef PCGA_TILE_ROWS
+#define PCGA_TILE_ROWS 4
+#endif
+constexpr int kTileRows = PCGA_TILE_ROWS;
+__host__ __device__ inline int tile_count(int nx, int ny) {
+    return ((nx + kBS - 1) / kBS) * ((ny + kTileRows - 1) / kTileRows);
+}
 // Default workgroups per kernel (256 CUs), as the autotuner picks them at
 // 1442 x 1021 with the default slice widths: FP64 4 per CU, mixed 6 per CU.
 constexpr int kDefaultBlocks = 1024;

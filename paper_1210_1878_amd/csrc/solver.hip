@@ -980,34 +980,34 @@ void launch_kernel(pcga_solver &S, const IterBufs<T> &B, int p, int which) {
             else if (a32_inner<T>(S)) {
                 if constexpr (std::is_same_v<T, float>) {
                     if (S.jacobi)
-                        k_stencil<T, true, float><<<S.g_st, kBS, 0, S.stream>>>(
+                        k_stencil<T, true, float><<<S.g_tile, kBS, 0, S.stream>>>(
                             S.A32, B.s, B.d[p], B.d[p ^ 1], B.q, B.cb, B.P, S.g_st, p);
                     else
-                        k_stencil<T, false, float><<<S.g_st, kBS, 0, S.stream>>>(
+                        k_stencil<T, false, float><<<S.g_tile, kBS, 0, S.stream>>>(
                             S.A32, B.s, B.d[p], B.d[p ^ 1], B.q, B.cb, B.P, S.g_prec(), p);
                 }
             } else if (S.jacobi)
-                k_stencil<T, true><<<S.g_st, kBS, 0, S.stream>>>(B.A, B.s, B.d[p], B.d[p ^ 1], B.q,
-                                                                 B.cb, B.P, S.g_st, p);
+                k_stencil<T, true><<<S.g_tile, kBS, 0, S.stream>>>(
+                    B.A, B.s, B.d[p], B.d[p ^ 1], B.q, B.cb, B.P, S.g_st, p);
             else
-                k_stencil<T, false><<<S.g_st, kBS, 0, S.stream>>>(B.A, B.s, B.d[p], B.d[p ^ 1], B.q,
-                                                                  B.cb, B.P, S.g_prec(), p);
+                k_stencil<T, false><<<S.g_tile, kBS, 0, S.stream>>>(
+                    B.A, B.s, B.d[p], B.d[p ^ 1], B.q, B.cb, B.P, S.g_prec(), p);
             break;
         case 1:
             if (S.jacobi) {
                 k_jacobi<T, false><<<S.g_st, kBS, 0, S.stream>>>(
                     B.dinv, B.r[p], B.q, B.d[p ^ 1], B.r[p ^ 1], B.x, B.s, (int)S.n, B.cb, B.P,
-                    S.g_st, p);
+                    S.g_dq(), p);
                 break;
             }
             if (S.band_q > 0) {
                 k_zt_band<T, true><<<S.g_st, kBS, 0, S.stream>>>(
                     B.zb, S.band_q, B.dinv, B.r[p], B.q, B.d[p ^ 1], B.r[p ^ 1], B.x, B.t, (int)S.n,
-                    B.cb, B.P, S.g_op(), p);
+                    B.cb, B.P, S.g_dq(), p);
                 break;
             }
             launch_zt<T, true>(B.zt, S.fmt_zt, S.g_zt, S.stream, B.dinv, (const T *)B.r[p], (const T *)B.q,
-                               (const T *)B.d[p ^ 1], B.r[p ^ 1], B.x, B.t, B.cb, B.P, S.g_op(), p);
+                               (const T *)B.d[p ^ 1], B.r[p ^ 1], B.x, B.t, B.cb, B.P, S.g_dq(), p);
             break;
         default:
             if (S.band_q > 0) {
@@ -1459,21 +1459,21 @@ int pcga_step_stencil(pcga_solver_t *S, const double *s_dev, const double *d_dev
     const int gc = (int)std::min<int64_t>(4096, (R.n + kBS - 1) / kBS);
     k_step_state<<<1, 1, 0, R.stream>>>(R.cb, R.P, beta);
     if (R.precision == PCGA_FP64) {
-        k_stencil<double, false><<<R.g_st, kBS, 0, R.stream>>>(R.A64, s_dev, d_dev, dnew_dev, q_dev,
-                                                               R.cb, R.P, 1, 0);
+        k_stencil<double, false><<<R.g_tile, kBS, 0, R.stream>>>(R.A64, s_dev, d_dev, dnew_dev,
+                                                                     q_dev, R.cb, R.P, 1, 0);
     } else {
         k_convert<double, float><<<gc, kBS, 0, R.stream>>>((int)R.n, s_dev, R.s32);
         k_convert<double, float><<<gc, kBS, 0, R.stream>>>((int)R.n, d_dev, R.d32[0]);
         if (R.precision == PCGA_MIXED_A32)
-            k_stencil<float, false, float><<<R.g_st, kBS, 0, R.stream>>>(
+            k_stencil<float, false, float><<<R.g_tile, kBS, 0, R.stream>>>(
                 R.A32, R.s32, R.d32[0], R.d32[1], R.q32, R.cb, R.P, 1, 0);
         else
-            k_stencil<float, false><<<R.g_st, kBS, 0, R.stream>>>(R.A64, R.s32, R.d32[0], R.d32[1],
-                                                                  R.q32, R.cb, R.P, 1, 0);
+            k_stencil<float, false><<<R.g_tile, kBS, 0, R.stream>>>(
+                R.A64, R.s32, R.d32[0], R.d32[1], R.q32, R.cb, R.P, 1, 0);
         k_convert<float, double><<<gc, kBS, 0, R.stream>>>((int)R.n, R.d32[1], dnew_dev);
         k_convert<float, double><<<gc, kBS, 0, R.stream>>>((int)R.n, R.q32, q_dev);
     }
-    k_step_dq<<<1, kBS, 0, R.stream>>>(R.P, R.g_st);
+    k_step_dq<<<1, kBS, 0, R.stream>>>(R.P, R.g_dq());
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(dq, R.P.res, sizeof(double), hipMemcpyDeviceToHost, R.stream));
     HIP_TRY(hipStreamSynchronize(R.stream));

@@ -50,6 +50,7 @@ struct pcga_solver {
     hipEvent_t ev[2] = {nullptr, nullptr};
 
     int g_st = 1, g_zt = 1, g_z = 1;
+    int g_tile = 1;   // k_stencil workgroups (five-point operator)
     int max_blocks = pcga::kDefaultBlocks;
     int chunk = 32;
     bool use_graph = true;
@@ -84,6 +85,10 @@ struct pcga_solver {
         };
         const int nsteps = (int)((n + pcga::kStep - 1) / pcga::kStep);
         g_st = std::max(1, std::min(nsteps, cap(0)));
+        // one tile per workgroup up to kMaxBlocks (its loads all in flight at
+        // once), unless capped explicitly
+        g_tile = std::max(1, std::min(pcga::tile_count(nx, ny),
+                                      g_cap[0] > 0 ? g_cap[0] : pcga::kMaxBlocks));
         const int nsz = precision == PCGA_FP64 ? zt64.nslices : zt32.nslices;
         const int nsr = precision == PCGA_FP64 ? z64.nslices : z32.nslices;
         g_zt = std::max(1, std::min((nsz + pcga::kWavesPerBlock - 1) / pcga::kWavesPerBlock, cap(1)));
@@ -94,4 +99,7 @@ struct pcga_solver {
     // workgroups of the operator kernels (their partial sums are read by the
     // next kernel): the five-point kernels, or the sliced-ELL sweep of a CSR A
     int g_op() const { return csr ? g_a : g_st; }
+    // workgroups writing the (d, q) partials of an iteration: the tiled
+    // five-point step, or the sliced-ELL sweep of a CSR A
+    int g_dq() const { return csr ? g_a : g_tile; }
 };
