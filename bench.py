@@ -38,19 +38,42 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+FMT_NT_X, FMT_X_DEF = 8, 16   # Z^T format bits: x streamed; x += alpha d in the stencil
+
+
+def x_in_stencil(S):
+    return bool(S.formats[0] & FMT_X_DEF)
+
+
 def kernel_names(word, formats):
     """Iteration kernels as rocprofv3 names them (template arguments: value
-    type, fused/dot flags, storage/read format of Z^T and Z)."""
+    type, fused/dot flags, storage/read format of Z^T and Z; the stencil's
+    coefficient type and x-update mode when the solver reports the update
+    moved into the stencil: 1, 2 with x streamed)."""
     t = "double" if word == 8 else "float"
-    return {"stencil": f"k_stencil<{t}, false>", "axpy_zt": f"k_zt<{t}, true, {formats[0]}>",
+    f0 = formats[0]
+    if f0 & FMT_X_DEF:
+        xd = 2 if f0 & FMT_NT_X else 1
+        return {"stencil": f"k_stencil<{t}, false, double, {xd}>",
+                "axpy_zt": f"k_zt<{t}, true, {f0 & ~FMT_NT_X}>",
+                "z_dot": f"k_z<{t}, true, false, {formats[1]}>"}
+    return {"stencil": f"k_stencil<{t}, false, double, 0>", "axpy_zt": f"k_zt<{t}, true, {f0}>",
             "z_dot": f"k_z<{t}, true, false, {formats[1]}>"}
 
 
-def kernel_bytes(n, nnz_off, word, index_bytes=4):
+def kernel_bytes(n, nnz_off, word, index_bytes=4, x_in_stencil=False):
     """Algorithmic bytes per launch of the three iteration kernels (each array
     once; a Z entry = its value + its index: a 4-byte column or a 2-byte
-    distance).  word = 8 (FP64) or 4 (FP32)."""
+    distance).  word = 8 (FP64) or 4 (FP32).  x_in_stencil: x += alpha d
+    done by the stencil (x read and written there; d and x not touched by
+    the Z^T kernel)."""
     e = word + index_bytes
+    if x_in_stencil:
+        return {
+            "stencil": 6 * word * n + 24 * n,      # s, d_old, x in; d, q, x out; FP64 diag, ae, an
+            "axpy_zt": 5 * word * n + e * nnz_off,  # r, q, D^-1 in; r', t out; Z^T
+            "z_dot": 3 * word * n + e * nnz_off,    # t, r' in; s out; Z
+        }
     return {
         "stencil": 4 * word * n + 24 * n,      # s, d_old in; d, q out; FP64 diag, ae, an in
         "axpy_zt": 8 * word * n + e * nnz_off,  # r, q, d, x, D^-1 in; r', x, t out; Z^T
@@ -58,13 +81,16 @@ def kernel_bytes(n, nnz_off, word, index_bytes=4):
     }
 
 
-def survey_bytes(n, nnz_off):
+def survey_bytes(n, nnz_off, x_in_stencil=False):
     """Compulsory bytes of one FP64 iteration by method step (FP64 values,
     int32 column per nonzero of Z, each array counted once per step):
     direction update + five-point product + (d,q) 56 n; alpha, the two axpys
-    and ||r||^2 48 n; t = D^-1 Z^T r 24 n + 12 nnz; s = Z t and (s,r)
-    24 n + 12 nnz.  The Z^T kernel fuses the second and third steps."""
-    return {"stencil": 56 * n, "axpy_zt": 48 * n + 24 * n + 12 * nnz_off,
+    and ||r||^2 48 n (r' = r - alpha q 24 n, x' = x + alpha d 24 n);
+    t = D^-1 Z^T r 24 n + 12 nnz; s = Z t and (s,r) 24 n + 12 nnz.  The Z^T
+    kernel fuses the second and third steps; with x_in_stencil the x axpy
+    is done by the stencil instead."""
+    xa = 24 * n if x_in_stencil else 0
+    return {"stencil": 56 * n + xa, "axpy_zt": 48 * n - xa + 24 * n + 12 * nnz_off,
             "z_dot": 24 * n + 12 * nnz_off, "iteration": 152 * n + 24 * nnz_off}
 
 
@@ -321,7 +347,14 @@ def bench_csr(P, torch, dev, log):
 
 SERVE_CLASS_CELLS = (2_000_000,)
 SERVE_SOLO_CELLS = 1_000_000   # grids served by a lane of their own (single-grid mixed solve)
-SERVE_BUDGET_FRAC = 0.6        # memory budget: this share of all grids' request vectors
+SERVE_BUDGET_FRAC = 0.6        # memory budget: the largest grid's request vectors plus this
+                               # share of all other grids' (every grid fits alone, not all at once)
+
+
+def serve_budget(item_bytes, frac=None):
+    frac = SERVE_BUDGET_FRAC if frac is None else frac
+    big = max(item_bytes)
+    return int(big + frac * (sum(item_bytes) - big))
 SERVE_GUESS = (2.0, -1.0)      # x0 = 2 D^{t-1} - D^{t-2}
 
 
@@ -365,7 +398,8 @@ def fp64_sequential(P, torch, dev, probs, seconds, log):
 
 
 def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=15.0,
-                class_cells=SERVE_CLASS_CELLS, coupled=False, compare_fp64=False):
+                class_cells=SERVE_CLASS_CELLS, coupled=False, compare_fp64=False,
+                solo_cells=SERVE_SOLO_CELLS, budget_frac=None):
     """Time-step solves on a catalogue of resident grids from 182x149 to
     4322x3059 (mixed precision to 1e-10, warm starts, continuous batching).
     Capacity first: a closed loop keeps every grid busy and gives each grid's
@@ -379,8 +413,8 @@ def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=
     t0 = time.perf_counter()
     probs = [orca.orca_problem(nx, ny, orca.CONFIG_SEED_BASE + 40 + i) for i, (nx, ny) in enumerate(shapes)]
     srv = serve.Server(probs, drop_tol=0.05, device=dev, chunk=16, class_cells=class_cells,
-                       solo_cells=SERVE_SOLO_CELLS)
-    srv.budget = int(SERVE_BUDGET_FRAC * sum(srv.item_bytes))
+                       solo_cells=solo_cells)
+    srv.budget = serve_budget(srv.item_bytes, budget_frac)
     log(f"serving: {len(probs)} resident grids ({srv.resident_bytes / 2**30:.2f} GiB), "
         f"request-memory budget {srv.budget / 2**20:.0f} MiB, setup {time.perf_counter() - t0:.1f}s")
     if coupled:
@@ -393,7 +427,7 @@ def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=
     srv.run(warm, make_rhs=stepper, on_done=stepper.done)
     srv.budget = None        # the closed loop keeps every grid busy
     done, el = srv.saturate(saturate_s, make_rhs=stepper, on_done=stepper.done)
-    srv.budget = int(SERVE_BUDGET_FRAC * sum(srv.item_bytes))
+    srv.budget = serve_budget(srv.item_bytes, budget_frac)
     cap = [sum(1 for r in done if r.grid == g) / el for g in range(len(probs))]
     cap_bytes = served_bytes(done, srv.solvers)
     log(f"capacity (closed loop, {el:.1f}s): {sum(cap):.1f} solves/s; per grid "
@@ -407,7 +441,7 @@ def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=
            "grids": [f"{a}x{b}" for a, b in shapes],
            "size_classes": "grids split at " + ", ".join(f"{c:,} cells" for c in sorted(class_cells))
                            + "; one batch per class, each on its own stream, running concurrently; "
-                           f"grids of at least {SERVE_SOLO_CELLS:,} cells are served by a lane of "
+                           f"grids of at least {solo_cells:,} cells are served by a lane of "
                            "their own (single-grid mixed solve on a host thread)",
            "grid_class": srv.klass,
            "solo_grids": [f"{a}x{b}" for (a, b), so in zip(shapes, srv.solo) if so],
@@ -424,7 +458,16 @@ def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=
     for i, L in enumerate(loads):
         reqs = serve.poisson_arrivals_per_grid([L * c for c in cap], horizon_s,
                                                seed=CONFIG_SERVE_SEED + 1 + i)
-        res = srv.run(reqs, make_rhs=stepper, on_done=stepper.done)
+        # a progress line about every 30 s of a long horizon
+        tick = {"t": time.perf_counter(), "n": 0}
+
+        def on_done(req, tick=tick, total=len(reqs), L=L):
+            stepper.done(req)
+            tick["n"] += 1
+            if time.perf_counter() - tick["t"] > 30.0:
+                tick["t"] = time.perf_counter()
+                log(f"load {L:.2f}: {tick['n']} of {total} requests done")
+        res = srv.run(reqs, make_rhs=stepper, on_done=on_done)
         st = serve.latency_stats(res, srv.klass, per_grid=True)
         st["held_for_memory"] = srv.held_for_memory
         span = max(r.finished for r in res) - min(r.arrival for r in res)
@@ -511,6 +554,16 @@ def main():
     ap.add_argument("--no-timestep", action="store_true", help="skip the coupled time steps")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner report")
     ap.add_argument("--no-csr", action="store_true", help="skip the general sparse operator")
+    ap.add_argument("--serve-horizon", type=float, default=15.0,
+                    help="seconds of Poisson arrivals per load factor in the serving runs")
+    ap.add_argument("--serve-solo-cells", type=int, default=SERVE_SOLO_CELLS,
+                    help="grids of at least this many cells get a serving lane of their own")
+    ap.add_argument("--serve-budget-frac", type=float, default=SERVE_BUDGET_FRAC,
+                    help="request-memory budget: the largest grid's vectors plus this share of "
+                         "the other grids' (1: never binding)")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the two serving workloads (a long horizon gives the largest "
+                         "grids enough requests) and print their results as one JSON line")
     ap.add_argument("--kernels-only", action="store_true",
                     help="profiling driver: a 256 MiB device copy (counter calibration), then the "
                          "three FP64 and FP32 iteration kernels, --reps launches each")
@@ -530,6 +583,17 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a ROCm device"
     dev = torch.device("cuda:0")
+    if args.serve_only:
+        out = {"serve_only": True, "horizon_s": args.serve_horizon,
+               "served": bench_serve(P, torch, dev, log, horizon_s=args.serve_horizon,
+                                     solo_cells=args.serve_solo_cells,
+                                     budget_frac=args.serve_budget_frac),
+               "served_coupled_time_steps": bench_serve(
+                   P, torch, dev, lambda m: log("coupled " + m), loads=(0.8,), coupled=True,
+                   horizon_s=args.serve_horizon, solo_cells=args.serve_solo_cells,
+                   budget_frac=args.serve_budget_frac)}
+        print(json.dumps(out), flush=True)
+        return
     t0 = time.perf_counter()
     p = orca.orca_problem(NX, NY, orca.CONFIG_SEED_BASE + 2)
     log(f"generated {NX}x{NY} in {time.perf_counter() - t0:.1f}s")
@@ -579,8 +643,8 @@ def main():
             S64.ts_guess(faces[1], faces[3], 2.0, -1.0)
             S64.ts_eta(faces[1], faces[3], 0.5)
         torch.cuda.synchronize()
-        kb = kernel_bytes(p.n, G.nnz_off, 8, S64.index_bytes)
-        kb32 = kernel_bytes(p.n, G.nnz_off, 4, Smx.index_bytes)
+        kb = kernel_bytes(p.n, G.nnz_off, 8, S64.index_bytes, x_in_stencil(S64))
+        kb32 = kernel_bytes(p.n, G.nnz_off, 4, Smx.index_bytes, x_in_stencil(Smx))
         for tag, t, byt in (("fp64", ms, kb), ("fp32", ms32, kb32)):
             log(tag + " " + ", ".join(f"{k}={t[i] * 1e3:.2f} us ({byt[k] / (t[i] * 1e-3) / 1e9:.0f} GB/s)"
                                       for i, k in enumerate(byt))
@@ -711,9 +775,9 @@ def main():
     # ---- roofline of the dominant kernel (HIP events on the solver stream) --
     ms = S64.profile_iteration(b, reps=100, mode=1)
     ms32 = Smx.profile_iteration(b, reps=100, mode=1)
-    kb = kernel_bytes(p.n, G.nnz_off, 8, S64.index_bytes)
-    kb32 = kernel_bytes(p.n, G.nnz_off, 4, Smx.index_bytes)
-    sb = survey_bytes(p.n, G.nnz_off)
+    kb = kernel_bytes(p.n, G.nnz_off, 8, S64.index_bytes, x_in_stencil(S64))
+    kb32 = kernel_bytes(p.n, G.nnz_off, 4, Smx.index_bytes, x_in_stencil(Smx))
+    sb = survey_bytes(p.n, G.nnz_off, x_in_stencil(S64))
     names = list(kb)
     gbs = {k: kb[k] / (ms[i] * 1e-3) / 1e9 for i, k in enumerate(names)}
     gbs32 = {k: kb32[k] / (ms32[i] * 1e-3) / 1e9 for i, k in enumerate(names)}
@@ -726,7 +790,7 @@ def main():
     # land cells are identity rows with no Z entries: the same per-iteration
     # bytes counted over ocean cells only (Z entries are all ocean)
     n_ocean = int(p.ocean.sum())
-    b_iter_ocean = sum(kernel_bytes(n_ocean, G.nnz_off, 8, S64.index_bytes).values())
+    b_iter_ocean = sum(kernel_bytes(n_ocean, G.nnz_off, 8, S64.index_bytes, x_in_stencil(S64)).values())
     b_iter32 = sum(kb32.values())
     it_time = ms[3] * 1e-3
     kname = kernel_names(8, S64.formats)[names[dom]]
@@ -742,8 +806,11 @@ def main():
                             "to memory, including reads served by the 256 MiB memory-side cache, "
                             "so an upper bound of the HBM traffic (" + tnote + ")",
             "bytes_per_launch": dom_bytes,
-            "bytes_model": "method steps alpha + axpys + ||r||^2 (48 n) and D^-1 Z^T r "
-                           "(24 n + 12 nnz_off), FP64 values and int32 indices",
+            "bytes_model": ("method steps alpha, r' = r - alpha q and ||r||^2 (24 n; the x axpy "
+                            "is done by the stencil) and D^-1 Z^T r (24 n + 12 nnz_off)"
+                            if x_in_stencil(S64) else
+                            "method steps alpha + axpys + ||r||^2 (48 n) and D^-1 Z^T r "
+                            "(24 n + 12 nnz_off)") + ", FP64 values and int32 indices",
             "ms_per_launch": ms[dom],
             "rocprof_us_per_launch": rp_us,
             "frac_rocprof": None if rp_us is None else round(dom_bytes / (rp_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
@@ -755,9 +822,14 @@ def main():
                               "model": "152 n + 24 nnz_off bytes per FP64 iteration"}}
 
     batched = None if args.no_batch else bench_batch(P, torch, dev, log)
-    served = None if args.no_serve else bench_serve(P, torch, dev, log, compare_fp64=True)
+    served = None if args.no_serve else bench_serve(P, torch, dev, log, compare_fp64=True,
+                                                    horizon_s=args.serve_horizon,
+                                                    solo_cells=args.serve_solo_cells,
+                                                    budget_frac=args.serve_budget_frac)
     served_coupled = None if args.no_serve or args.no_timestep else bench_serve(
-        P, torch, dev, lambda m: log("coupled " + m), loads=(0.8,), coupled=True)
+        P, torch, dev, lambda m: log("coupled " + m), loads=(0.8,), coupled=True,
+        horizon_s=args.serve_horizon, solo_cells=args.serve_solo_cells,
+        budget_frac=args.serve_budget_frac)
 
     cpu = None
     err_ora = err_a32_ora = None

@@ -227,7 +227,14 @@ int pcga_solver_create_ex(const pcga_a5_t *A, const pcga_ainv_t *F, int precisio
  * formats[0], formats[1]: how Z^T and Z are stored and read (bit 0: 16-bit
  * distances; bit 1: indices, bit 2: values read with non-temporal loads,
  * chosen so that the rest of an iteration's data fits the 256 MiB
- * memory-side cache); formats[2]: q when every entry of Z lies within q <= 8
+ * memory-side cache; formats[0] only: bit 3, the solution x read and
+ * written with non-temporal loads and stores, bit 4, the update
+ * x += alpha d of Algorithm 1 applied by the next iteration's five-point
+ * kernel instead of the Z^T kernel, which then reads neither d nor x: the
+ * FP32 inner iterations of a mixed solve of a five-point operator with a
+ * sliced-ELL Z, where the bytes above count one vector pass less, 80 n);
+ * formats[2]:
+ * q when every entry of Z lies within q <= 8
  * rows above the diagonal (e.g. the banded factor of T), which the solve
  * then applies from diagonals (no index arrays, no gathers), else 0.  Any
  * output pointer may be NULL. */

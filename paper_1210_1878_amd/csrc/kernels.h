@@ -255,7 +255,9 @@ __device__ __forceinline__ SliceMeta header_of(const SliceHeaders &h, int i) {
 // Non-temporal reads keep a stream out of the caches, so that the data the
 // host chose to keep resident in the 256 MB memory-side cache (the vectors,
 // then as much of Z as fits) is not evicted by a stream that cannot fit.
-constexpr int kFmtNarrow = 1, kFmtNtIdx = 2, kFmtNtVal = 4, kFmtNtX = 8;
+//   bit 4 (Z^T kernel only): x += alpha d left to the next iteration's
+//   stencil (k_zt neither reads d and x nor writes x).
+constexpr int kFmtNarrow = 1, kFmtNtIdx = 2, kFmtNtVal = 4, kFmtNtX = 8, kFmtXDef = 16;
 
 template <bool NT, typename P>
 __device__ __forceinline__ P stream_load(const P *p) {
@@ -503,6 +505,12 @@ __device__ __forceinline__ bool stop_test(CtlBlock *cb, double rr, int k) {
 // test on ||r_k|| from the previous k_jacobi's partials runs here first.
 // C: type of the coefficients and of the product's arithmetic (double also
 // for FP32 vectors; float for the mixed form with an FP32 operator).
+// XD (x update deferred from the previous iteration's k_zt, whose alpha is
+// in the control block): 0 none; 1 x += alpha_{k-1} d_old on the tile's
+// cells for k > 0 (the same fma on the same values as k_zt would do, so x
+// is bitwise the same); 2 the same with x streamed non-temporally.  The
+// update of the iteration that ends a solve is left pending and applied by
+// k_x_pending.
 // Column held at a tile's LDS position for grid column i in [-1, nx]: the
 // periodic wrap, else clamped (a clamped column's value is never used).
 __device__ __forceinline__ int tile_col(int i, int nx, bool periodic) {
@@ -511,11 +519,12 @@ __device__ __forceinline__ int tile_col(int i, int nx, bool periodic) {
     return i;
 }
 
-template <typename T, bool STOP, typename C = double>
+template <typename T, bool STOP, typename C = double, int XD = 0>
 __global__ __launch_bounds__(kBS) void k_stencil(DevOp<C> A, const T *__restrict__ s,
                                                  const T *__restrict__ dold,
                                                  T *__restrict__ dnew, T *__restrict__ q,
-                                                 CtlBlock *cb, Partials P, int g_sr, int par) {
+                                                 T *__restrict__ x, CtlBlock *cb, Partials P,
+                                                 int g_sr, int par) {
     Ctl *c = &cb->c;
     if (c->done) return;
     const PartialsLoad<1> pr = load_partials<1>(P.rr, STOP ? g_sr : 0);
@@ -535,6 +544,7 @@ __global__ __launch_bounds__(kBS) void k_stencil(DevOp<C> A, const T *__restrict
     struct Tile {
         T sv[TH], dv[TH], hs, hd;
         C an[TR + 1], ae[TR], dg[TR], hae;
+        T xv[XD ? TR : 1];
     };
     auto load_tile = [&](int tile, Tile &w) {
         const int tr = tile / ntc, i0 = (tile - tr * ntc) * kBS, j0 = tr * TR;
@@ -555,6 +565,7 @@ __global__ __launch_bounds__(kBS) void k_stencil(DevOp<C> A, const T *__restrict
             const int k = min(j0 + r, ny - 1) * nx + i;
             w.ae[r] = A.ae[k];
             w.dg[r] = A.diag[k];
+            if (XD) w.xv[r] = stream_load<XD == 2>(x + k);
         }
         if (halo) {
             const int hr = tx >> 1;
@@ -588,8 +599,13 @@ __global__ __launch_bounds__(kBS) void k_stencil(DevOp<C> A, const T *__restrict
         return;
     }
     const double beta = (k == 0) ? 0.0 : rho / c->rho[par ^ 1];
-    if (blockIdx.x == 0 && threadIdx.x == 0) c->rho[par] = rho;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        c->rho[par] = rho;
+        if (XD && k > 0) c->xa = k - 1;
+    }
     const T bt = (T)beta;
+    const bool xup = XD && k > 0;
+    const T axp = xup ? (T)c->alpha : T(0);   // alpha_{k-1}
     double acc = 0.0;
     for (int tile = t0; tile < t1; tile++) {
         if (tile > t0) {
@@ -634,6 +650,11 @@ __global__ __launch_bounds__(kBS) void k_stencil(DevOp<C> A, const T *__restrict
                     dnew[kc] = vC;
                     q[kc] = y;
                     acc += (double)vC * (double)y;
+                    if (XD && xup) {
+                        const T xn = fma(axp, w.dv[r + 1], w.xv[XD ? r : 0]);
+                        if (XD == 2) __builtin_nontemporal_store(xn, x + kc);
+                        else x[kc] = xn;
+                    }
                 }
             }
         }
@@ -644,7 +665,8 @@ __global__ __launch_bounds__(kBS) void k_stencil(DevOp<C> A, const T *__restrict
 
 // ---------------------------------------------------------------------------
 // k_zt: t = D^-1 Z^T r'.  FUSED: alpha = rho_k / (d,q); r' = r - alpha q
-// (written to rnext), x += alpha d, ||r'||^2 partials.  Not fused: r' = r.
+// (written to rnext), x += alpha d (unless FMT has kFmtXDef: then the next
+// iteration's stencil applies it), ||r'||^2 partials.  Not fused: r' = r.
 // Rows of Z^T are the columns of Z; the unit diagonal is added last.
 // ---------------------------------------------------------------------------
 template <typename T, bool FUSED, int FMT>
@@ -678,14 +700,15 @@ __global__ __launch_bounds__(kBS) void k_zt(DevSell<T> Zt, const T *__restrict__
     struct OwnZt {
         T rj, qj, dj, xj, ij;
     };
+    constexpr bool XUPD = FUSED && !(FMT & kFmtXDef);   // x += alpha d here
     auto ownf = [&](const SliceMeta &m) {
         const int row = m.row0 + (lane >> m.lg);
         const int rw = row < Zt.nrows ? row : Zt.nrows - 1;
         OwnZt o;
         o.rj = rcur[rw];
         o.qj = FUSED ? q[rw] : T(0);
-        o.dj = FUSED ? dcur[rw] : T(0);
-        o.xj = FUSED ? stream_load<(FMT & kFmtNtX) != 0>(x + rw) : T(0);
+        o.dj = XUPD ? dcur[rw] : T(0);
+        o.xj = XUPD ? stream_load<(FMT & kFmtNtX) != 0>(x + rw) : T(0);
         o.ij = dinv[rw];
         return o;
     };
@@ -696,10 +719,12 @@ __global__ __launch_bounds__(kBS) void k_zt(DevSell<T> Zt, const T *__restrict__
             const T rj = FUSED ? fma(-at, o.qj, o.rj) : o.rj;
             if (FUSED) {
                 rnext[row] = rj;
-                if (FMT & kFmtNtX)
-                    __builtin_nontemporal_store(fma(at, o.dj, o.xj), x + row);
-                else
-                    x[row] = fma(at, o.dj, o.xj);
+                if (XUPD) {
+                    if (FMT & kFmtNtX)
+                        __builtin_nontemporal_store(fma(at, o.dj, o.xj), x + row);
+                    else
+                        x[row] = fma(at, o.dj, o.xj);
+                }
                 rr += (double)rj * (double)rj;
             }
             t[row] = (acc + rj) * o.ij;
@@ -717,7 +742,10 @@ __global__ __launch_bounds__(kBS) void k_zt(DevSell<T> Zt, const T *__restrict__
             return false;
         }
         const double alpha = c->rho[par] / dq[0];
-        if (blockIdx.x == 0 && threadIdx.x == 0) c->alpha = alpha;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            c->alpha = alpha;
+            c->ax = c->kk[par];
+        }
         at = (T)alpha;
         return true;
     };
@@ -1133,6 +1161,8 @@ __global__ __launch_bounds__(kBS) void k_fin_residual(CtlBlock *cb, Partials P, 
     c->kk[0] = 0;
     c->kk[1] = 0;
     c->k = 0;
+    c->ax = -1;
+    c->xa = -1;
     c->status = kStOk;
     c->done = 0;
     const double rel = (nb > 0.0) ? sqrt(v[1]) / nb : 0.0;
@@ -1204,6 +1234,8 @@ static __global__ __launch_bounds__(kBS) void k_fin_refine(CtlBlock *cb, Partial
     c->kk[0] = 0;
     c->kk[1] = 0;
     c->k = 0;
+    c->ax = -1;
+    c->xa = -1;
     c->status = kStOk;
     c->relres = 1.0;
     cb->hist[0] = 1.0;
@@ -1225,6 +1257,21 @@ static __global__ __launch_bounds__(kBS) void k_apply_a(DevOp<double> A, const d
 
 // v = 0 (a fill kernel rather than a memset, so that it is an ordinary node
 // when the caller captures the stream).
+// The x += alpha d of a solve's last iteration when the stencil that would
+// have applied it did not run (the solve stopped): pending when the last
+// alpha formed (iteration ax) is newer than the last update applied (xa).
+// d_new of iteration k is in d[(k & 1) ^ 1].
+template <typename T>
+__global__ __launch_bounds__(kBS) void k_x_pending(int n, T *__restrict__ x, const T *__restrict__ d0,
+                                                   const T *__restrict__ d1, const CtlBlock *cb) {
+    const Ctl *c = &cb->c;
+    const int ax = c->ax;
+    if (ax < 0 || ax <= c->xa) return;
+    const T a = (T)c->alpha;
+    const T *d = (ax & 1) ? d0 : d1;
+    for (int i = blockIdx.x * kBS + threadIdx.x; i < n; i += gridDim.x * kBS) x[i] = fma(a, d[i], x[i]);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBS) void k_zero(int n, T *__restrict__ v) {
     for (int k = blockIdx.x * kBS + threadIdx.x; k < n; k += gridDim.x * kBS) v[k] = T(0);

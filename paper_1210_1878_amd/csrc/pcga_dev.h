@@ -104,7 +104,10 @@ struct Ctl {
     int32_t kk[2];               // iteration count k, slot k & 1 (read by kernels)
     int32_t maxit, done, status;
     int32_t k;                   // iteration count for the host (never read by kernels)
-    int32_t pad[5];
+    // x += alpha_k d_k deferred to the next iteration's stencil: the last
+    // iteration whose alpha was formed, and the last whose update was applied
+    int32_t ax, xa;
+    int32_t pad[3];
 };
 
 struct CtlBlock {

@@ -598,6 +598,9 @@ int create_impl(const OpDesc &D, const pcga_ainv_t *F, int precision, int32_t sl
     //   zt: r, q, d, x, dinv read; r', x, t written; Z^T entries     8 n words + E_zt
     //   z:  t, r' read; s written; Z entries                         3 n words + E_z
     //   (an entry: its value and a 4-byte column or 2-byte distance)
+    //   with x += alpha d in the stencil (FP32 inner iteration): the stencil
+    //   also reads and writes x, the zt kernel no longer reads d and x nor
+    //   writes x: 1 n word less
     const double E = (double)S->sell_entries;
     S->index_bytes = H.zt.narrow ? 2 : 4;
     cache_plan(*S, H);
@@ -608,12 +611,15 @@ int create_impl(const OpDesc &D, const pcga_ainv_t *F, int precision, int32_t sl
     //   7 n words)
     if (S->csr)
         S->bytes_per_iter = 8.0 * 15.0 * n + 12.0 * (double)S->nnz_a + (8.0 + S->index_bytes) * E;
-    else if (precision == PCGA_FP64)
-        S->bytes_per_iter = 8.0 * 18.0 * n + (8.0 + S->index_bytes) * E;
-    else if (precision == PCGA_MIXED_A32)
-        S->bytes_per_iter = 4.0 * 15.0 * n + 12.0 * n + (4.0 + S->index_bytes) * E;
-    else
-        S->bytes_per_iter = 4.0 * 15.0 * n + 24.0 * n + (4.0 + S->index_bytes) * E;
+    else {
+        const double words = S->x_deferred() ? 14.0 : 15.0;
+        if (precision == PCGA_FP64)
+            S->bytes_per_iter = 8.0 * words * n + 24.0 * n + (8.0 + S->index_bytes) * E;
+        else if (precision == PCGA_MIXED_A32)
+            S->bytes_per_iter = 4.0 * words * n + 12.0 * n + (4.0 + S->index_bytes) * E;
+        else
+            S->bytes_per_iter = 4.0 * words * n + 24.0 * n + (4.0 + S->index_bytes) * E;
+    }
     *out = S;
     return PCGA_OK;
 }
@@ -857,7 +863,7 @@ int pcga_solver_info(const pcga_solver_t *S, int64_t *n, int64_t *nnz_off, int32
     if (!S) return fail(PCGA_EINVAL, "S is NULL");
     if (index_bytes) *index_bytes = S->index_bytes;
     if (formats) {
-        formats[0] = S->fmt_zt;
+        formats[0] = S->fmt_zt | (S->x_deferred() ? kFmtXDef : 0);
         formats[1] = S->fmt_z;
         formats[2] = S->band_q;
     }
@@ -939,10 +945,16 @@ IterBufs<float> bufs32(pcga_solver &S) {
         default: KERNEL(7)<<<grid, kBS, 0, st>>>(__VA_ARGS__); break;    \
     }
 
+// xdef: the x update is left to the next stencil (k_zt then ignores kFmtNtX)
 template <typename T, bool FUSED, typename... Args>
-void launch_zt(const DevSell<T> &M, int fmt, int grid, hipStream_t st, Args... args) {
+void launch_zt(const DevSell<T> &M, int fmt, bool xdef, int grid, hipStream_t st, Args... args) {
 #define PCGA_K(F) k_zt<T, FUSED, F>
-    if (FUSED && (fmt & kFmtNtX)) {
+    if (FUSED && xdef) {
+        fmt &= ~kFmtNtX;
+#define PCGA_KD(F) k_zt<T, FUSED, F | kFmtXDef>
+        PCGA_FMT_CASES(PCGA_KD, M, args...)
+#undef PCGA_KD
+    } else if (FUSED && (fmt & kFmtNtX)) {
         fmt &= ~kFmtNtX;
 #define PCGA_KX(F) k_zt<T, FUSED, F | kFmtNtX>
         PCGA_FMT_CASES(PCGA_KX, M, args...)
@@ -968,6 +980,21 @@ bool a32_inner(const pcga_solver &S) {
     return std::is_same_v<T, float> && S.precision == PCGA_MIXED_A32;
 }
 
+// Where x += alpha d is left to the next iteration's stencil (which has
+// d_old at hand): k_zt then reads neither d nor x (one vector pass less).
+bool x_deferred(const pcga_solver &S) { return S.x_deferred(); }
+
+// Stencil of the deferred path: XD 1 (x resident) or 2 (x streamed).
+template <typename T, typename C>
+void launch_stencil_xd(pcga_solver &S, const DevOp<C> &A, const IterBufs<T> &B, int p, int g_sr) {
+    if (S.fmt_zt & kFmtNtX)
+        k_stencil<T, false, C, 2><<<S.g_tile, kBS, 0, S.stream>>>(A, B.s, B.d[p], B.d[p ^ 1], B.q,
+                                                                  B.x, B.cb, B.P, g_sr, p);
+    else
+        k_stencil<T, false, C, 1><<<S.g_tile, kBS, 0, S.stream>>>(A, B.s, B.d[p], B.d[p ^ 1], B.q,
+                                                                  B.x, B.cb, B.P, g_sr, p);
+}
+
 // One kernel of iteration parity p: 0 stencil, 1 axpy + Z^T, 2 Z + dot.
 template <typename T>
 void launch_kernel(pcga_solver &S, const IterBufs<T> &B, int p, int which) {
@@ -981,17 +1008,21 @@ void launch_kernel(pcga_solver &S, const IterBufs<T> &B, int p, int which) {
                 if constexpr (std::is_same_v<T, float>) {
                     if (S.jacobi)
                         k_stencil<T, true, float><<<S.g_tile, kBS, 0, S.stream>>>(
-                            S.A32, B.s, B.d[p], B.d[p ^ 1], B.q, B.cb, B.P, S.g_st, p);
+                            S.A32, B.s, B.d[p], B.d[p ^ 1], B.q, nullptr, B.cb, B.P, S.g_st, p);
+                    else if (x_deferred(S))
+                        launch_stencil_xd<T, float>(S, S.A32, B, p, S.g_prec());
                     else
                         k_stencil<T, false, float><<<S.g_tile, kBS, 0, S.stream>>>(
-                            S.A32, B.s, B.d[p], B.d[p ^ 1], B.q, B.cb, B.P, S.g_prec(), p);
+                            S.A32, B.s, B.d[p], B.d[p ^ 1], B.q, nullptr, B.cb, B.P, S.g_prec(), p);
                 }
             } else if (S.jacobi)
                 k_stencil<T, true><<<S.g_tile, kBS, 0, S.stream>>>(
-                    B.A, B.s, B.d[p], B.d[p ^ 1], B.q, B.cb, B.P, S.g_st, p);
+                    B.A, B.s, B.d[p], B.d[p ^ 1], B.q, nullptr, B.cb, B.P, S.g_st, p);
+            else if (x_deferred(S))
+                launch_stencil_xd<T, double>(S, B.A, B, p, S.g_prec());
             else
                 k_stencil<T, false><<<S.g_tile, kBS, 0, S.stream>>>(
-                    B.A, B.s, B.d[p], B.d[p ^ 1], B.q, B.cb, B.P, S.g_prec(), p);
+                    B.A, B.s, B.d[p], B.d[p ^ 1], B.q, nullptr, B.cb, B.P, S.g_prec(), p);
             break;
         case 1:
             if (S.jacobi) {
@@ -1006,8 +1037,9 @@ void launch_kernel(pcga_solver &S, const IterBufs<T> &B, int p, int which) {
                     B.cb, B.P, S.g_dq(), p);
                 break;
             }
-            launch_zt<T, true>(B.zt, S.fmt_zt, S.g_zt, S.stream, B.dinv, (const T *)B.r[p], (const T *)B.q,
-                               (const T *)B.d[p ^ 1], B.r[p ^ 1], B.x, B.t, B.cb, B.P, S.g_dq(), p);
+            launch_zt<T, true>(B.zt, S.fmt_zt, x_deferred(S), S.g_zt, S.stream, B.dinv, (const T *)B.r[p],
+                               (const T *)B.q, (const T *)B.d[p ^ 1], B.r[p ^ 1], B.x, B.t, B.cb, B.P,
+                               S.g_dq(), p);
             break;
         default:
             if (S.band_q > 0) {
@@ -1074,7 +1106,7 @@ int prologue_prec(pcga_solver &S, const IterBufs<T> &B) {
         HIP_TRY(hipGetLastError());
         return PCGA_OK;
     }
-    launch_zt<T, false>(B.zt, S.fmt_zt, S.g_zt, S.stream, B.dinv, (const T *)B.r[0], (const T *)nullptr,
+    launch_zt<T, false>(B.zt, S.fmt_zt, false, S.g_zt, S.stream, B.dinv, (const T *)B.r[0], (const T *)nullptr,
                         (const T *)nullptr, (T *)nullptr, (T *)nullptr, B.t, B.cb, B.P, 0, 0);
     launch_z<T, true, true>(B.z, S.fmt_z, S.g_z, S.stream, (const T *)B.t, (const T *)B.r[0], B.s, B.cb,
                             B.P, 0, 0);
@@ -1136,6 +1168,17 @@ int ensure_graph(pcga_solver &S, const IterBufs<T> &B) {
 
 // Run chunks until the device sets `done`.  hist_out receives entries 1..k
 // as they arrive; final_slot names the snapshot holding the final state.
+// After the last chunk of a solve: the x update its final iteration left
+// to a stencil that did not run (a no-op on the paths that update x in
+// their second kernel: there the pending counter never moves).
+template <typename T>
+int launch_x_pending(pcga_solver &S, const IterBufs<T> &B) {
+    if (!x_deferred(S)) return PCGA_OK;
+    k_x_pending<T><<<zero_grid(S.n), kBS, 0, S.stream>>>((int)S.n, B.x, B.d[0], B.d[1], B.cb);
+    HIP_TRY(hipGetLastError());
+    return PCGA_OK;
+}
+
 template <typename T>
 int run_chunks(pcga_solver &S, const IterBufs<T> &B, double *hist_out, int64_t hist_cap,
                int64_t maxit, int &final_slot, bool graph_ok = true) {
@@ -1222,6 +1265,7 @@ int solve64(pcga_solver &R, const IterBufs<double> &B, const double *b_dev, doub
     int slot = 0;
     if (!c0.done) {
         if ((st = run_chunks<double>(R, B, hist_host, hist_cap, maxit, slot, graph_ok))) return st;
+        if ((st = launch_x_pending<double>(R, B))) return st;
     }
     const Ctl cf = R.snap[slot]->c;
     // true residual ||b - A x|| in FP64
@@ -1375,6 +1419,7 @@ int pcga_pcg_solve_mixed(pcga_solver_t *S, const double *b_dev, double *x_dev, d
         int slot = 0;
         if (!R.snap[0]->c.done) {
             if ((st = run_chunks<float>(R, B, nullptr, 0, inner_maxit, slot))) return st;
+            if ((st = launch_x_pending<float>(R, B))) return st;
         }
         const Ctl ci = R.snap[slot]->c;
         const int is = map_status(ci.status);
@@ -1427,14 +1472,14 @@ int pcga_apply_prec(pcga_solver_t *S, const double *r_dev, double *t_dev, double
         k_convert<float, double><<<gc, kBS, 0, S->stream>>>((int)S->n, S->t32, t_dev);
         k_convert<float, double><<<gc, kBS, 0, S->stream>>>((int)S->n, S->tmp32, s_dev);
     } else if (S->precision == PCGA_FP64) {
-        launch_zt<double, false>(S->zt64, S->fmt_zt, S->g_zt, S->stream, (const double *)S->dinv64, r_dev,
+        launch_zt<double, false>(S->zt64, S->fmt_zt, false, S->g_zt, S->stream, (const double *)S->dinv64, r_dev,
                                  (const double *)nullptr, (const double *)nullptr, (double *)nullptr,
                                  (double *)nullptr, t_dev, S->cb, S->P, 0, 0);
         launch_z<double, false, false>(S->z64, S->fmt_z, S->g_z, S->stream, (const double *)t_dev,
                                        (const double *)nullptr, s_dev, S->cb, S->P, 0, 0);
     } else {
         k_convert<double, float><<<gc, kBS, 0, S->stream>>>((int)S->n, r_dev, S->r32[0]);
-        launch_zt<float, false>(S->zt32, S->fmt_zt, S->g_zt, S->stream, (const float *)S->dinv32,
+        launch_zt<float, false>(S->zt32, S->fmt_zt, false, S->g_zt, S->stream, (const float *)S->dinv32,
                                 (const float *)S->r32[0], (const float *)nullptr,
                                 (const float *)nullptr, (float *)nullptr, (float *)nullptr, S->t32,
                                 S->cb, S->P, 0, 0);
@@ -1460,16 +1505,16 @@ int pcga_step_stencil(pcga_solver_t *S, const double *s_dev, const double *d_dev
     k_step_state<<<1, 1, 0, R.stream>>>(R.cb, R.P, beta);
     if (R.precision == PCGA_FP64) {
         k_stencil<double, false><<<R.g_tile, kBS, 0, R.stream>>>(R.A64, s_dev, d_dev, dnew_dev,
-                                                                     q_dev, R.cb, R.P, 1, 0);
+                                                                     q_dev, nullptr, R.cb, R.P, 1, 0);
     } else {
         k_convert<double, float><<<gc, kBS, 0, R.stream>>>((int)R.n, s_dev, R.s32);
         k_convert<double, float><<<gc, kBS, 0, R.stream>>>((int)R.n, d_dev, R.d32[0]);
         if (R.precision == PCGA_MIXED_A32)
             k_stencil<float, false, float><<<R.g_tile, kBS, 0, R.stream>>>(
-                R.A32, R.s32, R.d32[0], R.d32[1], R.q32, R.cb, R.P, 1, 0);
+                R.A32, R.s32, R.d32[0], R.d32[1], R.q32, nullptr, R.cb, R.P, 1, 0);
         else
             k_stencil<float, false><<<R.g_tile, kBS, 0, R.stream>>>(
-                R.A64, R.s32, R.d32[0], R.d32[1], R.q32, R.cb, R.P, 1, 0);
+                R.A64, R.s32, R.d32[0], R.d32[1], R.q32, nullptr, R.cb, R.P, 1, 0);
         k_convert<float, double><<<gc, kBS, 0, R.stream>>>((int)R.n, R.d32[1], dnew_dev);
         k_convert<float, double><<<gc, kBS, 0, R.stream>>>((int)R.n, R.q32, q_dev);
     }

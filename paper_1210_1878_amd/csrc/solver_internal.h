@@ -63,6 +63,12 @@ struct pcga_solver {
     // two launches per iteration (k_stencil<STOP>, k_jacobi) instead of three
     bool jacobi = false;
     int kernels_per_iter() const { return jacobi ? 2 : 3; }
+    // the FP32 inner iteration of a five-point mixed solve leaves
+    // x += alpha d to the next iteration's stencil; the FP64 iteration and
+    // the band, diagonal and CSR paths keep it in their second kernel (the
+    // FP64 stencil, at its register limit, streamed x slower than the Z^T
+    // kernel: 96.2 against 95.4 us per iteration at 1442 x 1021)
+    bool x_deferred() const { return !csr && !jacobi && band_q == 0 && precision != PCGA_FP64; }
     // Banded Z (every entry within band_q <= kMaxBand rows above the
     // diagonal, e.g. the banded factor of T): stored by diagonals, applied by
     // k_zt_band / k_z_band (elementwise launches of g_st workgroups)

@@ -30,7 +30,7 @@ def test_kernel_bytes_model(word, b):
 
 def test_kernel_names_carry_formats():
     k = bench.kernel_names(8, (3, 7))
-    assert k == {"stencil": "k_stencil<double, false>", "axpy_zt": "k_zt<double, true, 3>",
+    assert k == {"stencil": "k_stencil<double, false, double, 0>", "axpy_zt": "k_zt<double, true, 3>",
                  "z_dot": "k_z<double, true, false, 7>"}
     assert bench.kernel_names(4, (1, 1))["z_dot"] == "k_z<float, true, false, 1>"
 
@@ -92,3 +92,21 @@ def test_cpu_baseline_helpers_small():
     threads = os.cpu_count() or 1
     assert abs(e["solves_per_s_all_threads"] - e["solves_per_s_per_core"] * threads) <= 0.1 * threads
     assert bench.host_cpu_model() is None or isinstance(bench.host_cpu_model(), str)
+
+
+def test_deferred_x_update_names_and_bytes():
+    """With the x update moved into the stencil (format bit 16), the kernels
+    carry the stencil's x mode and the Z^T kernel's launched format, and one
+    vector pass moves from the Z^T kernel's count to nowhere (8 n less)."""
+    k = bench.kernel_names(8, (11 | 16, 7))
+    assert k == {"stencil": "k_stencil<double, false, double, 2>",
+                 "axpy_zt": "k_zt<double, true, 19>", "z_dot": "k_z<double, true, false, 7>"}
+    assert bench.kernel_names(8, (3 | 16, 7))["stencil"] == "k_stencil<double, false, double, 1>"
+    n, E = 1000, 5000
+    a = bench.kernel_bytes(n, E, 8, 2, x_in_stencil=False)
+    b = bench.kernel_bytes(n, E, 8, 2, x_in_stencil=True)
+    assert sum(a.values()) - sum(b.values()) == 8 * n
+    assert b["stencil"] - a["stencil"] == 16 * n and a["axpy_zt"] - b["axpy_zt"] == 24 * n
+    sa, sb = bench.survey_bytes(n, E), bench.survey_bytes(n, E, x_in_stencil=True)
+    assert sa["iteration"] == sb["iteration"] == 152 * n + 24 * E
+    assert sb["stencil"] + sb["axpy_zt"] == sa["stencil"] + sa["axpy_zt"]
