@@ -490,7 +490,7 @@ __device__ __forceinline__ bool stop_test(CtlBlock *cb, double rr, int k) {
 // k_stencil: rho_k, beta; d_new = s + beta d_old; q = A d_new; (d_new,q) partials
 // par = k & 1 (fixed per position in a captured chunk; chunks are even).
 // ---------------------------------------------------------------------------
-// The grid is cut into tiles of kTileRows rows by kBS columns, one column per
+// The grid is cut into tiles of TR rows by kBS columns, one column per
 // thread and one tile per workgroup (a workgroup takes a contiguous range of
 // tiles when there are more tiles than workgroups).  Each thread reads s and
 // d_old of its column once, over the tile's rows and one halo row either
@@ -528,7 +528,7 @@ __global__ __launch_bounds__(kBS) void k_stencil(DevOp<C> A, const T *__restrict
     Ctl *c = &cb->c;
     if (c->done) return;
     const PartialsLoad<1> pr = load_partials<1>(P.rr, STOP ? g_sr : 0);
-    constexpr int TR = kTileRows, TH = kTileRows + 2, TW = kBS + 2;
+    constexpr int TR = tile_rows<T>(), TH = TR + 2, TW = kBS + 2;
     __shared__ T vt[TH][TW];          // d_new of the tile, halo included
     __shared__ C at[TR][kBS + 1];     // east couplings, column 0: the west halo
     const int nx = A.nx, ny = A.ny;

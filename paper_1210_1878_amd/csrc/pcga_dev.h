@@ -18,13 +18,19 @@ constexpr int kCPT = PCGA_CPT;     // cells per thread per step (elementwise ker
 constexpr int kStep = kBS * kCPT;  // cells per workgroup step
 constexpr int kHistRing = 4096;    // residual-history ring (entries)
 constexpr int kMaxBlocks = 2048;   // workgroups per kernel = partial sums per reduction
-// k_stencil: grid rows per tile (tiles are kTileRows x kBS cells)
-#ifndef PCGA_TILE_ROWS
-#define PCGA_TILE_ROWS 4
+// k_stencil: grid rows per tile (tiles are TR x kBS cells), by vector type:
+// FP64 8 rows (1442 x 1021: 94.0 us per iteration, 4 rows 95.4, 2 rows
+// 98.5), FP32 4 rows (48.8 us per inner iteration, 8 rows 49.1)
+#ifndef PCGA_TILE_ROWS_F64
+#define PCGA_TILE_ROWS_F64 8
 #endif
-constexpr int kTileRows = PCGA_TILE_ROWS;
-__host__ __device__ inline int tile_count(int nx, int ny) {
-    return ((nx + kBS - 1) / kBS) * ((ny + kTileRows - 1) / kTileRows);
+#ifndef PCGA_TILE_ROWS_F32
+#define PCGA_TILE_ROWS_F32 4
+#endif
+template <typename T>
+constexpr int tile_rows() { return sizeof(T) == 8 ? PCGA_TILE_ROWS_F64 : PCGA_TILE_ROWS_F32; }
+__host__ __device__ inline int tile_count(int nx, int ny, int tr) {
+    return ((nx + kBS - 1) / kBS) * ((ny + tr - 1) / tr);
 }
 // Default workgroups per kernel (256 CUs), as the autotuner picks them at
 // 1442 x 1021 with the default slice widths: FP64 4 per CU, mixed 6 per CU.

@@ -598,9 +598,8 @@ int create_impl(const OpDesc &D, const pcga_ainv_t *F, int precision, int32_t sl
     //   zt: r, q, d, x, dinv read; r', x, t written; Z^T entries     8 n words + E_zt
     //   z:  t, r' read; s written; Z entries                         3 n words + E_z
     //   (an entry: its value and a 4-byte column or 2-byte distance)
-    //   with x += alpha d in the stencil (FP32 inner iteration): the stencil
-    //   also reads and writes x, the zt kernel no longer reads d and x nor
-    //   writes x: 1 n word less
+    //   with x += alpha d in the stencil: the stencil also reads and writes
+    //   x, the zt kernel no longer reads d and x nor writes x: 1 n word less
     const double E = (double)S->sell_entries;
     S->index_bytes = H.zt.narrow ? 2 : 4;
     cache_plan(*S, H);

@@ -63,12 +63,10 @@ struct pcga_solver {
     // two launches per iteration (k_stencil<STOP>, k_jacobi) instead of three
     bool jacobi = false;
     int kernels_per_iter() const { return jacobi ? 2 : 3; }
-    // the FP32 inner iteration of a five-point mixed solve leaves
-    // x += alpha d to the next iteration's stencil; the FP64 iteration and
-    // the band, diagonal and CSR paths keep it in their second kernel (the
-    // FP64 stencil, at its register limit, streamed x slower than the Z^T
-    // kernel: 96.2 against 95.4 us per iteration at 1442 x 1021)
-    bool x_deferred() const { return !csr && !jacobi && band_q == 0 && precision != PCGA_FP64; }
+    // the five-point three-kernel iteration leaves x += alpha d to the next
+    // iteration's stencil; the band, diagonal and CSR paths keep it in
+    // their second kernel
+    bool x_deferred() const { return !csr && !jacobi && band_q == 0; }
     // Banded Z (every entry within band_q <= kMaxBand rows above the
     // diagonal, e.g. the banded factor of T): stored by diagonals, applied by
     // k_zt_band / k_z_band (elementwise launches of g_st workgroups)
@@ -93,7 +91,10 @@ struct pcga_solver {
         g_st = std::max(1, std::min(nsteps, cap(0)));
         // one tile per workgroup up to kMaxBlocks (its loads all in flight at
         // once), unless capped explicitly
-        g_tile = std::max(1, std::min(pcga::tile_count(nx, ny),
+        // (the stencil's vector type: FP64 for a PCGA_FP64 solver, FP32 for
+        // the inner iteration of the mixed forms)
+        const int tr = precision == PCGA_FP64 ? pcga::tile_rows<double>() : pcga::tile_rows<float>();
+        g_tile = std::max(1, std::min(pcga::tile_count(nx, ny, tr),
                                       g_cap[0] > 0 ? g_cap[0] : pcga::kMaxBlocks));
         const int nsz = precision == PCGA_FP64 ? zt64.nslices : zt32.nslices;
         const int nsr = precision == PCGA_FP64 ? z64.nslices : z32.nslices;
