@@ -17,7 +17,11 @@ thread that runs the grid's steps through the single-grid mixed solve on the
 grid's stream (its kernels stream the large grid's arrays better than the
 batched kernels do), concurrently with the batches.  Latency is measured
 from arrival to the moment the solution is back in the request's output
-tensor.
+tensor.  The classes and lanes only overlap when their streams reach
+different hardware queues: the runtime gives a process 4 by default and
+maps streams onto them in turn, so a process that serves several classes
+and lanes (and has made other streams before) wants more, set by
+GPU_MAX_HW_QUEUES before the runtime starts.
 """
 from __future__ import annotations
 
