@@ -233,7 +233,8 @@ int pcga_solver_create_ex(const pcga_a5_t *A, const pcga_ainv_t *F, int precisio
  * kernel instead of the Z^T kernel, which then reads neither d nor x: the
  * FP64 solves and the FP32 inner iterations of the mixed solves of a
  * five-point operator with a sliced-ELL Z, where the bytes above count one
- * vector pass less, 136 n and 80 n); formats[2]:
+ * vector pass less, 136 n and 80 n; formats[1] only: bit 5, the values of
+ * Z's table steps read from Z^T's value array, FP64); formats[2]:
  * q when every entry of Z lies within q <= 8
  * rows above the diagonal (e.g. the banded factor of T), which the solve
  * then applies from diagonals (no index arrays, no gathers), else 0.  Any

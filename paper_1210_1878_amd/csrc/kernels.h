@@ -257,7 +257,10 @@ __device__ __forceinline__ SliceMeta header_of(const SliceHeaders &h, int i) {
 // then as much of Z as fits) is not evicted by a stream that cannot fit.
 //   bit 4 (Z^T kernel only): x += alpha d left to the next iteration's
 //   stencil (k_zt neither reads d and x nor writes x).
-constexpr int kFmtNarrow = 1, kFmtNtIdx = 2, kFmtNtVal = 4, kFmtNtX = 8, kFmtXDef = 16;
+//   bit 5 (Z kernel only): the values of mapped table steps read from Z^T's
+//   value array (DevSell::alt), which stays resident, instead of Z's own.
+constexpr int kFmtNarrow = 1, kFmtNtIdx = 2, kFmtNtVal = 4, kFmtNtX = 8, kFmtXDef = 16,
+              kFmtZtVal = 32;
 
 template <bool NT, typename P>
 __device__ __forceinline__ P stream_load(const P *p) {
@@ -313,9 +316,22 @@ __device__ __forceinline__ bool sell_stream(const DevSell<T> &M, int first, int 
         return row < M.nrows ? row : nlast;
     };
     // offset table of a table slice: lane c holds table[min(c, width - 1)]
+    // (and, for Z with kFmtZtVal, the step's map into Z^T's values)
+    constexpr bool ztv = (FMT & kFmtZtVal) != 0;
+    struct Tab {
+        int o, a, b, k;
+    };
     auto load_tab = [&](const SliceMeta &m) {
-        int v = 0;
-        if (m.toff >= 0 && m.width > 0) v = M.tab[m.toff + (lane < m.width ? lane : m.width - 1)];
+        Tab v{0, 0, 0, -1};
+        if (m.toff >= 0 && m.width > 0) {
+            const int i = m.toff + (lane < m.width ? lane : m.width - 1);
+            v.o = M.tab[i];
+            if (ztv) {
+                v.a = M.alt_a[i];
+                v.b = M.alt_b[i];
+                v.k = M.alt_k[i];
+            }
+        }
         return v;
     };
     // values of steps c0..c0+U-1 (clamped to the last step; masked when summed)
@@ -329,15 +345,38 @@ __device__ __forceinline__ bool sell_stream(const DevSell<T> &M, int first, int 
         }
     };
     // gathers of a table slice's steps c0..c0+U-1 for a lane whose row is rowc
-    auto gather_tab = [&](const SliceMeta &m, int tabv, int rowc, int c0, GR (&gv)[U]) {
+    auto gather_tab = [&](const SliceMeta &m, const Tab &tv, int rowc, int c0, GR (&gv)[U]) {
         const int last = m.width > 0 ? m.width - 1 : 0;
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int c = c0 + u <= last ? c0 + u : last;
-            const int o = __builtin_amdgcn_readlane(tabv, c);
+            const int o = __builtin_amdgcn_readlane(tv.o, c);
             int k = rowc + o;
             k = k < 0 ? 0 : (k > nlast ? nlast : k);
             gv[u] = g(k);
+        }
+    };
+    // values of a table slice's steps c0..c0+U-1: Z's own, or through the map
+    auto load_vals_tab = [&](const SliceMeta &m, const Tab &tv, int c0, T (&zv)[U]) {
+        if constexpr (!ztv) {
+            load_vals(m, c0, zv);
+        } else {
+            const int last = m.width > 0 ? m.width - 1 : 0;
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int c = c0 + u <= last ? c0 + u : last;
+                const int kk = __builtin_amdgcn_readlane(tv.k, c);
+                const int ka = __builtin_amdgcn_readlane(tv.a, c);
+                const int kb = __builtin_amdgcn_readlane(tv.b, c);
+                // Z^T's values are resident: read them with ordinary loads (a
+                // non-temporal load of a resident line would mark it for early
+                // eviction, before the next Z^T sweep reads it); Z's own values
+                // of an unmapped step keep the stream's policy
+                if (kk < 0)
+                    zv[u] = stream_load<ntv>(M.val + (m.width > 0 ? m.off + lane + (int64_t)c * kWave : 0));
+                else
+                    zv[u] = M.alt[(lane < kk ? ka : kb) + lane];
+            }
         }
     };
     T acc = T(0);
@@ -352,7 +391,7 @@ __device__ __forceinline__ bool sell_stream(const DevSell<T> &M, int first, int 
     };
     // next slice's header, table and own-row operands (prefetched)
     SliceMeta mn{0, 0, 0, -1, 0};
-    int tabn = 0;
+    Tab tabn{0, 0, 0, -1};
     Own ownn{};
     auto prefetch = [&](int i) {
         mn = header_of(hd, i);
@@ -381,14 +420,14 @@ __device__ __forceinline__ bool sell_stream(const DevSell<T> &M, int first, int 
                 else __builtin_amdgcn_s_setprio(0);
             }
             const SliceMeta m = mn;
-            const int tabv = tabn;
+            const Tab tabv = tabn;
             const Own own = ownn;
             if (i + 1 < cnt) prefetch(i + 1);
             const int rowc = rowc_of(m);
             if (m.toff >= 0) {
                 T za[U], zb[U];
                 GR ga[U], gb[U];
-                load_vals(m, 0, za);
+                load_vals_tab(m, tabv, 0, za);
                 gather_tab(m, tabv, rowc, 0, ga);
                 // Chunks alternate between the buffers a and b; every chunk is
                 // summed with the next chunk's loads already issued.  The loop
@@ -400,18 +439,18 @@ __device__ __forceinline__ bool sell_stream(const DevSell<T> &M, int first, int 
                 const int nch = (m.width + U - 1) / U;
                 int c0 = 0;
                 for (int k = 2; k < nch; k += 2) {
-                    load_vals(m, c0 + U, zb);
+                    load_vals_tab(m, tabv, c0 + U, zb);
                     gather_tab(m, tabv, rowc, c0 + U, gb);
                     __builtin_amdgcn_sched_barrier(0);
                     accumulate_full(za, ga);
-                    load_vals(m, c0 + 2 * U, za);
+                    load_vals_tab(m, tabv, c0 + 2 * U, za);
                     gather_tab(m, tabv, rowc, c0 + 2 * U, ga);
                     __builtin_amdgcn_sched_barrier(0);
                     accumulate_full(zb, gb);
                     c0 += 2 * U;
                 }
                 if (c0 + U < m.width) {
-                    load_vals(m, c0 + U, zb);
+                    load_vals_tab(m, tabv, c0 + U, zb);
                     gather_tab(m, tabv, rowc, c0 + U, gb);
                     __builtin_amdgcn_sched_barrier(0);
                     accumulate_full(za, ga);

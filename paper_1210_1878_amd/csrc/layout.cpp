@@ -17,7 +17,9 @@
 // that of plain ELL (1.13x at 1442x1021).
 
 #include <algorithm>
+#include <climits>
 #include <cstdint>
+#include <cstring>
 
 #include "pcga_host.h"
 
@@ -144,6 +146,109 @@ bool sell_narrow(SellLayout &L, bool lower) {
     L.idx.shrink_to_fit();
     L.narrow = true;
     return true;
+}
+
+// Z's values are Z^T's values in another order: Z[i, i+o] = Z^T[i+o, i].
+// For a table slice of Z (rows R..R+63, one lane per row) the 64 values of
+// step c (offset o) are the entries at offset -o of Z^T's rows R+o..R+o+63.
+// A lane whose Z^T row lies in a table slice of Z^T with -o in its table
+// finds its value at that slice's step (consecutive lanes at consecutive
+// positions); a lane whose value is +0 may instead read the block of 64
+// zeros at zero_base (Z^T stores nothing there, or it lies in a slice
+// without a table).  A step is mapped when its lanes form at most two such
+// runs and every value agrees bitwise with the one Z stores (lanes past the
+// last row are free): lanes l < k[c] read zt.val[a[c] + l], lanes l >= k[c]
+// read zt.val[b[c] + l]; k[c] = -1: the step reads Z's own values.  a, b, k
+// run parallel to z.tab.
+int64_t sell_shared_values(const SellLayout &zt, const SellLayout &z, int64_t zero_base,
+                           std::vector<int32_t> &a, std::vector<int32_t> &b,
+                           std::vector<int32_t> &k) {
+    const int64_t n = z.nrows_total;
+    a.assign(z.tab.size(), 0);
+    b.assign(z.tab.size(), 0);
+    k.assign(z.tab.size(), -1);
+    if (zt.nrows_total != n || zero_base + 64 > INT32_MAX) return 0;
+    // the table slice of Z^T that holds row j with one lane per row, else -1
+    std::vector<int32_t> slice_of(n, -1);
+    for (int64_t s = 0; s < zt.nslices(); s++) {
+        if (zt.toff[s] < 0 || (zt.meta[s] & 255) != 0) continue;
+        for (int64_t r = zt.row0[s]; r < std::min<int64_t>(n, zt.row0[s] + 64); r++) slice_of[r] = (int32_t)s;
+    }
+    // step of offset -o in table slice s, or -1
+    auto step_of = [&](int64_t s, int64_t o) -> int64_t {
+        const int64_t w = zt.meta[s] >> 8;
+        const int32_t *t = zt.tab.data() + zt.toff[s];
+        const int32_t *p = std::lower_bound(t, t + w, (int32_t)-o);
+        return (p != t + w && *p == -o) ? (int64_t)(p - t) : -1;
+    };
+    // per lane: where its value can be read
+    constexpr int64_t kFree = INT64_MIN;       // lane past the last row (any in-bounds position)
+    constexpr int64_t kZero = INT64_MIN + 1;   // +0: the zero block
+    int64_t mapped = 0;
+    int64_t base[64];   // position - lane, or kFree / kZero
+    for (int64_t s = 0; s < z.nslices(); s++) {
+        if (z.toff[s] < 0 || (z.meta[s] & 255) != 0) continue;
+        const int64_t R = z.row0[s], w = z.meta[s] >> 8;
+        for (int64_t c = 0; c < w; c++) {
+            const int64_t ti = z.toff[s] + c;
+            const int64_t o = z.tab[ti];
+            bool ok = o > 0;
+            for (int64_t l = 0; ok && l < 64; l++) {
+                const int64_t i = R + l;
+                if (i >= n) {
+                    base[l] = kFree;
+                    continue;
+                }
+                const double zv = z.val[z.off[s] + c * 64 + l];
+                const int64_t j = i + o;
+                int64_t p = -1;
+                if (j < n && slice_of[j] >= 0) {
+                    const int64_t s1 = slice_of[j], c1 = step_of(s1, o);
+                    if (c1 >= 0) p = zt.off[s1] + c1 * 64 + (j - zt.row0[s1]);
+                }
+                const double zero = 0.0;
+                if (p >= 0 && std::memcmp(&zv, &zt.val[p], sizeof(double)) == 0)
+                    base[l] = p - l;
+                else if (std::memcmp(&zv, &zero, sizeof(double)) == 0)
+                    base[l] = kZero;
+                else
+                    ok = false;
+            }
+            if (!ok) continue;
+            // at most two runs (free lanes join any run): run 1 = lanes < split
+            int64_t r1 = kFree, r2 = kFree, split = 64, first1 = -1;
+            for (int64_t l = 0; ok && l < 64; l++) {
+                if (base[l] == kFree) continue;
+                if (split == 64) {
+                    if (r1 == kFree) {
+                        r1 = base[l];
+                        first1 = l;
+                    } else if (base[l] != r1) {
+                        split = l;
+                        r2 = base[l];
+                    }
+                } else if (base[l] != r2) {
+                    ok = false;
+                }
+            }
+            if (!ok || r1 == kFree) continue;
+            // a zero run reads zero_base + (lane - its first lane)
+            const int64_t b1 = r1 == kZero ? zero_base - first1 : r1;
+            const int64_t b2 = r2 == kFree ? b1 : (r2 == kZero ? zero_base - split : r2);
+            // positions of all lanes inside [0, zero_base + 64)
+            bool inb = true;
+            for (int64_t l = 0; l < 64; l++) {
+                const int64_t p = (l < split ? b1 : b2) + l;
+                if (p < 0 || p >= zero_base + 64) inb = false;
+            }
+            if (!inb || b1 > INT32_MAX || b2 > INT32_MAX || b2 < INT32_MIN) continue;
+            a[ti] = (int32_t)b1;
+            b[ti] = (int32_t)b2;
+            k[ti] = (int32_t)split;
+            mapped++;
+        }
+    }
+    return mapped;
 }
 
 }  // namespace pcga

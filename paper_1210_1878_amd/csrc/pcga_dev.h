@@ -89,6 +89,11 @@ struct DevSell {
     const int32_t *bounds;   // slice range of wave v = L * kWavesPerBlock + w: [bounds[v], bounds[v+1])
     const int32_t *bounds_b; // the same for the block count of a batch slot
     int32_t nslices, nrows;
+    // Z only (format bit kFmtZtVal): its table steps' values read from Z^T's
+    // value array `alt` (runs parallel to tab: lanes l < alt_k read
+    // alt[alt_a + l], the others alt[alt_b + l]; alt_k < 0: own values)
+    const T *alt;
+    const int32_t *alt_a, *alt_b, *alt_k;
 };
 
 // Per-workgroup partial sums of the three reductions of an iteration and of

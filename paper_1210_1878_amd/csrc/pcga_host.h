@@ -100,6 +100,14 @@ bool sell_check(const SellLayout &L);
 // else every column >= its row).  Returns whether it did.
 bool sell_narrow(SellLayout &L, bool lower);
 
+// Map the steps of Z's table slices onto Z^T's value array where the values
+// agree bitwise (see layout.cpp); a block of 64 zeros at zero_base (after
+// Z^T's entries) serves lanes whose value is +0.  a, b, k run parallel to
+// z.tab.  Returns the number of mapped steps.
+int64_t sell_shared_values(const SellLayout &zt, const SellLayout &z, int64_t zero_base,
+                           std::vector<int32_t> &a, std::vector<int32_t> &b,
+                           std::vector<int32_t> &k);
+
 std::string &last_error();
 int fail(int code, const std::string &msg);
 

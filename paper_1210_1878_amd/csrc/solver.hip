@@ -90,6 +90,9 @@ struct Carver {
 struct HostLayouts {
     SellLayout zt, z;
     SellLayout a;   // a general sparse A (CSR input); empty for the five-point operator
+    // FP64: Z's table steps mapped onto Z^T's values (sell_shared_values)
+    std::vector<int32_t> za, zb, zk;
+    int64_t zmapped = 0;
 };
 
 int build_layouts(const AinvFactor &F, int target_width, HostLayouts &H) {
@@ -146,7 +149,9 @@ size_t carve(pcga_solver &S, void *base, const HostLayouts &H) {
         S.A32.ae = C.take<float>(n);
         S.A32.an = C.take<float>(n);
     }
-    auto sell = [&](const SellLayout &L, auto &dst, auto tag) {
+    // extra: zeros after the values (the block that Z's mapped steps read
+    // for lanes whose value is zero)
+    auto sell = [&](const SellLayout &L, auto &dst, auto tag, int64_t extra = 0) {
         using T = decltype(tag);
         dst.row0 = C.take<int32_t>(L.nslices());
         dst.meta = C.take<int32_t>(L.nslices());
@@ -160,7 +165,7 @@ size_t carve(pcga_solver &S, void *base, const HostLayouts &H) {
             dst.idx = C.take<int32_t>(std::max<int64_t>(L.entries(), 1));
             dst.dist = nullptr;
         }
-        dst.val = C.take<T>(std::max<int64_t>(L.entries(), 1));
+        dst.val = C.take<T>(std::max<int64_t>(L.entries(), 1) + extra);
         dst.nslices = (int32_t)L.nslices();
         dst.nrows = (int32_t)L.nrows_total;
     };
@@ -176,8 +181,15 @@ size_t carve(pcga_solver &S, void *base, const HostLayouts &H) {
     }
     if (f64) {
         S.dinv64 = C.take<double>(n);
-        sell(H.zt, S.zt64, double());
+        sell(H.zt, S.zt64, double(), H.zmapped > 0 ? 64 : 0);
         sell(H.z, S.z64, double());
+        if (H.zmapped > 0) {
+            const int64_t nt = std::max<int64_t>((int64_t)H.z.tab.size(), 1);
+            S.z64.alt_a = C.take<int32_t>(nt);
+            S.z64.alt_b = C.take<int32_t>(nt);
+            S.z64.alt_k = C.take<int32_t>(nt);
+            S.z64.alt = S.zt64.val;
+        }
         S.x = C.take<double>(n);
         S.r[0] = C.take<double>(n);
         S.r[1] = C.take<double>(n);
@@ -309,6 +321,8 @@ void cache_plan(pcga_solver &S, const HostLayouts &H) {
     const int nar = H.zt.narrow ? kFmtNarrow : 0;
     S.fmt_zt = nar | (kept < 3 ? kFmtNtIdx : 0) | (kept < 1 ? kFmtNtVal : 0) | (nt_x ? kFmtNtX : 0);
     S.fmt_z = nar | (kept < 4 ? kFmtNtIdx : 0) | (kept < 2 ? kFmtNtVal : 0);
+    // Z's mapped steps read Z^T's values (resident when kept >= 1)
+    if (H.zmapped > 0 && S.precision == PCGA_FP64 && kept >= 1) S.fmt_z |= kFmtZtVal;
 }
 
 int upload_bounds(pcga_solver &S) {
@@ -412,6 +426,15 @@ int prepare(const OpDesc &D, const pcga_ainv_t *F, int precision, int slice_widt
     S.n = F->F.n;
     S.csr = D.is_csr();
     S.band_q = band_width(F->F);
+    // FP64: Z's values are read from Z^T's resident copy where they agree
+    // (the FP32 inner solve keeps both in the cache anyway)
+    if (precision == PCGA_FP64 && S.band_q == 0 && F->F.nnz_off() > 0) {
+        try {
+            H.zmapped = sell_shared_values(H.zt, H.z, H.zt.entries(), H.za, H.zb, H.zk);
+        } catch (const std::bad_alloc &) {
+            H.zmapped = 0;
+        }
+    }
     return PCGA_OK;
 }
 
@@ -566,6 +589,16 @@ int create_impl(const OpDesc &D, const pcga_ainv_t *F, int precision, int32_t sl
         CR(hipMemcpyAsync(S->dinv64, dinv.data(), nb8, hipMemcpyHostToDevice, sm));
         CR(up_sell(H.zt, S->zt64));
         CR(up_sell(H.z, S->z64));
+        if (H.zmapped > 0) {
+            const std::vector<double> zeros(64, 0.0);
+            CR(hipMemcpyAsync((void *)(S->zt64.val + H.zt.entries()), zeros.data(), 64 * 8,
+                              hipMemcpyHostToDevice, sm));
+            CR(hipStreamSynchronize(sm));   // zeros is a temporary
+            const size_t nt = H.z.tab.size() * 4;
+            CR(hipMemcpyAsync((void *)S->z64.alt_a, H.za.data(), nt, hipMemcpyHostToDevice, sm));
+            CR(hipMemcpyAsync((void *)S->z64.alt_b, H.zb.data(), nt, hipMemcpyHostToDevice, sm));
+            CR(hipMemcpyAsync((void *)S->z64.alt_k, H.zk.data(), nt, hipMemcpyHostToDevice, sm));
+        }
     } else {
         std::vector<float> f(n);
         for (int64_t k = 0; k < n; k++) f[k] = (float)dinv[k];
@@ -967,6 +1000,16 @@ void launch_zt(const DevSell<T> &M, int fmt, bool xdef, int grid, hipStream_t st
 
 template <typename T, bool DOT, bool FIRST, typename... Args>
 void launch_z(const DevSell<T> &M, int fmt, int grid, hipStream_t st, Args... args) {
+    if constexpr (std::is_same_v<T, double>) {
+        if (fmt & kFmtZtVal) {
+            fmt &= ~kFmtZtVal;
+#define PCGA_KV(F) k_z<T, DOT, FIRST, F | kFmtZtVal>
+            PCGA_FMT_CASES(PCGA_KV, M, args...)
+#undef PCGA_KV
+            return;
+        }
+    }
+    fmt &= ~kFmtZtVal;
 #define PCGA_K(F) k_z<T, DOT, FIRST, F>
     PCGA_FMT_CASES(PCGA_K, M, args...)
 #undef PCGA_K
