@@ -554,7 +554,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--chunk", type=int, default=32)
     ap.add_argument("--max-blocks", type=int, default=0,
-                    help="workgroups per kernel; 0 = the solver's default (FP64 1024, mixed 1536)")
+                    help="workgroups per kernel; 0 = the solver's default (FP64 1280, mixed 1536)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched ensemble")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
@@ -861,7 +861,7 @@ def main():
                                "PCG to relres 1e-10 from x0=0",
                    "nx": NX, "ny": NY, "n": p.n, "nnz_off": G.nnz_off, "index_bytes": S64.index_bytes, "formats": {"fp64": S64.formats, "mixed": Smx.formats}, "tol": TOL,
                    "drop_tol": TAU, "iters_per_solve": fp64_iters, "chunk": args.chunk,
-                   "graph": not args.no_graph, "max_blocks": args.max_blocks or "default: fp64 1024, mixed 1536",
+                   "graph": not args.no_graph, "max_blocks": args.max_blocks or "default: fp64 1280, mixed 1536",
                    "slice_width": {"fp64": S64.slice_width or 32, "mixed": Smx.slice_width or 24}},
         "fp64": {"iters": fp64_iters, "ms_per_solve": round(dt * 1e3 / args.steps, 3),
                  "true_relres": fp64_true, "model_bytes_per_iter": b_iter,

@@ -33,8 +33,9 @@ __host__ __device__ inline int tile_count(int nx, int ny, int tr) {
     return ((nx + kBS - 1) / kBS) * ((ny + tr - 1) / tr);
 }
 // Default workgroups per kernel (256 CUs), as the autotuner picks them at
-// 1442 x 1021 with the default slice widths: FP64 4 per CU, mixed 6 per CU.
-constexpr int kDefaultBlocks = 1024;
+// 1442 x 1021 with the default slice widths: FP64 5 per CU (86.6-87.4 us
+// per iteration against 89.0-89.7 with 4), mixed 6 per CU.
+constexpr int kDefaultBlocks = 1280;
 constexpr int kDefaultBlocksMixed = 1536;
 constexpr int kMaxBand = 8;          // widest band stored by diagonals
 // Memory-side cache (Infinity Cache) of one MI355X: 256 MiB.  The streams an

@@ -249,9 +249,10 @@ int check_a5(const pcga_a5_t *A) {
 }
 
 // Default sliced-ELL target width (entry steps) by precision, as the autotuner
-// picks it at 1442 x 1021 (FP64: 97-98 us per iteration at 32 against 100 at
-// 16; mixed inner: 51.5 us at 24 against 52.3 at 16).
-constexpr int kTargetWidth = 32, kTargetWidthMixed = 24;
+// picks it at 1442 x 1021 (FP64 with 1280 workgroups: 86.6-87.4 us per
+// iteration at 24 against 90.3-91.7 at 32; mixed inner: 51.5 us at 24
+// against 52.3 at 16).
+constexpr int kTargetWidth = 24, kTargetWidthMixed = 24;
 constexpr int kMaxSliceWidth = 64;
 int default_width(int precision) { return precision != PCGA_FP64 ? kTargetWidthMixed : kTargetWidth; }
 
