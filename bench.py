@@ -862,7 +862,7 @@ def main():
                    "nx": NX, "ny": NY, "n": p.n, "nnz_off": G.nnz_off, "index_bytes": S64.index_bytes, "formats": {"fp64": S64.formats, "mixed": Smx.formats}, "tol": TOL,
                    "drop_tol": TAU, "iters_per_solve": fp64_iters, "chunk": args.chunk,
                    "graph": not args.no_graph, "max_blocks": args.max_blocks or "default: fp64 1280, mixed 1536",
-                   "slice_width": {"fp64": S64.slice_width or 32, "mixed": Smx.slice_width or 24}},
+                   "slice_width": {"fp64": S64.slice_width or 24, "mixed": Smx.slice_width or 24}},
         "fp64": {"iters": fp64_iters, "ms_per_solve": round(dt * 1e3 / args.steps, 3),
                  "true_relres": fp64_true, "model_bytes_per_iter": b_iter,
                  "model_gbs_per_iter_kernels": round(b_iter / it_time / 1e9, 1),

@@ -93,6 +93,23 @@ typedef struct pcga_solver pcga_solver_t;   /* opaque device solver */
 const char *pcga_strerror(int status);
 const char *pcga_last_error(void);
 
+/* Streams for callers that run several solvers or batches concurrently
+ * (for instance continuous batching of time-step solves).
+ * pcga_stream_create makes a stream on the calling thread's current device,
+ * non-blocking with respect to the null stream, at the default priority.
+ * The HIP runtime gives a process a fixed number of hardware queues
+ * (GPU_MAX_HW_QUEUES) and binds each new stream to the queue that has the
+ * fewest streams; work on two streams bound to one queue runs one after the
+ * other.  Streams made together, after the process's other streams, thus
+ * land on distinct queues (up to the queue count), which streams taken from
+ * a framework's pool need not do.  The caller owns the stream (*stream;
+ * NULL on error) and passes it where a call takes `stream`.
+ * pcga_stream_destroy waits for the stream's work, then destroys it; every
+ * solver or batch made on it must be destroyed first (NULL: no-op).
+ * Errors: EINVAL (stream NULL), EHIP. */
+int pcga_stream_create(void **stream);
+int pcga_stream_destroy(void *stream);
+
 /* ---- preconditioner setup (host, FP64) ---------------------------------
  * pcga_ainv_setup: A-orthogonalisation of A with drop tolerance `drop_tol`
  * (Sec. 3-5; ref. [book4-14]).  Z := I; for i = 0..n-1 (natural order):
@@ -205,8 +222,8 @@ int pcga_workspace_bytes_csr(const pcga_csr_t *A, const pcga_ainv_t *F, int prec
 int pcga_solver_create_csr(const pcga_csr_t *A, const pcga_ainv_t *F, int precision,
                            int32_t slice_width, void *ws, size_t bytes, void *stream,
                            pcga_solver_t **out);
-/* The same with the sliced-ELL target width (1..64; 0: the default, 32 for
- * PCGA_FP64 and 24 for PCGA_MIXED): a slice
+/* The same with the sliced-ELL target width (1..64; 0: the default, 24 for
+ * PCGA_FP64 and PCGA_MIXED): a slice
  * starts with one lane per row and doubles its lanes per row (halving its
  * rows) until its longest row needs at most slice_width entry steps (or one
  * row has all 64 lanes).  Results are the same method; the summation order
@@ -246,7 +263,7 @@ int pcga_solver_info(const pcga_solver_t *S, int64_t *n, int64_t *nnz_off,
 /* Launch tuning (set by the autotuner): iterations per chunk (even,
  * 2..512), whether chunks are replayed through a captured HIP graph (1) or
  * launched directly (0), and the maximum number of workgroups per kernel
- * (8..2048; 0 selects the default, 1024 for PCGA_FP64 and 1536 for
+ * (8..2048; 0 selects the default, 1280 for PCGA_FP64 and 1536 for
  * PCGA_MIXED; each workgroup streams one contiguous range of the grid).
  * Takes effect at the next solve.  Results of a solve are bitwise
  * reproducible for fixed settings. */

@@ -47,6 +47,8 @@ _pdbl = ctypes.POINTER(ctypes.c_double)
 _SIGS = {
     "pcga_strerror": ([ctypes.c_int], ctypes.c_char_p),
     "pcga_last_error": ([], ctypes.c_char_p),
+    "pcga_stream_create": ([_pp], ctypes.c_int),
+    "pcga_stream_destroy": ([_p], ctypes.c_int),
     "pcga_ainv_setup": ([ctypes.POINTER(A5), _dbl, _pp], ctypes.c_int),
     "pcga_ainv_setup_fill": ([ctypes.POINTER(A5), _dbl, _i32, _pp], ctypes.c_int),
     "pcga_fsai_band_setup": ([ctypes.POINTER(A5), _i32, _pp], ctypes.c_int),

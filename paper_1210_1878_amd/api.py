@@ -324,12 +324,13 @@ class Solver:
 
     def _xb(self, b, x0):
         import torch
-        # order the solver's stream after the caller's work on b / x0
-        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         if x0 is None:
             x = torch.zeros(self.n, dtype=torch.float64, device=self.device)
         else:
             x = x0.clone()
+        # order the solver's stream after the caller's work on b and x0 and
+        # after the fill or copy of x just enqueued on the caller's stream
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         return _dev_ptr(b, torch.float64, self.n), x, _dev_ptr(x, torch.float64, self.n)
 
     def solve(self, b, x0=None, tol=1e-10, maxit=None, hist_cap=None) -> SolveResult:
@@ -500,6 +501,39 @@ class Solver:
         h = getattr(self, "_h", None)
         if h:
             _lib.load().pcga_solver_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HwStream:
+    """A stream made by the library (pcga_stream_create) on `device`, for
+    work that must overlap with work on other streams: streams made together
+    are bound to distinct hardware queues (up to GPU_MAX_HW_QUEUES), which
+    torch's pooled streams need not be.  `.torch` is the torch view of it
+    (pass that as a Solver's or Batch's stream); close() waits for its work
+    and destroys it, after every solver and batch on it has been closed."""
+
+    def __init__(self, device=None):
+        import torch
+        L = _lib.load()
+        self.device = torch.device("cuda" if device is None else device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(L.pcga_stream_create(ctypes.byref(h)), "pcga_stream_create")
+        self._h = h.value
+        self.torch = torch.cuda.ExternalStream(self._h, device=self.device)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            import torch
+            with torch.cuda.device(self.device):
+                check(_lib.load().pcga_stream_destroy(ctypes.c_void_p(h)), "pcga_stream_destroy")
             self._h = None
 
     def __del__(self):

@@ -677,6 +677,22 @@ const char *pcga_strerror(int s) {
 
 const char *pcga_last_error(void) { return last_error().c_str(); }
 
+int pcga_stream_create(void **stream) {
+    if (!stream) return fail(PCGA_EINVAL, "stream is NULL");
+    *stream = nullptr;
+    hipStream_t h = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&h, hipStreamNonBlocking));
+    *stream = (void *)h;
+    return PCGA_OK;
+}
+
+int pcga_stream_destroy(void *stream) {
+    if (!stream) return PCGA_OK;
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    HIP_TRY(hipStreamDestroy((hipStream_t)stream));
+    return PCGA_OK;
+}
+
 static int ainv_setup_impl(const pcga_a5_t *A, double drop_tol, int64_t fill,
                            pcga_ainv_t **out) {
     if (!out) return fail(PCGA_EINVAL, "out is NULL");

@@ -18,10 +18,13 @@ grid's stream (its kernels stream the large grid's arrays better than the
 batched kernels do), concurrently with the batches.  Latency is measured
 from arrival to the moment the solution is back in the request's output
 tensor.  The classes and lanes only overlap when their streams reach
-different hardware queues: the runtime gives a process 4 by default and
-maps streams onto them in turn, so a process that serves several classes
-and lanes (and has made other streams before) wants more, set by
-GPU_MAX_HW_QUEUES before the runtime starts.
+different hardware queues: the runtime gives a process a fixed number of
+them (GPU_MAX_HW_QUEUES, 4 by default, set before the runtime starts) and
+binds each new stream to the queue with the fewest streams.  The server
+makes the streams of its classes and lanes itself, one after the other
+(HwStream), so that they land on distinct queues whatever streams the
+process made before; torch's pooled streams, made in one burst when the
+pool starts, share queues in an order that depends on the queue count.
 """
 from __future__ import annotations
 
@@ -33,7 +36,7 @@ import time
 
 import numpy as np
 
-from .api import Batch, Solver, Stencil5, ainv_setup
+from .api import Batch, HwStream, Solver, Stencil5, ainv_setup
 
 
 REJECTED = -5   # the request's vectors alone exceed the memory budget (PCGA_ENOMEM)
@@ -107,16 +110,6 @@ class Server:
         self.torch = torch
         self.device = torch.device("cuda" if device is None else device)
         self.tol, self.inner_tol, self.max_outer = tol, inner_tol, max_outer
-        self.solvers = []
-        self.resident_bytes = 0
-        for p in problems:
-            A = Stencil5.from_problem(p)
-            S = Solver(A, ainv_setup(A, drop_tol), "mixed", device=self.device)
-            self.solvers.append(S)
-            self.resident_bytes += S.footprint_bytes
-        self.item_bytes = [Batch.item_bytes(S, 1) for S in self.solvers]
-        self.budget = hbm_budget            # bytes for in-flight request vectors (None: no limit)
-        self.max_slots = max_slots
         # size class of each grid: index of the first bound above its cell count;
         # grids of at least solo_cells cells form the last class, one lane each
         bounds = sorted(class_cells)
@@ -125,10 +118,28 @@ class Server:
         solo_class = len(bounds) + 1
         self.klass = [solo_class if so else k for k, so in zip(self.klass, self.solo)]
         used = sorted({k for k, so in zip(self.klass, self.solo) if not so})
+        # one stream per batch class and per lane, made together (distinct
+        # hardware queues); the other grids' solvers take pooled streams
+        self.hw_streams = {("batch", k): HwStream(self.device) for k in used}
+        self.hw_streams.update({("solo", g): HwStream(self.device)
+                                for g, so in enumerate(self.solo) if so})
+        self.solvers = []
+        self.resident_bytes = 0
+        for g, p in enumerate(problems):
+            A = Stencil5.from_problem(p)
+            hs = self.hw_streams.get(("solo", g))
+            S = Solver(A, ainv_setup(A, drop_tol), "mixed", device=self.device,
+                       stream=None if hs is None else hs.torch)
+            self.solvers.append(S)
+            self.resident_bytes += S.footprint_bytes
+        self.item_bytes = [Batch.item_bytes(S, 1) for S in self.solvers]
+        self.budget = hbm_budget            # bytes for in-flight request vectors (None: no limit)
+        self.max_slots = max_slots
         # class_grid: workgroups per launch of each class's batch (None: 2048),
         # so that a large grid's kernels can leave CUs to the other classes
         grids = class_grid or {}
         self.batches = {k: Batch(max_slots=max_slots, device=self.device, chunk=chunk,
+                                 stream=self.hw_streams[("batch", k)].torch,
                                  grid=grids.get(k)) for k in used}
         self.in_flight_bytes = 0
         self.busy = [False] * len(self.solvers)
@@ -138,9 +149,18 @@ class Server:
         self._solo_flying = 0
 
     def close(self):
+        """Stops the lanes, then releases the batches, the solvers and the
+        streams (the server cannot serve afterwards)."""
         for lane in self.lanes.values():
             lane.close()
         self.lanes = {}
+        for B in self.batches.values():
+            B.close()
+        for S in self.solvers:
+            S.close()
+        for hs in self.hw_streams.values():
+            hs.close()
+        self.hw_streams = {}
 
     def fits(self, grid):
         return self.budget is None or self.in_flight_bytes + self.item_bytes[grid] <= self.budget
