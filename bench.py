@@ -36,6 +36,7 @@ NX, NY, TAU, TOL = 1442, 1021, 0.05, 1e-10
 # fixed-fill AINV settings reported beside the threshold factor: (drop_tol, count)
 FIXED_FILL = ((0.01, 8),)
 SAMPLE_TOL = 1e-14      # stopping tolerance of the oracle's timed samples
+KEEP_SEGMENT = 0.1      # residual reduction of one inner run when the direction is kept
 PLACEMENTS = 1          # workspace bases the FP64 solver tries (1: the aligned base alone)
 PEAK_HBM_GBS = 8000.0
 METRIC = "PCG iter/s + HBM GB/s @1442x1021 FP64 vs mixed; served solves/s, p99 lat"
@@ -698,7 +699,18 @@ def main():
     log(f"mixed: {dtm * 1e3:.2f} ms/solve, outer {m.outer}, inner {m.inner_total}, "
         f"true relres {m.true_relres:.2e}, |x_mixed - x_fp64|/|x_fp64| {err_mx:.2e}")
     x_mixed = m.x.cpu().numpy()
-    # the spec reading of the mixed form: the inner operator in FP32 too
+    # the same refinement with the inner direction kept across corrections
+    Smx.solve_mixed(b, tol=TOL, refine="keep")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        mk = Smx.solve_mixed(b, tol=TOL, inner_tol=KEEP_SEGMENT, refine="keep")
+    torch.cuda.synchronize()
+    dtk = (time.perf_counter() - t0) / args.steps
+    x_keep = mk.x.cpu().numpy()
+    log(f"mixed, direction kept: {dtk * 1e3:.2f} ms/solve, corrections {mk.outer}, "
+        f"inner {mk.inner_total}, true relres {mk.true_relres:.2e}")
+    # the inner operator in FP32 too
     Sa32 = P.Solver(A, G, "mixed_a32", device=dev)
     Sa32.tune(chunk=args.chunk, use_graph=not args.no_graph, max_blocks=args.max_blocks)
     Sa32.solve_mixed(b, tol=TOL)
@@ -708,8 +720,18 @@ def main():
         ma = Sa32.solve_mixed(b, tol=TOL, inner_tol=1e-5, max_outer=30)
     torch.cuda.synchronize()
     dta = (time.perf_counter() - t0) / args.steps
+    Sa32.solve_mixed(b, tol=TOL, refine="keep")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        mak = Sa32.solve_mixed(b, tol=TOL, inner_tol=KEEP_SEGMENT, refine="keep")
+    torch.cuda.synchronize()
+    dtak = (time.perf_counter() - t0) / args.steps
     ms_a32 = Sa32.profile_iteration(b, reps=100, mode=1)
     x_a32 = ma.x.cpu().numpy()
+    x_a32k = mak.x.cpu().numpy()
+    log(f"mixed, FP32 operator, direction kept: {dtak * 1e3:.2f} ms/solve, corrections "
+        f"{mak.outer}, inner {mak.inner_total}")
     log(f"mixed, FP32 operator: {dta * 1e3:.2f} ms/solve, outer {ma.outer}, inner {ma.inner_total}, "
         f"true relres {ma.true_relres:.2e}, inner iteration {ms_a32[3] * 1e3:.1f} us")
     Sa32.close()
@@ -839,12 +861,14 @@ def main():
         budget_frac=args.serve_budget_frac)
 
     cpu = None
-    err_ora = err_a32_ora = None
+    err_ora = err_a32_ora = err_keep_ora = err_a32k_ora = None
     if not args.no_cpu:
         ora_thread.join()
         xo = oracle_x["x"]
         err_ora = float(np.linalg.norm(x_mixed - xo) / np.linalg.norm(xo))
         err_a32_ora = float(np.linalg.norm(x_a32 - xo) / np.linalg.norm(xo))
+        err_keep_ora = float(np.linalg.norm(x_keep - xo) / np.linalg.norm(xo))
+        err_a32k_ora = float(np.linalg.norm(x_a32k - xo) / np.linalg.norm(xo))
         log(f"mixed vs the FP64 oracle's solution ({oracle_x['iters']} iterations): "
             f"{err_ora:.2e}; with the FP32 operator {err_a32_ora:.2e}")
         log(f"cpu baseline (oracle, ~{args.cpu_seconds:.0f}s)")
@@ -882,11 +906,25 @@ def main():
                   "model_bytes_per_inner_iter": b_iter32,
                   "kernel_ms": dict(zip(names, [round(v, 5) for v in ms32[:3]])),
                   "iteration_ms": round(ms32[3], 5)},
+        "mixed_keep_direction": {
+            "refine": "inner direction kept across corrections (reliable updates), "
+                      f"each inner run reducing its residual by {KEEP_SEGMENT}",
+            "ms_per_solve": round(dtk * 1e3, 3), "corrections": mk.outer,
+            "inner_iters": mk.inner_total, "true_relres": mk.true_relres,
+            "rel_err_vs_oracle": err_keep_ora, "speedup_vs_fp64": round(dt / args.steps / dtk, 3),
+            "speedup_vs_restarted": round(dtm / dtk, 3)},
         "mixed_fp32_operator": {"ms_per_solve": round(dta * 1e3, 3), "outer": ma.outer,
                                 "inner_iters": ma.inner_total, "true_relres": ma.true_relres,
                                 "rel_err_vs_oracle": err_a32_ora,
                                 "speedup_vs_fp64": round(dt / args.steps / dta, 3),
-                                "iteration_ms": round(ms_a32[3], 5)},
+                                "iteration_ms": round(ms_a32[3], 5),
+                                "keep_direction": {"ms_per_solve": round(dtak * 1e3, 3),
+                                                   "corrections": mak.outer,
+                                                   "inner_iters": mak.inner_total,
+                                                   "true_relres": mak.true_relres,
+                                                   "rel_err_vs_oracle": err_a32k_ora,
+                                                   "speedup_vs_fp64":
+                                                       round(dt / args.steps / dtak, 3)}},
         "csr_unstructured": csr,
         "jacobi": {"iters": rj.iters, "ms_per_solve": round(dtj * 1e3, 3),
                    "true_relres": rj.true_relres},

@@ -331,6 +331,31 @@ int pcga_pcg_solve_mixed(pcga_solver_t *S, const double *b_dev, double *x_dev,
                          double *hist_host, int32_t hist_cap, int32_t *hist_len,
                          double *true_relres);
 
+/* pcga_pcg_solve_mixed_ex: pcga_pcg_solve_mixed with a choice of refinement.
+ * refine = PCGA_REFINE_RESTART: as pcga_pcg_solve_mixed (every inner PCG
+ *   starts from e = 0, d = s).
+ * refine = PCGA_REFINE_KEEP: the inner direction is kept across corrections
+ *   (reliable updates, Sleijpen and van der Vorst 1996).  Each inner run
+ *   stops once its FP32 recursive residual has dropped by the factor
+ *   max(inner_tol, tol / rel_o) (rel_o = ||b - A x_o|| / ||b||); its
+ *   correction is added to x in FP64, r is replaced by the FP64 b - A x, and
+ *   the next run continues from the last direction: d = s + (rho_new /
+ *   rho_old) d instead of d = s.  In exact arithmetic this is one PCG run
+ *   of Algorithm 1 whose residual is recomputed at each correction; the
+ *   FP64 parts are those of the restarted form.  inner_tol must be in
+ *   (0, 1); 0.1 is the usual choice (about one correction per decade).
+ *   *outer counts corrections, hist_host receives the true residual before
+ *   each of them and at the end.
+ * Other arguments, results and errors as pcga_pcg_solve_mixed; EINVAL for an
+ * unknown refine value. */
+#define PCGA_REFINE_RESTART 0
+#define PCGA_REFINE_KEEP 1
+int pcga_pcg_solve_mixed_ex(pcga_solver_t *S, const double *b_dev, double *x_dev, double tol,
+                            double inner_tol, int32_t max_outer, int32_t inner_maxit,
+                            int32_t refine, int32_t *outer, int32_t *inner_total,
+                            double *hist_host, int32_t hist_cap, int32_t *hist_len,
+                            double *true_relres);
+
 /* ---- single steps of the hot path (for parity tests and profiling) -------
  * y = A x (FP64, the five-point product of eq. (10)). */
 int pcga_apply_a(pcga_solver_t *S, const double *x_dev, double *y_dev);

@@ -127,6 +127,8 @@ def _declare(L):
     L.ora_pcg_mixed.restype = _int
     L.ora_pcg_mixed_ex.argtypes = L.ora_pcg_mixed.argtypes + [_int]
     L.ora_pcg_mixed_ex.restype = _int
+    L.ora_pcg_mixed_opt.argtypes = L.ora_pcg_mixed.argtypes + [_int, _int]
+    L.ora_pcg_mixed_opt.restype = _int
     L.ora_spmv32.argtypes = [_i64, _i64, _int, _p, _p, _p, _p, _p, _int]
     L.ora_spmv32.restype = None
     L.ora_fsai_band.argtypes = [_i64, _i64, _int, _p, _p, _p, _i64, _p, _p]
@@ -332,9 +334,11 @@ def spmv32(p, x, a32=False):
 
 
 def pcg_mixed(p, F: AInv, b=None, x0=None, tol=1e-10, inner_tol=1e-5, max_outer=30,
-              inner_maxit=None, a32=False) -> MixedResult:
+              inner_maxit=None, a32=False, keep=False) -> MixedResult:
     """FP64 refinement around an FP32 inner PCG (FP64 scalars).  a32: the
-    inner operator in FP32 as well (coefficients rounded, sums in FP32)."""
+    inner operator in FP32 as well (coefficients rounded, sums in FP32).
+    keep: the inner direction is kept across corrections (reliable updates);
+    inner_tol is then the residual reduction of one segment."""
     n = p.nx * p.ny
     b = _f64(p.b if b is None else b)
     x = np.zeros(n) if x0 is None else _f64(x0).copy()
@@ -342,11 +346,12 @@ def pcg_mixed(p, F: AInv, b=None, x0=None, tol=1e-10, inner_tol=1e-5, max_outer=
     hist = np.zeros(max_outer + 1)
     o = ctypes.c_int64()
     tot = ctypes.c_int64()
-    st = lib().ora_pcg_mixed_ex(p.nx, p.ny, int(p.periodic), _ptr(_f64(p.diag)),
-                             _ptr(_f64(p.ae)), _ptr(_f64(p.an)), _ptr(F.colptr),
-                             _ptr(F.rowidx), _ptr(F.val), _ptr(F.D), _ptr(b), _ptr(x),
-                             float(tol), float(inner_tol), int(max_outer), inner_maxit,
-                             ctypes.byref(o), ctypes.byref(tot), _ptr(hist), int(bool(a32)))
+    st = lib().ora_pcg_mixed_opt(p.nx, p.ny, int(p.periodic), _ptr(_f64(p.diag)),
+                              _ptr(_f64(p.ae)), _ptr(_f64(p.an)), _ptr(F.colptr),
+                              _ptr(F.rowidx), _ptr(F.val), _ptr(F.D), _ptr(b), _ptr(x),
+                              float(tol), float(inner_tol), int(max_outer), inner_maxit,
+                              ctypes.byref(o), ctypes.byref(tot), _ptr(hist), int(bool(a32)),
+                              int(bool(keep)))
     if st < 0:
         raise OracleError(st)
     return MixedResult(x, o.value, tot.value, hist[: o.value + 1].copy(), st)

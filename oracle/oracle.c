@@ -23,7 +23,8 @@
  *                   of Sec. 5).
  *   ora_prec_apply  s = Z D^-1 Z^T r (Algorithm 1, preconditioning step).
  *   ora_pcg         Algorithm 1 (FSAI/AINV-PCG), FP64.
- *   ora_pcg_mixed   FP64 iterative refinement around an FP32 inner PCG.
+ *   ora_pcg_mixed   FP64 iterative refinement around an FP32 inner PCG
+ *                   (restarted, or with the direction kept: ora_pcg_mixed_opt).
  *   ora_fsai_band   the paper's own banded factor of T (Sec. 3, six-step
  *                   pattern scheme, Propositions 2-3).
  *   ora_ts_*        the surrounding time step: the right-hand side of eq. (8)
@@ -699,6 +700,15 @@ int ora_pcg_csr(int64_t n, const int64_t *rowptr, const int64_t *col, const doub
 /*          coefficients rounded to float, q = A d summed in float): every   */
 /*          inner datum in FP32, FP64 kept for the residual, the solution    */
 /*          and the CG scalars.                                              */
+/* keep != 0: the direction is kept across corrections (reliable updates:  */
+/*          Sleijpen and van der Vorst, 1996).  After each correction the    */
+/*          inner solve continues from the new residual with the previous   */
+/*          direction, d = s + (rho_new/rho_old) d, instead of d = s; in     */
+/*          exact arithmetic the iterates are those of one PCG run, with the */
+/*          residual replaced by the true FP64 one at every correction.     */
+/*          The inner stop of outer step o is max(inner_tol, tol/rel_o),    */
+/*          rel_o = ||r_o||/||b||: a segment stops early when the remaining  */
+/*          reduction is below inner_tol.                                   */
 /* outer_hist[o] = ||b - A x_o||/||b|| (capacity max_outer+1).               */
 /* ------------------------------------------------------------------------ */
 static void spmv32(int64_t nx, int64_t ny, int periodic, const double *diag,
@@ -754,12 +764,12 @@ static void prec32(int64_t n, const int64_t *colptr, const int64_t *rowidx,
     }
 }
 
-int ora_pcg_mixed_ex(int64_t nx, int64_t ny, int periodic, const double *diag,
-                     const double *ae, const double *an, const int64_t *colptr,
-                     const int64_t *rowidx, const double *val, const double *D,
-                     const double *b, double *x, double tol, double inner_tol,
-                     int64_t max_outer, int64_t inner_maxit, int64_t *outer,
-                     int64_t *inner_total, double *outer_hist, int a32) {
+int ora_pcg_mixed_opt(int64_t nx, int64_t ny, int periodic, const double *diag,
+                      const double *ae, const double *an, const int64_t *colptr,
+                      const int64_t *rowidx, const double *val, const double *D,
+                      const double *b, double *x, double tol, double inner_tol,
+                      int64_t max_outer, int64_t inner_maxit, int64_t *outer,
+                      int64_t *inner_total, double *outer_hist, int a32, int keep) {
     int64_t n = nx * ny;
     int64_t nnz = colptr[n];
     double *r64 = (double *)malloc((size_t)n * sizeof(double));
@@ -789,6 +799,7 @@ int ora_pcg_mixed_ex(int64_t nx, int64_t ny, int periodic, const double *diag,
         goto out;
     }
     int64_t o = 0;
+    double rho = 0.0;   /* last rho of the inner run (kept across corrections) */
     for (;;) {
         ora_spmv(nx, ny, periodic, diag, ae, an, x, y64);
         for (int64_t k = 0; k < n; k++) r64[k] = b[k] - y64[k];
@@ -800,11 +811,21 @@ int ora_pcg_mixed_ex(int64_t nx, int64_t ny, int periodic, const double *diag,
         for (int64_t k = 0; k < n; k++) { r[k] = (float)r64[k]; e[k] = 0.0f; }
         double nr = sqrt(dot32(n, r, r));
         prec32(n, colptr, rowidx, val32, D32, r, s, t);
-        for (int64_t k = 0; k < n; k++) d[k] = s[k];
-        double rho = dot32(n, s, r);
+        double rho_new = dot32(n, s, r);
+        if (keep && o > 0) {
+            /* continue the previous inner run: its last rho divides */
+            if (!(rho_new > 0.0)) { st = ORA_EBREAKDOWN; goto out; }
+            float bf = (float)(rho_new / rho);
+            for (int64_t k = 0; k < n; k++) { float p = bf * d[k]; d[k] = s[k] + p; }
+        } else {
+            for (int64_t k = 0; k < n; k++) d[k] = s[k];
+        }
+        rho = rho_new;
+        double itol = inner_tol;
+        if (keep && tol / outer_hist[o] > itol) itol = tol / outer_hist[o];
         double rel = 1.0;
         int64_t it = 0;
-        while (rel > inner_tol && it < inner_maxit) {
+        while (rel > itol && it < inner_maxit) {
             spmv32(nx, ny, periodic, diag, ae, an, d, q, a32);
             double dq = dot32(n, d, q);
             if (!(dq > 0.0) || !(rho > 0.0)) { st = ORA_EBREAKDOWN; goto out; }
@@ -814,9 +835,9 @@ int ora_pcg_mixed_ex(int64_t nx, int64_t ny, int periodic, const double *diag,
             for (int64_t k = 0; k < n; k++) { float p = af * q[k]; r[k] = r[k] - p; }
             it++;
             rel = sqrt(dot32(n, r, r)) / nr;
-            if (rel <= inner_tol) break;
+            if (rel <= itol) break;
             prec32(n, colptr, rowidx, val32, D32, r, s, t);
-            double rho_new = dot32(n, s, r);
+            rho_new = dot32(n, s, r);
             if (!(rho_new > 0.0)) { st = ORA_EBREAKDOWN; goto out; }
             double beta = rho_new / rho;
             rho = rho_new;
@@ -832,6 +853,17 @@ out:
     free(r64); free(y64); free(val32); free(D32); free(e); free(r); free(s);
     free(d); free(q); free(t);
     return st;
+}
+
+int ora_pcg_mixed_ex(int64_t nx, int64_t ny, int periodic, const double *diag,
+                     const double *ae, const double *an, const int64_t *colptr,
+                     const int64_t *rowidx, const double *val, const double *D,
+                     const double *b, double *x, double tol, double inner_tol,
+                     int64_t max_outer, int64_t inner_maxit, int64_t *outer,
+                     int64_t *inner_total, double *outer_hist, int a32) {
+    return ora_pcg_mixed_opt(nx, ny, periodic, diag, ae, an, colptr, rowidx, val, D, b, x, tol,
+                             inner_tol, max_outer, inner_maxit, outer, inner_total, outer_hist,
+                             a32, 0);
 }
 
 int ora_pcg_mixed(int64_t nx, int64_t ny, int periodic, const double *diag,

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libpcgainv.so")
 OK, NOCONV, EINVAL, EBREAKDOWN, ENAN, EHIP, ENOMEM = 0, 1, -1, -2, -3, -4, -5
 PERIODIC_X = 1
 FP64, MIXED, MIXED_A32 = 0, 1, 2
+REFINE_RESTART, REFINE_KEEP = 0, 1
 NOALLOC_MAX_BYTES = 64 << 20   # PCGA_NOALLOC_MAX_BYTES
 
 
@@ -79,6 +80,8 @@ _SIGS = {
                                ctypes.c_int),
     "pcga_pcg_solve_mixed": ([_p, _p, _p, _dbl, _dbl, _i32, _i32, _pi32, _pi32, _p, _i32,
                               _pi32, _pdbl], ctypes.c_int),
+    "pcga_pcg_solve_mixed_ex": ([_p, _p, _p, _dbl, _dbl, _i32, _i32, _i32, _pi32, _pi32, _p,
+                                 _i32, _pi32, _pdbl], ctypes.c_int),
     "pcga_apply_a": ([_p, _p, _p], ctypes.c_int),
     "pcga_apply_prec": ([_p, _p, _p, _p], ctypes.c_int),
     "pcga_step_stencil": ([_p, _p, _p, _dbl, _p, _p, _pdbl], ctypes.c_int),

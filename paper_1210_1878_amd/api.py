@@ -369,9 +369,18 @@ class Solver:
         h = hist[: min(hl.value, cap)].copy() if hist is not None else np.zeros(0)
         return SolveResult(x, iters.value, h, st, tr.value)
 
-    def solve_mixed(self, b, x0=None, tol=1e-10, inner_tol=1e-5, max_outer=20,
-                    inner_maxit=None) -> SolveResult:
+    def solve_mixed(self, b, x0=None, tol=1e-10, inner_tol=None, max_outer=None,
+                    inner_maxit=None, refine="restart") -> SolveResult:
+        """FP64 refinement around the FP32 inner PCG.  refine="restart": every
+        inner run starts from d = s and stops at inner_tol (default 1e-5)
+        relative to its own start; refine="keep": the direction is kept across
+        corrections and inner_tol (default 0.1) is the reduction of one run."""
         L = _lib.load()
+        mode = {"restart": _lib.REFINE_RESTART, "keep": _lib.REFINE_KEEP}[refine]
+        if inner_tol is None:
+            inner_tol = 0.1 if mode == _lib.REFINE_KEEP else 1e-5
+        if max_outer is None:
+            max_outer = 200 if mode == _lib.REFINE_KEEP else 20
         bp, x, xp = self._xb(b, x0)
         cap = max_outer + 1
         hist = np.zeros(cap)
@@ -379,11 +388,12 @@ class Solver:
         tot = ctypes.c_int32()
         hl = ctypes.c_int32()
         tr = ctypes.c_double()
-        st = L.pcga_pcg_solve_mixed(self._h, bp, xp, float(tol), float(inner_tol), int(max_outer),
-                                    -1 if inner_maxit is None else int(inner_maxit),
-                                    ctypes.byref(outer), ctypes.byref(tot), hist.ctypes.data, cap,
-                                    ctypes.byref(hl), ctypes.byref(tr))
-        check(st, "pcga_pcg_solve_mixed", allow=(_lib.OK, _lib.NOCONV))
+        st = L.pcga_pcg_solve_mixed_ex(self._h, bp, xp, float(tol), float(inner_tol),
+                                       int(max_outer),
+                                       -1 if inner_maxit is None else int(inner_maxit), mode,
+                                       ctypes.byref(outer), ctypes.byref(tot), hist.ctypes.data,
+                                       cap, ctypes.byref(hl), ctypes.byref(tr))
+        check(st, "pcga_pcg_solve_mixed_ex", allow=(_lib.OK, _lib.NOCONV))
         return SolveResult(x, tot.value, hist[: hl.value].copy(), st, tr.value,
                            outer=outer.value, inner_total=tot.value)
 
@@ -550,12 +560,13 @@ def pcg_solve(A: Stencil5, F: AInv, b, x0=None, tol=1e-10, maxit=None, solver=No
     return S.solve(b, x0, tol=tol, maxit=maxit)
 
 
-def pcg_solve_mixed(A: Stencil5, F: AInv, b, x0=None, tol=1e-10, inner_tol=1e-5, max_outer=20,
-                    inner_maxit=None, solver=None) -> SolveResult:
-    """FP32 inner PCG with FP64 iterative refinement."""
+def pcg_solve_mixed(A: Stencil5, F: AInv, b, x0=None, tol=1e-10, inner_tol=None, max_outer=None,
+                    inner_maxit=None, solver=None, refine="restart") -> SolveResult:
+    """FP32 inner PCG with FP64 iterative refinement (restarted, or with the
+    direction kept across corrections: refine="keep")."""
     S = solver if solver is not None else Solver(A, F, "mixed", device=b.device)
     return S.solve_mixed(b, x0, tol=tol, inner_tol=inner_tol, max_outer=max_outer,
-                         inner_maxit=inner_maxit)
+                         inner_maxit=inner_maxit, refine=refine)
 
 
 class Batch:

@@ -637,7 +637,7 @@ __global__ __launch_bounds__(kBS) void k_stencil(DevOp<C> A, const T *__restrict
         }
         return;
     }
-    const double beta = (k == 0) ? 0.0 : rho / c->rho[par ^ 1];
+    const double beta = (k == 0 && !c->cont) ? 0.0 : rho / c->rho[par ^ 1];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         c->rho[par] = rho;
         if (XD && k > 0) c->xa = k - 1;
@@ -1202,6 +1202,7 @@ __global__ __launch_bounds__(kBS) void k_fin_residual(CtlBlock *cb, Partials P, 
     c->k = 0;
     c->ax = -1;
     c->xa = -1;
+    c->cont = 0;
     c->status = kStOk;
     c->done = 0;
     const double rel = (nb > 0.0) ? sqrt(v[1]) / nb : 0.0;
@@ -1258,8 +1259,15 @@ __global__ __launch_bounds__(kBS) void k_refine(DevOp<double> A, const double *_
     put_partials<3>(pv, P.res, L);
 }
 
+// keep (mixed solve with the direction kept across corrections): the inner
+// run stops at max(inner_tol, outer_tol / rel) relative to ||fl32(r)||, rel
+// = ||r|| / ||b||, and nothing runs (done) once rel <= outer_tol.  cont: the
+// run continues the last one; its first beta divides by that run's last
+// rho, formed at its iteration K-1 (K = c->k iterations) and stored in
+// rho[(K-1) & 1], which is moved to rho[1], the slot read at iteration 0.
 static __global__ __launch_bounds__(kBS) void k_fin_refine(CtlBlock *cb, Partials P, int g,
-                                                    double inner_tol, int inner_maxit) {
+                                                           double inner_tol, int inner_maxit,
+                                                           int keep, int cont, double outer_tol) {
     double v[3];
     sum_partials<3>(P.res, g, v);
     if (threadIdx.x != 0) return;
@@ -1268,7 +1276,16 @@ static __global__ __launch_bounds__(kBS) void k_fin_refine(CtlBlock *cb, Partial
     c->rr_true = v[1];
     c->inner_nb2 = v[2];
     c->nb = sqrt(v[2]);
-    c->tol = inner_tol;
+    double itol = inner_tol;
+    bool outer_done = false;
+    if (keep) {
+        const double rel = sqrt(v[1]) / sqrt(v[0]);
+        outer_done = rel <= outer_tol;
+        if (rel > 0.0 && outer_tol / rel > itol) itol = outer_tol / rel;
+    }
+    if (cont && c->k > 0 && (c->k & 1)) c->rho[1] = c->rho[0];
+    c->cont = cont ? 1 : 0;
+    c->tol = itol;
     c->maxit = inner_maxit;
     c->kk[0] = 0;
     c->kk[1] = 0;
@@ -1278,7 +1295,7 @@ static __global__ __launch_bounds__(kBS) void k_fin_refine(CtlBlock *cb, Partial
     c->status = kStOk;
     c->relres = 1.0;
     cb->hist[0] = 1.0;
-    c->done = (v[2] > 0.0) ? 0 : 1;
+    c->done = (v[2] > 0.0 && !outer_done) ? 0 : 1;
     if (is_bad(v[0]) || is_bad(v[1]) || is_bad(v[2])) {
         c->status = kStNan;
         c->done = 1;

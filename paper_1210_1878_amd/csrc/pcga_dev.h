@@ -36,6 +36,7 @@ __host__ __device__ inline int tile_count(int nx, int ny, int tr) {
 // 1442 x 1021 with the default slice widths: FP64 5 per CU (86.6-87.4 us
 // per iteration against 89.0-89.7 with 4), mixed 6 per CU.
 constexpr int kDefaultBlocks = 1280;
+constexpr int kTailChunk = 4;        // iterations of the short chunk launched near a stop
 constexpr int kDefaultBlocksMixed = 1536;
 constexpr int kMaxBand = 8;          // widest band stored by diagonals
 // Memory-side cache (Infinity Cache) of one MI355X: 256 MiB.  The streams an
@@ -119,7 +120,11 @@ struct Ctl {
     // x += alpha_k d_k deferred to the next iteration's stencil: the last
     // iteration whose alpha was formed, and the last whose update was applied
     int32_t ax, xa;
-    int32_t pad[3];
+    // 1: this inner run continues the previous one (mixed solve with the
+    // direction kept): its first iteration forms beta = rho_0 / rho[1]
+    // instead of taking d = s
+    int32_t cont;
+    int32_t pad[2];
 };
 
 struct CtlBlock {

@@ -898,7 +898,7 @@ int pcga_solver_create_csr(const pcga_csr_t *A, const pcga_ainv_t *F, int precis
 
 int pcga_solver_destroy(pcga_solver_t *S) {
     if (!S) return PCGA_OK;
-    if (S->graph) (void)hipGraphExecDestroy(S->graph);
+    S->drop_graphs();
     if (S->snap[0]) (void)hipHostFree(S->snap[0]);
     if (S->snap[1]) (void)hipHostFree(S->snap[1]);
     if (S->ev[0]) (void)hipEventDestroy(S->ev[0]);
@@ -930,10 +930,7 @@ int pcga_solver_tune(pcga_solver_t *S, int32_t chunk, int32_t use_graph, int32_t
     if (max_blocks == 0) max_blocks = S->precision != PCGA_FP64 ? kDefaultBlocksMixed : kDefaultBlocks;
     if (max_blocks < 8 || max_blocks > kMaxBlocks)
         return fail(PCGA_EINVAL, "max_blocks must be 0 or 8.." + std::to_string(kMaxBlocks));
-    if (S->graph && (chunk != S->graph_chunk || max_blocks != S->max_blocks)) {
-        (void)hipGraphExecDestroy(S->graph);
-        S->graph = nullptr;
-    }
+    if (S->graph && (chunk != S->graph_chunk || max_blocks != S->max_blocks)) S->drop_graphs();
     S->chunk = chunk;
     S->use_graph = use_graph != 0;
     S->max_blocks = max_blocks;
@@ -947,10 +944,7 @@ int pcga_solver_set_grids(pcga_solver_t *S, int32_t g_stencil, int32_t g_zt, int
     for (int i = 0; i < 3; i++)
         if (g[i] < 0 || g[i] > kMaxBlocks)
             return fail(PCGA_EINVAL, "workgroup counts must be 0..." + std::to_string(kMaxBlocks));
-    if (S->graph) {
-        (void)hipGraphExecDestroy(S->graph);
-        S->graph = nullptr;
-    }
+    S->drop_graphs();
     for (int i = 0; i < 3; i++) S->g_cap[i] = g[i];
     S->grids();
     return upload_bounds(*S);
@@ -1138,18 +1132,21 @@ void launch_true_residual(pcga_solver &S, CtlBlock *cb, const Partials &P, const
 }
 
 void launch_refine(pcga_solver &S, bool add_e, const double *x, double *xnew, const double *b,
-                   double inner_tol, int inner_maxit) {
+                   double inner_tol, int inner_maxit, bool keep = false, bool cont = false,
+                   double outer_tol = 0.0) {
     if (add_e)
         k_refine<true><<<S.g_st, kBS, 0, S.stream>>>(S.A64, x, S.e32, xnew, b, S.r32[0], S.P);
     else
         k_refine<false><<<S.g_st, kBS, 0, S.stream>>>(S.A64, x, nullptr, nullptr, b, S.r32[0], S.P);
-    k_fin_refine<<<1, kBS, 0, S.stream>>>(S.cb, S.P, S.g_st, inner_tol, inner_maxit);
+    k_fin_refine<<<1, kBS, 0, S.stream>>>(S.cb, S.P, S.g_st, inner_tol, inner_maxit, keep ? 1 : 0,
+                                          cont ? 1 : 0, outer_tol);
 }
 
-// t = D^-1 Z^T r0 ; s0 = Z t ; (s0, r0) partials ; d[0] = 0
+// t = D^-1 Z^T r0 ; s0 = Z t ; (s0, r0) partials ; d[0] = 0 (zero_d: a run
+// that continues the last one keeps its direction in d[0])
 template <typename T>
-int prologue_prec(pcga_solver &S, const IterBufs<T> &B) {
-    k_zero<T><<<zero_grid(S.n), kBS, 0, S.stream>>>((int)S.n, B.d[0]);
+int prologue_prec(pcga_solver &S, const IterBufs<T> &B, bool zero_d = true) {
+    if (zero_d) k_zero<T><<<zero_grid(S.n), kBS, 0, S.stream>>>((int)S.n, B.d[0]);
     if (S.jacobi) {
         k_jacobi<T, true><<<S.g_st, kBS, 0, S.stream>>>(B.dinv, B.r[0], nullptr, nullptr, nullptr,
                                                         nullptr, B.s, (int)S.n, B.cb, B.P, 0, 0);
@@ -1179,6 +1176,7 @@ int prologue_prec(pcga_solver &S, const IterBufs<T> &B) {
 // with beta = 0, iteration 0 (the kernel then takes d = s).
 __global__ void k_step_state(CtlBlock *cb, Partials P, double beta) {
     cb->c.done = 0;
+    cb->c.cont = 0;
     cb->c.kk[0] = beta > 0.0 ? 1 : 0;
     cb->c.rho[1] = 1.0;
     P.sr[0] = beta > 0.0 ? beta : 1.0;
@@ -1204,25 +1202,56 @@ int wait_snap(pcga_solver &S, int slot) {
 }
 
 template <typename T>
-int ensure_graph(pcga_solver &S, const IterBufs<T> &B) {
-    if (S.graph && S.graph_chunk == S.chunk) return PCGA_OK;
-    if (S.graph) {
-        (void)hipGraphExecDestroy(S.graph);
-        S.graph = nullptr;
-    }
+int capture_iters(pcga_solver &S, const IterBufs<T> &B, int count, hipGraphExec_t *out) {
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(S.stream, hipStreamCaptureModeThreadLocal));
-    launch_iters<T>(S, B, S.chunk);
+    launch_iters<T>(S, B, count);
     hipError_t e = hipStreamEndCapture(S.stream, &g);
     if (e != hipSuccess) return fail(PCGA_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&S.graph, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-        S.graph = nullptr;
+        *out = nullptr;
         return fail(PCGA_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    return PCGA_OK;
+}
+
+// The chunk graph (S.chunk iterations) and the tail graph (kTailChunk).
+template <typename T>
+int ensure_graph(pcga_solver &S, const IterBufs<T> &B) {
+    if (S.graph && S.graph_chunk == S.chunk && (S.graph_tail || S.chunk <= kTailChunk))
+        return PCGA_OK;
+    S.drop_graphs();
+    int st = capture_iters<T>(S, B, S.chunk, &S.graph);
+    if (st) return st;
+    if (S.chunk > kTailChunk && (st = capture_iters<T>(S, B, kTailChunk, &S.graph_tail))) {
+        S.drop_graphs();
+        return st;
     }
     S.graph_chunk = S.chunk;
     return PCGA_OK;
+}
+
+// Iterations left until the run stops, predicted from the residual history
+// of the last snapshot: the relative residual's mean decrease per iteration
+// since the run's start (or over the ring's length), extrapolated to the stop
+// tolerance, and the iteration cap.  Large when there is too little history
+// or no decrease.  (CG's residual is not monotone: a mean over many
+// iterations predicts the stop better than the last chunk's decrease.)
+int64_t predicted_left(const CtlBlock *sn) {
+    const Ctl &c = sn->c;
+    const int64_t k = c.k;
+    int64_t left = std::min<int64_t>((int64_t)c.maxit - k, (int64_t)1 << 40);
+    const int64_t span = std::min<int64_t>(k, kHistRing - 1);
+    if (span < 2 || !(c.tol > 0.0)) return left;
+    const double now = sn->hist[k & (kHistRing - 1)], then = sn->hist[(k - span) & (kHistRing - 1)];
+    if (!(now > 0.0) || !(then > now)) return left;
+    if (now <= c.tol) return 0;
+    const double per_iter = std::log(now / then) / (double)span;   // < 0
+    const double est = std::log(c.tol / now) / per_iter;
+    if (est < (double)left) left = (int64_t)std::ceil(est);
+    return left;
 }
 
 // Run chunks until the device sets `done`.  hist_out receives entries 1..k
@@ -1247,11 +1276,12 @@ int run_chunks(pcga_solver &S, const IterBufs<T> &B, double *hist_out, int64_t h
         st = ensure_graph<T>(S, B);
         if (st) return st;
     }
-    auto launch = [&](int slot) -> int {
+    const bool tail_ok = !use_graph || S.graph_tail;
+    auto launch = [&](int slot, int count) -> int {
         if (use_graph) {
-            HIP_TRY(hipGraphLaunch(S.graph, S.stream));
+            HIP_TRY(hipGraphLaunch(count == S.chunk ? S.graph : S.graph_tail, S.stream));
         } else {
-            launch_iters<T>(S, B, S.chunk);
+            launch_iters<T>(S, B, count);
             HIP_TRY(hipGetLastError());
         }
         return snapshot(S, B.cb, slot);
@@ -1259,15 +1289,27 @@ int run_chunks(pcga_solver &S, const IterBufs<T> &B, double *hist_out, int64_t h
     int64_t seen = 0;
     int64_t c = 0;
     // Guards against a device-side failure to finish: the iteration count
-    // must advance with every chunk and cannot exceed maxit.
-    const int64_t max_chunks = maxit / S.chunk + 4;
-    if ((st = launch(0))) return st;
+    // must advance with every chunk, and the device stops by maxit.
+    const int64_t max_launched = maxit + 4 * (int64_t)S.chunk;
+    int64_t launched = S.chunk;
+    int in_flight = S.chunk;   // iterations of chunk c, not yet read
+    int64_t left = (int64_t)1 << 40;   // predicted after the last snapshot read (unknown: large)
+    if ((st = launch(0, S.chunk))) return st;
     for (;;) {
-        if ((st = launch((c + 1) & 1))) return st;
+        // chunk c is in flight; its successor is a full chunk unless the run
+        // is predicted to stop before chunk c has finished or within two full
+        // chunks after it (a full chunk launched past the stop runs as
+        // no-op kernels, about 7 us each against 0.3 us per iteration of a
+        // short chunk's host round trip)
+        const int next = (tail_ok && S.chunk > kTailChunk && left - in_flight < 2 * S.chunk)
+                             ? kTailChunk : S.chunk;
+        if ((st = launch((c + 1) & 1, next))) return st;
+        in_flight = next;
+        launched += next;
         if ((st = wait_snap(S, c & 1))) return st;
         const CtlBlock *sn = S.snap[c & 1];
         const int64_t k = sn->c.k;
-        if (!sn->c.done && (k <= seen || c > max_chunks)) {
+        if (!sn->c.done && (k <= seen || launched > max_launched)) {
             (void)wait_snap(S, (c + 1) & 1);
             return fail(PCGA_EHIP, "device iteration did not advance (k=" + std::to_string(k) + ")");
         }
@@ -1281,6 +1323,7 @@ int run_chunks(pcga_solver &S, const IterBufs<T> &B, double *hist_out, int64_t h
             final_slot = c & 1;
             return PCGA_OK;
         }
+        left = predicted_left(sn);
         c++;
     }
 }
@@ -1427,19 +1470,14 @@ int pcga_pcg_solve_noalloc(pcga_solver_t *S, const double *b_dev, double *x_dev,
                    true_relres, false);
 }
 
-int pcga_pcg_solve_mixed(pcga_solver_t *S, const double *b_dev, double *x_dev, double tol,
-                         double inner_tol, int32_t max_outer, int32_t inner_maxit, int32_t *outer,
-                         int32_t *inner_total, double *hist_host, int32_t hist_cap,
-                         int32_t *hist_len, double *true_relres) {
-    if (!S || !b_dev || !x_dev) return fail(PCGA_EINVAL, "NULL argument");
-    if (S->precision != PCGA_MIXED && S->precision != PCGA_MIXED_A32)
-        return fail(PCGA_EINVAL, "pcga_pcg_solve_mixed needs a PCGA_MIXED or PCGA_MIXED_A32 solver");
-    if (!(tol >= 0.0) || !(inner_tol > 0.0) || max_outer < 0)
-        return fail(PCGA_EINVAL, "bad tolerances or max_outer");
-    if (inner_maxit < 0) inner_maxit = (int32_t)std::min<int64_t>(S->n, INT32_MAX);
-    if (hist_cap < 0 || (hist_cap > 0 && !hist_host)) return fail(PCGA_EINVAL, "bad history buffer");
-    HIP_TRY(hipSetDevice(S->device));
-    pcga_solver &R = *S;
+}  // extern "C"
+
+namespace {
+
+// Restarted refinement: every inner run starts from d = s.
+int mixed_restart(pcga_solver &R, const double *b_dev, double *x_dev, double tol, double inner_tol,
+                  int32_t max_outer, int32_t inner_maxit, int32_t *outer, int32_t *inner_total,
+                  double *hist_host, int32_t hist_cap, int32_t *hist_len, double *true_relres) {
     IterBufs<float> B = bufs32(R);
     const size_t nb8 = R.n * sizeof(double);
     HIP_TRY(hipMemcpyAsync(R.x64[0], x_dev, nb8, hipMemcpyDeviceToDevice, R.stream));
@@ -1496,6 +1534,110 @@ int pcga_pcg_solve_mixed(pcga_solver_t *S, const double *b_dev, double *x_dev, d
     if (hist_len) *hist_len = o + 1;
     if (true_relres) *true_relres = rel;
     return result;
+}
+
+
+// Refinement with the direction kept across corrections (reliable updates):
+// each inner run stops after reducing its residual by inner_tol (or by what
+// is left to reach tol); its correction is folded into x in FP64, the
+// residual is replaced by the FP64 b - A x, and the next run continues with
+// the last direction, d = s + (rho_new / rho_old) d.  Everything between two
+// runs is queued without a host wait: the refine's finaliser sets done when
+// the outer residual has reached tol, so the queued run does nothing.
+int mixed_keep(pcga_solver &R, const double *b_dev, double *x_dev, double tol, double inner_tol,
+               int32_t max_outer, int32_t inner_maxit, int32_t *outer, int32_t *inner_total,
+               double *hist_host, int32_t hist_cap, int32_t *hist_len, double *true_relres) {
+    IterBufs<float> B = bufs32(R);
+    const size_t nb8 = R.n * sizeof(double);
+    HIP_TRY(hipMemcpyAsync(R.x64[0], x_dev, nb8, hipMemcpyDeviceToDevice, R.stream));
+    int cur = 0, o = 0, total = 0, st = 0, result = PCGA_OK;
+    double rel = 0.0;
+    launch_refine(R, false, R.x64[0], nullptr, b_dev, inner_tol, inner_maxit, true, false, tol);
+    for (;;) {
+        HIP_TRY(hipMemsetAsync(B.x, 0, R.n * sizeof(float), R.stream));   // e = 0
+        if ((st = prologue_prec<float>(R, B, o == 0))) return st;
+        int slot = 0;
+        if ((st = run_chunks<float>(R, B, nullptr, 0, inner_maxit, slot))) return st;
+        const Ctl c = R.snap[slot]->c;
+        if (c.bb == 0.0) {
+            HIP_TRY(hipMemsetAsync(x_dev, 0, nb8, R.stream));
+            HIP_TRY(hipStreamSynchronize(R.stream));
+            if (outer) *outer = 0;
+            if (inner_total) *inner_total = 0;
+            if (hist_len) *hist_len = 1;
+            if (hist_cap > 0) hist_host[0] = 0.0;
+            if (true_relres) *true_relres = 0.0;
+            return PCGA_OK;
+        }
+        rel = std::sqrt(c.rr_true) / std::sqrt(c.bb);
+        if (o < hist_cap) hist_host[o] = rel;
+        if (c.status == kStNan || !(rel == rel) || std::isinf(rel)) {
+            result = fail(PCGA_ENAN, "NaN/Inf in residual");
+            break;
+        }
+        if (rel <= tol) { result = PCGA_OK; break; }
+        if (o == max_outer) { result = PCGA_NOCONV; break; }
+        const int is = map_status(c.status);
+        if (is == PCGA_EBREAKDOWN || is == PCGA_ENAN) {
+            result = fail(is, "inner FP32 PCG failed (breakdown or NaN)");
+            break;
+        }
+        total += c.k;
+        o++;
+        if ((st = launch_x_pending<float>(R, B))) return st;
+        // the run's last direction d_{K-1} is in d[K & 1]; the next run reads d[0]
+        if (c.k & 1)
+            HIP_TRY(hipMemcpyAsync(B.d[0], B.d[1], R.n * sizeof(float), hipMemcpyDeviceToDevice,
+                                   R.stream));
+        launch_refine(R, true, R.x64[cur], R.x64[cur ^ 1], b_dev, inner_tol, inner_maxit, true, true,
+                      tol);
+        cur ^= 1;
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipMemcpyAsync(x_dev, R.x64[cur], nb8, hipMemcpyDeviceToDevice, R.stream));
+    HIP_TRY(hipStreamSynchronize(R.stream));
+    if (outer) *outer = o;
+    if (inner_total) *inner_total = total;
+    if (hist_len) *hist_len = o + 1;
+    if (true_relres) *true_relres = rel;
+    return result;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pcga_pcg_solve_mixed_ex(pcga_solver_t *S, const double *b_dev, double *x_dev, double tol,
+                            double inner_tol, int32_t max_outer, int32_t inner_maxit,
+                            int32_t refine, int32_t *outer, int32_t *inner_total,
+                            double *hist_host, int32_t hist_cap, int32_t *hist_len,
+                            double *true_relres) {
+    if (!S || !b_dev || !x_dev) return fail(PCGA_EINVAL, "NULL argument");
+    if (S->precision != PCGA_MIXED && S->precision != PCGA_MIXED_A32)
+        return fail(PCGA_EINVAL, "pcga_pcg_solve_mixed needs a PCGA_MIXED or PCGA_MIXED_A32 solver");
+    if (!(tol >= 0.0) || !(inner_tol > 0.0) || max_outer < 0)
+        return fail(PCGA_EINVAL, "bad tolerances or max_outer");
+    if (refine != PCGA_REFINE_RESTART && refine != PCGA_REFINE_KEEP)
+        return fail(PCGA_EINVAL, "refine must be PCGA_REFINE_RESTART or PCGA_REFINE_KEEP");
+    if (refine == PCGA_REFINE_KEEP && !(inner_tol < 1.0))
+        return fail(PCGA_EINVAL, "PCGA_REFINE_KEEP needs inner_tol < 1");
+    if (inner_maxit < 0) inner_maxit = (int32_t)std::min<int64_t>(S->n, INT32_MAX);
+    if (hist_cap < 0 || (hist_cap > 0 && !hist_host)) return fail(PCGA_EINVAL, "bad history buffer");
+    HIP_TRY(hipSetDevice(S->device));
+    if (refine == PCGA_REFINE_KEEP)
+        return mixed_keep(*S, b_dev, x_dev, tol, inner_tol, max_outer, inner_maxit, outer, inner_total,
+                          hist_host, hist_cap, hist_len, true_relres);
+    return mixed_restart(*S, b_dev, x_dev, tol, inner_tol, max_outer, inner_maxit, outer, inner_total,
+                         hist_host, hist_cap, hist_len, true_relres);
+}
+
+int pcga_pcg_solve_mixed(pcga_solver_t *S, const double *b_dev, double *x_dev, double tol,
+                         double inner_tol, int32_t max_outer, int32_t inner_maxit, int32_t *outer,
+                         int32_t *inner_total, double *hist_host, int32_t hist_cap,
+                         int32_t *hist_len, double *true_relres) {
+    return pcga_pcg_solve_mixed_ex(S, b_dev, x_dev, tol, inner_tol, max_outer, inner_maxit,
+                                   PCGA_REFINE_RESTART, outer, inner_total, hist_host, hist_cap,
+                                   hist_len, true_relres);
 }
 
 int pcga_apply_a(pcga_solver_t *S, const double *x_dev, double *y_dev) {

@@ -56,6 +56,16 @@ struct pcga_solver {
     bool use_graph = true;
     hipGraphExec_t graph = nullptr;
     int graph_chunk = 0;
+    // kTailChunk iterations: launched instead of a full chunk when the run
+    // is predicted to stop within the next chunk (fewer iterations left to
+    // run as no-ops after the stop)
+    hipGraphExec_t graph_tail = nullptr;
+    void drop_graphs() {
+        if (graph) (void)hipGraphExecDestroy(graph);
+        if (graph_tail) (void)hipGraphExecDestroy(graph_tail);
+        graph = graph_tail = nullptr;
+        graph_chunk = 0;
+    }
     int64_t sell_entries = 0;
     int index_bytes = 4;   // 2 when Z^T and Z use 16-bit distances
     int fmt_zt = 0, fmt_z = 0;   // storage/read format of Z^T and Z (kFmt* bits)

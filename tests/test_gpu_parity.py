@@ -327,6 +327,65 @@ def test_mixed_reaches_fp64_residual(pkg, ora, name, form):
     assert abs(m.outer - om.outer) <= 1
 
 
+@pytest.mark.parametrize("name", ["box64x48", "orca182x149", "orca37x23_ragged",
+                                  "orca182x149_jacobi"])
+@pytest.mark.parametrize("form", ["mixed", "mixed_a32"])
+def test_mixed_keep_direction(pkg, ora, name, form):
+    """Refinement with the direction kept across corrections: the FP64 true
+    residual reaches the target, the corrections and the inner FP32
+    iterations match the oracle's run of the same form, and the inner total
+    stays near the FP64 PCG's count (the Krylov space survives corrections)."""
+    p, tau = case(name)
+    say(form, "keep", name)
+    A = pkg.Stencil5.from_problem(p)
+    S = pkg.Solver(A, pkg.ainv_setup(A, tau), form)
+    m = S.solve_mixed(dev(p.b), tol=1e-10, refine="keep")
+    assert m.status == 0
+    x = m.x.cpu().numpy()
+    true = np.linalg.norm(p.b - ora.spmv(p, x)) / np.linalg.norm(p.b)
+    assert true <= 1e-10
+    assert abs(true - m.true_relres) <= 1e-3 * true + 1e-13
+    F = ora.ainv_setup(p, tau)
+    om = ora.pcg_mixed(p, F, tol=1e-10, inner_tol=0.1, keep=True, max_outer=200,
+                       a32=(form == "mixed_a32"))
+    o64 = ora.pcg(p, F, tol=1e-10)
+    say(f"  outer {m.outer} (oracle {om.outer}) inner {m.inner_total} (oracle {om.inner_total}, "
+        f"FP64 PCG {o64.iters})")
+    assert abs(m.outer - om.outer) <= 1
+    assert abs(m.inner_total - om.inner_total) <= 3
+    # FP32 rounding perturbs the run: within 15% of the FP64 count
+    assert m.inner_total <= 1.15 * o64.iters + 3
+    # restarted corrections of the same length lose the Krylov space
+    r = S.solve_mixed(dev(p.b), tol=1e-10, inner_tol=0.1, max_outer=200)
+    assert r.status == 0 and r.inner_total > m.inner_total
+
+
+def test_mixed_keep_edges(pkg, ora):
+    """Keep form: zero right-hand side, a converged first guess (nothing
+    runs), a correction budget that ends early (NOCONV, x = x0 + the
+    corrections made), and a second solve on the same solver."""
+    p, tau = case("orca182x149")
+    say("edge: keep form")
+    A = pkg.Stencil5.from_problem(p)
+    S = pkg.Solver(A, pkg.ainv_setup(A, tau), "mixed")
+    z = S.solve_mixed(dev(np.zeros(p.n)), dev(np.ones(p.n)), refine="keep")
+    assert z.status == 0 and z.outer == 0 and float(z.x.abs().max()) == 0.0
+    full = S.solve_mixed(dev(p.b), tol=1e-10, refine="keep")
+    assert full.status == 0
+    warm = S.solve_mixed(dev(p.b), full.x, tol=1e-10, refine="keep")
+    assert warm.status == 0 and warm.outer == 0 and warm.inner_total == 0
+    assert torch.equal(warm.x, full.x)
+    few = S.solve_mixed(dev(p.b), tol=1e-10, max_outer=2, refine="keep")
+    assert few.status == 1 and few.outer == 2 and len(few.hist) == 3
+    x = few.x.cpu().numpy()
+    rel = np.linalg.norm(p.b - ora.spmv(p, x)) / np.linalg.norm(p.b)
+    assert abs(rel - few.hist[-1]) <= 1e-3 * rel
+    assert 1e-3 < rel < 0.05
+    again = S.solve_mixed(dev(p.b), tol=1e-10, refine="keep")
+    assert again.outer == full.outer and again.inner_total == full.inner_total
+    assert torch.equal(again.x, full.x)
+
+
 def test_edge_zero_rhs_and_warm_start(pkg, ora):
     p, tau = case("orca182x149")
     say("edge: zero rhs / warm start")
@@ -414,9 +473,11 @@ def orca025_stops(ora, orca025):
     releases the interpreter while it computes) while the device tests go on."""
     from concurrent.futures import ThreadPoolExecutor
     p, F, _, _ = orca025
-    ex = ThreadPoolExecutor(2)
+    ex = ThreadPoolExecutor(3)
     say("oracle natural stops at 1442x1021 started in the background")
     fut = {"threshold": ex.submit(lambda: ora.pcg(p, F, tol=1e-10)),
+           "keep": ex.submit(lambda: ora.pcg_mixed(p, F, tol=1e-10, inner_tol=0.1, keep=True,
+                                                   max_outer=200)),
            "fill8": ex.submit(lambda: (lambda Ff: (Ff, ora.pcg(p, Ff, tol=1e-10)))(
                ora.ainv_setup(p, 0.01, fill=8)))}
     yield fut
@@ -508,6 +569,28 @@ def test_full_size_jacobi_two_launch_path(pkg, ora, orca025):
     assert m.status == 0
     x = m.x.cpu().numpy()
     assert np.linalg.norm(p.b - ora.spmv(p, x)) / np.linalg.norm(p.b) <= 1e-8
+
+
+def test_full_size_mixed_keep(pkg, ora, orca025, orca025_stops):
+    """The keep form at 1442x1021: true FP64 residual at the target, the
+    error against the FP64 oracle's solution stated, and the corrections and
+    inner iterations against the oracle's run of the same form."""
+    p, F, A, G = orca025
+    say("full size: mixed, direction kept")
+    S = pkg.Solver(A, G, "mixed")
+    m = S.solve_mixed(dev(p.b), tol=1e-10, refine="keep")
+    assert m.status == 0
+    x = m.x.cpu().numpy()
+    true = np.linalg.norm(p.b - ora.spmv(p, x)) / np.linalg.norm(p.b)
+    on = orca025_stops["threshold"].result()
+    om = orca025_stops["keep"].result()
+    err = np.linalg.norm(x - on.x) / np.linalg.norm(on.x)
+    say(f"  outer {m.outer} (oracle {om.outer}) inner {m.inner_total} (oracle {om.inner_total}, "
+        f"FP64 {on.iters}) true relres {true:.3e}; |x_mixed - x_ora|/|x_ora| = {err:.2e}")
+    assert true <= 1e-10
+    assert err <= 1e-8
+    assert abs(m.outer - om.outer) <= 2
+    assert abs(m.inner_total - om.inner_total) <= max(10, om.inner_total // 20)
 
 
 @pytest.mark.parametrize("form", ["mixed", "mixed_a32"])

@@ -410,6 +410,53 @@ def test_mixed_refinement_reaches_fp64_residual(ora):
     assert np.linalg.norm(m.x - xs) <= np.linalg.cond(A) * 1e-10 * np.linalg.norm(xs)
 
 
+@pytest.mark.parametrize("nx,ny,seed,tau", [(60, 45, 41, 0.1), (182, 149, orca.CONFIG_SEED_BASE + 1, 0.1),
+                                          (120, 90, 7, 0.05)])
+def test_mixed_keep_direction_follows_one_pcg_run(ora, nx, ny, seed, tau):
+    """Refinement with the direction kept across corrections (reliable
+    updates, Sleijpen and van der Vorst 1996): in exact arithmetic the inner
+    iterates are those of one PCG run of Algorithm 1 whose residual is
+    replaced by b - A x at each correction, so the inner FP32 iterations add
+    up to the FP64 PCG's count, whatever the segment length; the restarted
+    form, which throws the Krylov space away at every correction, needs
+    about 30-60% more.  A dropped or wrong beta at a correction turns the
+    first into the second.  Each correction reduces the true residual by
+    about the segment factor, and the solution solves the dense system."""
+    p = orca.orca_problem(nx, ny, seed)
+    F = ora.ainv_setup(p, tau)
+    ref = ora.pcg(p, F, tol=1e-10)
+    for delta in (0.3, 0.1, 0.01):
+        k = ora.pcg_mixed(p, F, tol=1e-10, inner_tol=delta, keep=True, max_outer=200)
+        r = ora.pcg_mixed(p, F, tol=1e-10, inner_tol=delta, keep=False, max_outer=200)
+        assert k.status == ora.OK and k.outer_hist[-1] <= 1e-10
+        assert abs(k.inner_total - ref.iters) <= 2
+        assert r.inner_total >= 1.25 * ref.iters
+        h = k.outer_hist
+        # a run stops at max(delta, tol / h[i]) of its start
+        assert all(h[i + 1] <= 3.0 * max(delta, 1e-10 / h[i]) * h[i] for i in range(len(h) - 1))
+        # about one correction per factor delta of the 1e-10 reduction
+        assert k.outer <= int(np.ceil(10.0 / -np.log10(delta))) + 3
+    if p.n <= 3000:
+        A = p.dense()
+        true = np.linalg.norm(p.b - A @ k.x) / np.linalg.norm(p.b)
+        assert true <= 1e-10
+        xs = np.linalg.solve(A, p.b)
+        assert np.linalg.norm(k.x - xs) <= np.linalg.cond(A) * 1e-10 * np.linalg.norm(xs)
+
+
+def test_mixed_keep_first_segment_is_the_restarted_inner_run(ora):
+    """From x0 = 0 the first inner run of both forms starts from the same r0
+    and direction s0; with a segment factor below what is left to reach the
+    target, the keep form's first run stops at tol / rel_0 = tol, so a single
+    restarted correction with inner_tol = tol gives the same solution."""
+    p = orca.orca_problem(40, 30, 9)
+    F = ora.ainv_setup(p, 0.1)
+    k = ora.pcg_mixed(p, F, tol=1e-6, inner_tol=1e-9, keep=True, max_outer=1)
+    r = ora.pcg_mixed(p, F, tol=1e-6, inner_tol=1e-6, keep=False, max_outer=1)
+    assert k.outer == r.outer == 1 and k.inner_total == r.inner_total
+    assert np.array_equal(k.x, r.x)
+
+
 def test_evaluation_order_builds_compute_the_same_method(ora):
     """The oracle's evaluation-order builds (reversed or blocked inner-product
     sums, fused multiply-adds) differ from the default build by rounding only:
