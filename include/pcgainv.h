@@ -461,6 +461,17 @@ int pcga_batch_add(pcga_batch_t *B, pcga_solver_t *S, int32_t nrhs, const double
                    const double *const *x0_dev, double *const *x_out_dev, void *item_ws,
                    size_t item_bytes, double tol, double inner_tol, int32_t max_outer,
                    int32_t inner_maxit, int32_t *slot);
+/* pcga_batch_add_ex: pcga_batch_add with the refinement of
+ * pcga_pcg_solve_mixed_ex (refine = PCGA_REFINE_RESTART or
+ * PCGA_REFINE_KEEP; for KEEP, inner_tol in (0, 1) is the residual reduction
+ * of one inner run).  A slot's right-hand sides share its corrections: an
+ * inner run ends when every active right-hand side has met its own stop, and
+ * one that met it earlier rests (alpha = 0) with its direction and last rho
+ * kept until the correction. */
+int pcga_batch_add_ex(pcga_batch_t *B, pcga_solver_t *S, int32_t nrhs, const double *const *b_dev,
+                      const double *const *x0_dev, double *const *x_out_dev, void *item_ws,
+                      size_t item_bytes, double tol, double inner_tol, int32_t max_outer,
+                      int32_t inner_maxit, int32_t refine, int32_t *slot);
 
 /* Run up to `chunks` chunks of iterations (stops early once every item is
  * done); *active receives the number of items not yet done. */

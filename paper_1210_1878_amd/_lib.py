@@ -95,6 +95,8 @@ _SIGS = {
     "pcga_batch_destroy": ([_p], ctypes.c_int),
     "pcga_batch_add": ([_p, _p, _i32, _p, _p, _p, _p, _sz, _dbl, _dbl, _i32, _i32, _pi32],
                        ctypes.c_int),
+    "pcga_batch_add_ex": ([_p, _p, _i32, _p, _p, _p, _p, _sz, _dbl, _dbl, _i32, _i32, _i32, _pi32],
+                       ctypes.c_int),
     "pcga_batch_run": ([_p, _i32, _pi32], ctypes.c_int),
     "pcga_batch_launch": ([_p, _i32], ctypes.c_int),
     "pcga_batch_wait": ([_p, _i32, _pi32, _pi32], ctypes.c_int),

@@ -603,11 +603,19 @@ class Batch:
               "pcga_batch_item_bytes")
         return nb.value
 
-    def add(self, solver, B, X0=None, tol=1e-10, inner_tol=1e-5, max_outer=20, inner_maxit=None,
-            tag=None):
-        """B: [nrhs, n] float64 device tensor (nrhs in 1, 2, 4).  Returns the slot."""
+    def add(self, solver, B, X0=None, tol=1e-10, inner_tol=None, max_outer=None, inner_maxit=None,
+            tag=None, refine="restart"):
+        """B: [nrhs, n] float64 device tensor (nrhs in 1, 2, 4).  Returns the slot.
+        refine as in Solver.solve_mixed ("restart": inner_tol default 1e-5;
+        "keep": the inner direction kept across corrections, inner_tol
+        default 0.1)."""
         import torch
         L = _lib.load()
+        mode = {"restart": _lib.REFINE_RESTART, "keep": _lib.REFINE_KEEP}[refine]
+        if inner_tol is None:
+            inner_tol = 0.1 if mode == _lib.REFINE_KEEP else 1e-5
+        if max_outer is None:
+            max_outer = 200 if mode == _lib.REFINE_KEEP else 20
         if B.dim() == 1:
             B = B.unsqueeze(0)
         nrhs, n = B.shape
@@ -622,10 +630,11 @@ class Batch:
         xp = arr(*[X0[r].data_ptr() for r in range(nrhs)])
         op = arr(*[X[r].data_ptr() for r in range(nrhs)])
         slot = ctypes.c_int32()
-        check(L.pcga_batch_add(self._h, solver.handle, int(nrhs), bp, xp, op,
-                               ctypes.c_void_p(ws.data_ptr()), nbytes, float(tol), float(inner_tol),
-                               int(max_outer), -1 if inner_maxit is None else int(inner_maxit),
-                               ctypes.byref(slot)), "pcga_batch_add")
+        check(L.pcga_batch_add_ex(self._h, solver.handle, int(nrhs), bp, xp, op,
+                                  ctypes.c_void_p(ws.data_ptr()), nbytes, float(tol),
+                                  float(inner_tol), int(max_outer),
+                                  -1 if inner_maxit is None else int(inner_maxit), mode,
+                                  ctypes.byref(slot)), "pcga_batch_add_ex")
         self.items[slot.value] = dict(solver=solver, B=B, X=X, ws=ws, nrhs=nrhs, tag=tag)
         return slot.value
 

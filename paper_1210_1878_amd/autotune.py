@@ -78,13 +78,14 @@ def tune_solver(A, F, b, precision="fp64", widths=WIDTHS, blocks=None, chunks=CH
             "table": table, "chunks": timings}
 
 
-def tune_batch(make_items, widths=(8, 16, 32), chunks=(8, 16, 32), tol=1e-10, log=None):
+def tune_batch(make_items, widths=(8, 16, 32), chunks=(8, 16, 32), tol=1e-10, log=None,
+               refine="restart"):
     """Best (slice_width, chunk) for an ensemble.
 
     make_items(width) returns [(solver, B)] (a mixed solver built with that
     slice width and its right-hand sides [nrhs, n]); each candidate solves
-    the whole ensemble in one batch.  Returns {"slice_width", "chunk",
-    "table": [(width, chunk, ms)]}."""
+    the whole ensemble in one batch with the given refinement.  Returns
+    {"slice_width", "chunk", "table": [(width, chunk, ms)]}."""
     import torch
     table = []
     for w in widths:
@@ -92,10 +93,10 @@ def tune_batch(make_items, widths=(8, 16, 32), chunks=(8, 16, 32), tol=1e-10, lo
         for c in chunks:
             Bt = Batch(max_slots=len(items), chunk=c)
             for S, B in items:
-                Bt.add(S, B, tol=tol)
+                Bt.add(S, B, tol=tol, refine=refine)
             Bt.solve()                                        # capture, first touch
             for S, B in items:
-                Bt.add(S, B, tol=tol)
+                Bt.add(S, B, tol=tol, refine=refine)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             Bt.solve()

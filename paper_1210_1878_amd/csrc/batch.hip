@@ -63,6 +63,7 @@ enum : int { kActSkip = 0, kActCG = 1, kActResid = 2, kActDecide = 3, kActFirst 
 
 struct SlotCtl {
     double rho[2][kMaxR];      // rho_k, by graph parity
+    double rho_keep[kMaxR];    // rho of each right-hand side's last active CG step (keep)
     double nb[kMaxR];          // ||r32|| at the start of the inner solve
     double rel[kMaxR];         // last outer relative true residual
     double bb[kMaxR];          // ||b||^2
@@ -88,6 +89,8 @@ struct SlotDesc {
     double tol, inner_tol;
     int32_t max_outer, inner_maxit;
     int32_t R, G;
+    int32_t keep;   // refinement keeps the inner direction across corrections
+    int32_t pad;
 };
 
 struct BlkEnt {
@@ -161,6 +164,8 @@ __device__ void stencil_cg(const SlotDesc &D, int L, int par) {
     slot_sum<1, R>(D, 2, rs);
     const int k = c->kk[par];
     const int act = c->act[par];
+    // keep: the first step of a later inner run continues the last direction
+    const bool fresh = k == 0 && !(D.keep && c->outer > 1);
     float bt[R];
     bool bad = false, nan = false;
 #pragma unroll
@@ -170,7 +175,7 @@ __device__ void stencil_cg(const SlotDesc &D, int L, int par) {
             bad = true;
             nan = nan || is_bad(rs[0][r]);
         }
-        bt[r] = (k == 0 || !on) ? 0.f : (float)(rs[0][r] / c->rho[par ^ 1][r]);
+        bt[r] = (fresh || !on) ? 0.f : (float)(rs[0][r] / c->rho[par ^ 1][r]);
     }
     if (bad) {
         if (L == 0 && threadIdx.x == 0) {
@@ -182,7 +187,10 @@ __device__ void stencil_cg(const SlotDesc &D, int L, int par) {
     }
     if (L == 0 && threadIdx.x == 0) {
 #pragma unroll
-        for (int r = 0; r < R; r++) c->rho[par][r] = rs[0][r];
+        for (int r = 0; r < R; r++) {
+            c->rho[par][r] = rs[0][r];
+            if ((act >> r) & 1) c->rho_keep[r] = rs[0][r];
+        }
         c->st[1] = kActCG;
     }
     const DevOp<double> &A = D.A64;
@@ -207,8 +215,9 @@ __device__ void stencil_cg(const SlotDesc &D, int L, int par) {
         for (int r = 0; r < R; r++) {
             float v[5];
 #pragma unroll
-            for (int e = 0; e < 5; e++) v[e] = (k == 0) ? sv[e][r] : fmaf(bt[r], dv[e][r], sv[e][r]);
-            dn[r] = v[2];
+            for (int e = 0; e < 5; e++) v[e] = fresh ? sv[e][r] : fmaf(bt[r], dv[e][r], sv[e][r]);
+            // keep: a right-hand side at rest carries its direction forward
+            dn[r] = (D.keep && !fresh && !((act >> r) & 1)) ? dv[2][r] : v[2];
             qn[r] = (float)apply_row(m, (double)v[0], (double)v[1], (double)v[2], (double)v[3],
                                      (double)v[4]);
             acc[0][r] += (double)dn[r] * (double)qn[r];
@@ -228,6 +237,10 @@ __device__ void stencil_resid(const SlotDesc &D, int L, int par) {
     const DevOp<double> &A = D.A64;
     const double *x = D.x, *b = D.b;
     float *r32 = D.r[par ^ 1];
+    // keep: the last CG step wrote its direction to d[par]; the next run's
+    // first step, one graph iteration later, reads d[par ^ 1]
+    const float *dlast = D.d[par];
+    float *dnext = D.d[par ^ 1];
     double acc[3][R];
 #pragma unroll
     for (int i = 0; i < 3; i++)
@@ -253,6 +266,11 @@ __device__ void stencil_resid(const SlotDesc &D, int L, int par) {
             acc[2][r] += (double)rf[r] * (double)rf[r];
         }
         stv<R>(r32, kc, rf);
+        if (D.keep) {
+            float dv[R];
+            ldv<R>(dlast, kc, dv);
+            stv<R>(dnext, kc, dv);
+        }
     }
     slot_put<3, R>(D, 3, L, acc);
 }
@@ -583,7 +601,10 @@ __device__ void z_cg(const SlotDesc &D, int L, int par) {
         if (!((act >> r) & 1)) continue;
         const double rel = sqrt(rr[0][r]) / D.ctl->nb[r];
         nan = nan || is_bad(rel);
-        if (rel <= D.inner_tol) nact &= ~(1 << r);
+        // keep: a run stops at max(inner_tol, tol / outer residual)
+        double itol = D.inner_tol;
+        if (D.keep && c->rel[r] > 0.0 && D.tol / c->rel[r] > itol) itol = D.tol / c->rel[r];
+        if (rel <= itol) nact &= ~(1 << r);
     }
     const bool inner_done = nact == 0 || k >= D.inner_maxit;
     if (L == 0 && threadIdx.x == 0) {
@@ -631,6 +652,11 @@ __device__ void z_first(const SlotDesc &D, int L, int par) {
         c->act[par ^ 1] = c->act[par];
         c->outer += 1;
         c->st[0] = kActCG;
+        // keep: the next step's beta divides by the last active rho, read
+        // from the slot of this parity
+        if (D.keep)
+#pragma unroll
+            for (int r = 0; r < R; r++) c->rho[par][r] = c->rho_keep[r];
     }
     double sr[1][R];
 #pragma unroll
@@ -909,6 +935,14 @@ int pcga_batch_add(pcga_batch_t *B, pcga_solver_t *S, int32_t nrhs, const double
                    const double *const *x0_dev, double *const *x_out_dev, void *item_ws,
                    size_t item_bytes, double tol, double inner_tol, int32_t max_outer,
                    int32_t inner_maxit, int32_t *slot) {
+    return pcga_batch_add_ex(B, S, nrhs, b_dev, x0_dev, x_out_dev, item_ws, item_bytes, tol,
+                             inner_tol, max_outer, inner_maxit, PCGA_REFINE_RESTART, slot);
+}
+
+int pcga_batch_add_ex(pcga_batch_t *B, pcga_solver_t *S, int32_t nrhs, const double *const *b_dev,
+                      const double *const *x0_dev, double *const *x_out_dev, void *item_ws,
+                      size_t item_bytes, double tol, double inner_tol, int32_t max_outer,
+                      int32_t inner_maxit, int32_t refine, int32_t *slot) {
     if (B && B->in_flight) return fail(PCGA_EINVAL, "a launch of this batch is still in flight");
     if (!B || !S || !b_dev || !x0_dev || !x_out_dev || !item_ws || !slot)
         return fail(PCGA_EINVAL, "NULL argument");
@@ -916,6 +950,10 @@ int pcga_batch_add(pcga_batch_t *B, pcga_solver_t *S, int32_t nrhs, const double
     if (!(nrhs == 1 || nrhs == 2 || nrhs == 4)) return fail(PCGA_EINVAL, "nrhs must be 1, 2 or 4");
     if (!(tol >= 0.0) || !(inner_tol > 0.0) || max_outer < 0)
         return fail(PCGA_EINVAL, "bad tolerances or max_outer");
+    if (refine != PCGA_REFINE_RESTART && refine != PCGA_REFINE_KEEP)
+        return fail(PCGA_EINVAL, "refine must be PCGA_REFINE_RESTART or PCGA_REFINE_KEEP");
+    if (refine == PCGA_REFINE_KEEP && !(inner_tol < 1.0))
+        return fail(PCGA_EINVAL, "PCGA_REFINE_KEEP needs inner_tol < 1");
     if (((uintptr_t)item_ws & 255u) != 0) return fail(PCGA_EINVAL, "item workspace must be 256-byte aligned");
     const int G = slot_blocks(S->n);
     const ItemLayout IL = item_layout(S->n, nrhs, G);
@@ -951,6 +989,7 @@ int pcga_batch_add(pcga_batch_t *B, pcga_solver_t *S, int32_t nrhs, const double
     D.inner_maxit = inner_maxit < 0 ? (int32_t)std::min<int64_t>(S->n, INT32_MAX) : inner_maxit;
     D.R = nrhs;
     D.G = G;
+    D.keep = refine == PCGA_REFINE_KEEP ? 1 : 0;
     // interleave b and x0 into the item workspace; initial state: RESID
     const double **ptrs = (const double **)(w + IL.off_ptrs);
     std::vector<const double *> hp(2 * kMaxR, nullptr);

@@ -100,6 +100,60 @@ def test_batch_matches_single_solver_and_oracle(pkg, ora, ensemble):
         assert np.linalg.norm(m.x.cpu().numpy() - xo) <= bound * np.linalg.norm(xo)
 
 
+def test_batch_keep_direction(pkg, ora, ensemble):
+    """Batched refinement with the inner direction kept across corrections:
+    every right-hand side meets the FP64 target (oracle product); a
+    one-right-hand-side item takes the corrections and inner iterations of
+    the oracle's run of the same form; a four-right-hand-side slot, whose
+    members share their corrections, stays within 15% of its slowest
+    member's FP64 count and below the restarted batch; and an item is
+    bitwise the same alone and added to a running mix."""
+    ps, sol = ensemble
+    say("batch, direction kept: 4 grids x 4 rhs, plus 1-rhs items")
+    alone = {}
+    for i in (1, 3):
+        Bt = pkg.Batch(max_slots=2)
+        s = Bt.add(sol[i], torch.from_numpy(ps[i].B).cuda(), refine="keep")
+        alone[i] = Bt.solve()[s]
+    Bt = pkg.Batch(max_slots=16)
+    slots = {}
+    for i in (0, 2):
+        slots[Bt.add(sol[i], torch.from_numpy(ps[i].B).cuda(), refine="keep")] = (i, 4)
+        slots[Bt.add(sol[i], torch.from_numpy(ps[i].B[1:2]).cuda(), refine="keep")] = (i, 1)
+    Bt.run(1)
+    for i in (1, 3):
+        slots[Bt.add(sol[i], torch.from_numpy(ps[i].B).cuda(), refine="keep")] = (i, 4)
+    res = Bt.solve()
+    restarted = {}
+    Br = pkg.Batch(max_slots=8)
+    for i in range(len(ps)):
+        restarted[Br.add(sol[i], torch.from_numpy(ps[i].B).cuda())] = i
+    inner_restart = {restarted[s]: q["inner_total"] for s, (X, q) in Br.solve().items()}
+    for s, (X, q) in res.items():
+        i, nrhs = slots[s]
+        p = ps[i]
+        F = ora.ainv_setup(p, 0.1)
+        if nrhs == 1:
+            p1 = orca.Problem(p.nx, p.ny, p.periodic, p.diag, p.ae, p.an, p.ocean, p.B[1], B=p.B[1:2])
+            _check_item(ora, p1, X, q, 1)
+            om = ora.pcg_mixed(p, F, b=p.B[1], tol=1e-10, inner_tol=0.1, keep=True, max_outer=200)
+            say(f"  grid {i} 1 rhs: inner runs {q['outer']} (oracle {om.outer}) "
+                f"inner {q['inner_total']} (oracle {om.inner_total})")
+            assert abs(q["inner_total"] - om.inner_total) <= 3
+            assert abs(q["outer"] - om.outer) <= 1
+            continue
+        _check_item(ora, p, X, q, 4)
+        slowest = max(ora.pcg(p, F, b=p.B[r], tol=1e-10).iters for r in range(4))
+        say(f"  grid {i} 4 rhs: runs {q['outer']} inner {q['inner_total']} "
+            f"(slowest member's FP64 count {slowest}, restarted batch {inner_restart[i]})")
+        assert q["inner_total"] <= 1.15 * slowest + 10
+        assert q["inner_total"] <= inner_restart[i]
+        if slowest >= 60:
+            assert q["inner_total"] < 0.8 * inner_restart[i]
+        if i in alone:
+            assert torch.equal(X, alone[i][0]), i
+
+
 def test_batch_alone_equals_in_mix(pkg, ensemble):
     ps, sol = ensemble
     say("alone vs in the mix (bitwise)")
@@ -243,3 +297,34 @@ def test_batch_split_slot_with_ensemble_members(pkg, ora, split_mix):
             if r == 0:
                 say(f"  member {i} {p.nx}x{p.ny}: |x - x_ora|/|x_ora| "
                     f"{gap / np.linalg.norm(xo):.2e} (bound {bound / np.linalg.norm(xo):.2e})")
+
+
+def test_batch_split_slot_keep_direction(pkg, ora, split_mix):
+    """The large-slot path with the inner direction kept: the 1442x1021 slot
+    meets the target (oracle product), with inner iterations near the
+    single-grid keep solve's, and is bitwise the same alone and beside four
+    ensemble members."""
+    big, Sb, ens, sol = split_mix
+    say("keep: the 1442x1021 slot alone")
+    Bt = pkg.Batch(max_slots=2)
+    s = Bt.add(Sb, torch.from_numpy(big.B).cuda(), refine="keep")
+    big_alone, qa = Bt.solve()[s]
+    _check_item(ora, big, big_alone, qa, 1)
+    single = Sb.solve_mixed(torch.from_numpy(big.b).cuda(), tol=1e-10, refine="keep")
+    say(f"  runs {qa['outer']} inner {qa['inner_total']} (single-grid keep: "
+        f"{single.outer} runs, {single.inner_total} inner)")
+    assert abs(qa["inner_total"] - single.inner_total) <= max(10, single.inner_total // 20)
+    Bt = pkg.Batch(max_slots=8)
+    slot_of = {}
+    for i in range(2):
+        slot_of[Bt.add(sol[i], torch.from_numpy(ens[i].B).cuda(), refine="keep")] = i
+    Bt.run(1)
+    slot_of[Bt.add(Sb, torch.from_numpy(big.B).cuda(), refine="keep")] = "big"
+    for i in range(2, 4):
+        slot_of[Bt.add(sol[i], torch.from_numpy(ens[i].B).cuda(), refine="keep")] = i
+    for s, (X, q) in Bt.solve().items():
+        i = slot_of[s]
+        if i == "big":
+            assert torch.equal(X, big_alone)
+        else:
+            _check_item(ora, ens[i], X, q, 4)
