@@ -400,7 +400,7 @@ def fp64_sequential(P, torch, dev, probs, seconds, log):
     solvers = [P.Solver(P.Stencil5.from_problem(p), P.ainv_setup(P.Stencil5.from_problem(p), 0.05),
                         "fp64", device=dev) for p in probs]
     stepper = serve.TimeStepper(probs, dev, seed=CONFIG_SERVE_SEED + 9)
-    done, rid = 0, 0
+    done, rid, cells = 0, 0, 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     while True:
@@ -412,6 +412,7 @@ def fp64_sequential(P, torch, dev, probs, seconds, log):
             req.x = res.x
             stepper.done(req)
             done += 1
+            cells += probs[g].n
         if time.perf_counter() - t0 >= seconds:
             break
     torch.cuda.synchronize()
@@ -419,7 +420,8 @@ def fp64_sequential(P, torch, dev, probs, seconds, log):
     for S in solvers:
         S.close()
     log(f"fp64, one solve at a time: {done} solves in {el:.1f}s ({done / el:.2f} solves/s)")
-    return {"solves": done, "seconds": round(el, 2), "solves_per_s": round(done / el, 2)}
+    return {"solves": done, "seconds": round(el, 2), "solves_per_s": round(done / el, 2),
+            "cells_per_s": round(cells / el, 1)}
 
 
 def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=15.0,
@@ -473,6 +475,9 @@ def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=
            "hbm_budget_bytes": srv.budget,
            "capacity_solves_per_s": round(sum(cap), 2),
            "capacity_per_grid": [round(c, 3) for c in cap],
+           # solves weighted by grid size (a 4322x3059 solve is 488 of 182x149)
+           "capacity_cells_per_s": round(sum(c * p.n for c, p in zip(cap, probs)), 1),
+           "refine": srv.refine,
            "capacity_worst_true_relres": float(max(r.true_relres for r in done)),
            "capacity_roofline": {"bound": "hbm", "achieved": round(cap_bytes / el / 1e9, 1),
                                  "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -508,6 +513,8 @@ def bench_serve(P, torch, dev, log, loads=(0.5, 0.8), saturate_s=6.0, horizon_s=
         out["fp64_one_at_a_time"] = fp64_sequential(P, torch, dev, probs, saturate_s, log)
         out["fp64_one_at_a_time"]["served_capacity_ratio"] = round(
             sum(cap) / out["fp64_one_at_a_time"]["solves_per_s"], 2)
+        out["fp64_one_at_a_time"]["served_cells_ratio"] = round(
+            out["capacity_cells_per_s"] / out["fp64_one_at_a_time"]["cells_per_s"], 2)
     srv.close()
     return out
 

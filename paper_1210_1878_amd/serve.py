@@ -87,7 +87,7 @@ class _SoloLane:
             srv = self.srv
             try:
                 res = self.S.solve_mixed(req.b, x0=req.x0, tol=srv.tol, inner_tol=srv.inner_tol,
-                                         max_outer=srv.max_outer)
+                                         max_outer=srv.max_outer, refine=srv.refine)
                 q = {"status": res.status, "true_relres": [res.true_relres], "outer": res.outer,
                      "inner_total": res.inner_total}
                 self.done_q.put((req, res.x.unsqueeze(0), q))
@@ -104,12 +104,18 @@ class Server:
     """Holds resident grids and serves time-step solves by continuous batching."""
 
     def __init__(self, problems, drop_tol=0.05, device=None, hbm_budget=None, max_slots=64,
-                 tol=1e-10, inner_tol=1e-5, max_outer=30, chunk=16, class_cells=(2_000_000,),
-                 class_grid=None, solo_cells=None):
+                 tol=1e-10, inner_tol=None, max_outer=None, chunk=16, class_cells=(2_000_000,),
+                 class_grid=None, solo_cells=None, refine="keep"):
         import torch
         self.torch = torch
         self.device = torch.device("cuda" if device is None else device)
-        self.tol, self.inner_tol, self.max_outer = tol, inner_tol, max_outer
+        # refinement of every solve: "keep" (inner direction kept across
+        # corrections, runs of one decade) or "restart" (inner stop 1e-5)
+        keep = refine == "keep"
+        self.refine = refine
+        self.tol = tol
+        self.inner_tol = inner_tol if inner_tol is not None else (0.1 if keep else 1e-5)
+        self.max_outer = max_outer if max_outer is not None else (200 if keep else 30)
         # size class of each grid: index of the first bound above its cell count;
         # grids of at least solo_cells cells form the last class, one lane each
         bounds = sorted(class_cells)
@@ -187,7 +193,8 @@ class Server:
             return ("solo", req.rid)
         slot = self.batches[k].add(self.solvers[req.grid], req.b.unsqueeze(0),
                                    X0=req.x0.unsqueeze(0), tol=self.tol,
-                                   inner_tol=self.inner_tol, max_outer=self.max_outer, tag=req.rid)
+                                   inner_tol=self.inner_tol, max_outer=self.max_outer, tag=req.rid,
+                                   refine=self.refine)
         self.in_flight_bytes += self.item_bytes[req.grid]
         self.busy[req.grid] = True
         req.admitted = now

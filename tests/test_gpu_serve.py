@@ -28,10 +28,11 @@ def setup():
     return P, serve, probs
 
 
-def test_served_steps_correct_and_equal_alone(setup, ora):
+@pytest.mark.parametrize("refine", ["keep", "restart"])
+def test_served_steps_correct_and_equal_alone(setup, ora, refine):
     P, serve, probs = setup
-    say("serving 12 time steps on 3 grids")
-    srv = serve.Server(probs, drop_tol=0.1, device="cuda", chunk=8)
+    say("serving 12 time steps on 3 grids, refinement", refine)
+    srv = serve.Server(probs, drop_tol=0.1, device="cuda", chunk=8, refine=refine)
     reqs = serve.poisson_arrivals(rate=400.0, count=12, n_grids=len(probs), seed=7)
     stepper = serve.TimeStepper(probs, torch.device("cuda"), seed=3)
     done = srv.run(reqs, make_rhs=stepper, on_done=stepper.done)
@@ -45,8 +46,8 @@ def test_served_steps_correct_and_equal_alone(setup, ora):
         assert r.status == 0 and true <= 1e-10
         # the same solve alone in a fresh batch gives bitwise the same x
         Bt = P.Batch(max_slots=2, chunk=8)
-        s = Bt.add(srv.solvers[r.grid], r.b.unsqueeze(0), X0=r.x0.unsqueeze(0), tol=1e-10,
-                   inner_tol=1e-5, max_outer=30)
+        s = Bt.add(srv.solvers[r.grid], r.b.unsqueeze(0), X0=r.x0.unsqueeze(0), tol=srv.tol,
+                   inner_tol=srv.inner_tol, max_outer=srv.max_outer, refine=srv.refine)
         X, q = Bt.solve()[s]
         assert torch.equal(X[0], r.x)
         overlapped += any(o is not r and o.admitted < r.finished and o.finished > r.admitted
@@ -165,8 +166,9 @@ def test_solo_lane_for_large_grids(setup, ora):
             assert r.status == 0
             assert np.linalg.norm(b - ora.spmv(p, x)) / np.linalg.norm(b) <= 1e-10
             if r.grid == 3:
-                alone = srv.solvers[3].solve_mixed(r.b, x0=r.x0, tol=1e-10, inner_tol=1e-5,
-                                                   max_outer=30)
+                alone = srv.solvers[3].solve_mixed(r.b, x0=r.x0, tol=srv.tol,
+                                                   inner_tol=srv.inner_tol,
+                                                   max_outer=srv.max_outer, refine=srv.refine)
                 assert torch.equal(alone.x, r.x)
         rs = sorted(solo, key=lambda r: r.admitted)
         assert all(a.finished <= b.admitted for a, b in zip(rs, rs[1:]))
