@@ -593,6 +593,8 @@ def main():
     ap.add_argument("--serve-budget-frac", type=float, default=SERVE_BUDGET_FRAC,
                     help="request-memory budget: the largest grid's vectors plus this share of "
                          "the other grids' (1: never binding)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the batched ensemble (for profiling its kernels)")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the two serving workloads (a long horizon gives the largest "
                          "grids enough requests) and print their results as one JSON line")
@@ -615,6 +617,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a ROCm device"
     dev = torch.device("cuda:0")
+    if args.batch_only:
+        print(json.dumps({"batch_only": True, "batched": bench_batch(P, torch, dev, log)}), flush=True)
+        return
     if args.serve_only:
         out = {"serve_only": True, "horizon_s": args.serve_horizon,
                "served": bench_serve(P, torch, dev, log, horizon_s=args.serve_horizon,

@@ -97,6 +97,14 @@ struct BlkEnt {
     int32_t slot, L;
 };
 
+// One of a slot's two buffers by parity.  A select, not an index: an array
+// member indexed at run time would make the compiler keep the whole
+// descriptor in per-lane scratch memory instead of scalar registers.
+template <typename T>
+__device__ __forceinline__ T *pick(T *const (&a)[2], int i) {
+    return i ? a[1] : a[0];
+}
+
 __device__ __forceinline__ double *part_at(const SlotDesc &D, int kind, int r) {
     return D.part + ((size_t)kind * kMaxR + r) * D.G;
 }
@@ -142,16 +150,23 @@ __device__ __forceinline__ void slot_put(const SlotDesc &D, int kind0, int L, co
     }
 }
 
-// R consecutive values of an interleaved vector
+// R consecutive values of an interleaved vector.  The slot's vectors live in
+// global memory; the pointers come from the descriptor (read from memory, so
+// generic to the compiler, which would emit flat loads whose completion is
+// counted with LDS operations): the access goes through a global pointer.
+template <typename T>
+using gmem_t = __attribute__((address_space(1))) T;
 template <int R, typename T>
 __device__ __forceinline__ void ldv(const T *p, int k, T (&o)[R]) {
+    const gmem_t<T> *g = (const gmem_t<T> *)p;
 #pragma unroll
-    for (int r = 0; r < R; r++) o[r] = p[(size_t)k * R + r];
+    for (int r = 0; r < R; r++) o[r] = g[(size_t)k * R + r];
 }
 template <int R, typename T>
 __device__ __forceinline__ void stv(T *p, int k, const T (&o)[R]) {
+    gmem_t<T> *g = (gmem_t<T> *)p;
 #pragma unroll
-    for (int r = 0; r < R; r++) p[(size_t)k * R + r] = o[r];
+    for (int r = 0; r < R; r++) g[(size_t)k * R + r] = o[r];
 }
 
 // ---------------------------------------------------------------------------
@@ -194,36 +209,50 @@ __device__ void stencil_cg(const SlotDesc &D, int L, int par) {
         c->st[1] = kActCG;
     }
     const DevOp<double> &A = D.A64;
-    const float *s = D.s, *dold = D.d[par];
-    float *dnew = D.d[par ^ 1], *q = D.q;
+    const float *s = D.s, *dold = pick(D.d, par);
+    float *dnew = pick(D.d, par ^ 1), *q = D.q;
     double acc[1][R];
 #pragma unroll
     for (int r = 0; r < R; r++) acc[0][r] = 0.0;
     int c0, c1;
     range_of(L, D.G, A.n, c0, c1);
-    for (int kc = c0 + threadIdx.x; kc < c1; kc += kBS) {
-        const Nbr<double> m = neighbours(A, kc);
-        const int idx[5] = {m.kS, m.kW, kc, m.kE, m.kN};
-        float sv[5][R], dv[5][R];
+    // U cells per thread and pass, all their loads issued before any
+    // arithmetic (more loads in flight: a slot has few workgroups)
+    constexpr int U = R == 4 ? 2 : 4;
+    for (int base = c0 + threadIdx.x; base < c1; base += U * kBS) {
+        Nbr<double> m[U];
+        float sv[U][5][R], dv[U][5][R];
 #pragma unroll
-        for (int e = 0; e < 5; e++) {
-            ldv<R>(s, idx[e], sv[e]);
-            ldv<R>(dold, idx[e], dv[e]);
+        for (int u = 0; u < U; u++) {
+            const int kc = base + u * kBS < c1 ? base + u * kBS : base;
+            m[u] = neighbours(A, kc);
+            const int idx[5] = {m[u].kS, m[u].kW, kc, m[u].kE, m[u].kN};
+#pragma unroll
+            for (int e = 0; e < 5; e++) {
+                ldv<R>(s, idx[e], sv[u][e]);
+                ldv<R>(dold, idx[e], dv[u][e]);
+            }
         }
-        float dn[R], qn[R];
 #pragma unroll
-        for (int r = 0; r < R; r++) {
-            float v[5];
+        for (int u = 0; u < U; u++) {
+            const int kc = base + u * kBS;
+            if (kc >= c1) break;
+            float dn[R], qn[R];
 #pragma unroll
-            for (int e = 0; e < 5; e++) v[e] = fresh ? sv[e][r] : fmaf(bt[r], dv[e][r], sv[e][r]);
-            // keep: a right-hand side at rest carries its direction forward
-            dn[r] = (D.keep && !fresh && !((act >> r) & 1)) ? dv[2][r] : v[2];
-            qn[r] = (float)apply_row(m, (double)v[0], (double)v[1], (double)v[2], (double)v[3],
-                                     (double)v[4]);
-            acc[0][r] += (double)dn[r] * (double)qn[r];
+            for (int r = 0; r < R; r++) {
+                float v[5];
+#pragma unroll
+                for (int e = 0; e < 5; e++)
+                    v[e] = fresh ? sv[u][e][r] : fmaf(bt[r], dv[u][e][r], sv[u][e][r]);
+                // keep: a right-hand side at rest carries its direction forward
+                dn[r] = (D.keep && !fresh && !((act >> r) & 1)) ? dv[u][2][r] : v[2];
+                qn[r] = (float)apply_row(m[u], (double)v[0], (double)v[1], (double)v[2],
+                                         (double)v[3], (double)v[4]);
+                acc[0][r] += (double)dn[r] * (double)qn[r];
+            }
+            stv<R>(dnew, kc, dn);
+            stv<R>(q, kc, qn);
         }
-        stv<R>(dnew, kc, dn);
-        stv<R>(q, kc, qn);
     }
     slot_put<1, R>(D, 0, L, acc);
 }
@@ -236,11 +265,11 @@ __device__ void stencil_resid(const SlotDesc &D, int L, int par) {
     if (L == 0 && threadIdx.x == 0) c->st[1] = kActDecide;
     const DevOp<double> &A = D.A64;
     const double *x = D.x, *b = D.b;
-    float *r32 = D.r[par ^ 1];
+    float *r32 = pick(D.r, par ^ 1);
     // keep: the last CG step wrote its direction to d[par]; the next run's
     // first step, one graph iteration later, reads d[par ^ 1]
-    const float *dlast = D.d[par];
-    float *dnext = D.d[par ^ 1];
+    const float *dlast = pick(D.d, par);
+    float *dnext = pick(D.d, par ^ 1);
     double acc[3][R];
 #pragma unroll
     for (int i = 0; i < 3; i++)
@@ -333,7 +362,7 @@ __device__ void zt_apply_f(const SlotDesc &D, int L, const float (&al)[R], const
             float acc[R];
 #pragma unroll
             for (int r = 0; r < R; r++) acc[r] = 0.f;
-            const float *vp = M.val + m.off + lane;
+            const gmem_t<float> *vp = (const gmem_t<float> *)(M.val + m.off + lane);
             const int last = m.width - 1;
             constexpr int U = 4;
             for (int cc = 0; cc < m.width; cc += U) {
@@ -428,7 +457,7 @@ __device__ void zt_cg(const SlotDesc &D, int L, int par) {
     double rr[1][R];
 #pragma unroll
     for (int r = 0; r < R; r++) rr[0][r] = 0.0;
-    zt_apply<R, true>(D, L, al, D.r[par], D.r[par ^ 1], D.d[par ^ 1], rr);
+    zt_apply<R, true>(D, L, al, pick(D.r, par), pick(D.r, par ^ 1), pick(D.d, par ^ 1), rr);
     slot_put<1, R>(D, 1, L, rr);
 }
 
@@ -486,7 +515,7 @@ __device__ void zt_decide(const SlotDesc &D, int L, int par) {
 #pragma unroll
     for (int r = 0; r < R; r++) al[r] = 0.f;
     double rr[1][R];
-    zt_apply<R, false>(D, L, al, D.r[par ^ 1], nullptr, nullptr, rr);
+    zt_apply<R, false>(D, L, al, pick(D.r, par ^ 1), nullptr, nullptr, rr);
 }
 
 template <int R>
@@ -540,7 +569,7 @@ __device__ void z_apply_f(const SlotDesc &D, int L, const float *r, double (&sr)
             float acc[R];
 #pragma unroll
             for (int q = 0; q < R; q++) acc[q] = 0.f;
-            const float *vp = M.val + m.off + lane;
+            const gmem_t<float> *vp = (const gmem_t<float> *)(M.val + m.off + lane);
             const int last = m.width - 1;
             constexpr int U = 8;
             for (int cc = 0; cc < m.width; cc += U) {
@@ -640,7 +669,7 @@ __device__ void z_cg(const SlotDesc &D, int L, int par) {
     double sr[1][R];
 #pragma unroll
     for (int r = 0; r < R; r++) sr[0][r] = 0.0;
-    z_apply<R>(D, L, D.r[par ^ 1], sr);
+    z_apply<R>(D, L, pick(D.r, par ^ 1), sr);
     slot_put<1, R>(D, 2, L, sr);
 }
 
@@ -661,7 +690,7 @@ __device__ void z_first(const SlotDesc &D, int L, int par) {
     double sr[1][R];
 #pragma unroll
     for (int r = 0; r < R; r++) sr[0][r] = 0.0;
-    z_apply<R>(D, L, D.r[par ^ 1], sr);
+    z_apply<R>(D, L, pick(D.r, par ^ 1), sr);
     slot_put<1, R>(D, 2, L, sr);
 }
 

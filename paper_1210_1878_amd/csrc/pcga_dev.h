@@ -45,7 +45,7 @@ constexpr double kMallBytes = 268435456.0;
 constexpr double kResidentBudget = 0.95 * kMallBytes;
 // Above this share of the cache the resident set sheds the solution vector.
 constexpr double kSpillFraction = 0.90;
-constexpr int kSlotCells = 8192;   // cells per workgroup of a batch slot (target; 4096: 4% slower ensemble)
+constexpr int kSlotCells = 2048;   // cells per workgroup of a batch slot (target; ensemble 170 ms, 177 at 4096, 179 at 1024)
 
 // Workgroups of a batch slot: a function of the grid alone, so that a slot's
 // reductions do not depend on the rest of the batch.
