@@ -166,6 +166,18 @@ __device__ __forceinline__ void put_partials(double (&v)[NV], double *part, int 
 
 // Neighbour indices and couplings of cell k, branch-free: an absent
 // neighbour points at k itself with a zero coupling.
+// Loads through a global-memory pointer.  The operator and factor arrays are
+// in global memory; a kernel that takes them as arguments has its loads
+// known to be global, but one that reads its descriptors from memory (the
+// batch kernels) would otherwise get flat loads, whose completion is
+// counted with LDS and scalar operations.
+template <typename P>
+using gmem = __attribute__((address_space(1))) P;
+template <typename P>
+__device__ __forceinline__ P gload(const P *p) {
+    return *(const gmem<P> *)p;
+}
+
 template <typename T>
 struct Nbr {
     int kS, kW, kE, kN;
@@ -186,13 +198,13 @@ __device__ __forceinline__ Nbr<T> neighbours(const DevOp<T> &A, int k) {
     m.kN = (j < A.ny - 1) ? k + nx : k;
     m.kW = (i > 0) ? k - 1 : (A.periodic ? k + nx - 1 : k);
     m.kE = (i < nx - 1) ? k + 1 : (A.periodic ? k - nx + 1 : k);
-    const T aS = A.an[m.kS];
-    const T aW = A.ae[m.kW];
+    const T aS = gload(A.an + m.kS);
+    const T aW = gload(A.ae + m.kW);
     m.cS = hasS ? aS : T(0);
     m.cW = hasW ? aW : T(0);
-    m.cC = A.diag[k];
-    m.cE = A.ae[k];     // zero across a non-periodic east edge (input rule)
-    m.cN = A.an[k];     // zero on the last row (input rule)
+    m.cC = gload(A.diag + k);
+    m.cE = gload(A.ae + k);     // zero across a non-periodic east edge (input rule)
+    m.cN = gload(A.an + k);     // zero on the last row (input rule)
     return m;
 }
 
@@ -225,12 +237,12 @@ __device__ __forceinline__ SliceHeaders load_headers(const DevSell<T> &M, int fi
     SliceHeaders h{0, 0, 0, 0, -1};
     if (lane < count) {
         const int sl = first + lane * stride;
-        h.row0 = M.row0[sl];
-        h.meta = M.meta[sl];
-        const int64_t o = M.off[sl];
+        h.row0 = gload(M.row0 + sl);
+        h.meta = gload(M.meta + sl);
+        const int64_t o = gload(M.off + sl);
         h.off_lo = (int)(o & 0xffffffff);
         h.off_hi = (int)(o >> 32);
-        h.toff = M.toff[sl];
+        h.toff = gload(M.toff + sl);
     }
     return h;
 }
@@ -264,8 +276,8 @@ constexpr int kFmtNarrow = 1, kFmtNtIdx = 2, kFmtNtVal = 4, kFmtNtX = 8, kFmtXDe
 
 template <bool NT, typename P>
 __device__ __forceinline__ P stream_load(const P *p) {
-    if (NT) return __builtin_nontemporal_load(p);
-    return *p;
+    if (NT) return __builtin_nontemporal_load((const gmem<P> *)p);
+    return *(const gmem<P> *)p;
 }
 
 // One per-lane index (32-bit column or 16-bit distance), undecoded.
