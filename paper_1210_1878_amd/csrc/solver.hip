@@ -516,8 +516,11 @@ int create_impl(const OpDesc &D, const pcga_ainv_t *F, int precision, int32_t sl
     } while (0)
 
     CR(hipGetDevice(&S->device));
-    CR(hipHostMalloc((void **)&S->snap[0], sizeof(CtlBlock), hipHostMallocDefault));
-    CR(hipHostMalloc((void **)&S->snap[1], sizeof(CtlBlock), hipHostMallocDefault));
+    // coherent: the chunk graphs' last kernel writes them directly
+    CR(hipHostMalloc((void **)&S->snap[0], sizeof(CtlBlock), hipHostMallocCoherent));
+    CR(hipHostMalloc((void **)&S->snap[1], sizeof(CtlBlock), hipHostMallocCoherent));
+    CR(hipHostGetDevicePointer((void **)&S->snap_dev[0], S->snap[0], 0));
+    CR(hipHostGetDevicePointer((void **)&S->snap_dev[1], S->snap[1], 0));
     CR(hipEventCreateWithFlags(&S->ev[0], hipEventDisableTiming));
     CR(hipEventCreateWithFlags(&S->ev[1], hipEventDisableTiming));
 
@@ -930,7 +933,7 @@ int pcga_solver_tune(pcga_solver_t *S, int32_t chunk, int32_t use_graph, int32_t
     if (max_blocks == 0) max_blocks = S->precision != PCGA_FP64 ? kDefaultBlocksMixed : kDefaultBlocks;
     if (max_blocks < 8 || max_blocks > kMaxBlocks)
         return fail(PCGA_EINVAL, "max_blocks must be 0 or 8.." + std::to_string(kMaxBlocks));
-    if (S->graph && (chunk != S->graph_chunk || max_blocks != S->max_blocks)) S->drop_graphs();
+    if (S->graph[0] && (chunk != S->graph_chunk || max_blocks != S->max_blocks)) S->drop_graphs();
     S->chunk = chunk;
     S->use_graph = use_graph != 0;
     S->max_blocks = max_blocks;
@@ -1190,6 +1193,26 @@ __global__ __launch_bounds__(kBS) void k_step_dq(Partials P, int g) {
     if (threadIdx.x == 0) P.res[0] = v[0];
 }
 
+// The control block and the residual history of the last `span` iterations
+// (ending at the iteration count), written by the device to a snapshot slot
+// in pinned host memory: the last node of a chunk graph.  A copy by the
+// runtime (a DMA blit after the chunk) left the device idle for about 20 us
+// per chunk.
+static_assert(sizeof(Ctl) % sizeof(int32_t) == 0, "Ctl is copied as 32-bit words");
+__global__ __launch_bounds__(kBS) void k_snap(const CtlBlock *cb, CtlBlock *dst, int span) {
+    const int words = (int)(sizeof(Ctl) / sizeof(int32_t));
+    const int32_t *src = (const int32_t *)&cb->c;
+    int32_t *out = (int32_t *)&dst->c;
+    for (int i = threadIdx.x; i < words; i += kBS) out[i] = src[i];
+    const int k = cb->c.k;
+    for (int j = threadIdx.x; j < span && j <= k; j += kBS)
+        dst->hist[(k - j) & (kHistRing - 1)] = cb->hist[(k - j) & (kHistRing - 1)];
+}
+
+// History entries a graph-written snapshot carries: more than a chunk adds
+// between two snapshots, and enough for predicted_left's mean rate.
+int snap_span(const pcga_solver &S) { return std::min(kHistRing, std::max(S.chunk + 8, 512)); }
+
 int snapshot(pcga_solver &S, const CtlBlock *cb, int slot) {
     HIP_TRY(hipMemcpyAsync(S.snap[slot], cb, sizeof(CtlBlock), hipMemcpyDeviceToHost, S.stream));
     HIP_TRY(hipEventRecord(S.ev[slot], S.stream));
@@ -1202,10 +1225,11 @@ int wait_snap(pcga_solver &S, int slot) {
 }
 
 template <typename T>
-int capture_iters(pcga_solver &S, const IterBufs<T> &B, int count, hipGraphExec_t *out) {
+int capture_iters(pcga_solver &S, const IterBufs<T> &B, int count, int slot, hipGraphExec_t *out) {
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(S.stream, hipStreamCaptureModeThreadLocal));
     launch_iters<T>(S, B, count);
+    k_snap<<<1, kBS, 0, S.stream>>>(B.cb, S.snap_dev[slot], snap_span(S));
     hipError_t e = hipStreamEndCapture(S.stream, &g);
     if (e != hipSuccess) return fail(PCGA_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
     e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
@@ -1217,17 +1241,21 @@ int capture_iters(pcga_solver &S, const IterBufs<T> &B, int count, hipGraphExec_
     return PCGA_OK;
 }
 
-// The chunk graph (S.chunk iterations) and the tail graph (kTailChunk).
+// The chunk graphs (S.chunk iterations) and the tail graphs (kTailChunk),
+// one of each per snapshot slot.
 template <typename T>
 int ensure_graph(pcga_solver &S, const IterBufs<T> &B) {
-    if (S.graph && S.graph_chunk == S.chunk && (S.graph_tail || S.chunk <= kTailChunk))
+    if (S.graph[0] && S.graph_chunk == S.chunk && (S.graph_tail[0] || S.chunk <= kTailChunk))
         return PCGA_OK;
     S.drop_graphs();
-    int st = capture_iters<T>(S, B, S.chunk, &S.graph);
-    if (st) return st;
-    if (S.chunk > kTailChunk && (st = capture_iters<T>(S, B, kTailChunk, &S.graph_tail))) {
-        S.drop_graphs();
-        return st;
+    for (int slot = 0; slot < 2; slot++) {
+        int st = capture_iters<T>(S, B, S.chunk, slot, &S.graph[slot]);
+        if (!st && S.chunk > kTailChunk)
+            st = capture_iters<T>(S, B, kTailChunk, slot, &S.graph_tail[slot]);
+        if (st) {
+            S.drop_graphs();
+            return st;
+        }
     }
     S.graph_chunk = S.chunk;
     return PCGA_OK;
@@ -1239,11 +1267,11 @@ int ensure_graph(pcga_solver &S, const IterBufs<T> &B) {
 // tolerance, and the iteration cap.  Large when there is too little history
 // or no decrease.  (CG's residual is not monotone: a mean over many
 // iterations predicts the stop better than the last chunk's decrease.)
-int64_t predicted_left(const CtlBlock *sn) {
+int64_t predicted_left(const CtlBlock *sn, int hist_span) {
     const Ctl &c = sn->c;
     const int64_t k = c.k;
     int64_t left = std::min<int64_t>((int64_t)c.maxit - k, (int64_t)1 << 40);
-    const int64_t span = std::min<int64_t>(k, kHistRing - 1);
+    const int64_t span = std::min<int64_t>(k, hist_span - 1);
     if (span < 2 || !(c.tol > 0.0)) return left;
     const double now = sn->hist[k & (kHistRing - 1)], then = sn->hist[(k - span) & (kHistRing - 1)];
     if (!(now > 0.0) || !(then > now)) return left;
@@ -1276,14 +1304,17 @@ int run_chunks(pcga_solver &S, const IterBufs<T> &B, double *hist_out, int64_t h
         st = ensure_graph<T>(S, B);
         if (st) return st;
     }
-    const bool tail_ok = !use_graph || S.graph_tail;
+    const bool tail_ok = !use_graph || S.graph_tail[0];
+    // history entries a snapshot holds (a graph writes the last snap_span)
+    const int hist_span = use_graph ? snap_span(S) : kHistRing;
     auto launch = [&](int slot, int count) -> int {
         if (use_graph) {
-            HIP_TRY(hipGraphLaunch(count == S.chunk ? S.graph : S.graph_tail, S.stream));
-        } else {
-            launch_iters<T>(S, B, count);
-            HIP_TRY(hipGetLastError());
+            HIP_TRY(hipGraphLaunch(count == S.chunk ? S.graph[slot] : S.graph_tail[slot], S.stream));
+            HIP_TRY(hipEventRecord(S.ev[slot], S.stream));
+            return PCGA_OK;
         }
+        launch_iters<T>(S, B, count);
+        HIP_TRY(hipGetLastError());
         return snapshot(S, B.cb, slot);
     };
     int64_t seen = 0;
@@ -1323,7 +1354,7 @@ int run_chunks(pcga_solver &S, const IterBufs<T> &B, double *hist_out, int64_t h
             final_slot = c & 1;
             return PCGA_OK;
         }
-        left = predicted_left(sn);
+        left = predicted_left(sn, hist_span);
         c++;
     }
 }

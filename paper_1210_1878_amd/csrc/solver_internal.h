@@ -47,6 +47,7 @@ struct pcga_solver {
     pcga::Partials P{};
     pcga::CtlBlock *cb = nullptr;
     pcga::CtlBlock *snap[2] = {nullptr, nullptr};   // pinned host
+    pcga::CtlBlock *snap_dev[2] = {nullptr, nullptr};   // the same, as device addresses
     hipEvent_t ev[2] = {nullptr, nullptr};
 
     int g_st = 1, g_zt = 1, g_z = 1;
@@ -54,16 +55,21 @@ struct pcga_solver {
     int max_blocks = pcga::kDefaultBlocks;
     int chunk = 32;
     bool use_graph = true;
-    hipGraphExec_t graph = nullptr;
+    // Chunk graphs, one per snapshot slot: `chunk` iterations, then a
+    // one-workgroup kernel that writes the control block to that slot's
+    // pinned host copy.  The tail graphs hold kTailChunk iterations: they
+    // are launched instead of a full chunk when the run is predicted to
+    // stop within the next chunk (fewer iterations left to run as no-ops
+    // after the stop).
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t graph_tail[2] = {nullptr, nullptr};
     int graph_chunk = 0;
-    // kTailChunk iterations: launched instead of a full chunk when the run
-    // is predicted to stop within the next chunk (fewer iterations left to
-    // run as no-ops after the stop)
-    hipGraphExec_t graph_tail = nullptr;
     void drop_graphs() {
-        if (graph) (void)hipGraphExecDestroy(graph);
-        if (graph_tail) (void)hipGraphExecDestroy(graph_tail);
-        graph = graph_tail = nullptr;
+        for (int i = 0; i < 2; i++) {
+            if (graph[i]) (void)hipGraphExecDestroy(graph[i]);
+            if (graph_tail[i]) (void)hipGraphExecDestroy(graph_tail[i]);
+            graph[i] = graph_tail[i] = nullptr;
+        }
         graph_chunk = 0;
     }
     int64_t sell_entries = 0;
