@@ -152,6 +152,48 @@ def test_fill_matches_dense_brute_force(ora, make, tau, fill):
     assert np.allclose(F.D, Dr, rtol=1e-12, atol=0)
 
 
+def _drop_when_final(A, tau):
+    """The other timing of the drop rule: updates kept in full, small
+    entries of a column removed only once the column is final."""
+    n = A.shape[0]
+    Z = np.eye(n)
+    for i in range(n):
+        for r in range(i):
+            if Z[r, i] != 0.0 and abs(Z[r, i]) < tau:
+                Z[r, i] = 0.0
+        p = A[i] @ Z[:, i]
+        for j in range(i + 1, n):
+            c = A[i] @ Z[:, j]
+            if c != 0.0:
+                Z[:, j] -= (c / p) * Z[:, i]
+    return Z
+
+
+@pytest.mark.parametrize("tau", [0.005, 0.02, 0.05, 0.1])
+@pytest.mark.parametrize("make", [lambda: orca.orca_problem(7, 6, 3),
+                                  lambda: orca.orca_problem(9, 8, 11),
+                                  lambda: const_periodic(6, 5),
+                                  lambda: mixed_sign_dominant(7, 6, True, 3),
+                                  lambda: mixed_sign_dominant(8, 5, False, 4)])
+def test_threshold_factor_matches_dense_brute_force(ora, make, tau):
+    """The plain threshold factor (no count cap) on 2-D grids against the
+    dense right-looking restatement with a cap that never binds: the drop
+    test after every column update, not only at the end, decides which
+    entries survive (with a binding tau the two timings give different
+    patterns on these grids)."""
+    p = make()
+    A = _dense_a(p)
+    Zr, Dr = _brute_force(A, tau, A.shape[0])
+    F = ora.ainv_setup(p, tau)
+    Z = F.dense_z()
+    assert np.array_equal(Z != 0, Zr != 0)
+    assert np.allclose(Z, Zr, rtol=1e-12, atol=0)
+    assert np.allclose(F.D, Dr, rtol=1e-12, atol=0)
+    if tau >= 0.02:
+        # the test tells the two timings apart on these grids
+        assert not np.array_equal(Z != 0, _drop_when_final(A, tau) != 0)
+
+
 def test_fill_rejects_negative(ora):
     with pytest.raises(ValueError):
         ora.ainv_setup(laplace1d(5), 0.0, fill=-1)
