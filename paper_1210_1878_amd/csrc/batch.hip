@@ -22,11 +22,17 @@
 //               t = D^-1 Z^T r
 //   kb_z        inner stop test; s = Z t,      FIRST: s = Z t, (s,r); the next
 //               (s,r); or, once the inner      CG step is inner iteration 0
-//               solve ended, x += e -> RESID   (beta = 0, d = s)
+//               solve ended, x += e -> RESID   (beta = 0, d = s; with the
+//                                              direction kept, after the
+//                                              first run: beta = rho / the
+//                                              last run's rho, d = s + beta d)
 //
 // A slot's right-hand sides share its state; one whose inner solve converged
 // is frozen (alpha = 0) until the slot's refinement step, and one that met the
-// outer tolerance stays frozen.  A kernel reads only its own state word and
+// outer tolerance stays frozen (with the direction kept, a frozen right-hand
+// side carries its direction and last rho to the next run).  The stop of an
+// inner run is inner_tol relative to its start (restarted refinement) or
+// max(inner_tol, tol / the outer residual) (direction kept).  A kernel reads only its own state word and
 // writes the next kernel's, and values read by all workgroups of a launch and
 // updated by workgroup 0 (rho, iteration count, active set) are
 // double-buffered by the parity of the graph iteration.
