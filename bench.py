@@ -604,8 +604,8 @@ def main():
     ap.add_argument("--reps", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "the solver runs on one GPU; multi-GPU sharding is a "
-                                   "design only (latitude bands + halo exchange), not implemented",
+        print(json.dumps({"error": "the solver runs on one GPU; multi-GPU sharding (latitude "
+                                   "bands + halo exchange) is designed but not implemented",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
